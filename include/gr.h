@@ -1,0 +1,218 @@
+/*
+ * gr.h - C ABI of the frontier-centric graph traversal library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library implements the data-centric abstraction of "Gunrock: GPU Graph
+ * Analytics" (Wang et al., ACM TOPC 2017): a traversal is a sequence of
+ * bulk-synchronous steps that map a vertex frontier to the next one (Sec. 3)
+ * using two operators,
+ *   - advance: expand the neighbour lists of the frontier (Sec. 4.1, Sec. 5.1:
+ *     dynamic grouping "TWC", merge-based load balancing "LB", and pull
+ *     traversal over the unvisited vertices, Alg. 2), and
+ *   - filter: cull visited vertices, remove duplicates and compact the output
+ *     frontier (Sec. 4.2, Sec. 5.2),
+ * driving breadth-first search (Sec. 6.1) and single-source shortest paths
+ * with atomic-min relaxation (Sec. 6.2, Alg. 1).
+ *
+ * Conventions for every entry point:
+ *   - Return GR_OK (0) or a negative gr_status; gr_last_error() then holds a
+ *     message (thread-local, valid until the next failing call on that thread).
+ *   - Arguments are validated on the host before any device work is enqueued.
+ *     Output contents are unspecified after an error.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it; traversal calls return only after their
+ *     results are complete (they synchronise the stream).
+ *   - Output arrays are caller-owned DEVICE buffers of exactly the stated size.
+ *     Index arrays of sources are HOST arrays.
+ *   - Graph storage: int32 CSR (row_offsets[V+1], col_indices[E]) with
+ *     optional uint32 weights[E] aligned with col_indices (Sec. 5.4).
+ *   - Result conventions (Alg. 1, Set_Problem_Data): an unreached vertex has
+ *     depth -1, parent -1, distance UINT32_MAX; a source has depth 0 /
+ *     distance 0 and parent -1.
+ *   - Parents are canonical: among all valid predecessors the one with the
+ *     smallest vertex id, so results are unique and do not depend on the
+ *     traversal strategy, the schedule or the thread count.
+ *   - A gr_ctx and its graphs must not be used by two host threads at once.
+ */
+#ifndef GR_H
+#define GR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GR_ABI_VERSION 1
+
+typedef enum gr_status {
+  GR_OK = 0,
+  GR_EINVAL = -1,         /* invalid argument or malformed CSR */
+  GR_ERANGE = -2,         /* a size or a possible distance exceeds the supported range */
+  GR_ENOMEM = -3,         /* device or host allocation failed */
+  GR_EHIP = -4,           /* a HIP runtime call failed (message holds the HIP error) */
+  GR_ENODEV = -5,         /* no usable gfx950 device */
+  GR_EUNSUPPORTED = -6    /* valid request this build cannot serve */
+} gr_status;
+
+/* How the per-iteration strategy is chosen (Sec. 5.1 heuristics). */
+typedef enum gr_policy {
+  GR_POLICY_HEURISTIC = 0, /* the paper's fixed thresholds (average degree, frontier size, do_a/do_b) */
+  GR_POLICY_LEARNED = 1,   /* the selector MLP loaded with gr_ctx_set_policy (falls back to heuristic if none) */
+  GR_POLICY_FIXED = 2,     /* always opts.fixed_action (pull falls back to push where pull is not allowed) */
+  GR_POLICY_RANDOM = 3     /* a seeded random action per iteration (testing: results must not change) */
+} gr_policy;
+
+/* Per-iteration advance strategies (Sec. 5.1, Table "traversal strategies"). */
+typedef enum gr_action {
+  GR_PUSH_TWC = 0, /* push, dynamic grouping by degree: workgroup / wavefront / lane tiers */
+  GR_PUSH_LB = 1,  /* push, merge-based load balance (input-balanced below lb_light_threshold) */
+  GR_PULL_TWC = 2, /* pull over the unvisited frontier, dynamic grouping per unvisited vertex */
+  GR_PULL_LB = 3   /* pull over the unvisited frontier, fixed-width edge groups per vertex */
+} gr_action;
+
+/* gr_graph_from_csr flags */
+#define GR_SYMMETRIC 0x1u       /* the CSR holds both (u,v) and (v,u) for every edge: pull may use it */
+#define GR_DEVICE_INPUT 0x2u    /* row_offsets/col_indices/weights are device pointers */
+
+typedef struct gr_ctx gr_ctx;
+typedef struct gr_graph gr_graph;
+
+/* One record per iteration when opts.trace is set (features of Sec. 5.1's
+ * direction heuristic, plus the measured time of the chosen step). */
+typedef struct gr_level_trace {
+  int32_t level;       /* iteration index d (frontier = vertices at depth d for BFS) */
+  int32_t action;      /* gr_action used */
+  int64_t n_f;         /* frontier vertices */
+  int64_t m_f;         /* sum of frontier degrees */
+  int64_t n_u;         /* unvisited vertices (BFS) */
+  int64_t m_u;         /* sum of unvisited degrees (BFS) */
+  int64_t max_deg_f;   /* largest frontier degree */
+  float features[8];   /* selector input features (see gr_features) */
+  float step_us;       /* device time of the iteration's advance+filter (event-timed) */
+  int32_t pad;
+} gr_level_trace;
+
+typedef struct gr_opts {
+  uint32_t struct_size;      /* sizeof(gr_opts); set by gr_opts_default */
+  int32_t policy;            /* gr_policy */
+  int32_t fixed_action;      /* gr_action for GR_POLICY_FIXED */
+  int32_t lb_light_threshold;/* PUSH_LB uses input-frontier balance below this frontier size (paper: 4096) */
+  uint64_t policy_seed;      /* seed for GR_POLICY_RANDOM */
+  float do_a;                /* push -> pull when m_f > m_u * do_a (Sec. 5.1, direction switch) */
+  float do_b;                /* pull -> push when m_f < m_u * do_b */
+  float lb_min_avg_degree;   /* LB when average degree >= this, else TWC (paper: 5) */
+  int32_t max_iterations;    /* stop after this many iterations (<= 0: unlimited) */
+  int32_t lb_chunk;          /* edges per workgroup in output-balanced LB (0 = library default) */
+  int32_t trace_capacity;    /* records available in trace */
+  gr_level_trace* trace;     /* host array, nullable: per-iteration records */
+  int32_t trace_count;       /* out: records written (may exceed capacity; extra are dropped) */
+  int32_t reserved[7];
+} gr_opts;
+
+typedef struct gr_run_stats {
+  int32_t iterations;        /* bulk-synchronous iterations executed */
+  int32_t action_count[4];   /* iterations per gr_action */
+  int64_t teps_edges;        /* sum of degrees of reached vertices, summed over sources (Sec. 7 TEPS) */
+  int64_t inspected_edges;   /* edges read by advance (push: m_f; pull: neighbours scanned) */
+  float device_ms;           /* event-timed device time of the call (after validation/setup) */
+  int32_t pad;
+} gr_run_stats;
+
+typedef struct gr_graph_info {
+  int64_t n_vertices;
+  int64_t n_edges;
+  int64_t max_degree;
+  uint32_t flags;            /* as given to gr_graph_from_csr */
+  int32_t weighted;          /* 1 if weights were given */
+  uint32_t max_weight;       /* largest weight (0 if unweighted) */
+  int32_t resorted;          /* 1 if ingest had to sort some adjacency list */
+} gr_graph_info;
+
+/* ---- library, context -------------------------------------------------- */
+
+int32_t gr_abi_version(void);
+const char* gr_last_error(void);
+
+/* sizeof() of the ABI structs, for bindings to check their layouts:
+ * which = 0 gr_opts, 1 gr_run_stats, 2 gr_level_trace, 3 gr_graph_info;
+ * -1 for anything else. */
+int32_t gr_abi_sizeof(int32_t which);
+
+/* Fill *opts with defaults: heuristic policy, do_a = 1/14, do_b = 1/576,
+ * lb_light_threshold = 4096, lb_min_avg_degree = 5, no trace. */
+void gr_opts_default(gr_opts* opts);
+
+/* Create a context on HIP device `device`.  GR_ENODEV if there is no such
+ * device or it is not gfx950.  The context owns pooled scratch memory. */
+gr_status gr_ctx_create(int32_t device, gr_ctx** out);
+gr_status gr_ctx_destroy(gr_ctx* ctx);
+
+/* Load selector MLP parameters (host float array of GR_MLP_N_PARAMS values,
+ * layout given at gr_mlp_forward).  params = NULL unloads (heuristic again). */
+#define GR_MLP_N_PARAMS 1476
+gr_status gr_ctx_set_policy(gr_ctx* ctx, const float* params, int32_t n_params);
+
+/* ---- graphs (Sec. 5.4: CSR storage) ----------------------------------- */
+
+/* Host-only validation of a CSR (no device work):
+ *   1 <= n_vertices <= 2^31 - 2, 0 <= n_edges <= 2^31 - 1,
+ *   row_offsets[0] = 0, row_offsets non-decreasing, row_offsets[V] = n_edges,
+ *   0 <= col_indices[i] < n_vertices.  Pointers must be host pointers. */
+gr_status gr_validate_csr(int64_t n_vertices, int64_t n_edges, const int32_t* row_offsets,
+                          const int32_t* col_indices);
+
+/* Copy a CSR graph into device memory owned by the returned handle.  Inputs
+ * are read-only and stay owned by the caller (host pointers unless
+ * GR_DEVICE_INPUT; device inputs are validated on the device).  Ingest sorts
+ * every adjacency list ascending by neighbour id (weights follow), computes
+ * degree statistics and, for SSSP, the largest weight.  weights may be NULL
+ * (unweighted: gr_sssp then fails with GR_EINVAL).  Without GR_SYMMETRIC the
+ * graph is treated as directed and pull strategies are not used. */
+gr_status gr_graph_from_csr(gr_ctx* ctx, int64_t n_vertices, int64_t n_edges,
+                            const int32_t* row_offsets, const int32_t* col_indices,
+                            const uint32_t* weights, uint32_t flags, void* stream,
+                            gr_graph** out);
+gr_status gr_graph_free(gr_graph* graph);
+gr_status gr_graph_get_info(const gr_graph* graph, gr_graph_info* out);
+/* Copy the ingested (sorted) CSR back into caller DEVICE buffers
+ * (row_offsets[V+1], col_indices[E], weights[E] or NULL). */
+gr_status gr_graph_export(const gr_graph* graph, int32_t* row_offsets, int32_t* col_indices,
+                          uint32_t* weights, void* stream);
+
+/* ---- traversals -------------------------------------------------------- */
+
+/* Breadth-first search from `source` (Sec. 6.1; direction-optimising
+ * traversal of Alg. 2).  depth: device int32[V] (required); parent: device
+ * int32[V] or NULL.  depth(v) = fewest edges from the source; parent(v) = the
+ * smallest-id in-neighbour at depth(v) - 1.  opts may be NULL (defaults);
+ * stats may be NULL. */
+gr_status gr_bfs(gr_ctx* ctx, const gr_graph* graph, int32_t source, int32_t* depth,
+                 int32_t* parent, gr_opts* opts, void* stream, gr_run_stats* stats);
+
+/* Shortest paths from n_sources host-given sources (Sec. 6.2, Alg. 1:
+ * advance with atomic-min relaxation, filter removing redundant vertices).
+ * dist: device uint32[V] (required) = least summed weight from any source;
+ * pred: device int32[V] or NULL = smallest-id in-neighbour u with
+ * dist(u) + w(u,v) = dist(v) (-1 at sources and unreached vertices).
+ * Needs weights.  GR_ERANGE when max_weight * (V - 1) >= 2^32 - 1 (a
+ * distance might not fit).  Only push strategies are used. */
+gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t n_sources,
+                  uint32_t* dist, int32_t* pred, gr_opts* opts, void* stream,
+                  gr_run_stats* stats);
+
+/* k independent BFS runs sharing each sweep over the graph (the paper's
+ * future-work task parallelism, Sec. 8: several BFS at once).  Sources are
+ * processed 64 per pass, one bit per source in per-vertex 64-bit masks.
+ * depth: device int32[k][V] (required), parent: device int32[k][V] or NULL,
+ * row s holding the single-source result for sources[s].  Needs GR_SYMMETRIC
+ * (parents are found by pulling over in-edges). */
+gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
+                       int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
+                       gr_run_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GR_H */

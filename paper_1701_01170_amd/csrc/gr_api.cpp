@@ -1,0 +1,654 @@
+// Host runtime of the gr_* C ABI: contexts, scratch pool, graph ingest and
+// validation, and the enactors that drive the bulk-synchronous traversal loop
+// (Sec. 3: a sequence of frontier-to-frontier steps until the frontier is
+// empty; Alg. 1 for SSSP, Alg. 2 for direction-optimising BFS).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gr_internal.h"
+#include "gr_policy.h"
+
+namespace gr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+gr_status fail(gr_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+gr_status pool_get(gr_ctx* ctx, Slot s, size_t bytes, void** out) {
+  DevBuf& b = ctx->pool[s];
+  if (bytes == 0) bytes = 1;
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      GR_HIP(hipFree(b.ptr));
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    size_t alloc = bytes + bytes / 8;  // head-room so slowly growing requests do not thrash
+    hipError_t e = hipMalloc(&b.ptr, alloc);
+    if (e != hipSuccess) {
+      b.ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(GR_ENOMEM, "device allocation of " + std::to_string(alloc) + " bytes failed: " +
+                                 hipGetErrorString(e));
+    }
+    b.bytes = alloc;
+  }
+  *out = b.ptr;
+  return GR_OK;
+}
+
+namespace {
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline int64_t words_for(int64_t V) { return (V + 31) / 32; }
+
+template <typename T>
+gr_status pool_typed(gr_ctx* ctx, Slot s, size_t count, T** out) {
+  void* p = nullptr;
+  GR_TRY(pool_get(ctx, s, count * sizeof(T), &p));
+  *out = static_cast<T*>(p);
+  return GR_OK;
+}
+
+gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st) {
+  GR_HIP(hipMemcpyAsync(ctx->host_ctrl, dev, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  GR_HIP(hipStreamSynchronize(st));
+  return GR_OK;
+}
+
+constexpr int kDefaultChunk = 2048;
+
+}  // namespace
+}  // namespace gr
+
+using namespace gr;
+
+// ============================================================================
+// library, context
+// ============================================================================
+
+extern "C" int32_t gr_abi_version(void) { return GR_ABI_VERSION; }
+
+extern "C" const char* gr_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int32_t gr_abi_sizeof(int32_t which) {
+  switch (which) {
+    case 0: return (int32_t)sizeof(gr_opts);
+    case 1: return (int32_t)sizeof(gr_run_stats);
+    case 2: return (int32_t)sizeof(gr_level_trace);
+    case 3: return (int32_t)sizeof(gr_graph_info);
+    default: return -1;
+  }
+}
+
+extern "C" void gr_opts_default(gr_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(gr_opts);
+  o->policy = GR_POLICY_HEURISTIC;
+  o->fixed_action = GR_PUSH_LB;
+  o->lb_light_threshold = 4096;
+  o->policy_seed = 0;
+  o->do_a = 1.0f / 14.0f;
+  o->do_b = 1.0f / 576.0f;
+  o->lb_min_avg_degree = 5.0f;
+  o->max_iterations = 0;
+  o->lb_chunk = 0;
+  o->trace_capacity = 0;
+  o->trace = nullptr;
+  o->trace_count = 0;
+}
+
+extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
+  if (!out) return fail(GR_EINVAL, "gr_ctx_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(GR_ENODEV, "no HIP device available");
+  }
+  if (device < 0 || device >= n)
+    return fail(GR_ENODEV, "device " + std::to_string(device) + " out of range (" +
+                               std::to_string(n) + " devices)");
+  hipDeviceProp_t prop;
+  GR_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GR_ENODEV, std::string("device is ") + prop.gcnArchName + ", this build targets gfx950");
+  DeviceGuard g(device);
+  gr_ctx* c = new gr_ctx();
+  c->device = device;
+  c->cu_count = prop.multiProcessorCount;
+  void* hc = nullptr;
+  if (hipHostMalloc(&hc, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(GR_ENOMEM, "pinned host allocation failed");
+  }
+  c->host_ctrl = static_cast<Ctrl*>(hc);
+  if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
+      hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess) {
+    gr_ctx_destroy(c);
+    return fail(GR_EHIP, "hipEventCreate failed");
+  }
+  *out = c;
+  return GR_OK;
+}
+
+extern "C" gr_status gr_ctx_destroy(gr_ctx* c) {
+  if (!c) return GR_OK;
+  DeviceGuard g(c->device);
+  for (auto& b : c->pool)
+    if (b.ptr) (void)hipFree(b.ptr);
+  if (c->host_ctrl) (void)hipHostFree(c->host_ctrl);
+  for (hipEvent_t ev : {c->ev_start, c->ev_stop, c->ev_a, c->ev_b})
+    if (ev) (void)hipEventDestroy(ev);
+  delete c;
+  return GR_OK;
+}
+
+// ============================================================================
+// graphs
+// ============================================================================
+
+extern "C" gr_status gr_validate_csr(int64_t V, int64_t E, const int32_t* R, const int32_t* C) {
+  if (V < 1 || V > (int64_t)INT32_MAX - 1)
+    return fail(GR_ERANGE, "n_vertices must be in [1, 2^31 - 2], got " + std::to_string(V));
+  if (E < 0 || E > (int64_t)INT32_MAX)
+    return fail(GR_ERANGE, "n_edges must be in [0, 2^31 - 1], got " + std::to_string(E));
+  if (!R) return fail(GR_EINVAL, "row_offsets is NULL");
+  if (E > 0 && !C) return fail(GR_EINVAL, "col_indices is NULL");
+  if (R[0] != 0) return fail(GR_EINVAL, "row_offsets[0] must be 0");
+  for (int64_t v = 0; v < V; ++v)
+    if (R[v + 1] < R[v])
+      return fail(GR_EINVAL, "row_offsets decreases at vertex " + std::to_string(v));
+  if ((int64_t)R[V] != E)
+    return fail(GR_EINVAL, "row_offsets[V] = " + std::to_string(R[V]) + " != n_edges = " +
+                               std::to_string(E));
+  for (int64_t e = 0; e < E; ++e)
+    if (C[e] < 0 || (int64_t)C[e] >= V)
+      return fail(GR_EINVAL, "col_indices[" + std::to_string(e) + "] = " + std::to_string(C[e]) +
+                                 " out of range");
+  return GR_OK;
+}
+
+namespace {
+
+void free_graph_buffers(gr_graph* g) {
+  if (g->R) (void)hipFree(g->R);
+  if (g->C) (void)hipFree(g->C);
+  if (g->W) (void)hipFree(g->W);
+  g->R = nullptr;
+  g->C = nullptr;
+  g->W = nullptr;
+}
+
+gr_status ingest(gr_ctx* ctx, gr_graph* g, const int32_t* R, const int32_t* C, const uint32_t* W,
+                 bool device_input, hipStream_t st) {
+  const int64_t V = g->V, E = g->E;
+  const hipMemcpyKind kind = device_input ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  GR_HIP(hipMalloc(&g->R, sizeof(int32_t) * (V + 1)));
+  GR_HIP(hipMalloc(&g->C, sizeof(int32_t) * std::max<int64_t>(E, 1)));
+  if (W) GR_HIP(hipMalloc(&g->W, sizeof(uint32_t) * std::max<int64_t>(E, 1)));
+  GR_HIP(hipMemcpyAsync(g->R, R, sizeof(int32_t) * (V + 1), kind, st));
+  if (E > 0) GR_HIP(hipMemcpyAsync(g->C, C, sizeof(int32_t) * E, kind, st));
+  if (W && E > 0) GR_HIP(hipMemcpyAsync(g->W, W, sizeof(uint32_t) * E, kind, st));
+
+  // small scratch: [0] csr flags, [1] max degree, [2] max weight, [3] unsorted count
+  int64_t* tmp = nullptr;
+  GR_HIP(hipMalloc(&tmp, sizeof(int64_t) * 4));
+  struct TmpFree {
+    int64_t* p;
+    ~TmpFree() { (void)hipFree(p); }
+  } tf{tmp};
+  GR_HIP(hipMemsetAsync(tmp, 0, sizeof(int64_t) * 4, st));
+  int64_t host4[4] = {0, 0, 0, 0};
+  if (device_input) {
+    GR_HIP(launch_csr_check(g->R, g->C, V, E, tmp, st));
+    GR_HIP(hipMemcpyAsync(host4, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    if (host4[0]) {
+      std::string why;
+      if (host4[0] & 1) why += " row_offsets[0] != 0;";
+      if (host4[0] & 2) why += " row_offsets[V] != n_edges;";
+      if (host4[0] & 4) why += " row_offsets decreasing;";
+      if (host4[0] & 8) why += " col_indices out of range;";
+      return fail(GR_EINVAL, "malformed device CSR:" + why);
+    }
+  }
+  // adjacency lists must be ascending (pull traversal, canonical parents)
+  int32_t* rows = nullptr;
+  GR_HIP(hipMalloc(&rows, sizeof(int32_t) * V));
+  struct RowsFree {
+    int32_t* p;
+    ~RowsFree() { (void)hipFree(p); }
+  } rf{rows};
+  uint32_t* ucount = reinterpret_cast<uint32_t*>(tmp + 3);
+  GR_HIP(launch_find_unsorted(g->R, g->C, g->W, V, rows, ucount, st));
+  GR_HIP(hipMemcpyAsync(&host4[3], tmp + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  GR_HIP(hipStreamSynchronize(st));
+  const int64_t n_unsorted = (int64_t)(uint32_t)(host4[3] & 0xffffffff);
+  if (n_unsorted > 0) {
+    uint64_t* scratch = nullptr;
+    GR_HIP(hipMalloc(&scratch, sizeof(uint64_t) * std::max<int64_t>(E, 1)));
+    hipError_t e1 = launch_row_sort(g->R, g->C, g->W, V, rows, n_unsorted, scratch, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(scratch);
+    GR_HIP(e1);
+    GR_HIP(e2);
+    g->resorted = 1;
+  }
+  GR_HIP(launch_graph_stats(g->R, g->W, V, E, tmp + 1, st));
+  GR_HIP(hipMemcpyAsync(&host4[1], tmp + 1, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  GR_HIP(hipStreamSynchronize(st));
+  g->max_degree = host4[1];
+  g->max_weight = (uint32_t)host4[2];
+  (void)ctx;
+  return GR_OK;
+}
+
+}  // namespace
+
+extern "C" gr_status gr_graph_from_csr(gr_ctx* ctx, int64_t V, int64_t E, const int32_t* R,
+                                       const int32_t* C, const uint32_t* W, uint32_t flags,
+                                       void* stream, gr_graph** out) {
+  if (!out) return fail(GR_EINVAL, "gr_graph_from_csr: out is NULL");
+  *out = nullptr;
+  if (flags & ~(GR_SYMMETRIC | GR_DEVICE_INPUT)) return fail(GR_EINVAL, "unknown flags");
+  const bool device_input = (flags & GR_DEVICE_INPUT) != 0;
+  if (device_input) {
+    if (V < 1 || V > (int64_t)INT32_MAX - 1)
+      return fail(GR_ERANGE, "n_vertices must be in [1, 2^31 - 2], got " + std::to_string(V));
+    if (E < 0 || E > (int64_t)INT32_MAX)
+      return fail(GR_ERANGE, "n_edges must be in [0, 2^31 - 1], got " + std::to_string(E));
+    if (!R || (E > 0 && !C)) return fail(GR_EINVAL, "CSR pointer is NULL");
+  } else {
+    GR_TRY(gr_validate_csr(V, E, R, C));
+  }
+  if (!ctx) return fail(GR_EINVAL, "ctx is NULL");
+  DeviceGuard dg(ctx->device);
+  gr_graph* g = new gr_graph();
+  g->ctx = ctx;
+  g->V = V;
+  g->E = E;
+  g->flags = flags;
+  gr_status s = ingest(ctx, g, R, C, W, device_input, static_cast<hipStream_t>(stream));
+  if (s != GR_OK) {
+    free_graph_buffers(g);
+    delete g;
+    return s;
+  }
+  *out = g;
+  return GR_OK;
+}
+
+extern "C" gr_status gr_graph_free(gr_graph* g) {
+  if (!g) return GR_OK;
+  DeviceGuard dg(g->ctx->device);
+  free_graph_buffers(g);
+  delete g;
+  return GR_OK;
+}
+
+extern "C" gr_status gr_graph_get_info(const gr_graph* g, gr_graph_info* out) {
+  if (!g || !out) return fail(GR_EINVAL, "gr_graph_get_info: NULL argument");
+  out->n_vertices = g->V;
+  out->n_edges = g->E;
+  out->max_degree = g->max_degree;
+  out->flags = g->flags;
+  out->weighted = g->W != nullptr;
+  out->max_weight = g->max_weight;
+  out->resorted = g->resorted;
+  return GR_OK;
+}
+
+extern "C" gr_status gr_graph_export(const gr_graph* g, int32_t* R, int32_t* C, uint32_t* W,
+                                     void* stream) {
+  if (!g || !R || (g->E > 0 && !C)) return fail(GR_EINVAL, "gr_graph_export: NULL argument");
+  if (W && !g->W) return fail(GR_EINVAL, "graph has no weights");
+  DeviceGuard dg(g->ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  GR_HIP(hipMemcpyAsync(R, g->R, sizeof(int32_t) * (g->V + 1), hipMemcpyDeviceToDevice, st));
+  if (g->E > 0) {
+    GR_HIP(hipMemcpyAsync(C, g->C, sizeof(int32_t) * g->E, hipMemcpyDeviceToDevice, st));
+    if (W) GR_HIP(hipMemcpyAsync(W, g->W, sizeof(uint32_t) * g->E, hipMemcpyDeviceToDevice, st));
+  }
+  GR_HIP(hipStreamSynchronize(st));
+  return GR_OK;
+}
+
+// ============================================================================
+// traversal helpers
+// ============================================================================
+
+namespace {
+
+gr_status check_opts(gr_opts* opts, gr_opts* local) {
+  if (!opts) {
+    gr_opts_default(local);
+    return GR_OK;
+  }
+  if (opts->struct_size != sizeof(gr_opts))
+    return fail(GR_EINVAL, "opts->struct_size mismatch (call gr_opts_default)");
+  if (opts->policy < GR_POLICY_HEURISTIC || opts->policy > GR_POLICY_RANDOM)
+    return fail(GR_EINVAL, "opts->policy out of range");
+  if (opts->fixed_action < GR_PUSH_TWC || opts->fixed_action > GR_PULL_LB)
+    return fail(GR_EINVAL, "opts->fixed_action out of range");
+  if (!(opts->do_a >= 0.0f) || !(opts->do_b >= 0.0f)) return fail(GR_EINVAL, "do_a/do_b must be >= 0");
+  if (opts->lb_chunk < 0 || (opts->lb_chunk > 0 && (opts->lb_chunk < 256 || opts->lb_chunk > (1 << 20))))
+    return fail(GR_EINVAL, "opts->lb_chunk must be 0 or in [256, 2^20]");
+  if (opts->trace_capacity < 0 || (opts->trace_capacity > 0 && !opts->trace))
+    return fail(GR_EINVAL, "opts->trace is NULL with a positive capacity");
+  *local = *opts;
+  return GR_OK;
+}
+
+void record_trace(gr_opts* opts, const LevelFeatures& lf, int action, float step_us) {
+  if (!opts || !opts->trace) return;
+  int i = opts->trace_count++;
+  if (i >= opts->trace_capacity) return;
+  gr_level_trace& t = opts->trace[i];
+  t.level = lf.level;
+  t.action = action;
+  t.n_f = lf.n_f;
+  t.m_f = lf.m_f;
+  t.n_u = lf.n_u;
+  t.m_u = lf.m_u;
+  t.max_deg_f = lf.max_deg_f;
+  selector_features(lf, t.features);
+  t.step_us = step_us;
+  t.pad = 0;
+}
+
+}  // namespace
+
+// ============================================================================
+// BFS enactor (Sec. 6.1, Alg. 2)
+// ============================================================================
+
+extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth,
+                            int32_t* parent, gr_opts* opts_in, void* stream, gr_run_stats* stats) {
+  if (!ctx || !g) return fail(GR_EINVAL, "gr_bfs: ctx or graph is NULL");
+  if (g->ctx != ctx) return fail(GR_EINVAL, "gr_bfs: graph belongs to another context");
+  if (!depth) return fail(GR_EINVAL, "gr_bfs: depth is NULL");
+  if (source < 0 || (int64_t)source >= g->V)
+    return fail(GR_EINVAL, "gr_bfs: source " + std::to_string(source) + " out of range");
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t V = g->V, E = g->E, NW = words_for(V);
+  const bool pull_ok = (g->flags & GR_SYMMETRIC) != 0;
+  const int G = stats_grid();
+  const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+
+  uint32_t *bmA, *bmB;
+  int32_t *qA, *qB, *uA = nullptr, *uB = nullptr, *offsets;
+  int64_t* bsums;
+  Ctrl* ctrl;
+  GR_TRY(pool_typed(ctx, S_BM_A, NW, &bmA));
+  GR_TRY(pool_typed(ctx, S_BM_B, NW, &bmB));
+  GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
+  GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  if (pull_ok) {
+    GR_TRY(pool_typed(ctx, S_U_A, V, &uA));
+    GR_TRY(pool_typed(ctx, S_U_B, V, &uB));
+  }
+  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, 3 * G + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
+  Ctrl* hc = ctx->host_ctrl;
+
+  int32_t* q[2] = {qA, qB};
+  int32_t* ul[2] = {uA, uB};
+  uint32_t* bm_old = bmA;
+  uint32_t* bm_live = bmB;
+
+  GR_HIP(hipEventRecord(ctx->ev_start, st));
+  GR_HIP(launch_bfs_init(depth, parent, V, bm_old, bm_live, NW, source, qA, ctrl, st));
+  int cur = 0, ucur = 0;
+  GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+                               &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
+  GR_TRY(read_ctrl(ctx, ctrl, st));
+
+  Selector sel;
+  sel.init(opts, g->V, g->E, pull_ok, /*is_sssp=*/false, ctx->policy_loaded);
+  LevelFeatures lf{};
+  lf.V = V;
+  lf.E = E;
+  int64_t n_f = hc->n_f, m_f = hc->m_f;
+  int64_t visited_n = n_f, visited_m = m_f;
+  int64_t n_ulist = 0;
+  bool have_unv = false;
+  int64_t inspected_prev = 0, inspected_push = 0;
+  int level = 0;
+  gr_run_stats rs{};
+  const bool tracing = opts_in && opts_in->trace;
+
+  while (n_f > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
+    lf.level = level;
+    lf.n_f = n_f;
+    lf.m_f = m_f;
+    lf.max_deg_f = hc->max_deg;
+    lf.n_u = V - visited_n;
+    lf.m_u = E - visited_m;
+    lf.prev_pull = sel.mode_pull ? 1 : 0;
+    const int action = sel.decide(lf);
+    if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+    const int next_depth = level + 1;
+    if (action == GR_PUSH_LB || action == GR_PUSH_TWC) {
+      if (action == GR_PUSH_TWC) {
+        GR_HIP(launch_bfs_push_twc(q[cur], n_f, g->R, g->C, bm_old, bm_live, depth, parent,
+                                   next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1], st));
+      } else if (n_f < opts.lb_light_threshold) {
+        GR_HIP(launch_bfs_push_light(q[cur], n_f, g->R, g->C, bm_old, bm_live, depth, parent,
+                                     next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1], st));
+      } else {
+        GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, offsets, bm_live, st));
+        GR_HIP(launch_bfs_push_lb(q[cur], offsets, n_f, m_f, g->R, g->C, bm_old, bm_live, depth,
+                                  parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1], chunk,
+                                  st));
+      }
+      inspected_push += m_f;
+      have_unv = false;
+    } else {
+      if (!have_unv) {
+        GR_HIP(launch_fill_u32(&ctrl->u_count[ucur], 1, 0u, st));
+        GR_HIP(launch_gen_unvisited(bm_old, g->R, V, ul[ucur], &ctrl->u_count[ucur], st));
+        GR_TRY(read_ctrl(ctx, ctrl, st));
+        n_ulist = hc->u_count[ucur];
+        have_unv = true;
+      }
+      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, ul[ucur], n_ulist, g->R, g->C, bm_old, bm_live,
+                             depth, parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1],
+                             ul[ucur ^ 1], &ctrl->u_count[ucur ^ 1], &ctrl->inspected, st));
+      GR_HIP(launch_bitmap_or(bm_live, bm_old, NW, st));
+      ucur ^= 1;
+    }
+    if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+    rs.action_count[action]++;
+    std::swap(bm_old, bm_live);
+    cur ^= 1;
+    ++level;
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+                                 &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
+    GR_TRY(read_ctrl(ctx, ctrl, st));
+    if (tracing) {
+      float ms = 0.f;
+      GR_HIP(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
+      record_trace(opts_in, lf, action, ms * 1000.0f);
+    }
+    n_f = hc->n_f;
+    m_f = hc->m_f;
+    if (have_unv) n_ulist = hc->u_count[ucur];
+    visited_n += n_f;
+    visited_m += m_f;
+  }
+  GR_HIP(hipEventRecord(ctx->ev_stop, st));
+  GR_HIP(hipEventSynchronize(ctx->ev_stop));
+  if (stats) {
+    float ms = 0.f;
+    GR_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    rs.iterations = level;
+    // when stopped early the last frontier is reached but not expanded
+    rs.teps_edges = visited_m;
+    rs.inspected_edges = inspected_push + (hc->inspected - inspected_prev);
+    rs.device_ms = ms;
+    *stats = rs;
+  }
+  return GR_OK;
+}
+
+// ============================================================================
+// SSSP enactor (Sec. 6.2, Alg. 1)
+// ============================================================================
+
+extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sources,
+                             int32_t n_sources, uint32_t* dist, int32_t* pred, gr_opts* opts_in,
+                             void* stream, gr_run_stats* stats) {
+  if (!ctx || !g) return fail(GR_EINVAL, "gr_sssp: ctx or graph is NULL");
+  if (g->ctx != ctx) return fail(GR_EINVAL, "gr_sssp: graph belongs to another context");
+  if (!dist) return fail(GR_EINVAL, "gr_sssp: dist is NULL");
+  if (!sources || n_sources < 1) return fail(GR_EINVAL, "gr_sssp: need at least one source");
+  if (!g->W) return fail(GR_EINVAL, "gr_sssp: graph has no weights");
+  for (int32_t i = 0; i < n_sources; ++i)
+    if (sources[i] < 0 || (int64_t)sources[i] >= g->V)
+      return fail(GR_EINVAL, "gr_sssp: source " + std::to_string(sources[i]) + " out of range");
+  if ((uint64_t)g->max_weight * (uint64_t)(g->V - 1) >= 0xffffffffull)
+    return fail(GR_ERANGE, "gr_sssp: max_weight * (V - 1) >= 2^32 - 1, distances may not fit uint32");
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t V = g->V, E = g->E;
+  const int G = stats_grid();
+  const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+
+  std::vector<int32_t> uniq(sources, sources + n_sources);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  const int32_t n_src = (int32_t)uniq.size();
+
+  int32_t *qA, *qB, *offsets, *tags, *src_dev;
+  unsigned long long* keys;
+  int64_t* bsums;
+  Ctrl* ctrl;
+  GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
+  GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, 3 * G + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
+  GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
+  GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
+  GR_TRY(pool_typed(ctx, S_TMP0, n_src, &src_dev));
+  Ctrl* hc = ctx->host_ctrl;
+  int32_t* q[2] = {qA, qB};
+
+  GR_HIP(hipMemcpyAsync(src_dev, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
+  GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
+  GR_HIP(hipStreamSynchronize(st));  // the host vector must outlive the copies
+  GR_HIP(hipEventRecord(ctx->ev_start, st));
+  GR_HIP(launch_sssp_init(keys, tags, V, ctrl, st));
+  GR_HIP(launch_sssp_seed(src_dev, n_src, keys, tags, ctrl, st));
+  int cur = 0;
+  GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+                               &ctrl->q_count[cur ^ 1], nullptr, st));
+  GR_TRY(read_ctrl(ctx, ctrl, st));
+
+  Selector sel;
+  sel.init(opts, V, E, /*pull_ok=*/false, /*is_sssp=*/true, ctx->policy_loaded);
+  LevelFeatures lf{};
+  lf.V = V;
+  lf.E = E;
+  int64_t n_f = hc->n_f, m_f = hc->m_f;
+  int it = 0;
+  int64_t inspected = 0;
+  gr_run_stats rs{};
+  const bool tracing = opts_in && opts_in->trace;
+  while (n_f > 0 && (opts.max_iterations <= 0 || it < opts.max_iterations)) {
+    lf.level = it;
+    lf.n_f = n_f;
+    lf.m_f = m_f;
+    lf.max_deg_f = hc->max_deg;
+    lf.n_u = 0;
+    lf.m_u = 0;
+    lf.prev_pull = 0;
+    const int action = sel.decide(lf);
+    if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+    const bool lb = action == GR_PUSH_LB;
+    const bool light = lb && n_f < opts.lb_light_threshold;
+    if (lb && !light) GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, offsets, nullptr, st));
+    GR_HIP(launch_sssp_relax(lb ? 1 : 0, light, q[cur], offsets, n_f, m_f, g->R, g->C, g->W, keys,
+                             tags, it + 1, q[cur ^ 1], &ctrl->q_count[cur ^ 1], chunk, st));
+    if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+    inspected += m_f;
+    rs.action_count[action]++;
+    cur ^= 1;
+    ++it;
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+                                 &ctrl->q_count[cur ^ 1], nullptr, st));
+    GR_TRY(read_ctrl(ctx, ctrl, st));
+    if (tracing) {
+      float ms = 0.f;
+      GR_HIP(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
+      record_trace(opts_in, lf, action, ms * 1000.0f);
+    }
+    n_f = hc->n_f;
+    m_f = hc->m_f;
+  }
+  int64_t* reached = &ctrl->reached_edges;
+  GR_HIP(launch_sssp_finalize(keys, g->R, V, dist, pred, src_dev, n_src, reached, st));
+  GR_HIP(hipEventRecord(ctx->ev_stop, st));
+  GR_TRY(read_ctrl(ctx, ctrl, st));
+  if (stats) {
+    float ms = 0.f;
+    GR_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    rs.iterations = it;
+    rs.teps_edges = hc->reached_edges;
+    rs.inspected_edges = inspected;
+    rs.device_ms = ms;
+    *stats = rs;
+  }
+  return GR_OK;
+}
+
+// ============================================================================
+// multi-source BFS
+// ============================================================================
+
+extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t* sources,
+                                  int32_t k, int32_t* depth, int32_t* parent, gr_opts* opts,
+                                  void* stream, gr_run_stats* stats) {
+  (void)ctx; (void)g; (void)sources; (void)k; (void)depth; (void)parent; (void)opts;
+  (void)stream; (void)stats;
+  return fail(GR_EUNSUPPORTED, "gr_bfs_multi is not built yet");
+}
+
+extern "C" gr_status gr_ctx_set_policy(gr_ctx* ctx, const float* params, int32_t n_params) {
+  (void)params; (void)n_params;
+  if (!ctx) return fail(GR_EINVAL, "ctx is NULL");
+  return fail(GR_EUNSUPPORTED, "learned policy is not built yet");
+}

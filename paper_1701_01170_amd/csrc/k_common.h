@@ -1,0 +1,100 @@
+// Device-side building blocks for gfx950 (CDNA4, 64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gr {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// Number of set bits of `m` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Wave-aggregated append: every active lane with `pred` gets a distinct slot
+// in a global queue whose tail is `*counter`; one atomic per wavefront.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  uint64_t m = __ballot(pred);
+  uint32_t base = 0;
+  if (m != 0) {
+    int leader = __ffsll((unsigned long long)m) - 1;
+    if (lane() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+  }
+  return base + lanes_below(m);
+}
+
+// Inclusive prefix sum across the wavefront (all 64 lanes must be active).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(x, o);
+    if (lane() >= o) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T y = __shfl_xor(x, o);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Exclusive prefix sum over a workgroup of BLOCK threads (all active).
+// `wave_tot` must hold BLOCK/64 + 1 entries of shared memory.  Returns the
+// exclusive prefix of the calling thread; *total receives the block total.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T* wave_tot, T* total) {
+  constexpr int NW = BLOCK / kWave;
+  const int w = threadIdx.x / kWave;
+  T inc = wave_incl_scan(x);
+  if (lane() == kWave - 1) wave_tot[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (int i = 0; i < NW; ++i) {
+      T t = wave_tot[i];
+      wave_tot[i] = run;
+      run += t;
+    }
+    wave_tot[NW] = run;
+  }
+  __syncthreads();
+  T r = wave_tot[w] + inc - x;
+  *total = wave_tot[NW];
+  __syncthreads();
+  return r;
+}
+
+// Largest index i in [lo, hi] with a[i] <= key (a ascending, a[lo] <= key).
+template <typename T, typename K>
+__device__ __forceinline__ int upper_index(const T* a, int lo, int hi, K key) {
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if ((K)a[mid] <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool bm_test(const uint32_t* bm, int32_t v) {
+  return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+
+}  // namespace gr

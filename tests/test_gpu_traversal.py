@@ -1,0 +1,242 @@
+"""GPU parity: gr_bfs / gr_sssp through the C ABI against the CPU oracle,
+element by element, bit-exact (all arithmetic is integer).  Sizes span many
+workgroups and end in ragged tails; every strategy and policy is exercised
+(the strategy may change only the time, never the result)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1701_01170_amd as gr
+from conftest import golden_graph, load_golden
+from paper_1701_01170_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+U32MAX = 0xFFFFFFFF
+POLICIES = [
+    ("heuristic", dict()),
+    ("push_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC)),
+    ("push_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB)),
+    ("push_lb_nolight", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0)),
+    ("push_lb_light", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=1 << 30)),
+    ("pull_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_TWC)),
+    ("pull_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_LB)),
+    ("random1", dict(policy=gr.POLICY_RANDOM, policy_seed=1)),
+    ("random2", dict(policy=gr.POLICY_RANDOM, policy_seed=2, lb_light_threshold=0)),
+    ("small_chunk", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
+                         lb_chunk=256)),
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gr.Context(0)
+
+
+def np_of(t):
+    return t.cpu().numpy()
+
+
+def run_bfs_all(ctx, hg, sources, symmetric=True, policies=POLICIES):
+    g = gr.Graph.from_host(ctx, hg, symmetric=symmetric)
+    for s in sources:
+        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
+        for name, kw in policies:
+            d, p, st = gr.bfs(g, int(s), opts=gr.default_opts(**kw))
+            np.testing.assert_array_equal(np_of(d), ed, err_msg=f"depth src={s} policy={name}")
+            np.testing.assert_array_equal(np_of(p), ep, err_msg=f"parent src={s} policy={name}")
+            assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed >= 0)
+            assert st["iterations"] == int(ed.max()) + 1
+    g.free()
+
+
+def run_sssp_all(ctx, hg, source_sets, symmetric=True, policies=POLICIES):
+    g = gr.Graph.from_host(ctx, hg, symmetric=symmetric)
+    for srcs in source_sets:
+        ed, ep = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, srcs)
+        for name, kw in policies:
+            d, p, st = gr.sssp(g, srcs, opts=gr.default_opts(**kw))
+            np.testing.assert_array_equal(np_of(d).view(np.uint32), ed,
+                                          err_msg=f"dist srcs={list(srcs)[:4]} policy={name}")
+            np.testing.assert_array_equal(np_of(p), ep,
+                                          err_msg=f"pred srcs={list(srcs)[:4]} policy={name}")
+            assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed != U32MAX)
+    g.free()
+
+
+@pytest.mark.parametrize("name", ["directed7.txt", "undirected_ties8.txt"])
+def test_golden(ctx, name):
+    fx = load_golden(name)
+    hg = golden_graph(fx)
+    g = gr.Graph.from_host(ctx, hg, symmetric=fx["undirected"])
+    for case in fx["bfs"]:
+        for pname, kw in POLICIES:
+            d, p, _ = gr.bfs(g, case["source"], opts=gr.default_opts(**kw))
+            np.testing.assert_array_equal(np_of(d), case["depth"], err_msg=pname)
+            np.testing.assert_array_equal(np_of(p), case["parent"], err_msg=pname)
+    for case in fx["sssp"]:
+        for pname, kw in POLICIES:
+            d, p, _ = gr.sssp(g, [case["source"]], opts=gr.default_opts(**kw))
+            np.testing.assert_array_equal(np_of(d).view(np.uint32).astype(np.int64), case["dist"],
+                                          err_msg=pname)
+            np.testing.assert_array_equal(np_of(p), case["pred"], err_msg=pname)
+
+
+def test_rmat14_bfs_all_policies(ctx, rmat14):
+    run_bfs_all(ctx, rmat14, gg.sources(rmat14, 6, seed=1000))
+
+
+def test_rmat14_sssp_all_policies(ctx, rmat14):
+    srcs = gg.sources(rmat14, 3, seed=1000)
+    run_sssp_all(ctx, rmat14, [[int(s)] for s in srcs] + [srcs.tolist()])
+
+
+def test_grid_bfs_sssp(ctx):
+    hg = gg.add_weights(gg.grid(61, 173), seed=5)
+    run_bfs_all(ctx, hg, [0, 61 * 173 // 2 + 17, 61 * 173 - 1])
+    run_sssp_all(ctx, hg, [[0], [5000, 9], [61 * 173 - 1]])
+
+
+def test_er_bfs_sssp(ctx):
+    hg = gg.add_weights(gg.erdos_renyi(30001, 6, seed=3), seed=8)
+    run_bfs_all(ctx, hg, gg.sources(hg, 3, seed=4))
+    run_sssp_all(ctx, hg, [[int(s)] for s in gg.sources(hg, 2, seed=4)])
+
+
+def test_unsorted_input_is_sorted_on_ingest(ctx, rmat14):
+    hg = rmat14
+    rng = np.random.default_rng(0)
+    C = hg.col_indices.copy()
+    W = hg.weights.copy()
+    R = hg.row_offsets
+    for v in rng.choice(hg.n_vertices, 500, replace=False):
+        a, b = R[v], R[v + 1]
+        perm = rng.permutation(b - a)
+        C[a:b] = C[a:b][perm]
+        W[a:b] = W[a:b][perm]
+    shuffled = gg.HostGraph(R.copy(), C, W)
+    g = gr.Graph.from_host(ctx, shuffled)
+    assert g.resorted
+    R2, C2, W2 = g.export()
+    np.testing.assert_array_equal(np_of(C2), hg.col_indices)
+    np.testing.assert_array_equal(np_of(W2).view(np.uint32), hg.weights)
+    g.free()
+    srcs = gg.sources(hg, 2, seed=9)
+    run_bfs_all(ctx, shuffled, srcs)
+    run_sssp_all(ctx, shuffled, [[int(srcs[0])]])
+
+
+def test_long_unsorted_rows(ctx):
+    # a star whose centre list (5000 > LDS sort size) arrives reversed
+    n = 5001
+    edges = [(0, i) for i in range(n - 1, 0, -1)] + [(i, 0) for i in range(1, n)]
+    w = [(i * 7) % 64 + 1 for i in range(len(edges))]
+    hg = gg.from_edges(n, edges, w)
+    g = gr.Graph.from_host(ctx, hg)
+    assert g.resorted
+    _, C2, _ = g.export()
+    np.testing.assert_array_equal(np_of(C2)[:n - 1], np.arange(1, n))
+    g.free()
+    run_bfs_all(ctx, hg, [0, 17])
+    run_sssp_all(ctx, hg, [[0], [17]])
+
+
+def test_directed_random(ctx):
+    rng = np.random.default_rng(3)
+    V = 20000
+    e = rng.integers(0, V, size=(120000, 2))
+    w = rng.integers(1, 65, size=120000)
+    hg = gg.sort_adjacency(gg.from_edges(V, e, w))
+    srcs = rng.integers(0, V, size=3)
+    run_bfs_all(ctx, hg, srcs, symmetric=False)
+    run_sssp_all(ctx, hg, [[int(s)] for s in srcs], symmetric=False)
+
+
+def test_degenerate_graphs(ctx):
+    # one vertex, no edges
+    hg = gg.HostGraph(np.array([0, 0], np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint32))
+    run_bfs_all(ctx, hg, [0])
+    run_sssp_all(ctx, hg, [[0]])
+    # isolated source inside a bigger graph, self-loops and duplicate edges
+    hg = gg.from_edges(6, [(1, 2), (2, 1), (2, 2), (2, 3), (3, 2), (2, 3), (3, 2), (4, 4)],
+                       [3, 3, 1, 9, 9, 2, 2, 1])
+    hg = gg.sort_adjacency(hg)
+    run_bfs_all(ctx, hg, [0, 1, 4], symmetric=False)
+    run_sssp_all(ctx, hg, [[0], [1], [1, 4]], symmetric=False)
+    # zero weights: ties at distance 0, sources keep pred -1
+    hg = gg.from_edges(5, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4)], [0, 0, 0, 0, 5], symmetric=True)
+    hg = gg.sort_adjacency(hg)
+    run_sssp_all(ctx, hg, [[0], [0, 2], [4]])
+
+
+def test_hub_frontier_spans_many_chunks(ctx):
+    # two hubs of degree 60000 -> frontier segments far longer than one LB chunk
+    n = 60002
+    edges = [(0, i) for i in range(2, n)] + [(1, i) for i in range(2, n)]
+    hg = gg.add_weights(gg.sort_adjacency(gg.from_edges(n, edges, symmetric=True)), seed=2)
+    run_bfs_all(ctx, hg, [0, 5])
+    run_sssp_all(ctx, hg, [[0], [5]])
+
+
+def test_errors_on_device(ctx, rmat14):
+    g = gr.Graph.from_host(ctx, rmat14)
+    with pytest.raises(gr.GrError) as ei:
+        gr.bfs(g, rmat14.n_vertices)
+    assert ei.value.code == gr.GR_EINVAL
+    with pytest.raises(gr.GrError) as ei:
+        gr.sssp(g, [-1])
+    assert ei.value.code == gr.GR_EINVAL
+    g2 = gr.Graph.from_csr(ctx, rmat14.row_offsets, rmat14.col_indices)
+    with pytest.raises(gr.GrError) as ei:
+        gr.sssp(g2, [0])
+    assert ei.value.code == gr.GR_EINVAL
+    big = gg.from_edges(3, [(0, 1), (1, 2)], [0xF0000000, 0x20000000])
+    g3 = gr.Graph.from_host(ctx, big, symmetric=False)
+    with pytest.raises(gr.GrError) as ei:
+        gr.sssp(g3, [0])
+    assert ei.value.code == gr.GR_ERANGE
+
+
+def test_device_input_csr(ctx, rmat14):
+    import torch
+    R = torch.from_numpy(rmat14.row_offsets).cuda()
+    C = torch.from_numpy(rmat14.col_indices).cuda()
+    W = torch.from_numpy(rmat14.weights.view(np.int32)).cuda()
+    g = gr.Graph.from_csr(ctx, R, C, W)
+    assert g.n_edges == rmat14.n_edges and g.max_degree == rmat14.degrees().max()
+    s = int(gg.sources(rmat14, 1)[0])
+    d, p, _ = gr.bfs(g, s)
+    ed, ep = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, s)
+    np.testing.assert_array_equal(np_of(d), ed)
+    np.testing.assert_array_equal(np_of(p), ep)
+    bad = C.clone()
+    bad[7] = rmat14.n_vertices
+    with pytest.raises(gr.GrError) as ei:
+        gr.Graph.from_csr(ctx, R, bad, W)
+    assert ei.value.code == gr.GR_EINVAL
+
+
+def test_max_iterations_stops_early(ctx, rmat14):
+    g = gr.Graph.from_host(ctx, rmat14)
+    s = int(gg.sources(rmat14, 1)[0])
+    ed, _ = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, s)
+    d, _, st = gr.bfs(g, s, opts=gr.default_opts(max_iterations=2))
+    exp = np.where(ed <= 2, ed, -1)
+    np.testing.assert_array_equal(np_of(d), exp)
+    assert st["iterations"] == 2
+
+
+def test_trace_records(ctx, rmat14):
+    g = gr.Graph.from_host(ctx, rmat14)
+    s = int(gg.sources(rmat14, 1)[0])
+    ed, _ = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, s)
+    prof = oracle.level_profile(rmat14.row_offsets, ed)
+    cap = 64
+    buf = (gr.LevelTrace * cap)()
+    o = gr.default_opts(trace=buf, trace_capacity=cap)
+    gr.bfs(g, s, opts=o)
+    assert o.trace_count == len(prof)
+    for t, ref in zip(buf[:o.trace_count], prof):
+        assert (t.level, t.n_f, t.m_f, t.n_u, t.m_u, t.max_deg_f) == (
+            ref["level"], ref["n_f"], ref["m_f"], ref["n_u"], ref["m_u"], ref["maxdeg_f"])
+        assert t.step_us > 0
