@@ -103,7 +103,7 @@ typedef struct gr_opts {
   float do_b;                /* pull -> push when m_f < m_u * do_b */
   float lb_min_avg_degree;   /* LB when average degree >= this, else TWC (paper: 5) */
   int32_t max_iterations;    /* stop after this many iterations (<= 0: unlimited) */
-  int32_t lb_chunk;          /* edges per workgroup in output-balanced LB (0 = library default) */
+  int32_t lb_chunk;          /* edges per workgroup in output-balanced LB: 0 (default 8192), 2048, 4096, 8192, 16384 */
   int32_t trace_capacity;    /* records available in trace */
   gr_level_trace* trace;     /* host array, nullable: per-iteration records */
   int32_t trace_count;       /* out: records written (may exceed capacity; extra are dropped) */

@@ -78,7 +78,7 @@ gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st) {
   return GR_OK;
 }
 
-constexpr int kDefaultChunk = 2048;
+constexpr int kDefaultChunk = 8192;
 
 }  // namespace
 }  // namespace gr
@@ -356,8 +356,9 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
   if (opts->fixed_action < GR_PUSH_TWC || opts->fixed_action > GR_PULL_LB)
     return fail(GR_EINVAL, "opts->fixed_action out of range");
   if (!(opts->do_a >= 0.0f) || !(opts->do_b >= 0.0f)) return fail(GR_EINVAL, "do_a/do_b must be >= 0");
-  if (opts->lb_chunk < 0 || (opts->lb_chunk > 0 && (opts->lb_chunk < 256 || opts->lb_chunk > (1 << 20))))
-    return fail(GR_EINVAL, "opts->lb_chunk must be 0 or in [256, 2^20]");
+  if (opts->lb_chunk != 0 && opts->lb_chunk != 2048 && opts->lb_chunk != 4096 &&
+      opts->lb_chunk != 8192 && opts->lb_chunk != 16384)
+    return fail(GR_EINVAL, "opts->lb_chunk must be 0 (default), 2048, 4096, 8192 or 16384");
   if (opts->trace_capacity < 0 || (opts->trace_capacity > 0 && !opts->trace))
     return fail(GR_EINVAL, "opts->trace is NULL with a positive capacity");
   *local = *opts;
@@ -387,6 +388,31 @@ void record_trace(gr_opts* opts, const LevelFeatures& lf, int action, float step
 // BFS enactor (Sec. 6.1, Alg. 2)
 // ============================================================================
 
+namespace {
+// Push steps on symmetric graphs find parents either with an atomic min during
+// the expansion (cheap while the frontier has few edges) or with the
+// ascending-scan fix-up afterwards (cheap once the frontier is large: the first
+// frontier neighbour is found early).  Both give the smallest-id parent.
+constexpr int64_t kAtomicParentMaxEdges = 1 << 20;
+// Push levels whose frontier has at least V / kMarksFilterDivisor edges use the
+// non-atomic filter (byte marks + one ordered compaction pass over all V);
+// smaller ones cull with atomics on the visited bitmap.
+constexpr int64_t kMarksFilterDivisor = 4;
+
+// The byte-mark buffer is all zero between uses (the compaction clears what it
+// reads); a fresh allocation is cleared once here.
+gr_status marks_buffer(gr_ctx* ctx, int64_t V, uint8_t** out, hipStream_t st) {
+  const size_t bytes = (size_t)((V + 31) / 32) * 32;
+  const bool fresh = ctx->pool[S_MARKS].bytes < bytes;
+  void* p = nullptr;
+  GR_TRY(pool_get(ctx, S_MARKS, bytes, &p));
+  if (fresh) GR_HIP(launch_fill_u32(static_cast<uint32_t*>(p), (int64_t)(ctx->pool[S_MARKS].bytes / 4),
+                                    0u, st));
+  *out = static_cast<uint8_t*>(p);
+  return GR_OK;
+}
+}  // namespace
+
 extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth,
                             int32_t* parent, gr_opts* opts_in, void* stream, gr_run_stats* stats) {
   if (!ctx || !g) return fail(GR_EINVAL, "gr_bfs: ctx or graph is NULL");
@@ -404,12 +430,11 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const int G = stats_grid();
   const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
 
-  uint32_t *bmA, *bmB;
-  int32_t *qA, *qB, *uA = nullptr, *uB = nullptr, *offsets;
+  uint32_t* bm;
+  int32_t *qA, *qB, *uA = nullptr, *uB = nullptr, *offsets, *rstart, *chunks;
   int64_t* bsums;
   Ctrl* ctrl;
-  GR_TRY(pool_typed(ctx, S_BM_A, NW, &bmA));
-  GR_TRY(pool_typed(ctx, S_BM_B, NW, &bmB));
+  GR_TRY(pool_typed(ctx, S_BM, 2 * NW, &bm));
   GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
   GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
   if (pull_ok) {
@@ -417,19 +442,19 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     GR_TRY(pool_typed(ctx, S_U_B, V, &uB));
   }
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
-  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, 3 * G + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   Ctrl* hc = ctx->host_ctrl;
 
   int32_t* q[2] = {qA, qB};
   int32_t* ul[2] = {uA, uB};
-  uint32_t* bm_old = bmA;
-  uint32_t* bm_live = bmB;
 
   GR_HIP(hipEventRecord(ctx->ev_start, st));
-  GR_HIP(launch_bfs_init(depth, parent, V, bm_old, bm_live, NW, source, qA, ctrl, st));
-  int cur = 0, ucur = 0;
-  GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+  GR_HIP(launch_bfs_init(depth, parent, V, bm, NW, source, qA, ctrl, st));
+  int cur = 0, ucur = 0, sp = 0, p = 0;
+  GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
   GR_TRY(read_ctrl(ctx, ctrl, st));
 
@@ -438,11 +463,11 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   LevelFeatures lf{};
   lf.V = V;
   lf.E = E;
-  int64_t n_f = hc->n_f, m_f = hc->m_f;
+  int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], max_deg = hc->max_deg[sp];
   int64_t visited_n = n_f, visited_m = m_f;
   int64_t n_ulist = 0;
   bool have_unv = false;
-  int64_t inspected_prev = 0, inspected_push = 0;
+  int64_t inspected_push = 0;
   int level = 0;
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
@@ -451,7 +476,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     lf.level = level;
     lf.n_f = n_f;
     lf.m_f = m_f;
-    lf.max_deg_f = hc->max_deg;
+    lf.max_deg_f = max_deg;
     lf.n_u = V - visited_n;
     lf.m_u = E - visited_m;
     lf.prev_pull = sel.mode_pull ? 1 : 0;
@@ -459,40 +484,49 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
     const int next_depth = level + 1;
     if (action == GR_PUSH_LB || action == GR_PUSH_TWC) {
-      if (action == GR_PUSH_TWC) {
-        GR_HIP(launch_bfs_push_twc(q[cur], n_f, g->R, g->C, bm_old, bm_live, depth, parent,
-                                   next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1], st));
-      } else if (n_f < opts.lb_light_threshold) {
-        GR_HIP(launch_bfs_push_light(q[cur], n_f, g->R, g->C, bm_old, bm_live, depth, parent,
-                                     next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1], st));
+      const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
+      if (mode == 2)
+        GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
+                                       chunks, chunk, st));
+      const bool atomic_parent = parent && (!pull_ok || m_f <= kAtomicParentMaxEdges);
+      if (!atomic_parent && m_f >= V / kMarksFilterDivisor) {
+        uint8_t* marks;
+        GR_TRY(marks_buffer(ctx, V, &marks, st));
+        GR_HIP(launch_bfs_push_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
+                                     bm, p, marks, V, depth, next_depth, q[cur ^ 1],
+                                     &ctrl->q_count[cur ^ 1], chunk, st));
       } else {
-        GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, offsets, bm_live, st));
-        GR_HIP(launch_bfs_push_lb(q[cur], offsets, n_f, m_f, g->R, g->C, bm_old, bm_live, depth,
-                                  parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1], chunk,
-                                  st));
+        GR_HIP(launch_bfs_push(mode, atomic_parent, q[cur], offsets, rstart, chunks, n_f, m_f,
+                               g->R, g->C, bm, p, depth, parent, next_depth, q[cur ^ 1],
+                               &ctrl->q_count[cur ^ 1], chunk, st));
       }
+      if (parent && !atomic_parent)
+        GR_HIP(launch_bfs_parent_fixup(q[cur ^ 1], &ctrl->q_count[cur ^ 1],
+                                       std::min<int64_t>(V - visited_n, m_f), g->R, g->C, bm, p,
+                                       parent, st));
       inspected_push += m_f;
       have_unv = false;
     } else {
       if (!have_unv) {
         GR_HIP(launch_fill_u32(&ctrl->u_count[ucur], 1, 0u, st));
-        GR_HIP(launch_gen_unvisited(bm_old, g->R, V, ul[ucur], &ctrl->u_count[ucur], st));
+        GR_HIP(launch_gen_unvisited(bm, p, g->R, V, ul[ucur], &ctrl->u_count[ucur], st));
         GR_TRY(read_ctrl(ctx, ctrl, st));
         n_ulist = hc->u_count[ucur];
         have_unv = true;
       }
-      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, ul[ucur], n_ulist, g->R, g->C, bm_old, bm_live,
-                             depth, parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1],
+      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, ul[ucur], n_ulist, g->R, g->C, bm, p, depth,
+                             parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1],
                              ul[ucur ^ 1], &ctrl->u_count[ucur ^ 1], &ctrl->inspected, st));
-      GR_HIP(launch_bitmap_or(bm_live, bm_old, NW, st));
       ucur ^= 1;
     }
+    GR_HIP(launch_bitmap_merge(bm, p, NW, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
     rs.action_count[action]++;
-    std::swap(bm_old, bm_live);
+    p ^= 1;
     cur ^= 1;
+    sp ^= 1;
     ++level;
-    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
     GR_TRY(read_ctrl(ctx, ctrl, st));
     if (tracing) {
@@ -500,8 +534,9 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       GR_HIP(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
       record_trace(opts_in, lf, action, ms * 1000.0f);
     }
-    n_f = hc->n_f;
-    m_f = hc->m_f;
+    n_f = hc->n_f[sp];
+    m_f = hc->m_f[sp];
+    max_deg = hc->max_deg[sp];
     if (have_unv) n_ulist = hc->u_count[ucur];
     visited_n += n_f;
     visited_m += m_f;
@@ -514,7 +549,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     rs.iterations = level;
     // when stopped early the last frontier is reached but not expanded
     rs.teps_edges = visited_m;
-    rs.inspected_edges = inspected_push + (hc->inspected - inspected_prev);
+    rs.inspected_edges = inspected_push + hc->inspected;
     rs.device_ms = ms;
     *stats = rs;
   }
@@ -552,14 +587,16 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
   const int32_t n_src = (int32_t)uniq.size();
 
-  int32_t *qA, *qB, *offsets, *tags, *src_dev;
+  int32_t *qA, *qB, *offsets, *rstart, *chunks, *tags, *src_dev;
   unsigned long long* keys;
   int64_t* bsums;
   Ctrl* ctrl;
   GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
   GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
-  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, 3 * G + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
@@ -573,8 +610,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_HIP(hipEventRecord(ctx->ev_start, st));
   GR_HIP(launch_sssp_init(keys, tags, V, ctrl, st));
   GR_HIP(launch_sssp_seed(src_dev, n_src, keys, tags, ctrl, st));
-  int cur = 0;
-  GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+  int cur = 0, sp = 0;
+  GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                &ctrl->q_count[cur ^ 1], nullptr, st));
   GR_TRY(read_ctrl(ctx, ctrl, st));
 
@@ -583,7 +620,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   LevelFeatures lf{};
   lf.V = V;
   lf.E = E;
-  int64_t n_f = hc->n_f, m_f = hc->m_f;
+  int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], max_deg = hc->max_deg[sp];
   int it = 0;
   int64_t inspected = 0;
   gr_run_stats rs{};
@@ -592,23 +629,25 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     lf.level = it;
     lf.n_f = n_f;
     lf.m_f = m_f;
-    lf.max_deg_f = hc->max_deg;
+    lf.max_deg_f = max_deg;
     lf.n_u = 0;
     lf.m_u = 0;
     lf.prev_pull = 0;
     const int action = sel.decide(lf);
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
-    const bool lb = action == GR_PUSH_LB;
-    const bool light = lb && n_f < opts.lb_light_threshold;
-    if (lb && !light) GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, offsets, nullptr, st));
-    GR_HIP(launch_sssp_relax(lb ? 1 : 0, light, q[cur], offsets, n_f, m_f, g->R, g->C, g->W, keys,
+    const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
+    if (mode == 2)
+      GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
+                                     chunks, chunk, st));
+    GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W, keys,
                              tags, it + 1, q[cur ^ 1], &ctrl->q_count[cur ^ 1], chunk, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
     inspected += m_f;
     rs.action_count[action]++;
     cur ^= 1;
+    sp ^= 1;
     ++it;
-    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl,
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[cur ^ 1], nullptr, st));
     GR_TRY(read_ctrl(ctx, ctrl, st));
     if (tracing) {
@@ -616,8 +655,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       GR_HIP(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
       record_trace(opts_in, lf, action, ms * 1000.0f);
     }
-    n_f = hc->n_f;
-    m_f = hc->m_f;
+    n_f = hc->n_f[sp];
+    m_f = hc->m_f[sp];
+    max_deg = hc->max_deg[sp];
   }
   int64_t* reached = &ctrl->reached_edges;
   GR_HIP(launch_sssp_finalize(keys, g->R, V, dist, pred, src_dev, n_src, reached, st));

@@ -38,37 +38,40 @@ struct DevBuf {
 
 // Slots of the per-context scratch pool.
 enum Slot : int {
-  S_BM_A = 0,      // visited bitmap (ping)
-  S_BM_B,          // visited bitmap (pong)
+  S_BM = 0,        // visited bitmaps, interleaved word pairs (old/live)
   S_Q_A,           // vertex frontier queue (ping)
   S_Q_B,           // vertex frontier queue (pong)
   S_U_A,           // unvisited frontier (ping)
   S_U_B,           // unvisited frontier (pong)
   S_OFFSETS,       // exclusive scan of frontier degrees [n_f + 1]
-  S_BLOCK_SUMS,    // per-block partial sums/max for the frontier scan
+  S_RSTART,        // row start of every frontier vertex [n_f]
+  S_BLOCK_SUMS,    // per-block partial sums for the frontier scan
   S_CTRL,          // device control block (counters and level statistics)
-  S_KEYS,          // SSSP packed (dist << 32 | pred) keys [V]
-  S_TAGS,          // SSSP output-queue tags [V]
+  S_KEYS,          // shortest-path packed (dist << 32 | pred) keys [V]
+  S_TAGS,          // shortest-path output-queue tags [V]
   S_MASK_A,        // multi-source masks
   S_MASK_B,
   S_MASK_C,
   S_MLP,           // selector parameters on the device
-  S_TMP0,
-  S_TMP1,
+  S_TMP0,          // small per-call staging (source lists)
+  S_CHUNKS,        // LB chunk -> first frontier segment map
+  S_MARKS,         // one byte per vertex, all zero between uses
   S_NSLOTS
 };
 
-// Device control block.  Counters used for appends are 32-bit; sums are 64-bit.
+// Device control block.  Counters used for appends are 32-bit; sums are
+// 64-bit.  Frontier statistics use two slots selected by the parity of the
+// statistics call, so each call can clear the slot the next one accumulates in.
 struct Ctrl {
   uint32_t q_count[2];      // frontier queue lengths (ping/pong)
   uint32_t u_count[2];      // unvisited frontier lengths (ping/pong)
-  int64_t m_f;              // sum of frontier degrees
-  int64_t max_deg;          // largest frontier degree
-  int64_t n_f;              // frontier size as seen by the statistics kernel
+  int64_t m_f[2];           // sum of frontier degrees
+  int64_t max_deg[2];       // largest frontier degree
+  int64_t n_f[2];           // frontier size as seen by the statistics kernel
   int64_t inspected;        // pull: neighbours scanned (accumulated)
+  int64_t reached_edges;    // sum of degrees over reached vertices (end of run)
   int32_t action;           // action chosen on the device (learned policy)
   int32_t pad0;
-  int64_t reached_edges;    // sum of degrees over reached vertices (end of run)
   int64_t misc[4];
 };
 
@@ -113,53 +116,60 @@ hipError_t launch_graph_stats(const int32_t* R, const uint32_t* W, int64_t V, in
 
 // frontier statistics and scan
 int stats_grid();
+// Degree sum / max / size of the frontier (size read on the device), into slot
+// `parity` of the control block; clears the other slot and the two counters.
 hipError_t launch_frontier_stats(const int32_t* frontier, const uint32_t* n_f_dev, const int32_t* R,
-                                 int64_t* block_sums, Ctrl* ctrl, uint32_t* zero_a,
+                                 int64_t* block_sums, Ctrl* ctrl, int parity, uint32_t* zero_a,
                                  uint32_t* zero_b, hipStream_t st);
 hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const int32_t* R,
-                                   const int64_t* block_sums, int32_t* offsets,
-                                   uint32_t* live_bm, hipStream_t st);
+                                   const int64_t* block_sums, const int64_t* total,
+                                   int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
+                                   int32_t chunk, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
 
-// BFS
-hipError_t launch_bfs_init(int32_t* depth, int32_t* parent, int64_t V, uint32_t* bm_old,
-                           uint32_t* bm_live, int64_t n_words, int32_t source, int32_t* queue,
-                           Ctrl* ctrl, hipStream_t st);
-hipError_t launch_bfs_push_lb(const int32_t* frontier, const int32_t* offsets, int64_t n_f,
-                              int64_t m_f, const int32_t* R, const int32_t* C,
-                              const uint32_t* bm_old, uint32_t* bm_live, int32_t* depth,
-                              int32_t* parent, int32_t next_depth, int32_t* out_q,
-                              uint32_t* out_count, int chunk, hipStream_t st);
-hipError_t launch_bfs_push_light(const int32_t* frontier, int64_t n_f, const int32_t* R,
-                                 const int32_t* C, const uint32_t* bm_old, uint32_t* bm_live,
-                                 int32_t* depth, int32_t* parent, int32_t next_depth,
-                                 int32_t* out_q, uint32_t* out_count, hipStream_t st);
-hipError_t launch_bfs_push_twc(const int32_t* frontier, int64_t n_f, const int32_t* R,
-                               const int32_t* C, const uint32_t* bm_old, uint32_t* bm_live,
-                               int32_t* depth, int32_t* parent, int32_t next_depth,
-                               int32_t* out_q, uint32_t* out_count, hipStream_t st);
-hipError_t launch_gen_unvisited(const uint32_t* bm_old, const int32_t* R, int64_t V,
+// BFS.  Visited state: one array of word pairs, bm[2w + p] = "old" word w
+// (depth <= d) and bm[2w + 1 - p] = "live" word w, p = level parity.
+hipError_t launch_bfs_init(int32_t* depth, int32_t* parent, int64_t V, uint32_t* bm,
+                           int64_t n_words, int32_t source, int32_t* queue, Ctrl* ctrl,
+                           hipStream_t st);
+// mode: 0 = TWC, 1 = LB_LIGHT (input balanced), 2 = LB (output balanced)
+hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier,
+                           const int32_t* offsets, const int32_t* rstart,
+                           const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
+                           const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
+                           int32_t next_depth, int32_t* out_q, uint32_t* out_count, int chunk,
+                           hipStream_t st);
+// Push with the non-atomic filter: byte marks (all zero before and after),
+// then an ordered compaction of the marked vertices.
+hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
+                                 const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                 int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
+                                 int p, uint8_t* marks, int64_t V, int32_t* depth,
+                                 int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                 int chunk, hipStream_t st);
+hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
+                                   const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
+                                   int32_t* parent, hipStream_t st);
+hipError_t launch_gen_unvisited(const uint32_t* bm, int p, const int32_t* R, int64_t V,
                                 int32_t* out_list, uint32_t* out_count, hipStream_t st);
 hipError_t launch_bfs_pull(bool lb, const int32_t* unvisited, int64_t n_u, const int32_t* R,
-                           const int32_t* C, const uint32_t* bm_old, uint32_t* bm_live,
-                           int32_t* depth, int32_t* parent, int32_t next_depth,
-                           int32_t* out_active, uint32_t* out_active_count,
+                           const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
+                           int32_t next_depth, int32_t* out_active, uint32_t* out_active_count,
                            int32_t* out_unvisited, uint32_t* out_unvisited_count,
                            int64_t* inspected, hipStream_t st);
-hipError_t launch_bitmap_or(uint32_t* dst, const uint32_t* src, int64_t n_words, hipStream_t st);
-hipError_t launch_reached_edges(const int32_t* depth, const int32_t* R, int64_t V, int64_t* out,
-                                hipStream_t st);
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
+// live |= old (live = depth <= d + 1 after level d)
+hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
 
 // SSSP
 hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int64_t V, Ctrl* ctrl,
                             hipStream_t st);
 hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long long* keys,
                             int32_t* tags, Ctrl* ctrl, hipStream_t st);
-hipError_t launch_sssp_relax(int action_lb, bool light, const int32_t* frontier,
-                             const int32_t* offsets, int64_t n_f, int64_t m_f, const int32_t* R,
-                             const int32_t* C, const uint32_t* W, unsigned long long* keys,
-                             int32_t* tags, int32_t next_tag, int32_t* out_q, uint32_t* out_count,
-                             int chunk, hipStream_t st);
+hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* offsets,
+                             const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                             int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
+                             unsigned long long* keys, int32_t* tags, int32_t next_tag,
+                             int32_t* out_q, uint32_t* out_count, int chunk, hipStream_t st);
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
                                 uint32_t* dist, int32_t* pred, const int32_t* src_dev,
                                 int32_t n_src, int64_t* reached_edges, hipStream_t st);

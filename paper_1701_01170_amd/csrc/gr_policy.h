@@ -77,8 +77,10 @@ struct Selector {
         if ((double)lf.m_f < (double)lf.m_u * (double)o.do_b) pull = false;
       }
     }
+    // The paper has a single pull advance; its early exit makes per-vertex
+    // dynamic grouping the natural mapping, so the heuristic pulls with TWC.
+    if (pull) return GR_PULL_TWC;
     const bool lb = avg_degree >= (double)o.lb_min_avg_degree;
-    if (pull) return lb ? GR_PULL_LB : GR_PULL_TWC;
     return lb ? GR_PUSH_LB : GR_PUSH_TWC;
   }
 

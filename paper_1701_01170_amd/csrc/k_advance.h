@@ -2,15 +2,23 @@
 // expansion (Sec. 5.3: functors compiled into the operator kernels, and the
 // filter fused with the advance so that no intermediate edge frontier is
 // written).  A functor provides
-//   int32_t seg_payload(int32_t u)            per-source value (e.g. dist[u])
-//   void    on_frontier(int32_t u)            once per frontier vertex
-//   bool    visit(u, payload, v, e)           true => append v to the output
+//   int32_t  seg_payload(int32_t u)          per-source value (e.g. dist[u])
+//   uint32_t edge_value(int64_t e)           per-edge value (e.g. weight)
+//   bool     probe(u, payload, v, ev)        read-only test: may the edge update v?
+//   bool     commit(u, payload, v, ev)       atomic update; true => append v
+// Edges are handled in batches: every lane first issues all of its
+// column-index loads, then all probe loads, then the atomics of the edges
+// that survive, then one wavefront-aggregated append; independent loads are
+// in flight together instead of one dependent chain per edge.
+//
 // Three workload mappings (Sec. 5.1):
 //   k_push_lb    - output-frontier load balance: equal edge chunks per
-//                  workgroup over the degree prefix sum, source found by a
-//                  binary search of the chunk's offsets staged in LDS;
+//                  workgroup; the chunk -> first-segment map is scattered by
+//                  the offsets kernel (the sorted search of 0, N, 2N, ... in the
+//                  degree prefix sum), and each edge finds its segment with an
+//                  LDS max-scan of segment starts;
 //   k_push_light - input-frontier load balance: equal frontier slices per
-//                  workgroup, their degrees scanned in LDS, the slice's edges
+//                  workgroup, degrees scanned in LDS, the slice's edges
 //                  strip-mined across the workgroup;
 //   k_push_twc   - dynamic grouping: lists longer than the workgroup are
 //                  expanded by the whole workgroup, lists longer than a
@@ -26,25 +34,65 @@ namespace gr {
 constexpr int kAdvBlock = 256;
 constexpr int kLbCap = 2048;  // frontier segments staged in LDS per pass
 
-template <class F>
+// Process up to B edges per lane: ok[r] marks a real edge (u[r], pay[r], ce[r]).
+template <class F, int B>
+__device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict__ C, bool (&ok)[B],
+                                           const int32_t (&u)[B], const int32_t (&pay)[B],
+                                           const int32_t (&ce)[B], int32_t* __restrict__ out_q,
+                                           uint32_t* __restrict__ out_count) {
+  int32_t v[B];
+  uint32_t ev[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    v[r] = ok[r] ? C[ce[r]] : 0;
+    ev[r] = ok[r] ? f.edge_value(ce[r]) : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r) ok[r] = ok[r] && f.probe(u[r], pay[r], v[r], ev[r]);
+  uint32_t n_app = 0;
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    ok[r] = ok[r] && f.commit(u[r], pay[r], v[r], ev[r]);
+    n_app += ok[r] ? 1u : 0u;
+  }
+  // wavefront-aggregated append of every lane's survivors
+  const uint64_t any = __ballot(n_app != 0);
+  if (any == 0) return;
+  const uint32_t inc = wave_incl_scan(n_app);
+  uint32_t base = 0;
+  if (lane() == kWave - 1) base = atomicAdd(out_count, inc);
+  base = __shfl(base, kWave - 1) + inc - n_app;
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+    if (ok[r]) out_q[base++] = v[r];
+}
+
+// One workgroup per chunk of NB * EPT * 256 edges of the output frontier.  The
+// frontier segments overlapping the chunk are staged in LDS (kLbCap per pass);
+// a 16-bit segment index per edge slot comes from scattering segment starts and
+// a max-scan; the edges are then processed in NB batches of EPT per thread
+// (EPT independent loads in flight per lane).
+template <class F, int EPT, int NB>
 __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
-    const int32_t* __restrict__ frontier, const int32_t* __restrict__ offsets, int32_t n_f,
-    int32_t m_f, const int32_t* __restrict__ R, const int32_t* __restrict__ C, F f,
-    int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count, int32_t chunk) {
+    const int32_t* __restrict__ frontier, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ rstart, const int32_t* __restrict__ chunk_start, int32_t n_f,
+    int32_t m_f, const int32_t* __restrict__ C, F f,
+    int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count) {
+  constexpr int BATCH = kAdvBlock * EPT;
+  constexpr int N = BATCH * NB;
+  constexpr int SPT = N / kAdvBlock;  // segment-map slots per thread
+  __shared__ uint16_t s_seg[N];
   __shared__ int32_t s_off[kLbCap + 1];
   __shared__ int32_t s_u[kLbCap];
   __shared__ int32_t s_rb[kLbCap];
   __shared__ int32_t s_pay[kLbCap];
-  __shared__ int32_t s_rng[2];
-  const int64_t e0 = (int64_t)blockIdx.x * chunk;
-  if (e0 >= m_f) return;
-  const int64_t e1 = e0 + chunk < m_f ? e0 + chunk : m_f;
-  if (threadIdx.x == 0) {
-    s_rng[0] = upper_index(offsets, 0, n_f - 1, e0);
-    s_rng[1] = upper_index(offsets, 0, n_f - 1, e1 - 1);
-  }
-  __syncthreads();
-  const int sb = s_rng[0], se = s_rng[1];
+  __shared__ int32_t s_tmp[kAdvBlock / kWave + 1];
+  const int c = blockIdx.x;
+  const int64_t e0 = (int64_t)c * N;
+  const int64_t e1 = e0 + N < m_f ? e0 + N : m_f;
+  const int nchunks = (int)(((int64_t)m_f + N - 1) / N);
+  const int sb = chunk_start[c];
+  const int se = c + 1 < nchunks ? chunk_start[c + 1] : n_f - 1;
   for (int pb = sb; pb <= se; pb += kLbCap) {
     const int cnt = (se - pb + 1) < kLbCap ? (se - pb + 1) : kLbCap;
     for (int i = threadIdx.x; i < cnt; i += kAdvBlock) {
@@ -52,21 +100,64 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
       const int32_t u = frontier[s];
       s_off[i] = offsets[s];
       s_u[i] = u;
-      s_rb[i] = R[u];
+      s_rb[i] = rstart[s];
       s_pay[i] = f.seg_payload(u);
     }
     if (threadIdx.x == 0) s_off[cnt] = offsets[pb + cnt];
+    for (int j = threadIdx.x; j < N; j += kAdvBlock) s_seg[j] = 0;
     __syncthreads();
     const int64_t lo = e0 > (int64_t)s_off[0] ? e0 : (int64_t)s_off[0];
     const int64_t hi = e1 < (int64_t)s_off[cnt] ? e1 : (int64_t)s_off[cnt];
-    for (int64_t e = lo + threadIdx.x; e < hi; e += kAdvBlock) {
-      const int k = upper_index(s_off, 0, cnt - 1, e);
-      const int32_t u = s_u[k];
-      const int64_t ce = (int64_t)s_rb[k] + (e - s_off[k]);
-      const int32_t v = C[ce];
-      const bool app = f.visit(u, s_pay[k], v, ce);
-      const uint32_t slot = wave_append(out_count, app);
-      if (app) out_q[slot] = v;
+    // starts of the non-empty segments inside [lo, hi) (exactly one non-empty
+    // segment starts at any edge position; empty ones own no edge)
+    for (int k = 1 + threadIdx.x; k < cnt; k += kAdvBlock) {
+      const int64_t pos = (int64_t)s_off[k] - lo;
+      if (pos < hi - lo && s_off[k + 1] > s_off[k]) s_seg[pos] = (uint16_t)k;
+    }
+    __syncthreads();
+    // inclusive max-scan over s_seg[0, N): SPT consecutive slots per thread
+    {
+      int32_t run = 0;
+      for (int r = 0; r < SPT; ++r) {
+        const int32_t x = s_seg[threadIdx.x * SPT + r];
+        run = x > run ? x : run;
+      }
+      int32_t inc = run;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o);
+        if (lane() >= o) inc = y > inc ? y : inc;
+      }
+      if (lane() == kWave - 1) s_tmp[threadIdx.x / kWave] = inc;
+      __syncthreads();
+      int32_t ex = 0;
+      for (int i = 0; i < (int)threadIdx.x / kWave; ++i) ex = s_tmp[i] > ex ? s_tmp[i] : ex;
+      int32_t wx = __shfl_up(inc, 1);
+      if (lane() == 0) wx = 0;
+      run = wx > ex ? wx : ex;
+      for (int r = 0; r < SPT; ++r) {
+        const int32_t x = s_seg[threadIdx.x * SPT + r];
+        run = x > run ? x : run;
+        s_seg[threadIdx.x * SPT + r] = (uint16_t)run;
+      }
+    }
+    __syncthreads();
+    for (int b = 0; b < NB; ++b) {
+      if (lo + (int64_t)b * BATCH >= hi) break;
+      bool ok[EPT];
+      int32_t u[EPT], pay[EPT];
+      int32_t ce[EPT];
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) {
+        const int j = b * BATCH + r * kAdvBlock + threadIdx.x;
+        const int64_t e = lo + j;
+        ok[r] = e < hi;
+        const int k = ok[r] ? (int)s_seg[j] : 0;
+        u[r] = s_u[k];
+        pay[r] = s_pay[k];
+        ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
+      }
+      edge_batch<F, EPT>(f, C, ok, u, pay, ce, out_q, out_count);
     }
     __syncthreads();
   }
@@ -77,34 +168,41 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_light(
     const int32_t* __restrict__ frontier, int32_t n_f, const int32_t* __restrict__ R,
     const int32_t* __restrict__ C, F f, int32_t* __restrict__ out_q,
     uint32_t* __restrict__ out_count) {
+  constexpr int B = 4;
   __shared__ int32_t s_off[kAdvBlock];
   __shared__ int32_t s_u[kAdvBlock];
   __shared__ int32_t s_rb[kAdvBlock];
   __shared__ int32_t s_pay[kAdvBlock];
   __shared__ int64_t s_tot[kAdvBlock / kWave + 1];
   const int64_t i = (int64_t)blockIdx.x * kAdvBlock + threadIdx.x;
-  int32_t u = 0, rb = 0, d = 0, pay = 0;
+  int32_t u0 = 0, rb = 0, d = 0, pay0 = 0;
   if (i < n_f) {
-    u = frontier[i];
-    rb = R[u];
-    d = R[u + 1] - rb;
-    pay = f.seg_payload(u);
-    f.on_frontier(u);
+    u0 = frontier[i];
+    rb = R[u0];
+    d = R[u0 + 1] - rb;
+    pay0 = f.seg_payload(u0);
   }
   int64_t total;
   const int64_t ex = block_excl_scan<kAdvBlock>((int64_t)d, s_tot, &total);
   s_off[threadIdx.x] = (int32_t)ex;
-  s_u[threadIdx.x] = u;
+  s_u[threadIdx.x] = u0;
   s_rb[threadIdx.x] = rb;
-  s_pay[threadIdx.x] = pay;
+  s_pay[threadIdx.x] = pay0;
   __syncthreads();
-  for (int64_t e = threadIdx.x; e < total; e += kAdvBlock) {
-    const int k = upper_index(s_off, 0, kAdvBlock - 1, e);
-    const int64_t ce = (int64_t)s_rb[k] + (e - s_off[k]);
-    const int32_t v = C[ce];
-    const bool app = f.visit(s_u[k], s_pay[k], v, ce);
-    const uint32_t slot = wave_append(out_count, app);
-    if (app) out_q[slot] = v;
+  for (int64_t base = 0; base < total; base += (int64_t)kAdvBlock * B) {
+    bool ok[B];
+    int32_t u[B], pay[B];
+    int32_t ce[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int64_t e = base + r * kAdvBlock + threadIdx.x;
+      ok[r] = e < total;
+      const int k = ok[r] ? upper_index(s_off, 0, kAdvBlock - 1, e) : 0;
+      u[r] = s_u[k];
+      pay[r] = s_pay[k];
+      ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
+    }
+    edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
   }
 }
 
@@ -114,6 +212,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
     const int32_t* __restrict__ C, F f, int32_t* __restrict__ out_q,
     uint32_t* __restrict__ out_count) {
   constexpr int NW = kAdvBlock / kWave;
+  constexpr int B = 4;
   __shared__ int32_t s_claim;
   __shared__ int32_t s_cu, s_crb, s_cd, s_cpay;
   __shared__ int32_t s_woff[NW][kWave];
@@ -122,13 +221,12 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
   __shared__ int32_t s_wpay[NW][kWave];
   const int64_t i = (int64_t)blockIdx.x * kAdvBlock + threadIdx.x;
   const int w = threadIdx.x / kWave;
-  int32_t u = 0, rb = 0, d = 0, pay = 0;
+  int32_t u0 = 0, rb = 0, d = 0, pay0 = 0;
   if (i < n_f) {
-    u = frontier[i];
-    rb = R[u];
-    d = R[u + 1] - rb;
-    pay = f.seg_payload(u);
-    f.on_frontier(u);
+    u0 = frontier[i];
+    rb = R[u0];
+    d = R[u0 + 1] - rb;
+    pay0 = f.seg_payload(u0);
   }
   // workgroup tier: lists longer than the workgroup
   bool big = d > kAdvBlock;
@@ -140,20 +238,27 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
     const int c = s_claim;
     if (c < 0) break;
     if (c == (int)threadIdx.x) {
-      s_cu = u;
+      s_cu = u0;
       s_crb = rb;
       s_cd = d;
-      s_cpay = pay;
+      s_cpay = pay0;
       big = false;
     }
     __syncthreads();
     const int32_t cu = s_cu, crb = s_crb, cd = s_cd, cpay = s_cpay;
-    for (int j = threadIdx.x; j < cd; j += kAdvBlock) {
-      const int64_t ce = (int64_t)crb + j;
-      const int32_t v = C[ce];
-      const bool app = f.visit(cu, cpay, v, ce);
-      const uint32_t slot = wave_append(out_count, app);
-      if (app) out_q[slot] = v;
+    for (int base = 0; base < cd; base += kAdvBlock * B) {
+      bool ok[B];
+      int32_t u[B], pay[B];
+      int32_t ce[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        const int j = base + r * kAdvBlock + threadIdx.x;
+        ok[r] = j < cd;
+        u[r] = cu;
+        pay[r] = cpay;
+        ce[r] = crb + j;
+      }
+      edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
     }
     __syncthreads();
   }
@@ -162,33 +267,86 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
   while (med) {
     const int l = __ffsll((unsigned long long)med) - 1;
     med &= med - 1;
-    const int32_t cu = __shfl(u, l), crb = __shfl(rb, l), cd = __shfl(d, l), cpay = __shfl(pay, l);
-    for (int j = lane(); j < cd; j += kWave) {
-      const int64_t ce = (int64_t)crb + j;
-      const int32_t v = C[ce];
-      const bool app = f.visit(cu, cpay, v, ce);
-      const uint32_t slot = wave_append(out_count, app);
-      if (app) out_q[slot] = v;
+    const int32_t cu = __shfl(u0, l), crb = __shfl(rb, l), cd = __shfl(d, l), cpay = __shfl(pay0, l);
+    bool ok[B];
+    int32_t u[B], pay[B];
+    int32_t ce[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int j = r * kWave + lane();
+      ok[r] = j < cd;
+      u[r] = cu;
+      pay[r] = cpay;
+      ce[r] = crb + j;
     }
+    edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
   }
   // lane tier: scan-based gather of the short lists across the wavefront
   const int32_t ds = d <= kWave ? d : 0;
   const int32_t inc = wave_incl_scan(ds);
   const int32_t tot = __shfl(inc, kWave - 1);
   s_woff[w][lane()] = inc - ds;
-  s_wu[w][lane()] = u;
+  s_wu[w][lane()] = u0;
   s_wrb[w][lane()] = rb;
-  s_wpay[w][lane()] = pay;
+  s_wpay[w][lane()] = pay0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  for (int e = lane(); e < tot; e += kWave) {
-    const int k = upper_index(s_woff[w], 0, kWave - 1, e);
-    const int64_t ce = (int64_t)s_wrb[w][k] + (e - s_woff[w][k]);
-    const int32_t v = C[ce];
-    const bool app = f.visit(s_wu[w][k], s_wpay[w][k], v, ce);
-    const uint32_t slot = wave_append(out_count, app);
-    if (app) out_q[slot] = v;
+  for (int base = 0; base < tot; base += kWave * B) {
+    bool ok[B];
+    int32_t u[B], pay[B];
+    int32_t ce[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int e = base + r * kWave + lane();
+      ok[r] = e < tot;
+      const int k = ok[r] ? upper_index(s_woff[w], 0, kWave - 1, e) : 0;
+      u[r] = s_wu[w][k];
+      pay[r] = s_wpay[w][k];
+      ce[r] = s_wrb[w][k] + (e - s_woff[w][k]);
+    }
+    edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
   }
+}
+
+inline unsigned adv_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// mode: 0 = TWC, 1 = LB_LIGHT, 2 = LB with `chunk` edges per workgroup
+// (2048, 4096, 8192 or 16384).
+template <class F>
+inline hipError_t push_dispatch(int mode, const int32_t* frontier, const int32_t* offsets,
+                         const int32_t* rstart, const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
+                         const int32_t* C, const F& f, int32_t* out_q, uint32_t* out_count,
+                         int chunk, hipStream_t st) {
+  if (n_f <= 0) return hipSuccess;
+  if (mode == 0) {
+    k_push_twc<F><<<adv_blocks(n_f, kAdvBlock), kAdvBlock, 0, st>>>(frontier, (int32_t)n_f, R, C, f,
+                                                                   out_q, out_count);
+  } else if (mode == 1) {
+    k_push_light<F><<<adv_blocks(n_f, kAdvBlock), kAdvBlock, 0, st>>>(frontier, (int32_t)n_f, R, C,
+                                                                     f, out_q, out_count);
+  } else {
+    if (m_f <= 0) return hipSuccess;
+    const unsigned g = adv_blocks(m_f, chunk);
+    switch (chunk) {
+      case 2048:
+        k_push_lb<F, 8, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
+                                                    (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
+        break;
+      case 4096:
+        k_push_lb<F, 16, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
+                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
+        break;
+      case 16384:
+        k_push_lb<F, 32, 2><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
+                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
+        break;
+      default:
+        k_push_lb<F, 32, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
+                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
+        break;
+    }
+  }
+  return hipGetLastError();
 }
 
 }  // namespace gr

@@ -2,56 +2,211 @@
 // visited-bitmap filter, and pull advance over the unvisited frontier
 // (Sec. 5.1 push vs. pull, Alg. 2).
 //
-// Visited state lives in two bitmaps, `old` and `live`.  At the start of level
-// d: old = vertices at depth <= d, live = vertices at depth <= d - 1.
-//  * push: every frontier vertex is marked in live; an edge (u, v) with v in
-//    old is culled; otherwise v gets depth d + 1, u competes for parent[v] by
-//    an unsigned atomic min (the smallest-id parent wins, -1 = 0xffffffff
-//    loses to any id), and the first thread to set v's live bit appends v to
-//    the next frontier exactly once.  Afterwards live = depth <= d + 1.
-//  * pull: a vertex u is in the frontier iff it is in old and not in live.
-//    Each unvisited v scans its ascending adjacency and stops at the first
-//    frontier neighbour, which is therefore the smallest-id parent.  New
-//    vertices are marked in live; the host then ORs old into live.
-// The host swaps the two bitmaps after every level.
+// Visited state is one array of 32-bit word pairs: at level d with parity p,
+// word 2w + p ("old") holds vertices at depth <= d and word 2w + 1 - p ("live")
+// holds vertices at depth <= d - 1 plus the vertices found so far at d + 1.
+// One 8-byte load answers both questions for a vertex: a vertex u is in the
+// current frontier iff it is in old and not in live.  During the level only
+// vertices outside old get live bits, so that test stays valid for the whole
+// level.  After the level the host ORs old into live (live = depth <= d + 1)
+// and flips the parity.
+//  * push: an edge (u, v) with v in old or live is culled; the first thread to
+//    set v's live bit writes depth d + 1 and appends v to the next frontier
+//    exactly once.  Parents: either every frontier in-neighbour competes with
+//    an unsigned atomic min (-1 = 0xffffffff loses to any id), or, on
+//    symmetric graphs, a fix-up pass scans each new vertex's ascending
+//    adjacency for its first frontier neighbour (= the smallest-id parent).
+//  * pull: each unvisited v scans its ascending adjacency and stops at the
+//    first frontier neighbour, which is therefore the smallest-id parent.
 #include "k_advance.h"
 
 namespace gr {
 
 namespace {
 
+__device__ __forceinline__ uint2 bm_pair(const uint32_t* bm, int32_t w) {
+  return reinterpret_cast<const uint2*>(bm)[w];
+}
+
+template <bool ATOMIC_PARENT>
 struct BfsVisit {
-  const uint32_t* __restrict__ old_bm;
-  uint32_t* __restrict__ live_bm;
+  uint32_t* __restrict__ bm;
   int32_t* __restrict__ depth;
   int32_t* __restrict__ parent;
   int32_t next_depth;
+  int32_t p;  // parity: old word = 2w + p
 
   __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
-  __device__ __forceinline__ void on_frontier(int32_t u) const {
-    atomicOr(&live_bm[u >> 5], 1u << (u & 31));
-  }
-  __device__ __forceinline__ bool visit(int32_t u, int32_t, int32_t v, int64_t) const {
+  __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
+  __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
+    const uint2 x = bm_pair(bm, v >> 5);
+    const uint32_t old = p ? x.y : x.x, live = p ? x.x : x.y;
     const uint32_t bit = 1u << (v & 31);
-    const int32_t w = v >> 5;
-    if (old_bm[w] & bit) return false;
-    if (parent) atomicMin(reinterpret_cast<uint32_t*>(&parent[v]), (uint32_t)u);
-    if (live_bm[w] & bit) return false;
-    const uint32_t prev = atomicOr(&live_bm[w], bit);
+    if (ATOMIC_PARENT) return !(old & bit);
+    return !((old | live) & bit);
+  }
+  __device__ __forceinline__ bool commit(int32_t u, int32_t, int32_t v, uint32_t) const {
+    const uint32_t bit = 1u << (v & 31);
+    uint32_t* live = &bm[2 * (v >> 5) + 1 - p];
+    if (ATOMIC_PARENT) {
+      if (parent) atomicMin(reinterpret_cast<uint32_t*>(&parent[v]), (uint32_t)u);
+      if (*live & bit) return false;
+    }
+    const uint32_t prev = atomicOr(live, bit);
     if (prev & bit) return false;
     depth[v] = next_depth;
     return true;
   }
 };
 
-__device__ __forceinline__ bool in_frontier(const uint32_t* old_bm, const uint32_t* live_bm,
-                                            int32_t u) {
-  const int32_t w = u >> 5;
-  return ((old_bm[w] & ~live_bm[w]) >> (u & 31)) & 1u;
+// Push without atomics (for levels that discover many vertices): every edge
+// into a vertex outside old and live stores a one-byte mark; all writers store
+// the same value, so the race is benign.  k_bfs_mark_compact then turns the
+// marks into depths, live bits and an ordered next frontier.
+struct BfsMark {
+  const uint32_t* __restrict__ bm;
+  uint8_t* __restrict__ marks;
+  int32_t p;
+
+  __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
+  __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
+  __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
+    const uint2 x = bm_pair(bm, v >> 5);
+    return !(((x.x | x.y) >> (v & 31)) & 1u);
+  }
+  __device__ __forceinline__ bool commit(int32_t, int32_t, int32_t v, uint32_t) const {
+    marks[v] = 1;
+    return false;
+  }
+};
+
+// One thread per bitmap word (32 vertices): gather the marks, clear them, set
+// the live bits (the thread owns the word), write depths and append the new
+// vertices in ascending order within each wavefront.
+__global__ __launch_bounds__(256) void k_bfs_mark_compact(uint8_t* __restrict__ marks, int64_t V,
+                                                          uint32_t* __restrict__ bm, int p,
+                                                          int32_t* __restrict__ depth,
+                                                          int32_t next_depth,
+                                                          int32_t* __restrict__ out_q,
+                                                          uint32_t* __restrict__ out_count) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_words = (V + 31) / 32;
+  uint32_t mask = 0;
+  if (w < n_words) {
+    const int64_t v0 = w * 32;
+    if (v0 + 32 <= V) {
+      const uint4* m4 = reinterpret_cast<const uint4*>(marks + v0);
+      const uint4 a = m4[0], b = m4[1];
+      const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if ((q[i] >> (8 * k)) & 0xffu) mask |= 1u << (4 * i + k);
+      if (mask) {
+        uint4* z = reinterpret_cast<uint4*>(marks + v0);
+        z[0] = make_uint4(0, 0, 0, 0);
+        z[1] = make_uint4(0, 0, 0, 0);
+      }
+    } else {
+      for (int64_t v = v0; v < V; ++v)
+        if (marks[v]) {
+          mask |= 1u << (v - v0);
+          marks[v] = 0;
+        }
+    }
+    if (mask) bm[2 * w + 1 - p] |= mask;
+  }
+  const uint32_t n = __popc(mask);
+  const uint32_t inc = wave_incl_scan(n);
+  uint32_t base = 0;
+  if (lane() == kWave - 1 && inc) base = atomicAdd(out_count, inc);
+  base = __shfl(base, kWave - 1) + inc - n;
+  while (mask) {
+    const int b = __ffs(mask) - 1;
+    mask &= mask - 1;
+    const int32_t v = (int32_t)(w * 32 + b);
+    depth[v] = next_depth;
+    out_q[base++] = v;
+  }
 }
 
-__device__ __forceinline__ void pull_emit(bool valid, int32_t v, int32_t found,
-                                          uint32_t* live_bm, int32_t* depth, int32_t* parent,
+__device__ __forceinline__ bool in_frontier(const uint32_t* bm, int p, int32_t u) {
+  const uint2 x = bm_pair(bm, u >> 5);
+  const uint32_t f = p ? (x.y & ~x.x) : (x.x & ~x.y);
+  return (f >> (u & 31)) & 1u;
+}
+
+// Smallest-id frontier neighbour of the vertex owned by each lane, with
+// dynamic grouping: a lane scans a list of at most LANE_MAX neighbours by
+// itself (ascending, early exit); longer lists are scanned by the whole
+// wavefront, U * 64 neighbours per step with U independent loads per lane,
+// the first hit taken by ballot.  Returns -1 when there is none; *scanned
+// counts neighbours read.
+template <int LANE_MAX>
+__device__ __forceinline__ int32_t first_frontier_nbr(bool valid, int32_t rb, int32_t re,
+                                                      const int32_t* __restrict__ C,
+                                                      const uint32_t* __restrict__ bm, int p,
+                                                      int64_t* scanned) {
+  constexpr int U = 8;
+  int32_t found = -1;
+  int64_t sc = 0;
+  if (valid && re - rb <= LANE_MAX) {
+    // U neighbours per step: U independent loads, then U independent probes
+    for (int32_t j0 = rb; j0 < re && found < 0; j0 += U) {
+      int32_t u[U];
+      bool hit[U];
+#pragma unroll
+      for (int r = 0; r < U; ++r) u[r] = j0 + r < re ? C[j0 + r] : -1;
+#pragma unroll
+      for (int r = 0; r < U; ++r) hit[r] = u[r] >= 0 && in_frontier(bm, p, u[r]);
+#pragma unroll
+      for (int r = U - 1; r >= 0; --r)
+        if (hit[r]) found = u[r];
+      sc += (re - j0) < U ? (re - j0) : U;
+    }
+  }
+  uint64_t big = __ballot(valid && re - rb > LANE_MAX);
+  while (big) {
+    const int l = __ffsll((unsigned long long)big) - 1;
+    big &= big - 1;
+    const int32_t vb = __shfl(rb, l), ve = __shfl(re, l);
+    int32_t f = -1;
+    int64_t s2 = 0;
+    for (int32_t base = vb; base < ve; base += U * kWave) {
+      int32_t u[U];
+      bool hit[U];
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const int32_t j = base + r * kWave + lane();
+        u[r] = j < ve ? C[j] : -1;
+      }
+#pragma unroll
+      for (int r = 0; r < U; ++r) hit[r] = u[r] >= 0 && in_frontier(bm, p, u[r]);
+      bool done = false;
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const uint64_t b = __ballot(hit[r]);
+        if (!done && b) {
+          f = __shfl(u[r], __ffsll((unsigned long long)b) - 1);
+          s2 += (int64_t)r * kWave + __ffsll((unsigned long long)b);
+          done = true;
+        }
+      }
+      if (done) break;
+      s2 += (ve - base) < U * kWave ? (ve - base) : U * kWave;
+    }
+    if (lane() == l) {
+      found = f;
+      sc = s2;
+    }
+  }
+  *scanned = sc;
+  return found;
+}
+
+__device__ __forceinline__ void pull_emit(bool valid, int32_t v, int32_t found, uint32_t* bm,
+                                          int p, int32_t* depth, int32_t* parent,
                                           int32_t next_depth, int32_t* out_a, uint32_t* cnt_a,
                                           int32_t* out_u, uint32_t* cnt_u) {
   const bool hit = valid && found >= 0;
@@ -59,7 +214,7 @@ __device__ __forceinline__ void pull_emit(bool valid, int32_t v, int32_t found,
   if (hit) {
     depth[v] = next_depth;
     if (parent) parent[v] = found;
-    atomicOr(&live_bm[v >> 5], 1u << (v & 31));
+    atomicOr(&bm[2 * (v >> 5) + 1 - p], 1u << (v & 31));
   }
   const uint32_t sa = wave_append(cnt_a, hit);
   if (hit) out_a[sa] = v;
@@ -67,17 +222,19 @@ __device__ __forceinline__ void pull_emit(bool valid, int32_t v, int32_t found,
   if (miss) out_u[su] = v;
 }
 
-// Pull with dynamic grouping: one lane per unvisited vertex for short lists
-// (sequential ascending scan with early exit), one wavefront per vertex for
-// lists longer than kPullLane (64 neighbours per step, first hit by ballot).
-constexpr int kPullLane = 32;
+__device__ __forceinline__ void add_inspected(int64_t* inspected, int64_t scanned) {
+  if (!inspected) return;
+  const int64_t s = wave_sum(scanned);
+  if (lane() == 0 && s) atomicAdd((unsigned long long*)inspected, (unsigned long long)s);
+}
 
+// PULL_TWC: one lane per unvisited vertex, whole wavefront for lists > 32.
 __global__ __launch_bounds__(256) void k_bfs_pull_twc(
     const int32_t* __restrict__ unv, int32_t n_u, const int32_t* __restrict__ R,
-    const int32_t* __restrict__ C, const uint32_t* __restrict__ old_bm,
-    uint32_t* __restrict__ live_bm, int32_t* __restrict__ depth, int32_t* __restrict__ parent,
-    int32_t next_depth, int32_t* __restrict__ out_a, uint32_t* __restrict__ cnt_a,
-    int32_t* __restrict__ out_u, uint32_t* __restrict__ cnt_u, int64_t* __restrict__ inspected) {
+    const int32_t* __restrict__ C, uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth,
+    int32_t* __restrict__ parent, int32_t next_depth, int32_t* __restrict__ out_a,
+    uint32_t* __restrict__ cnt_a, int32_t* __restrict__ out_u, uint32_t* __restrict__ cnt_u,
+    int64_t* __restrict__ inspected) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < n_u;
   int32_t v = 0, rb = 0, re = 0;
@@ -86,84 +243,52 @@ __global__ __launch_bounds__(256) void k_bfs_pull_twc(
     rb = R[v];
     re = R[v + 1];
   }
-  int32_t found = -1;
-  int64_t scanned = 0;
-  if (valid && re - rb <= kPullLane) {
-    for (int32_t j = rb; j < re; ++j) {
-      const int32_t u = C[j];
-      ++scanned;
-      if (in_frontier(old_bm, live_bm, u)) {
-        found = u;
-        break;
-      }
-    }
-  }
-  uint64_t big = __ballot(valid && re - rb > kPullLane);
-  while (big) {
-    const int l = __ffsll((unsigned long long)big) - 1;
-    big &= big - 1;
-    const int32_t vb = __shfl(rb, l), ve = __shfl(re, l);
-    int32_t f = -1;
-    int64_t sc = 0;
-    for (int32_t base = vb; base < ve; base += kWave) {
-      const int32_t j = base + lane();
-      int32_t u = -1;
-      bool hit = false;
-      if (j < ve) {
-        u = C[j];
-        hit = in_frontier(old_bm, live_bm, u);
-      }
-      const uint64_t b = __ballot(hit);
-      sc += (ve - base) < kWave ? (ve - base) : kWave;
-      if (b) {
-        f = __shfl(u, __ffsll((unsigned long long)b) - 1);
-        break;
-      }
-    }
-    if (lane() == l) {
-      found = f;
-      scanned = sc;
-    }
-  }
-  pull_emit(valid, v, found, live_bm, depth, parent, next_depth, out_a, cnt_a, out_u, cnt_u);
-  if (inspected) {
-    const int64_t s = wave_sum(scanned);
-    if (lane() == 0 && s) atomicAdd((unsigned long long*)inspected, (unsigned long long)s);
-  }
+  int64_t scanned;
+  const int32_t found = first_frontier_nbr<32>(valid, rb, re, C, bm, p, &scanned);
+  pull_emit(valid, v, found, bm, p, depth, parent, next_depth, out_a, cnt_a, out_u, cnt_u);
+  add_inspected(inspected, scanned);
 }
 
-// Pull with fixed-width edge groups: GW lanes per unvisited vertex, every
-// group checks GW consecutive neighbours per step; the lowest hit lane of the
-// first step with a hit holds the smallest-id frontier neighbour.
+// PULL_LB: fixed-width groups of GW lanes per unvisited vertex, each group
+// checking GW consecutive neighbours per step (the lowest hit lane of the
+// first step with a hit is the smallest-id frontier neighbour); lists longer
+// than 64 neighbours are handed to the whole wavefront.
 template <int GW>
 __global__ __launch_bounds__(256) void k_bfs_pull_groups(
     const int32_t* __restrict__ unv, int32_t n_u, const int32_t* __restrict__ R,
-    const int32_t* __restrict__ C, const uint32_t* __restrict__ old_bm,
-    uint32_t* __restrict__ live_bm, int32_t* __restrict__ depth, int32_t* __restrict__ parent,
-    int32_t next_depth, int32_t* __restrict__ out_a, uint32_t* __restrict__ cnt_a,
-    int32_t* __restrict__ out_u, uint32_t* __restrict__ cnt_u, int64_t* __restrict__ inspected) {
-  static_assert(GW > 0 && GW < kWave && (kWave % GW) == 0, "group width");
-  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GW;
+    const int32_t* __restrict__ C, uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth,
+    int32_t* __restrict__ parent, int32_t next_depth, int32_t* __restrict__ out_a,
+    uint32_t* __restrict__ cnt_a, int32_t* __restrict__ out_u, uint32_t* __restrict__ cnt_u,
+    int64_t* __restrict__ inspected) {
+  static_assert(GW > 1 && GW < kWave && (kWave % GW) == 0, "group width");
+  constexpr int GPW = kWave / GW;  // groups (vertices) per wavefront
+  const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int sub = lane() % GW;
-  const int gbase = lane() - sub;
-  const bool valid = g < n_u;
-  int32_t v = 0, rb = 0, re = 0;
-  if (valid) {
-    v = unv[g];
-    rb = R[v];
-    re = R[v + 1];
+  const int grp = lane() / GW;
+  const int gbase = grp * GW;
+  // lane l < GPW loads the vertex of group l of this wavefront
+  const int64_t mine = wave_id * GPW + lane();
+  int32_t mv = 0, mrb = 0, mre = 0;
+  const bool mvalid = lane() < GPW && mine < n_u;
+  if (mvalid) {
+    mv = unv[mine];
+    mrb = R[mv];
+    mre = R[mv + 1];
   }
+  const int32_t v = __shfl(mv, grp), rb = __shfl(mrb, grp), re = __shfl(mre, grp);
+  const bool valid = __shfl((int)mvalid, grp) != 0;
+  const bool small = valid && re - rb <= kWave;
   int32_t found = -1;
   int64_t scanned = 0;
   for (int32_t base = rb;; base += GW) {
-    const bool active = valid && found < 0 && base < re;
+    const bool active = small && found < 0 && base < re;
     if (!__any(active)) break;
     const int32_t j = base + sub;
     int32_t u = -1;
     bool hit = false;
     if (active && j < re) {
       u = C[j];
-      hit = in_frontier(old_bm, live_bm, u);
+      hit = in_frontier(bm, p, u);
     }
     const uint64_t b = __ballot(hit);
     const uint64_t gm = (b >> gbase) & ((1ull << GW) - 1ull);
@@ -174,68 +299,100 @@ __global__ __launch_bounds__(256) void k_bfs_pull_groups(
       if (gm) found = cand;
     }
   }
+  // long lists: whole wavefront per vertex (group leaders hold the vertex)
   const bool leader = sub == 0;
-  pull_emit(valid && leader, v, found, live_bm, depth, parent, next_depth, out_a, cnt_a, out_u,
-            cnt_u);
-  if (inspected) {
-    const int64_t s = wave_sum(leader ? scanned : (int64_t)0);
-    if (lane() == 0 && s) atomicAdd((unsigned long long*)inspected, (unsigned long long)s);
+  int64_t sc_big = 0;
+  const int32_t fb = first_frontier_nbr<0>(leader && valid && !small, rb, re, C, bm, p, &sc_big);
+  if (leader && valid && !small) {
+    found = fb;
+    scanned = sc_big;
   }
+  pull_emit(valid && leader, v, found, bm, p, depth, parent, next_depth, out_a, cnt_a, out_u,
+            cnt_u);
+  add_inspected(inspected, leader ? scanned : 0);
+}
+
+// Parents of the vertices a push step discovered (symmetric graphs): the
+// first frontier neighbour in ascending order.
+__global__ __launch_bounds__(256) void k_bfs_parent_fixup(const int32_t* __restrict__ list,
+                                                          const uint32_t* __restrict__ count,
+                                                          const int32_t* __restrict__ R,
+                                                          const int32_t* __restrict__ C,
+                                                          const uint32_t* __restrict__ bm, int p,
+                                                          int32_t* __restrict__ parent) {
+  const int64_t n = *count;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)blockIdx.x * blockDim.x >= n) return;  // whole block past the end
+  const bool valid = i < n;
+  int32_t v = 0, rb = 0, re = 0;
+  if (valid) {
+    v = list[i];
+    rb = R[v];
+    re = R[v + 1];
+  }
+  int64_t scanned;
+  const int32_t par = first_frontier_nbr<32>(valid, rb, re, C, bm, p, &scanned);
+  if (valid) parent[v] = par;
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_bfs_push_lb(const int32_t* frontier, const int32_t* offsets, int64_t n_f,
-                              int64_t m_f, const int32_t* R, const int32_t* C,
-                              const uint32_t* bm_old, uint32_t* bm_live, int32_t* depth,
-                              int32_t* parent, int32_t next_depth, int32_t* out_q,
-                              uint32_t* out_count, int chunk, hipStream_t st) {
-  if (m_f <= 0) return hipSuccess;
-  BfsVisit f{bm_old, bm_live, depth, parent, next_depth};
-  k_push_lb<BfsVisit><<<blocks_for(m_f, chunk), kAdvBlock, 0, st>>>(
-      frontier, offsets, (int32_t)n_f, (int32_t)m_f, R, C, f, out_q, out_count, chunk);
+hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier,
+                           const int32_t* offsets, const int32_t* rstart,
+                           const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
+                           const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
+                           int32_t next_depth, int32_t* out_q, uint32_t* out_count, int chunk,
+                           hipStream_t st) {
+  if (atomic_parent) {
+    BfsVisit<true> f{bm, depth, parent, next_depth, p};
+    return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
+                         out_count, chunk, st);
+  }
+  BfsVisit<false> f{bm, depth, nullptr, next_depth, p};
+  return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
+                       out_count, chunk, st);
+}
+
+hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
+                                 const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                 int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
+                                 int p, uint8_t* marks, int64_t V, int32_t* depth,
+                                 int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                 int chunk, hipStream_t st) {
+  BfsMark f{bm, marks, p};
+  hipError_t e = push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f,
+                               out_q, out_count, chunk, st);
+  if (e != hipSuccess) return e;
+  const int64_t n_words = (V + 31) / 32;
+  k_bfs_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, bm, p, depth, next_depth,
+                                                               out_q, out_count);
   return hipGetLastError();
 }
 
-hipError_t launch_bfs_push_light(const int32_t* frontier, int64_t n_f, const int32_t* R,
-                                 const int32_t* C, const uint32_t* bm_old, uint32_t* bm_live,
-                                 int32_t* depth, int32_t* parent, int32_t next_depth,
-                                 int32_t* out_q, uint32_t* out_count, hipStream_t st) {
-  if (n_f <= 0) return hipSuccess;
-  BfsVisit f{bm_old, bm_live, depth, parent, next_depth};
-  k_push_light<BfsVisit><<<blocks_for(n_f, kAdvBlock), kAdvBlock, 0, st>>>(
-      frontier, (int32_t)n_f, R, C, f, out_q, out_count);
-  return hipGetLastError();
-}
-
-hipError_t launch_bfs_push_twc(const int32_t* frontier, int64_t n_f, const int32_t* R,
-                               const int32_t* C, const uint32_t* bm_old, uint32_t* bm_live,
-                               int32_t* depth, int32_t* parent, int32_t next_depth,
-                               int32_t* out_q, uint32_t* out_count, hipStream_t st) {
-  if (n_f <= 0) return hipSuccess;
-  BfsVisit f{bm_old, bm_live, depth, parent, next_depth};
-  k_push_twc<BfsVisit><<<blocks_for(n_f, kAdvBlock), kAdvBlock, 0, st>>>(
-      frontier, (int32_t)n_f, R, C, f, out_q, out_count);
+hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
+                                   const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
+                                   int32_t* parent, hipStream_t st) {
+  if (max_count <= 0) return hipSuccess;
+  k_bfs_parent_fixup<<<blocks_for(max_count, 256), 256, 0, st>>>(list, count, R, C, bm, p, parent);
   return hipGetLastError();
 }
 
 hipError_t launch_bfs_pull(bool lb, const int32_t* unvisited, int64_t n_u, const int32_t* R,
-                           const int32_t* C, const uint32_t* bm_old, uint32_t* bm_live,
-                           int32_t* depth, int32_t* parent, int32_t next_depth,
-                           int32_t* out_active, uint32_t* out_active_count,
+                           const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
+                           int32_t next_depth, int32_t* out_active, uint32_t* out_active_count,
                            int32_t* out_unvisited, uint32_t* out_unvisited_count,
                            int64_t* inspected, hipStream_t st) {
   if (n_u <= 0) return hipSuccess;
   if (lb) {
-    constexpr int GW = 8;
+    constexpr int GW = 4;
     k_bfs_pull_groups<GW><<<blocks_for(n_u * GW, 256), 256, 0, st>>>(
-        unvisited, (int32_t)n_u, R, C, bm_old, bm_live, depth, parent, next_depth, out_active,
+        unvisited, (int32_t)n_u, R, C, bm, p, depth, parent, next_depth, out_active,
         out_active_count, out_unvisited, out_unvisited_count, inspected);
   } else {
     k_bfs_pull_twc<<<blocks_for(n_u, 256), 256, 0, st>>>(
-        unvisited, (int32_t)n_u, R, C, bm_old, bm_live, depth, parent, next_depth, out_active,
+        unvisited, (int32_t)n_u, R, C, bm, p, depth, parent, next_depth, out_active,
         out_active_count, out_unvisited, out_unvisited_count, inspected);
   }
   return hipGetLastError();

@@ -14,8 +14,7 @@ constexpr int kStatsGrid = 512;
 
 __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
                                                   int32_t* __restrict__ parent, int64_t V,
-                                                  uint32_t* __restrict__ bm_old,
-                                                  uint32_t* __restrict__ bm_live, int64_t n_words,
+                                                  uint32_t* __restrict__ bm, int64_t n_words,
                                                   int32_t source, int32_t* __restrict__ queue,
                                                   Ctrl* __restrict__ ctrl) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -24,9 +23,10 @@ __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
     depth[v] = (v == source) ? 0 : -1;
     if (parent) parent[v] = -1;
   }
+  // level 0 has parity 0: old = even words (the source), live = odd words (empty)
   for (int64_t w = i0; w < n_words; w += stride) {
-    bm_old[w] = (w == (source >> 5)) ? (1u << (source & 31)) : 0u;
-    bm_live[w] = 0u;
+    bm[2 * w] = (w == (source >> 5)) ? (1u << (source & 31)) : 0u;
+    bm[2 * w + 1] = 0u;
   }
   if (i0 == 0) {
     queue[0] = source;
@@ -34,25 +34,23 @@ __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
     ctrl->q_count[1] = 0;
     ctrl->u_count[0] = 0;
     ctrl->u_count[1] = 0;
+    ctrl->m_f[0] = ctrl->m_f[1] = 0;
+    ctrl->max_deg[0] = ctrl->max_deg[1] = 0;
     ctrl->inspected = 0;
     ctrl->reached_edges = 0;
-    ctrl->misc[0] = 0;  // statistics ticket
   }
 }
 
-// Per-block degree sum / max over a contiguous slice of the frontier.  The
-// last block to finish (ticket in ctrl->misc[0]) scans the block sums into
-// exclusive block prefixes, publishes m_f / max degree / n_f in the control
-// block and clears the two queue counters the next step will append to.
-// block_sums layout: [0,G) sums, [G,2G) maxima, [2G,3G) exclusive prefixes,
-// [3G] total.
+// Degree sum / max of the frontier, one contiguous slice per block.  Block
+// sums go to block_sums[b] (the offsets kernel scans them); totals are
+// accumulated atomically in slot `parity`, which the previous call cleared.
+// Block 0 clears the other slot and the two counters the next step appends to.
 __global__ __launch_bounds__(kStatsBlock) void k_frontier_stats(
     const int32_t* __restrict__ frontier, const uint32_t* __restrict__ n_f_dev,
     const int32_t* __restrict__ R, int64_t* __restrict__ block_sums, Ctrl* __restrict__ ctrl,
-    uint32_t* zero_a, uint32_t* zero_b) {
+    int parity, uint32_t* zero_a, uint32_t* zero_b) {
   __shared__ int64_t s_sum[kStatsBlock / kWave];
   __shared__ int64_t s_max[kStatsBlock / kWave];
-  __shared__ bool s_last;
   const int G = gridDim.x;
   const int64_t n_f = (int64_t)*n_f_dev;
   const int64_t per = (n_f + G - 1) / G;
@@ -60,8 +58,8 @@ __global__ __launch_bounds__(kStatsBlock) void k_frontier_stats(
   const int64_t hi = lo + per < n_f ? lo + per : n_f;
   int64_t sum = 0, mx = 0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kStatsBlock) {
-    int32_t u = frontier[i];
-    int64_t d = (int64_t)R[u + 1] - R[u];
+    const int32_t u = frontier[i];
+    const int64_t d = (int64_t)R[u + 1] - R[u];
     sum += d;
     mx = d > mx ? d : mx;
   }
@@ -74,114 +72,92 @@ __global__ __launch_bounds__(kStatsBlock) void k_frontier_stats(
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t bs = 0, bm = 0;
+    int64_t bs = 0, bmx = 0;
     for (int i = 0; i < kStatsBlock / kWave; ++i) {
       bs += s_sum[i];
-      bm = s_max[i] > bm ? s_max[i] : bm;
+      bmx = s_max[i] > bmx ? s_max[i] : bmx;
     }
     block_sums[blockIdx.x] = bs;
-    block_sums[G + blockIdx.x] = bm;
-    __threadfence();
-    unsigned long long t = atomicAdd((unsigned long long*)&ctrl->misc[0], 1ull);
-    s_last = (t == (unsigned long long)(G - 1));
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // last block: scan G block sums (G <= 64 * kStatsBlock / kWave * ... handled serially per thread)
-  __shared__ int64_t s_tot[kStatsBlock / kWave + 1];
-  int64_t run_base = 0, total_max = 0;
-  for (int base = 0; base < G; base += kStatsBlock) {
-    int b = base + threadIdx.x;
-    int64_t x = b < G ? block_sums[b] : 0;
-    int64_t m = b < G ? block_sums[G + b] : 0;
-    int64_t tot;
-    int64_t ex = block_excl_scan<kStatsBlock>(x, s_tot, &tot);
-    if (b < G) block_sums[2 * G + b] = run_base + ex;
-    run_base += tot;
-    m = wave_max(m);
-    if (lane() == 0) s_max[w] = m;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int i = 0; i < kStatsBlock / kWave; ++i) total_max = s_max[i] > total_max ? s_max[i] : total_max;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    block_sums[3 * G] = run_base;
-    ctrl->m_f = run_base;
-    ctrl->max_deg = total_max;
-    ctrl->n_f = n_f;
-    ctrl->misc[0] = 0;
-    if (zero_a) *zero_a = 0;
-    if (zero_b) *zero_b = 0;
+    if (bs) atomicAdd((unsigned long long*)&ctrl->m_f[parity], (unsigned long long)bs);
+    if (bmx) atomicMax((unsigned long long*)&ctrl->max_deg[parity], (unsigned long long)bmx);
+    if (blockIdx.x == 0) {
+      ctrl->n_f[parity] = n_f;
+      ctrl->m_f[parity ^ 1] = 0;
+      ctrl->max_deg[parity ^ 1] = 0;
+      if (zero_a) *zero_a = 0;
+      if (zero_b) *zero_b = 0;
+    }
   }
 }
 
-// Exclusive scan of frontier degrees into offsets[0..n_f] using the block
-// prefixes of k_frontier_stats (same slicing).  Also marks every frontier
-// vertex in the live visited bitmap (push steps keep live = visited through
-// the next level).
+// Exclusive scan of frontier degrees into offsets[0..n_f] (same slicing as
+// k_frontier_stats; each block sums the block totals before it), the row
+// start of every frontier vertex, and the chunk -> segment map of
+// output-balanced LB: chunk_start[c] = the frontier index whose neighbour list
+// holds edge c * chunk (the sorted search of 0, N, 2N, ... in the offsets).
 __global__ __launch_bounds__(kStatsBlock) void k_frontier_offsets(
     const int32_t* __restrict__ frontier, int64_t n_f, const int32_t* __restrict__ R,
-    const int64_t* __restrict__ block_sums, int32_t* __restrict__ offsets,
-    uint32_t* __restrict__ live_bm) {
+    const int64_t* __restrict__ block_sums, const int64_t* __restrict__ total,
+    int32_t* __restrict__ offsets, int32_t* __restrict__ rstart, int32_t* __restrict__ chunk_start,
+    int32_t chunk) {
   __shared__ int64_t s_tot[kStatsBlock / kWave + 1];
   const int G = gridDim.x;
   const int64_t per = (n_f + G - 1) / G;
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = lo + per < n_f ? lo + per : n_f;
-  int64_t run = block_sums[2 * G + blockIdx.x];
+  // prefix of the block sums before this block
+  int64_t pre = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kStatsBlock) pre += block_sums[b];
+  {
+    int64_t t;
+    block_excl_scan<kStatsBlock>(pre, s_tot, &t);
+    pre = t;
+  }
+  int64_t run = pre;
   for (int64_t base = lo; base < hi; base += kStatsBlock) {
-    int64_t i = base + threadIdx.x;
+    const int64_t i = base + threadIdx.x;
     int64_t d = 0;
+    int32_t rb = 0;
     if (i < hi) {
-      int32_t u = frontier[i];
-      d = (int64_t)R[u + 1] - R[u];
-      if (live_bm) atomicOr(&live_bm[u >> 5], 1u << (u & 31));
+      const int32_t u = frontier[i];
+      rb = R[u];
+      d = (int64_t)R[u + 1] - rb;
     }
     int64_t tot;
-    int64_t ex = block_excl_scan<kStatsBlock>(d, s_tot, &tot);
-    if (i < hi) offsets[i] = (int32_t)(run + ex);
+    const int64_t ex = block_excl_scan<kStatsBlock>(d, s_tot, &tot);
+    if (i < hi) {
+      const int64_t o = run + ex;
+      offsets[i] = (int32_t)o;
+      rstart[i] = rb;
+      for (int64_t c = (o + chunk - 1) / chunk; c * chunk < o + d; ++c) chunk_start[c] = (int32_t)i;
+    }
     run += tot;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n_f] = (int32_t)block_sums[3 * G];
+  if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n_f] = (int32_t)*total;
 }
 
 // Alg. 2, GenerateUnvisitedFrontier: every vertex not yet visited.  Vertices of
 // degree zero are left out: in a symmetric graph nothing can reach them.
-__global__ __launch_bounds__(256) void k_gen_unvisited(const uint32_t* __restrict__ bm_old,
+__global__ __launch_bounds__(256) void k_gen_unvisited(const uint32_t* __restrict__ bm, int p,
                                                        const int32_t* __restrict__ R, int64_t V,
                                                        int32_t* __restrict__ out,
                                                        uint32_t* __restrict__ count) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool keep = false;
-  if (v < V) keep = !bm_test(bm_old, (int32_t)v) && R[v + 1] > R[v];
-  uint32_t slot = wave_append(count, keep);
+  if (v < V) keep = !((bm[2 * (v >> 5) + p] >> (v & 31)) & 1u) && R[v + 1] > R[v];
+  const uint32_t slot = wave_append(count, keep);
   if (keep) out[slot] = (int32_t)v;
 }
 
-__global__ __launch_bounds__(256) void k_bitmap_or(uint32_t* __restrict__ dst,
-                                                   const uint32_t* __restrict__ src,
-                                                   int64_t n_words) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_words) dst[i] |= src[i];
-}
-
-__global__ __launch_bounds__(256) void k_reached_edges(const int32_t* __restrict__ depth,
-                                                       const int32_t* __restrict__ R, int64_t V,
-                                                       int64_t* __restrict__ out) {
-  __shared__ int64_t s[256 / kWave];
-  int64_t acc = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
-       v += (int64_t)gridDim.x * blockDim.x)
-    if (depth[v] >= 0) acc += (int64_t)R[v + 1] - R[v];
-  acc = wave_sum(acc);
-  if (lane() == 0) s[threadIdx.x / kWave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t t = 0;
-    for (int i = 0; i < 256 / kWave; ++i) t += s[i];
-    atomicAdd((unsigned long long*)out, (unsigned long long)t);
+// live |= old over all word pairs
+__global__ __launch_bounds__(256) void k_bitmap_merge(uint32_t* __restrict__ bm, int p,
+                                                      int64_t n_words) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < n_words) {
+    uint2 x = reinterpret_cast<uint2*>(bm)[w];
+    if (p == 0) x.y |= x.x;
+    else x.x |= x.y;
+    reinterpret_cast<uint2*>(bm)[w] = x;
   }
 }
 
@@ -195,58 +171,51 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  k_fill_u32<<<blocks_for(n, 256), 256, 0, st>>>(p, n, value);
-  return hipGetLastError();
-}
-
 int stats_grid() { return kStatsGrid; }
 
-hipError_t launch_bfs_init(int32_t* depth, int32_t* parent, int64_t V, uint32_t* bm_old,
-                           uint32_t* bm_live, int64_t n_words, int32_t source, int32_t* queue,
-                           Ctrl* ctrl, hipStream_t st) {
-  int64_t n = V > n_words ? V : n_words;
+hipError_t launch_bfs_init(int32_t* depth, int32_t* parent, int64_t V, uint32_t* bm,
+                           int64_t n_words, int32_t source, int32_t* queue, Ctrl* ctrl,
+                           hipStream_t st) {
+  const int64_t n = V > n_words ? V : n_words;
   unsigned g = blocks_for(n, 256);
   if (g > 4096) g = 4096;
-  k_bfs_init<<<g, 256, 0, st>>>(depth, parent, V, bm_old, bm_live, n_words, source, queue, ctrl);
+  k_bfs_init<<<g, 256, 0, st>>>(depth, parent, V, bm, n_words, source, queue, ctrl);
   return hipGetLastError();
 }
 
 hipError_t launch_frontier_stats(const int32_t* frontier, const uint32_t* n_f_dev, const int32_t* R,
-                                 int64_t* block_sums, Ctrl* ctrl, uint32_t* zero_a,
+                                 int64_t* block_sums, Ctrl* ctrl, int parity, uint32_t* zero_a,
                                  uint32_t* zero_b, hipStream_t st) {
   k_frontier_stats<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f_dev, R, block_sums, ctrl,
-                                                       zero_a, zero_b);
+                                                       parity, zero_a, zero_b);
   return hipGetLastError();
 }
 
 hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const int32_t* R,
-                                   const int64_t* block_sums, int32_t* offsets,
-                                   uint32_t* live_bm, hipStream_t st) {
-  k_frontier_offsets<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f, R, block_sums, offsets,
-                                                         live_bm);
+                                   const int64_t* block_sums, const int64_t* total,
+                                   int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
+                                   int32_t chunk, hipStream_t st) {
+  k_frontier_offsets<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f, R, block_sums, total,
+                                                         offsets, rstart, chunk_start, chunk);
   return hipGetLastError();
 }
 
-hipError_t launch_gen_unvisited(const uint32_t* bm_old, const int32_t* R, int64_t V,
+hipError_t launch_gen_unvisited(const uint32_t* bm, int p, const int32_t* R, int64_t V,
                                 int32_t* out_list, uint32_t* out_count, hipStream_t st) {
   if (V <= 0) return hipSuccess;
-  k_gen_unvisited<<<blocks_for(V, 256), 256, 0, st>>>(bm_old, R, V, out_list, out_count);
+  k_gen_unvisited<<<blocks_for(V, 256), 256, 0, st>>>(bm, p, R, V, out_list, out_count);
   return hipGetLastError();
 }
 
-hipError_t launch_bitmap_or(uint32_t* dst, const uint32_t* src, int64_t n_words, hipStream_t st) {
+hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st) {
   if (n_words <= 0) return hipSuccess;
-  k_bitmap_or<<<blocks_for(n_words, 256), 256, 0, st>>>(dst, src, n_words);
+  k_bitmap_merge<<<blocks_for(n_words, 256), 256, 0, st>>>(bm, p, n_words);
   return hipGetLastError();
 }
 
-hipError_t launch_reached_edges(const int32_t* depth, const int32_t* R, int64_t V, int64_t* out,
-                                hipStream_t st) {
-  unsigned g = blocks_for(V, 256);
-  if (g > 2048) g = 2048;
-  k_reached_edges<<<g, 256, 0, st>>>(depth, R, V, out);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill_u32<<<blocks_for(n, 256), 256, 0, st>>>(p, n, value);
   return hipGetLastError();
 }
 

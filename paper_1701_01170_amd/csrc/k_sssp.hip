@@ -25,12 +25,16 @@ struct SsspVisit {
   __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
     return (int32_t)(uint32_t)(keys[u] >> 32);
   }
-  __device__ __forceinline__ void on_frontier(int32_t) const {}
-  __device__ __forceinline__ bool visit(int32_t u, int32_t du, int32_t v, int64_t e) const {
-    const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)W[e];
+  __device__ __forceinline__ uint32_t edge_value(int64_t e) const { return W[e]; }
+  __device__ __forceinline__ bool probe(int32_t u, int32_t du, int32_t v, uint32_t w) const {
+    const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
     if (cand >= 0xffffffffull) return false;  // cannot be a shortest distance (range checked at entry)
     const unsigned long long nk = (cand << 32) | (uint32_t)u;
-    if (nk >= keys[v]) return false;           // keys only decrease: nothing to gain
+    return nk < keys[v];                       // keys only decrease: otherwise nothing to gain
+  }
+  __device__ __forceinline__ bool commit(int32_t u, int32_t du, int32_t v, uint32_t w) const {
+    const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
+    const unsigned long long nk = (cand << 32) | (uint32_t)u;
     const unsigned long long old = atomicMin(&keys[v], nk);
     if (cand >= (old >> 32)) return false;     // no distance improvement (at most a better pred)
     return atomicExch(&tags[v], next_tag) != next_tag;
@@ -51,7 +55,8 @@ __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restric
     ctrl->u_count[1] = 0;
     ctrl->inspected = 0;
     ctrl->reached_edges = 0;
-    ctrl->misc[0] = 0;
+    ctrl->m_f[0] = ctrl->m_f[1] = 0;
+    ctrl->max_deg[0] = ctrl->max_deg[1] = 0;
   }
 }
 
@@ -118,25 +123,14 @@ hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long lon
   return hipGetLastError();
 }
 
-hipError_t launch_sssp_relax(int action_lb, bool light, const int32_t* frontier,
-                             const int32_t* offsets, int64_t n_f, int64_t m_f, const int32_t* R,
-                             const int32_t* C, const uint32_t* W, unsigned long long* keys,
-                             int32_t* tags, int32_t next_tag, int32_t* out_q, uint32_t* out_count,
-                             int chunk, hipStream_t st) {
-  if (n_f <= 0) return hipSuccess;
+hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* offsets,
+                             const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                             int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
+                             unsigned long long* keys, int32_t* tags, int32_t next_tag,
+                             int32_t* out_q, uint32_t* out_count, int chunk, hipStream_t st) {
   SsspVisit f{W, keys, tags, next_tag};
-  if (action_lb && !light) {
-    if (m_f <= 0) return hipSuccess;
-    k_push_lb<SsspVisit><<<blocks_for(m_f, chunk), kAdvBlock, 0, st>>>(
-        frontier, offsets, (int32_t)n_f, (int32_t)m_f, R, C, f, out_q, out_count, chunk);
-  } else if (action_lb) {
-    k_push_light<SsspVisit><<<blocks_for(n_f, kAdvBlock), kAdvBlock, 0, st>>>(
-        frontier, (int32_t)n_f, R, C, f, out_q, out_count);
-  } else {
-    k_push_twc<SsspVisit><<<blocks_for(n_f, kAdvBlock), kAdvBlock, 0, st>>>(
-        frontier, (int32_t)n_f, R, C, f, out_q, out_count);
-  }
-  return hipGetLastError();
+  return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
+                       out_count, chunk, st);
 }
 
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
