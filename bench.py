@@ -4,29 +4,69 @@ on one MI355X.
 
 A step is one pass of the traversal hot path over the resident graph: a
 direction-optimising BFS (depths + canonical parents) and an SSSP (distances +
-canonical predecessors) from the same seeded source, each selecting its
-advance strategy per iteration with the fixed-threshold heuristic.  The graph
-is generated on the host and uploaded before the timed region.  Throughput is
-GTEPS = (sum over the step's traversals of the degrees of reached vertices) /
-step time, the paper's TEPS convention (Sec. 7, measurement methodology).
+canonical predecessors) from the same seeded source, each choosing its advance
+strategy per iteration with the fixed-threshold heuristic of the paper (library
+defaults).  The graph is generated on the host and uploaded before the timed
+region.  Throughput is GTEPS = (sum over the step's traversals of the degrees
+of the reached vertices) / step time, the paper's TEPS convention (Sec. 7,
+measurement methodology).
 
-Prints ONE JSON line (see --help).  The CPU oracle (single thread) is timed
-on a bounded sample of the same workload as `cpu_baseline`.
+The timed steps run with per-iteration tracing on, so every advance kernel is
+bracketed by HIP events on the traversal's stream; `roofline` divides the
+algorithmic bytes of the dominant advance kernel by its event-timed duration.
+`traffic` comes from committed rocprofv3 FETCH_SIZE/WRITE_SIZE summaries
+(profiles/traffic_*.json) when they were taken on the current kernel source,
+else null.  `cpu_baseline` times the CPU oracle (single thread) on one BFS and
+one SSSP of the same workload.
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {
+    ("bfs", 0): "k_push_twc<BfsVisit>", ("bfs", 1): "k_push_light<BfsVisit>",
+    ("bfs", 2): "k_push_lb<BfsVisit>", ("bfs", 3): "k_push_lb<BfsMark>",
+    ("bfs", 4): "k_bfs_pull_twc", ("bfs", 5): "k_bfs_pull_groups",
+    ("sssp", 0): "k_push_twc<SsspVisit>", ("sssp", 1): "k_push_light<SsspVisit>",
+    ("sssp", 2): "k_push_lb<SsspVisit>",
+}
+
+
+def algorithmic_bytes(kind: str, kernel: int, n_f: int, m_f: int, n_next: int) -> float | None:
+    """Bytes the method must move for one advance launch:
+    SSSP relax: per edge 4 B column + 4 B weight + 8 B packed atomic-min of the
+      target's (dist, pred) key; per frontier vertex 4 B id + 8 B row offsets;
+      per output vertex 4 B queue entry.
+    BFS push: per edge 4 B column (the visited test is one bit, cache
+      resident); per frontier vertex 12 B; per new vertex 4 B depth + 4 B
+      parent + 4 B queue entry."""
+    if kind == "sssp":
+        return 16.0 * m_f + 12.0 * n_f + 4.0 * n_next
+    if kind == "bfs" and kernel in (0, 1, 2, 3):
+        return 4.0 * m_f + 12.0 * n_f + 12.0 * n_next
+    return None
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1701_01170_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -37,14 +77,13 @@ def parse():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-breakdown", action="store_true")
     return ap.parse_args()
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+        print(f"bench.py measures one GPU; this build has no multi-GPU path (got --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -54,9 +93,8 @@ def main():
     t0 = time.time()
     hg = gg.add_weights(gg.rmat(args.scale, args.edge_factor, seed=1), seed=101)
     srcs = gg.sources(hg, args.steps + args.warmup, seed=1000)
-    gen_s = time.time() - t0
-    print(f"# generated {hg.name}: V={hg.n_vertices} E={hg.n_edges} in {gen_s:.1f}s", file=sys.stderr,
-          flush=True)
+    print(f"# generated {hg.name}: V={hg.n_vertices} E={hg.n_edges} in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
 
     ctx = gr.Context(0)
     g = gr.Graph.from_host(ctx, hg, symmetric=True)
@@ -66,19 +104,24 @@ def main():
     parent = torch.empty(V, dtype=torch.int32, device=dev)
     dist = torch.empty(V, dtype=torch.int32, device=dev)
     pred = torch.empty(V, dtype=torch.int32, device=dev)
-    opts = gr.default_opts()
+    cap = 4096
+    tb = (gr.LevelTrace * cap)()
+    ts = (gr.LevelTrace * cap)()
+    ob = gr.default_opts(trace=tb, trace_capacity=cap)
+    os_ = gr.default_opts(trace=ts, trace_capacity=cap)
+    stream = torch.cuda.current_stream()
 
     def step(s):
-        _, _, sb = gr.bfs(g, int(s), opts=opts, out=(depth, parent))
-        _, _, ss = gr.sssp(g, [int(s)], opts=opts, out=(dist, pred))
+        _, _, sb = gr.bfs(g, int(s), opts=ob, out=(depth, parent), stream=stream)
+        _, _, ss = gr.sssp(g, [int(s)], opts=os_, out=(dist, pred), stream=stream)
         return sb, ss
 
     for i in range(args.warmup):
         step(srcs[i])
     torch.cuda.synchronize()
-    teps = 0
+    per_kernel = {}  # (kind, kernel) -> [launches, sum_us, sum_bytes]
+    teps = bfs_teps = sssp_teps = 0
     bfs_ms = sssp_ms = 0.0
-    bfs_teps = sssp_teps = 0
     t0 = time.perf_counter()
     for i in range(args.steps):
         sb, ss = step(srcs[args.warmup + i])
@@ -87,10 +130,29 @@ def main():
         sssp_teps += ss["teps_edges"]
         bfs_ms += sb["device_ms"]
         sssp_ms += ss["device_ms"]
+        for kind, buf, o in (("bfs", tb, ob), ("sssp", ts, os_)):
+            for t in buf[:min(o.trace_count, cap)]:
+                a = per_kernel.setdefault((kind, t.kernel), [0, 0.0, 0.0])
+                a[0] += 1
+                a[1] += t.kernel_us
+                b = algorithmic_bytes(kind, t.kernel, t.n_f, t.m_f, t.n_next)
+                a[2] += b if b is not None else float("nan")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     value = teps / wall / 1e9
+
+    dom = max(per_kernel, key=lambda k: per_kernel[k][1])
+    launches, sum_us, sum_bytes = per_kernel[dom]
+    achieved = sum_bytes / (sum_us * 1e-6) / 1e9 if sum_us > 0 else None
+    copy_gbs = gr.copy_bandwidth(ctx, 1 << 30, 20)
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAMES[dom].split('<')[0]}_{dom[0]}_rmat{args.scale}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tj.get("hbm_bytes_per_launch")
 
     out = {
         "metric": "GTEPS BFS/SSSP RMAT-22, learned+batched vs plain; % HBM peak",
@@ -105,22 +167,37 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"rmat_s{args.scale}_e{args.edge_factor} BFS+SSSP single source, heuristic",
-                   "n_vertices": V, "n_edges": hg.n_edges, "sources_per_step": 1},
+        "config": {"workload": f"rmat_s{args.scale}_e{args.edge_factor} BFS+SSSP from one seeded source "
+                               f"per step, paper heuristic, int32 CSR, uint32 weights 1..64",
+                   "n_vertices": V, "n_edges": hg.n_edges},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": KERNEL_NAMES[dom],
+            "achieved": None if achieved is None else round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "launches": launches,
+            "avg_launch_us": round(sum_us / launches, 2),
+            "algorithmic_bytes_per_launch": round(sum_bytes / launches),
+            "copy_ceiling_gbs": round(copy_gbs, 1),
+        },
         "breakdown": {
             "bfs_gteps_device": round(bfs_teps / (bfs_ms / 1e3) / 1e9, 3),
             "sssp_gteps_device": round(sssp_teps / (sssp_ms / 1e3) / 1e9, 3),
             "bfs_ms": round(bfs_ms / args.steps, 4),
             "sssp_ms": round(sssp_ms / args.steps, 4),
+            "kernel_us_per_step": {f"{k[0]}:{KERNEL_NAMES[k]}": round(v[1] / args.steps, 1)
+                                   for k, v in sorted(per_kernel.items())},
         },
-        "roofline": None,
         "cpu_baseline": None,
     }
 
     if not args.no_cpu_baseline:
         import oracle
-        t0 = time.perf_counter()
         s0 = int(srcs[args.warmup])
+        t0 = time.perf_counter()
         d, _ = oracle.bfs(hg.row_offsets, hg.col_indices, s0)
         t_b = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -129,8 +206,9 @@ def main():
         te = oracle.teps_edges(hg.row_offsets, d >= 0) + oracle.teps_edges(hg.row_offsets, dd != 0xFFFFFFFF)
         out["cpu_baseline"] = {"value": round(te / (t_b + t_s) / 1e9, 6), "unit": "GTEPS", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"one BFS + one SSSP (with parent/pred passes) from source {s0}, "
-                                         f"bfs {t_b:.2f}s sssp {t_s:.2f}s"}
+                               "sample": f"one BFS and one SSSP (each with its parent/predecessor pass) "
+                                         f"from source {s0} of the same graph: bfs {t_b:.2f}s, "
+                                         f"sssp {t_s:.2f}s, single thread"}
     print(json.dumps(out))
 
 

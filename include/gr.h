@@ -89,8 +89,11 @@ typedef struct gr_level_trace {
   int64_t m_u;         /* sum of unvisited degrees (BFS) */
   int64_t max_deg_f;   /* largest frontier degree */
   float features[8];   /* selector input features (see gr_features) */
-  float step_us;       /* device time of the iteration's advance+filter (event-timed) */
-  int32_t pad;
+  float step_us;       /* device time of the whole iteration (advance, filter, bookkeeping) */
+  float kernel_us;     /* device time of the advance kernel alone (event-timed) */
+  int32_t kernel;      /* advance kernel: 0 TWC, 1 LB_LIGHT, 2 LB, 3 LB with byte-mark filter,
+                          4 pull TWC, 5 pull groups */
+  int64_t n_next;      /* size of the output frontier */
 } gr_level_trace;
 
 typedef struct gr_opts {
@@ -210,6 +213,15 @@ gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, in
 gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);
+
+/* ---- measurement --------------------------------------------------------- */
+
+/* HBM calibration: copy `bytes` (a positive multiple of 16) between two device
+ * buffers the call allocates and frees, `reps` times (after one untimed copy),
+ * with a plain kernel that moves 16 bytes per lane access, and report the
+ * achieved bandwidth in GB/s counting bytes read plus bytes written.  This is
+ * the measured ceiling quoted next to the datasheet HBM peak. */
+gr_status gr_copy_bandwidth(gr_ctx* ctx, int64_t bytes, int32_t reps, void* stream, float* gbps);
 
 #ifdef __cplusplus
 }

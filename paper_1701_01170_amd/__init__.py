@@ -47,7 +47,7 @@ class LevelTrace(ctypes.Structure):
                 ("n_f", ctypes.c_int64), ("m_f", ctypes.c_int64), ("n_u", ctypes.c_int64),
                 ("m_u", ctypes.c_int64), ("max_deg_f", ctypes.c_int64),
                 ("features", ctypes.c_float * 8), ("step_us", ctypes.c_float),
-                ("pad", ctypes.c_int32)]
+                ("kernel_us", ctypes.c_float), ("kernel", ctypes.c_int32), ("n_next", ctypes.c_int64)]
 
 
 class Opts(ctypes.Structure):
@@ -102,6 +102,8 @@ _SIGNATURES = {
                                ctypes.POINTER(RunStats)]),
     "gr_bfs_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
                                     ctypes.POINTER(RunStats)]),
+    "gr_copy_bandwidth": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P,
+                                         ctypes.POINTER(ctypes.c_float)]),
 }
 
 
@@ -322,6 +324,14 @@ def bfs_multi(g: Graph, sources, want_parent: bool = True, opts: Opts | None = N
     check(lib().gr_bfs_multi(g.ctx.handle, g.handle, src.ctypes.data, k, _ptr(depth), _ptr(parent),
                              _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
     return depth, parent, st.as_dict()
+
+
+def copy_bandwidth(ctx: Context, nbytes: int = 1 << 30, reps: int = 20, stream=None) -> float:
+    """Measured HBM copy bandwidth in GB/s (read + write bytes per second)."""
+    out = ctypes.c_float()
+    check(lib().gr_copy_bandwidth(ctx.handle, int(nbytes), int(reps), _stream_handle(stream),
+                                  ctypes.byref(out)))
+    return float(out.value)
 
 
 def u32(t):

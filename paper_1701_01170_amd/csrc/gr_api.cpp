@@ -148,7 +148,8 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
   }
   c->host_ctrl = static_cast<Ctrl*>(hc);
   if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
-      hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess) {
+      hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess ||
+      hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess) {
     gr_ctx_destroy(c);
     return fail(GR_EHIP, "hipEventCreate failed");
   }
@@ -162,7 +163,7 @@ extern "C" gr_status gr_ctx_destroy(gr_ctx* c) {
   for (auto& b : c->pool)
     if (b.ptr) (void)hipFree(b.ptr);
   if (c->host_ctrl) (void)hipHostFree(c->host_ctrl);
-  for (hipEvent_t ev : {c->ev_start, c->ev_stop, c->ev_a, c->ev_b})
+  for (hipEvent_t ev : {c->ev_start, c->ev_stop, c->ev_a, c->ev_b, c->ev_k0, c->ev_k1})
     if (ev) (void)hipEventDestroy(ev);
   delete c;
   return GR_OK;
@@ -365,10 +366,16 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
   return GR_OK;
 }
 
-void record_trace(gr_opts* opts, const LevelFeatures& lf, int action, float step_us) {
-  if (!opts || !opts->trace) return;
+// Event-timed record of one iteration: ev_a..ev_b brackets the whole step,
+// ev_k0..ev_k1 the advance kernel alone.
+gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int action,
+                       int kernel, int64_t n_next) {
+  if (!opts || !opts->trace) return GR_OK;
   int i = opts->trace_count++;
-  if (i >= opts->trace_capacity) return;
+  if (i >= opts->trace_capacity) return GR_OK;
+  float step_ms = 0.f, kernel_ms = 0.f;
+  GR_HIP(hipEventElapsedTime(&step_ms, ctx->ev_a, ctx->ev_b));
+  GR_HIP(hipEventElapsedTime(&kernel_ms, ctx->ev_k0, ctx->ev_k1));
   gr_level_trace& t = opts->trace[i];
   t.level = lf.level;
   t.action = action;
@@ -378,8 +385,11 @@ void record_trace(gr_opts* opts, const LevelFeatures& lf, int action, float step
   t.m_u = lf.m_u;
   t.max_deg_f = lf.max_deg_f;
   selector_features(lf, t.features);
-  t.step_us = step_us;
-  t.pad = 0;
+  t.step_us = step_ms * 1000.0f;
+  t.kernel_us = kernel_ms * 1000.0f;
+  t.kernel = kernel;
+  t.n_next = n_next;
+  return GR_OK;
 }
 
 }  // namespace
@@ -483,6 +493,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     const int action = sel.decide(lf);
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
     const int next_depth = level + 1;
+    int kernel = 0;
     if (action == GR_PUSH_LB || action == GR_PUSH_TWC) {
       const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
       if (mode == 2)
@@ -492,13 +503,20 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       if (!atomic_parent && m_f >= V / kMarksFilterDivisor) {
         uint8_t* marks;
         GR_TRY(marks_buffer(ctx, V, &marks, st));
+        kernel = mode == 2 ? 3 : mode;
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                     bm, p, marks, V, depth, next_depth, q[cur ^ 1],
-                                     &ctrl->q_count[cur ^ 1], chunk, st));
+                                     bm, p, marks, chunk, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+        GR_HIP(launch_bfs_mark_compact(marks, V, bm, p, depth, next_depth, q[cur ^ 1],
+                                       &ctrl->q_count[cur ^ 1], st));
       } else {
+        kernel = mode;
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push(mode, atomic_parent, q[cur], offsets, rstart, chunks, n_f, m_f,
                                g->R, g->C, bm, p, depth, parent, next_depth, q[cur ^ 1],
                                &ctrl->q_count[cur ^ 1], chunk, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
       if (parent && !atomic_parent)
         GR_HIP(launch_bfs_parent_fixup(q[cur ^ 1], &ctrl->q_count[cur ^ 1],
@@ -514,9 +532,12 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         n_ulist = hc->u_count[ucur];
         have_unv = true;
       }
+      kernel = action == GR_PULL_LB ? 5 : 4;
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
       GR_HIP(launch_bfs_pull(action == GR_PULL_LB, ul[ucur], n_ulist, g->R, g->C, bm, p, depth,
                              parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1],
                              ul[ucur ^ 1], &ctrl->u_count[ucur ^ 1], &ctrl->inspected, st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       ucur ^= 1;
     }
     GR_HIP(launch_bitmap_merge(bm, p, NW, st));
@@ -529,11 +550,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
     GR_TRY(read_ctrl(ctx, ctrl, st));
-    if (tracing) {
-      float ms = 0.f;
-      GR_HIP(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
-      record_trace(opts_in, lf, action, ms * 1000.0f);
-    }
+    if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
     max_deg = hc->max_deg[sp];
@@ -639,8 +656,10 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     if (mode == 2)
       GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                      chunks, chunk, st));
+    if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
     GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W, keys,
                              tags, it + 1, q[cur ^ 1], &ctrl->q_count[cur ^ 1], chunk, st));
+    if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
     inspected += m_f;
     rs.action_count[action]++;
@@ -650,11 +669,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[cur ^ 1], nullptr, st));
     GR_TRY(read_ctrl(ctx, ctrl, st));
-    if (tracing) {
-      float ms = 0.f;
-      GR_HIP(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
-      record_trace(opts_in, lf, action, ms * 1000.0f);
-    }
+    if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, mode, hc->n_f[sp]));
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
     max_deg = hc->max_deg[sp];
@@ -691,4 +706,41 @@ extern "C" gr_status gr_ctx_set_policy(gr_ctx* ctx, const float* params, int32_t
   (void)params; (void)n_params;
   if (!ctx) return fail(GR_EINVAL, "ctx is NULL");
   return fail(GR_EUNSUPPORTED, "learned policy is not built yet");
+}
+
+// ============================================================================
+// measurement
+// ============================================================================
+
+extern "C" gr_status gr_copy_bandwidth(gr_ctx* ctx, int64_t bytes, int32_t reps, void* stream,
+                                       float* gbps) {
+  if (!ctx || !gbps) return fail(GR_EINVAL, "gr_copy_bandwidth: NULL argument");
+  if (bytes <= 0 || bytes % 16 != 0) return fail(GR_EINVAL, "bytes must be a positive multiple of 16");
+  if (reps < 1) return fail(GR_EINVAL, "reps must be >= 1");
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void *a = nullptr, *b = nullptr;
+  GR_HIP(hipMalloc(&a, (size_t)bytes));
+  hipError_t e = hipMalloc(&b, (size_t)bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(a);
+    return fail(GR_ENOMEM, "gr_copy_bandwidth: allocation failed");
+  }
+  struct Free2 {
+    void *x, *y;
+    ~Free2() {
+      (void)hipFree(x);
+      (void)hipFree(y);
+    }
+  } fr{a, b};
+  GR_HIP(launch_fill_u32(static_cast<uint32_t*>(a), bytes / 4, 1u, st));
+  GR_HIP(launch_copy(a, b, bytes, st));
+  GR_HIP(hipEventRecord(ctx->ev_k0, st));
+  for (int i = 0; i < reps; ++i) GR_HIP(launch_copy(a, b, bytes, st));
+  GR_HIP(hipEventRecord(ctx->ev_k1, st));
+  GR_HIP(hipEventSynchronize(ctx->ev_k1));
+  float ms = 0.f;
+  GR_HIP(hipEventElapsedTime(&ms, ctx->ev_k0, ctx->ev_k1));
+  *gbps = (float)(2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9);
+  return GR_OK;
 }

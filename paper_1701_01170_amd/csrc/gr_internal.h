@@ -84,6 +84,7 @@ struct gr_ctx {
   gr::Ctrl* host_ctrl = nullptr;   // pinned host mirror of the control block
   bool policy_loaded = false;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_a = nullptr, ev_b = nullptr;
+  hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the advance kernel when tracing
 };
 
 struct gr_graph {
@@ -144,9 +145,12 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                  const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                  int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
-                                 int p, uint8_t* marks, int64_t V, int32_t* depth,
-                                 int32_t next_depth, int32_t* out_q, uint32_t* out_count,
-                                 int chunk, hipStream_t st);
+                                 int p, uint8_t* marks, int chunk, hipStream_t st);
+hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int p, int32_t* depth,
+                                   int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                   hipStream_t st);
+// HBM copy of `bytes` (multiple of 16) from src to dst, 16 bytes per lane access.
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
                                    const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
                                    int32_t* parent, hipStream_t st);

@@ -358,13 +358,15 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                  const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                  int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
-                                 int p, uint8_t* marks, int64_t V, int32_t* depth,
-                                 int32_t next_depth, int32_t* out_q, uint32_t* out_count,
-                                 int chunk, hipStream_t st) {
+                                 int p, uint8_t* marks, int chunk, hipStream_t st) {
   BfsMark f{bm, marks, p};
-  hipError_t e = push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f,
-                               out_q, out_count, chunk, st);
-  if (e != hipSuccess) return e;
+  return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
+                       nullptr, chunk, st);
+}
+
+hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int p, int32_t* depth,
+                                   int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                   hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   k_bfs_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, bm, p, depth, next_depth,
                                                                out_q, out_count);

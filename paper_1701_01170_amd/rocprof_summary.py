@@ -1,0 +1,109 @@
+"""Summaries of rocprofv3 output for the committed profiles/ directory.
+
+  python -m paper_1701_01170_amd.rocprof_summary stats <rocpd_dir> <out.md> "<command>"
+      per-kernel call counts and durations (from --kernel-trace --stats runs)
+  python -m paper_1701_01170_amd.rocprof_summary traffic <fetch_dir> <write_dir> <kernel-substring> \
+          <copy_bytes> <out.json> "<command>"
+      HBM bytes per launch of one kernel from a FETCH_SIZE run and a WRITE_SIZE
+      run, each scaled by what the same counter reads for the calibration copy
+      kernel (k_copy16, copy_bytes read and copy_bytes written per launch)
+
+rocprofv3 writes a rocpd SQLite database; only its `kernels` and
+`counters_collection` views are read here.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _db(d: str) -> sqlite3.Connection:
+    files = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no rocpd database under {d}")
+    return sqlite3.connect(files[0])
+
+
+def short_name(n: str) -> str:
+    n = n.replace("(anonymous namespace)::", "")
+    n = re.sub(r"\(.*\)$", "", n)
+    return n.replace("gr::", "").replace("void ", "")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1701_01170_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats(d: str, out: str, command: str) -> None:
+    c = _db(d)
+    agg = {}
+    for name, dur in c.execute("select name, duration from kernels"):
+        k = short_name(name)
+        a = agg.setdefault(k, [0, 0.0, float("inf"), 0.0])
+        a[0] += 1
+        a[1] += dur
+        a[2] = min(a[2], dur)
+        a[3] = max(a[3], dur)
+    total = sum(a[1] for a in agg.values())
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             f"Kernel source hash: `{kernel_source_hash()}`", "",
+             "| kernel | calls | total us | avg us | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, (n, tot, mn, mx) in sorted(agg.items(), key=lambda x: -x[1][1]):
+        lines.append(f"| `{k}` | {n} | {tot / 1e3:.1f} | {tot / 1e3 / n:.2f} | {mn / 1e3:.2f} | "
+                     f"{mx / 1e3:.2f} | {100 * tot / total:.1f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:20]))
+
+
+def _counter_per_dispatch(d: str, counter: str):
+    c = _db(d)
+    rows = c.execute("select dispatch_id, kernel_name, value from counters_collection "
+                     "where counter_name = ?", (counter,))
+    return [(did, short_name(kn), v) for did, kn, v in rows]
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, out: str,
+            command: str) -> None:
+    res = {}
+    for label, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _counter_per_dispatch(d, counter)
+        copy = [v for _, n, v in rows if "k_copy16" in n]
+        kern = [v for _, n, v in rows if kernel in n]
+        if not copy or not kern:
+            raise RuntimeError(f"{counter}: no copy-kernel or '{kernel}' dispatches in {d}")
+        # counter values are KiB per dispatch; the copy kernel moves copy_bytes each way
+        scale = (copy_bytes / 1024.0) / (sum(copy) / len(copy))
+        res[label] = dict(kib_per_launch=sum(kern) / len(kern), launches=len(kern),
+                          copy_kib_per_launch=sum(copy) / len(copy), scale=scale)
+    hbm = 1024.0 * (res["fetch"]["kib_per_launch"] * res["fetch"]["scale"]
+                    + res["write"]["kib_per_launch"] * res["write"]["scale"])
+    j = dict(kernel=kernel, command=command, kernel_source_hash=kernel_source_hash(),
+             fetch=res["fetch"], write=res["write"], hbm_bytes_per_launch=round(hbm))
+    with open(out, "w") as f:
+        json.dump(j, f, indent=1)
+    print(json.dumps(j, indent=1))
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7])
+    else:
+        raise SystemExit(__doc__)
