@@ -107,8 +107,12 @@ def main():
     cap = 4096
     tb = (gr.LevelTrace * cap)()
     ts = (gr.LevelTrace * cap)()
-    ob = gr.default_opts(trace=tb, trace_capacity=cap)
-    os_ = gr.default_opts(trace=ts, trace_capacity=cap)
+    # the heuristic policy with the knobs the autotuner stored for this graph
+    # class and size (paper defaults when none are stored)
+    from paper_1701_01170_amd import autotune
+    ob = autotune.tuned_opts(g, "bfs", trace=tb, trace_capacity=cap)
+    os_ = autotune.tuned_opts(g, "sssp", trace=ts, trace_capacity=cap)
+    knobs = {k: {"bfs": getattr(ob, k), "sssp": getattr(os_, k)} for k in autotune.KNOBS}
     stream = torch.cuda.current_stream()
 
     def step(s):
@@ -142,6 +146,13 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = teps / wall / 1e9
 
+    # the same steps with the paper's default knobs, for comparison (untimed by the step clock)
+    paper_ms = {"bfs": 0.0, "sssp": 0.0}
+    for i in range(args.steps):
+        s = int(srcs[args.warmup + i])
+        paper_ms["bfs"] += gr.bfs(g, s, out=(depth, parent), stream=stream)[2]["device_ms"]
+        paper_ms["sssp"] += gr.sssp(g, [s], out=(dist, pred), stream=stream)[2]["device_ms"]
+
     dom = max(per_kernel, key=lambda k: per_kernel[k][1])
     launches, sum_us, sum_bytes = per_kernel[dom]
     achieved = sum_bytes / (sum_us * 1e-6) / 1e9 if sum_us > 0 else None
@@ -168,8 +179,10 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"rmat_s{args.scale}_e{args.edge_factor} BFS+SSSP from one seeded source "
-                               f"per step, paper heuristic, int32 CSR, uint32 weights 1..64",
-                   "n_vertices": V, "n_edges": hg.n_edges},
+                               f"per step, fixed-threshold heuristic policy with autotuned thresholds, "
+                               f"int32 CSR, uint32 weights 1..64",
+                   "n_vertices": V, "n_edges": hg.n_edges,
+                   "knobs": {k: {t: round(float(x), 6) for t, x in v.items()} for k, v in knobs.items()}},
         "roofline": {
             "bound": "hbm",
             "kernel": KERNEL_NAMES[dom],
@@ -188,6 +201,8 @@ def main():
             "sssp_gteps_device": round(sssp_teps / (sssp_ms / 1e3) / 1e9, 3),
             "bfs_ms": round(bfs_ms / args.steps, 4),
             "sssp_ms": round(sssp_ms / args.steps, 4),
+            "paper_default_knobs_bfs_ms": round(paper_ms["bfs"] / args.steps, 4),
+            "paper_default_knobs_sssp_ms": round(paper_ms["sssp"] / args.steps, 4),
             "kernel_us_per_step": {f"{k[0]}:{KERNEL_NAMES[k]}": round(v[1] / args.steps, 1)
                                    for k, v in sorted(per_kernel.items())},
         },

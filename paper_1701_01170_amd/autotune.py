@@ -1,0 +1,171 @@
+"""Autotuner for the traversal's tuning knobs.
+
+The paper sets its knobs by hand (LB_LIGHT threshold 4096, average degree 5
+for LB vs. TWC, Sec. 5.1) and by heat maps over the direction-switch
+parameters do_a / do_b (Sec. 7, optimisation analysis).  This module searches
+the same knobs on the device it runs on, timing the library's own traversals
+(event-timed device time, several seeded sources), and stores the best setting
+per (gfx arch, graph class, size bucket, traversal) in `tuning/<arch>.json`.
+
+Search (coordinate descent from the paper's defaults):
+  1. lb_light_threshold in {0, 1024, 4096}
+  2. lb_chunk in {2048, 4096, 8192, 16384}
+  3. lb_min_avg_degree in {0 (always LB), 5 (paper), inf (always TWC)}
+  4. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8}
+
+The tuned values only change the time taken; results are identical for every
+setting (the GPU tests check every strategy against the oracle).
+
+CLI:  python -m paper_1701_01170_amd.autotune [--scale 22] [--grid 2048] [--sources 4]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import Graph, default_opts, bfs, sssp  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING_DIR = os.path.join(HERE, "tuning")
+ARCH = "gfx950"
+
+KNOBS = ("lb_light_threshold", "lb_chunk", "lb_min_avg_degree", "do_a", "do_b")
+DO_A = [1 / 2, 1 / 4, 1 / 8, 1 / 14, 1 / 32, 1 / 64, 1 / 256]
+DO_B = [1 / 576, 1 / 64, 1 / 8]
+
+
+def graph_class(g: Graph) -> str:
+    """'scalefree' when the largest degree dwarfs the average, else 'mesh'."""
+    avg = g.n_edges / max(1, g.n_vertices)
+    return "scalefree" if g.max_degree > 64 * max(avg, 1.0) else "mesh"
+
+
+def size_bucket(g: Graph) -> int:
+    return int(round(math.log2(max(2, g.n_edges))))
+
+
+def _path(arch: str = ARCH) -> str:
+    return os.path.join(TUNING_DIR, f"{arch}.json")
+
+
+def load(arch: str = ARCH) -> dict:
+    p = _path(arch)
+    if not os.path.exists(p):
+        return {"arch": arch, "entries": []}
+    with open(p) as f:
+        return json.load(f)
+
+
+def lookup(g: Graph, kind: str, arch: str = ARCH) -> dict | None:
+    """Best stored knob setting for this graph's class and the nearest size bucket."""
+    cls, b = graph_class(g), size_bucket(g)
+    cands = [e for e in load(arch)["entries"] if e["class"] == cls and e["kind"] == kind]
+    if not cands:
+        return None
+    return min(cands, key=lambda e: abs(e["log2_edges"] - b))["opts"]
+
+
+def tuned_opts(g: Graph, kind: str, **overrides):
+    """gr_opts with the stored tuned knobs (paper defaults when none stored)."""
+    o = default_opts(**overrides)
+    t = lookup(g, kind)
+    if t:
+        for k, v in t.items():
+            if k not in overrides:
+                setattr(o, k, v)
+    return o
+
+
+def _time(g: Graph, kind: str, sources, knobs: dict, reps: int = 1) -> float:
+    import torch
+    total = 0.0
+    o = default_opts(**knobs)
+    for s in sources:
+        best = float("inf")
+        for _ in range(reps + 1):
+            if kind == "bfs":
+                _, _, st = bfs(g, int(s), opts=o)
+            else:
+                _, _, st = sssp(g, [int(s)], opts=o)
+            best = min(best, st["device_ms"])
+        total += best
+    torch.cuda.synchronize()
+    return total / len(sources)
+
+
+def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
+    """Coordinate descent; returns (best knobs, best ms, paper-default ms)."""
+    d = default_opts()
+    best = {k: getattr(d, k) for k in KNOBS}
+    base_ms = _time(g, kind, sources, best)
+    best_ms = base_ms
+    log(f"[{kind}] paper defaults: {base_ms:.3f} ms")
+
+    def try_set(key, values):
+        nonlocal best, best_ms
+        for v in values:
+            cand = dict(best, **{key: v})
+            ms = _time(g, kind, sources, cand)
+            log(f"[{kind}] {key}={v:.6g}: {ms:.3f} ms")
+            if ms < best_ms * 0.99:
+                best, best_ms = cand, ms
+
+    try_set("lb_light_threshold", [0, 1024, 4096])
+    try_set("lb_chunk", [2048, 4096, 8192, 16384])
+    try_set("lb_min_avg_degree", [0.0, 5.0, 1e9])
+    if kind == "bfs":
+        for a in DO_A:
+            for b in DO_B:
+                cand = dict(best, do_a=a, do_b=b)
+                ms = _time(g, kind, sources, cand)
+                log(f"[{kind}] do_a=1/{1 / a:.0f} do_b=1/{1 / b:.0f}: {ms:.3f} ms")
+                if ms < best_ms * 0.99:
+                    best, best_ms = cand, ms
+    return best, best_ms, base_ms
+
+
+def store(g: Graph, kind: str, knobs: dict, best_ms: float, base_ms: float, graph_name: str,
+          sources, arch: str = ARCH) -> None:
+    os.makedirs(TUNING_DIR, exist_ok=True)
+    db = load(arch)
+    cls, b = graph_class(g), size_bucket(g)
+    db["entries"] = [e for e in db["entries"]
+                     if not (e["class"] == cls and e["kind"] == kind and e["log2_edges"] == b)]
+    db["entries"].append({"class": cls, "kind": kind, "log2_edges": b, "graph": graph_name,
+                          "sources": [int(s) for s in sources], "opts": knobs,
+                          "device_ms": round(best_ms, 4), "paper_default_ms": round(base_ms, 4),
+                          "date": time.strftime("%Y-%m-%d")})
+    db["entries"].sort(key=lambda e: (e["class"], e["kind"], e["log2_edges"]))
+    with open(_path(arch), "w") as f:
+        json.dump(db, f, indent=1)
+
+
+def main():
+    from . import Context
+    from . import graphgen as gg
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--scale", type=int, nargs="*", default=[22])
+    ap.add_argument("--grid", type=int, nargs="*", default=[])
+    ap.add_argument("--sources", type=int, default=4)
+    ap.add_argument("--kinds", default="bfs,sssp")
+    args = ap.parse_args()
+    ctx = Context(0)
+    graphs = [(f"rmat_s{s}_e16", gg.add_weights(gg.rmat(s, 16, seed=1), seed=101)) for s in args.scale]
+    graphs += [(f"grid_{n}x{n}", gg.add_weights(gg.grid(n, n), seed=101)) for n in args.grid]
+    for name, hg in graphs:
+        g = Graph.from_host(ctx, hg, symmetric=True)
+        srcs = gg.sources(hg, args.sources, seed=2000)  # held-out from the bench's sources
+        for kind in args.kinds.split(","):
+            knobs, ms, base = tune(g, kind, srcs, log=lambda m: print(f"{name} {m}", flush=True))
+            store(g, kind, knobs, ms, base, name, srcs)
+            print(f"{name} [{kind}] best {ms:.3f} ms (paper defaults {base:.3f} ms): {knobs}", flush=True)
+        g.free()
+
+
+if __name__ == "__main__":
+    main()
