@@ -40,6 +40,7 @@ KERNEL_NAMES = {
     ("bfs", 4): "k_bfs_pull_twc", ("bfs", 5): "k_bfs_pull_groups",
     ("sssp", 0): "k_push_twc<SsspVisit>", ("sssp", 1): "k_push_light<SsspVisit>",
     ("sssp", 2): "k_push_lb<SsspVisit>",
+    ("bfs", 6): "k_dstep<BfsVisit>", ("sssp", 6): "k_dstep<SsspVisit>",
 }
 
 
@@ -53,7 +54,7 @@ def algorithmic_bytes(kind: str, kernel: int, n_f: int, m_f: int, n_next: int) -
       parent + 4 B queue entry."""
     if kind == "sssp":
         return 16.0 * m_f + 12.0 * n_f + 4.0 * n_next
-    if kind == "bfs" and kernel in (0, 1, 2, 3):
+    if kind == "bfs" and kernel in (0, 1, 2, 3, 6):
         return 4.0 * m_f + 12.0 * n_f + 12.0 * n_next
     return None
 

@@ -92,7 +92,8 @@ typedef struct gr_level_trace {
   float step_us;       /* device time of the whole iteration (advance, filter, bookkeeping) */
   float kernel_us;     /* device time of the advance kernel alone (event-timed) */
   int32_t kernel;      /* advance kernel: 0 TWC, 1 LB_LIGHT, 2 LB, 3 LB with byte-mark filter,
-                          4 pull TWC, 5 pull groups */
+                          4 pull TWC, 5 pull groups, 6 device-predicated step (step_us and
+                          kernel_us are then the block's time divided by its levels) */
   int64_t n_next;      /* size of the output frontier */
 } gr_level_trace;
 
@@ -110,7 +111,12 @@ typedef struct gr_opts {
   int32_t trace_capacity;    /* records available in trace */
   gr_level_trace* trace;     /* host array, nullable: per-iteration records */
   int32_t trace_count;       /* out: records written (may exceed capacity; extra are dropped) */
-  int32_t reserved[7];
+  int32_t device_max_edges;  /* iteration control: while the policy pushes and the frontier has at
+                                most 4096 vertices and at most this many edges, levels run in blocks
+                                of device-predicated steps with one host round trip per block
+                                (heuristic and fixed push policies only).  0: default 262144;
+                                < 0: off (one host round trip per level); at most 1 << 24 */
+  int32_t reserved[6];
 } gr_opts;
 
 typedef struct gr_run_stats {
@@ -213,6 +219,41 @@ gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, in
 gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);
+
+/* ---- selector network (learned per-iteration strategy) -------------------
+ *
+ * A small MLP predicts, from eight per-iteration features, the log2 step time
+ * of each of the four gr_action strategies; GR_POLICY_LEARNED runs the fused
+ * inference kernel on the device every iteration and takes the fastest allowed
+ * action.  The choice can only change the time taken: every action computes
+ * the exact same results.  (The paper picks strategies by fixed thresholds on
+ * the degree distribution, Sec. 5.1, and notes in Sec. 7 that the same
+ * parameters do not suit every graph; the network replaces the thresholds.)
+ *
+ * Architecture: 8 -> 32 -> 32 -> 4, ReLU on both hidden layers, fp32.
+ * Parameter layout (GR_MLP_N_PARAMS = 1476 floats, row-major):
+ *   W1[32][8], b1[32], W2[32][32], b2[32], W3[4][32], b3[4].
+ * Features (each log2(1 + x) / 32): n_f, m_f, n_u, m_u, largest frontier
+ * degree, V, E, and V if a pull step would first have to build the unvisited
+ * frontier (the previous step pushed) else 0 -- the same values as
+ * gr_level_trace.features.
+ *
+ * The training entry points take DEVICE pointers; all work is enqueued on
+ * `stream` (asynchronous: they do not synchronise). */
+
+/* Y[n][4] = network(X[n][8]). */
+gr_status gr_mlp_forward(gr_ctx* ctx, const float* params, const float* X, int32_t n, float* Y,
+                         void* stream);
+/* Masked mean squared error L = sum(M * (Y - T)^2) / max(1, sum M) over the
+ * batch X[n][8], targets T[n][4], mask M[n][4] (1 = target observed), and its
+ * gradient grad[1476] (deterministic summation order).  loss (device float[1])
+ * may be NULL. */
+gr_status gr_mlp_loss_grad(gr_ctx* ctx, const float* params, const float* X, const float* T,
+                           const float* M, int32_t n, float* grad, float* loss, void* stream);
+/* One Adam step (Kingma & Ba) on params[1476] with moment buffers m, v and
+ * 1-based step count `step`. */
+gr_status gr_mlp_adam(gr_ctx* ctx, float* params, const float* grad, float* m, float* v,
+                      int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
 
 /* ---- measurement --------------------------------------------------------- */
 

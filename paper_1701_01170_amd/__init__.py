@@ -57,7 +57,7 @@ class Opts(ctypes.Structure):
                 ("lb_min_avg_degree", ctypes.c_float), ("max_iterations", ctypes.c_int32),
                 ("lb_chunk", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
                 ("trace", ctypes.POINTER(LevelTrace)), ("trace_count", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("device_max_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class RunStats(ctypes.Structure):
@@ -104,6 +104,10 @@ _SIGNATURES = {
                                     ctypes.POINTER(RunStats)]),
     "gr_copy_bandwidth": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P,
                                          ctypes.POINTER(ctypes.c_float)]),
+    "gr_mlp_forward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P]),
+    "gr_mlp_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    "gr_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
 }
 
 
@@ -324,6 +328,35 @@ def bfs_multi(g: Graph, sources, want_parent: bool = True, opts: Opts | None = N
     check(lib().gr_bfs_multi(g.ctx.handle, g.handle, src.ctypes.data, k, _ptr(depth), _ptr(parent),
                              _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
     return depth, parent, st.as_dict()
+
+
+def mlp_forward(ctx: Context, params, X, stream=None):
+    """Y[n][4] for device float32 tensors params[1476], X[n][8]."""
+    import torch
+    n = X.shape[0]
+    Y = torch.empty((n, 4), dtype=torch.float32, device=X.device)
+    check(lib().gr_mlp_forward(ctx.handle, _ptr(params), _ptr(X), n, _ptr(Y), _stream_handle(stream)))
+    return Y
+
+
+def mlp_loss_grad(ctx: Context, params, X, T, M, grad=None, loss=None, stream=None):
+    """(grad[1476], loss[1]) device tensors for the masked MSE over X, T, M."""
+    import torch
+    if grad is None:
+        grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    check(lib().gr_mlp_loss_grad(ctx.handle, _ptr(params), _ptr(X), _ptr(T), _ptr(M), X.shape[0],
+                                 _ptr(grad), _ptr(loss), _stream_handle(stream)))
+    return grad, loss
+
+
+def mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    """In-place Adam step on device tensors params, m, v (1-based step)."""
+    check(lib().gr_mlp_adam(ctx.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                            float(lr), float(beta1), float(beta2), float(eps),
+                            _stream_handle(stream)))
 
 
 def copy_bandwidth(ctx: Context, nbytes: int = 1 << 30, reps: int = 20, stream=None) -> float:

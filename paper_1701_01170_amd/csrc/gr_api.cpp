@@ -362,20 +362,18 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->lb_chunk must be 0 (default), 2048, 4096, 8192 or 16384");
   if (opts->trace_capacity < 0 || (opts->trace_capacity > 0 && !opts->trace))
     return fail(GR_EINVAL, "opts->trace is NULL with a positive capacity");
+  if (opts->device_max_edges > (1 << 24))
+    return fail(GR_EINVAL, "opts->device_max_edges must be at most 1 << 24");
   *local = *opts;
   return GR_OK;
 }
 
-// Event-timed record of one iteration: ev_a..ev_b brackets the whole step,
-// ev_k0..ev_k1 the advance kernel alone.
-gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int action,
-                       int kernel, int64_t n_next) {
+// Trace record of one iteration with the given step and kernel times.
+gr_status record_trace_times(gr_opts* opts, const LevelFeatures& lf, int action, int kernel,
+                             int64_t n_next, float step_ms, float kernel_ms) {
   if (!opts || !opts->trace) return GR_OK;
   int i = opts->trace_count++;
   if (i >= opts->trace_capacity) return GR_OK;
-  float step_ms = 0.f, kernel_ms = 0.f;
-  GR_HIP(hipEventElapsedTime(&step_ms, ctx->ev_a, ctx->ev_b));
-  GR_HIP(hipEventElapsedTime(&kernel_ms, ctx->ev_k0, ctx->ev_k1));
   gr_level_trace& t = opts->trace[i];
   t.level = lf.level;
   t.action = action;
@@ -389,6 +387,48 @@ gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int 
   t.kernel_us = kernel_ms * 1000.0f;
   t.kernel = kernel;
   t.n_next = n_next;
+  return GR_OK;
+}
+
+// Event-timed record of one iteration: ev_a..ev_b brackets the whole step,
+// ev_k0..ev_k1 the advance kernel alone.
+gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int action,
+                       int kernel, int64_t n_next) {
+  if (!opts || !opts->trace || opts->trace_count >= opts->trace_capacity) {
+    if (opts && opts->trace) opts->trace_count++;
+    return GR_OK;
+  }
+  float step_ms = 0.f, kernel_ms = 0.f;
+  GR_HIP(hipEventElapsedTime(&step_ms, ctx->ev_a, ctx->ev_b));
+  GR_HIP(hipEventElapsedTime(&kernel_ms, ctx->ev_k0, ctx->ev_k1));
+  return record_trace_times(opts, lf, action, kernel, n_next, step_ms, kernel_ms);
+}
+
+// ---- iteration control: device-predicated blocks of push levels ----------
+constexpr int kDlFirstLen = 4;              // levels in the first block; doubles while blocks run whole
+constexpr int64_t kDlDefaultMaxEdges = 1 << 18;
+constexpr int kTraceKernelDstep = 6;
+
+struct DlPlan {
+  bool on = false;
+  int64_t max_m = 0;
+  double do_a = -1.0;   // device push -> pull test (< 0: none)
+  int len = kDlFirstLen;
+  int blocks = 256;
+  int64_t* log = nullptr;
+};
+
+gr_status dl_plan(gr_ctx* ctx, const gr_opts& o, bool pull_ok, bool learned, bool tracing,
+                  DlPlan* d) {
+  const bool heuristic = o.policy == GR_POLICY_HEURISTIC ||
+                         (o.policy == GR_POLICY_LEARNED && !learned);
+  d->on = o.device_max_edges >= 0 && (heuristic || o.policy == GR_POLICY_FIXED);
+  d->max_m = o.device_max_edges > 0 ? o.device_max_edges : kDlDefaultMaxEdges;
+  d->do_a = heuristic && pull_ok ? (double)o.do_a : -1.0;
+  d->len = kDlFirstLen;
+  d->blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
+  d->log = nullptr;
+  if (d->on && tracing) GR_TRY(pool_typed(ctx, S_DLOG, 3 * kDlMaxLevels, &d->log));
   return GR_OK;
 }
 
@@ -441,12 +481,13 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
 
   uint32_t* bm;
-  int32_t *qA, *qB, *uA = nullptr, *uB = nullptr, *offsets, *rstart, *chunks;
+  int32_t *qA, *qB, *qC, *uA = nullptr, *uB = nullptr, *offsets, *rstart, *chunks;
   int64_t* bsums;
   Ctrl* ctrl;
   GR_TRY(pool_typed(ctx, S_BM, 2 * NW, &bm));
   GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
   GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
   if (pull_ok) {
     GR_TRY(pool_typed(ctx, S_U_A, V, &uA));
     GR_TRY(pool_typed(ctx, S_U_B, V, &uB));
@@ -458,14 +499,18 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   Ctrl* hc = ctx->host_ctrl;
 
-  int32_t* q[2] = {qA, qB};
+  int32_t* q[3] = {qA, qB, qC};
   int32_t* ul[2] = {uA, uB};
 
   GR_HIP(hipEventRecord(ctx->ev_start, st));
   GR_HIP(launch_bfs_init(depth, parent, V, bm, NW, source, qA, ctrl, st));
   int cur = 0, ucur = 0, sp = 0, p = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                               &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
+                               &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+  const bool learned = opts.policy == GR_POLICY_LEARNED && ctx->policy_loaded;
+  const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr);
+  const int allowed = pull_ok ? 0xF : 0x3;
+  if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V, E, 0, allowed, st));
   GR_TRY(read_ctrl(ctx, ctrl, st));
 
   Selector sel;
@@ -481,6 +526,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   int level = 0;
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
+  DlPlan dl;
+  GR_TRY(dl_plan(ctx, opts, pull_ok, learned, tracing, &dl));
 
   while (n_f > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
     lf.level = level;
@@ -490,7 +537,72 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     lf.n_u = V - visited_n;
     lf.m_u = E - visited_m;
     lf.prev_pull = sel.mode_pull ? 1 : 0;
-    const int action = sel.decide(lf);
+    const int action = sel.decide(lf, learned ? hc->action : -1);
+    if (dl.on && (action == GR_PUSH_LB || action == GR_PUSH_TWC) && n_f <= kDlMaxN &&
+        m_f <= dl.max_m) {
+      // A block of device-predicated push levels (atomic parents, no merge
+      // pass); its first level is the one just decided on the host.
+      int kmax = dl.len;
+      if (opts.max_iterations > 0) kmax = (int)std::min<int64_t>(kmax, opts.max_iterations - level);
+      const int64_t vm0 = visited_m - m_f, vn0 = visited_n - n_f;
+      GR_HIP(launch_dl_begin(ctrl, cur, sp, vm0, vn0, st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+      for (int i = 0; i < kmax; ++i) {
+        const int qc = (cur + i) % 3;
+        const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, dl.do_a,
+                        dl.log, ctrl};
+        GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, level + i + 1, dl.blocks, st));
+      }
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+      GR_TRY(read_ctrl(ctx, ctrl, st));
+      const int k = hc->dl_levels;
+      if (k > 0) {
+        std::vector<int64_t> lg;
+        float block_ms = 0.f;
+        if (tracing) {
+          lg.resize(3 * (size_t)k);
+          GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
+          GR_HIP(hipEventElapsedTime(&block_ms, ctx->ev_a, ctx->ev_b));
+        }
+        dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
+        rs.action_count[action] += k;
+        inspected_push += hc->dl_vm[k & 1] - vm0;
+        visited_n = hc->dl_vn[k & 1];
+        visited_m = hc->dl_vm[k & 1];
+        p ^= k & 1;
+        cur = (cur + k) % 3;
+        sp ^= 1;
+        level += k;
+        have_unv = false;
+        GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                     &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+        GR_TRY(read_ctrl(ctx, ctrl, st));
+        if (tracing) {
+          int64_t vn = vn0, vm = vm0;
+          for (int i = 0; i < k; ++i) {
+            LevelFeatures li = lf;
+            li.level = level - k + i;
+            li.n_f = lg[3 * i];
+            li.m_f = lg[3 * i + 1];
+            li.max_deg_f = lg[3 * i + 2];
+            vn += li.n_f;
+            vm += li.m_f;
+            li.n_u = V - vn;
+            li.m_u = E - vm;
+            if (i > 0) li.prev_pull = 0;
+            const int64_t nn = i + 1 < k ? lg[3 * (i + 1)] : (int64_t)hc->n_f[sp];
+            GR_TRY(record_trace_times(opts_in, li, action, kTraceKernelDstep, nn, block_ms / k,
+                                      block_ms / k));
+          }
+        }
+        n_f = hc->n_f[sp];
+        m_f = hc->m_f[sp];
+        max_deg = hc->max_deg[sp];
+        visited_n += n_f;
+        visited_m += m_f;
+        continue;
+      }
+    }
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
     const int next_depth = level + 1;
     int kernel = 0;
@@ -508,18 +620,18 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         GR_HIP(launch_bfs_push_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
                                      bm, p, marks, chunk, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
-        GR_HIP(launch_bfs_mark_compact(marks, V, bm, p, depth, next_depth, q[cur ^ 1],
-                                       &ctrl->q_count[cur ^ 1], st));
+        GR_HIP(launch_bfs_mark_compact(marks, V, bm, p, depth, next_depth, q[(cur + 1) % 3],
+                                       &ctrl->q_count[(cur + 1) % 3], st));
       } else {
         kernel = mode;
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push(mode, atomic_parent, q[cur], offsets, rstart, chunks, n_f, m_f,
-                               g->R, g->C, bm, p, depth, parent, next_depth, q[cur ^ 1],
-                               &ctrl->q_count[cur ^ 1], chunk, st));
+                               g->R, g->C, bm, p, depth, parent, next_depth, q[(cur + 1) % 3],
+                               &ctrl->q_count[(cur + 1) % 3], chunk, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
       if (parent && !atomic_parent)
-        GR_HIP(launch_bfs_parent_fixup(q[cur ^ 1], &ctrl->q_count[cur ^ 1],
+        GR_HIP(launch_bfs_parent_fixup(q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
                                        std::min<int64_t>(V - visited_n, m_f), g->R, g->C, bm, p,
                                        parent, st));
       inspected_push += m_f;
@@ -535,7 +647,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       kernel = action == GR_PULL_LB ? 5 : 4;
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
       GR_HIP(launch_bfs_pull(action == GR_PULL_LB, ul[ucur], n_ulist, g->R, g->C, bm, p, depth,
-                             parent, next_depth, q[cur ^ 1], &ctrl->q_count[cur ^ 1],
+                             parent, next_depth, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
                              ul[ucur ^ 1], &ctrl->u_count[ucur ^ 1], &ctrl->inspected, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       ucur ^= 1;
@@ -544,11 +656,14 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
     rs.action_count[action]++;
     p ^= 1;
-    cur ^= 1;
+    cur = (cur + 1) % 3;
     sp ^= 1;
     ++level;
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                 &ctrl->q_count[cur ^ 1], &ctrl->u_count[ucur ^ 1], st));
+                                 &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+    if (learned)
+      GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V - visited_n, E - visited_m,
+                               sel.mode_pull ? 1 : 0, allowed, st));
     GR_TRY(read_ctrl(ctx, ctrl, st));
     if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
     n_f = hc->n_f[sp];
@@ -604,12 +719,13 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
   const int32_t n_src = (int32_t)uniq.size();
 
-  int32_t *qA, *qB, *offsets, *rstart, *chunks, *tags, *src_dev;
+  int32_t *qA, *qB, *qC, *offsets, *rstart, *chunks, *tags, *src_dev;
   unsigned long long* keys;
   int64_t* bsums;
   Ctrl* ctrl;
   GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
   GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
   GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
@@ -619,7 +735,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
   GR_TRY(pool_typed(ctx, S_TMP0, n_src, &src_dev));
   Ctrl* hc = ctx->host_ctrl;
-  int32_t* q[2] = {qA, qB};
+  int32_t* q[3] = {qA, qB, qC};
 
   GR_HIP(hipMemcpyAsync(src_dev, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
   GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
@@ -629,7 +745,10 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_HIP(launch_sssp_seed(src_dev, n_src, keys, tags, ctrl, st));
   int cur = 0, sp = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                               &ctrl->q_count[cur ^ 1], nullptr, st));
+                               &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+  const bool learned = opts.policy == GR_POLICY_LEARNED && ctx->policy_loaded;
+  const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr);
+  if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
   GR_TRY(read_ctrl(ctx, ctrl, st));
 
   Selector sel;
@@ -642,6 +761,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   int64_t inspected = 0;
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
+  DlPlan dl;
+  GR_TRY(dl_plan(ctx, opts, /*pull_ok=*/false, learned, tracing, &dl));
   while (n_f > 0 && (opts.max_iterations <= 0 || it < opts.max_iterations)) {
     lf.level = it;
     lf.n_f = n_f;
@@ -650,7 +771,57 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     lf.n_u = 0;
     lf.m_u = 0;
     lf.prev_pull = 0;
-    const int action = sel.decide(lf);
+    const int action = sel.decide(lf, learned ? hc->action : -1);
+    if (dl.on && n_f <= kDlMaxN && m_f <= dl.max_m) {
+      // A block of device-predicated relaxation rounds (Alg. 1 iterations).
+      int kmax = dl.len;
+      if (opts.max_iterations > 0) kmax = std::min(kmax, opts.max_iterations - it);
+      GR_HIP(launch_dl_begin(ctrl, cur, sp, 0, 0, st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+      for (int i = 0; i < kmax; ++i) {
+        const int qc = (cur + i) % 3;
+        const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
+                        dl.log, ctrl};
+        GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, it + i + 1, dl.blocks, st));
+      }
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+      GR_TRY(read_ctrl(ctx, ctrl, st));
+      const int k = hc->dl_levels;
+      if (k > 0) {
+        std::vector<int64_t> lg;
+        float block_ms = 0.f;
+        if (tracing) {
+          lg.resize(3 * (size_t)k);
+          GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
+          GR_HIP(hipEventElapsedTime(&block_ms, ctx->ev_a, ctx->ev_b));
+        }
+        dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
+        rs.action_count[action] += k;
+        inspected += hc->dl_vm[k & 1];
+        cur = (cur + k) % 3;
+        sp ^= 1;
+        it += k;
+        GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                     &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+        GR_TRY(read_ctrl(ctx, ctrl, st));
+        if (tracing) {
+          for (int i = 0; i < k; ++i) {
+            LevelFeatures li = lf;
+            li.level = it - k + i;
+            li.n_f = lg[3 * i];
+            li.m_f = lg[3 * i + 1];
+            li.max_deg_f = lg[3 * i + 2];
+            const int64_t nn = i + 1 < k ? lg[3 * (i + 1)] : (int64_t)hc->n_f[sp];
+            GR_TRY(record_trace_times(opts_in, li, action, kTraceKernelDstep, nn, block_ms / k,
+                                      block_ms / k));
+          }
+        }
+        n_f = hc->n_f[sp];
+        m_f = hc->m_f[sp];
+        max_deg = hc->max_deg[sp];
+        continue;
+      }
+    }
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
     const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
     if (mode == 2)
@@ -658,16 +829,17 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
                                      chunks, chunk, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
     GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W, keys,
-                             tags, it + 1, q[cur ^ 1], &ctrl->q_count[cur ^ 1], chunk, st));
+                             tags, it + 1, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], chunk, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
     inspected += m_f;
     rs.action_count[action]++;
-    cur ^= 1;
+    cur = (cur + 1) % 3;
     sp ^= 1;
     ++it;
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                 &ctrl->q_count[cur ^ 1], nullptr, st));
+                                 &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+    if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
     GR_TRY(read_ctrl(ctx, ctrl, st));
     if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, mode, hc->n_f[sp]));
     n_f = hc->n_f[sp];
@@ -694,18 +866,193 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
 // multi-source BFS
 // ============================================================================
 
+namespace {
+// The multi-source expansion pulls (every vertex with unreached source bits
+// ORs its neighbours' frontier masks) once the active vertices carry at least
+// E / kMsPullDivisor edges, and pushes from the active vertices before that.
+constexpr int64_t kMsPullDivisor = 16;
+}  // namespace
+
 extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t* sources,
-                                  int32_t k, int32_t* depth, int32_t* parent, gr_opts* opts,
+                                  int32_t k, int32_t* depth, int32_t* parent, gr_opts* opts_in,
                                   void* stream, gr_run_stats* stats) {
-  (void)ctx; (void)g; (void)sources; (void)k; (void)depth; (void)parent; (void)opts;
-  (void)stream; (void)stats;
-  return fail(GR_EUNSUPPORTED, "gr_bfs_multi is not built yet");
+  if (!ctx || !g) return fail(GR_EINVAL, "gr_bfs_multi: ctx or graph is NULL");
+  if (g->ctx != ctx) return fail(GR_EINVAL, "gr_bfs_multi: graph belongs to another context");
+  if (!depth) return fail(GR_EINVAL, "gr_bfs_multi: depth is NULL");
+  if (!sources || k < 1) return fail(GR_EINVAL, "gr_bfs_multi: need at least one source");
+  for (int32_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || (int64_t)sources[i] >= g->V)
+      return fail(GR_EINVAL, "gr_bfs_multi: source " + std::to_string(sources[i]) + " out of range");
+  if (!(g->flags & GR_SYMMETRIC))
+    return fail(GR_EUNSUPPORTED, "gr_bfs_multi needs a symmetric graph (parents are pulled over in-edges)");
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t V = g->V, E = g->E;
+  const int G = stats_grid();
+  const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+  const bool use_lb = (double)E / (double)V >= (double)opts.lb_min_avg_degree;
+  using u64 = unsigned long long;
+
+  u64 *visit, *front[2], *next;
+  int32_t *qA, *qB, *qC, *offsets, *rstart, *chunks, *src_dev;
+  int64_t* bsums;
+  Ctrl* ctrl;
+  GR_TRY(pool_typed(ctx, S_MASK_A, V, &visit));
+  GR_TRY(pool_typed(ctx, S_MASK_B, V, &front[0]));
+  GR_TRY(pool_typed(ctx, S_MASK_C, V, &front[1]));
+  GR_TRY(pool_typed(ctx, S_KEYS, V, &next));
+  GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
+  GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
+  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
+  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
+  GR_TRY(pool_typed(ctx, S_TMP0, 64, &src_dev));
+  Ctrl* hc = ctx->host_ctrl;
+  int32_t* q[3] = {qA, qB, qC};
+
+  GR_HIP(hipEventRecord(ctx->ev_start, st));
+  GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(depth), (int64_t)k * V, 0xffffffffu, st));
+  if (parent)
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(parent), (int64_t)k * V, 0xffffffffu, st));
+  GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->reached_edges), 2, 0u, st));
+  gr_run_stats rs{};
+  int64_t inspected = 0;
+  int max_levels = 0;
+  for (int32_t p0 = 0; p0 < k; p0 += 64) {
+    const int32_t kk = std::min<int32_t>(64, k - p0);
+    const u64 full = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
+    int32_t* dpass = depth + (int64_t)p0 * V;
+    int32_t* ppass = parent ? parent + (int64_t)p0 * V : nullptr;
+    std::vector<int32_t> srcs(sources + p0, sources + p0 + kk);
+    std::vector<int32_t> uniq(srcs);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    for (u64* m : {visit, front[0], front[1], next})
+      GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(m), 2 * V, 0u, st));
+    GR_HIP(hipMemcpyAsync(src_dev, srcs.data(), sizeof(int32_t) * kk, hipMemcpyHostToDevice, st));
+    GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * uniq.size(), hipMemcpyHostToDevice, st));
+    GR_HIP(launch_fill_u32(&ctrl->q_count[0], 1, (uint32_t)uniq.size(), st));
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
+    GR_HIP(launch_ms_seed(src_dev, kk, visit, front[0], dpass, V, st));
+    int cur = 0, fc = 0, sp = 0, level = 0;
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                 &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+    GR_TRY(read_ctrl(ctx, ctrl, st));  // also keeps the host source vectors alive for the copies
+    int64_t n_a = hc->n_f[sp], m_a = hc->m_f[sp];
+    while (n_a > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
+      const bool pull = m_a * kMsPullDivisor >= E;
+      if (pull) {
+        GR_HIP(launch_ms_pull(V, g->R, g->C, front[fc], visit, full, next, q[(cur + 1) % 3],
+                              &ctrl->q_count[(cur + 1) % 3], st));
+        rs.action_count[GR_PULL_TWC]++;
+      } else {
+        const int mode = !use_lb ? 0 : (n_a < opts.lb_light_threshold ? 1 : 2);
+        if (mode == 2)
+          GR_HIP(launch_frontier_offsets(q[cur], n_a, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
+                                         chunks, chunk, st));
+        GR_HIP(launch_ms_push(mode, q[cur], offsets, rstart, chunks, n_a, m_a, g->R, g->C,
+                              front[fc], visit, next, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], chunk,
+                              st));
+        rs.action_count[use_lb ? GR_PUSH_LB : GR_PUSH_TWC]++;
+      }
+      inspected += pull ? E : m_a;
+      GR_HIP(launch_ms_finalize(q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], pull ? V : std::min(V, m_a),
+                                g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass, ppass, V,
+                                level + 1, st));
+      GR_HIP(launch_ms_clear(q[cur], &ctrl->q_count[cur], n_a, front[fc], st));
+      fc ^= 1;
+      cur = (cur + 1) % 3;
+      sp ^= 1;
+      ++level;
+      GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                   &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+      GR_TRY(read_ctrl(ctx, ctrl, st));
+      n_a = hc->n_f[sp];
+      m_a = hc->m_f[sp];
+    }
+    max_levels = std::max(max_levels, level);
+    GR_HIP(launch_ms_teps(visit, g->R, V, &ctrl->reached_edges, st));
+  }
+  GR_HIP(hipEventRecord(ctx->ev_stop, st));
+  GR_TRY(read_ctrl(ctx, ctrl, st));
+  if (stats) {
+    float ms = 0.f;
+    GR_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    rs.iterations = max_levels;
+    rs.teps_edges = hc->reached_edges;
+    rs.inspected_edges = inspected;
+    rs.device_ms = ms;
+    *stats = rs;
+  }
+  return GR_OK;
 }
 
 extern "C" gr_status gr_ctx_set_policy(gr_ctx* ctx, const float* params, int32_t n_params) {
-  (void)params; (void)n_params;
-  if (!ctx) return fail(GR_EINVAL, "ctx is NULL");
-  return fail(GR_EUNSUPPORTED, "learned policy is not built yet");
+  if (!ctx) return fail(GR_EINVAL, "gr_ctx_set_policy: ctx is NULL");
+  if (!params) {
+    ctx->policy_loaded = false;
+    return GR_OK;
+  }
+  if (n_params != GR_MLP_N_PARAMS)
+    return fail(GR_EINVAL, "gr_ctx_set_policy: expected " + std::to_string(GR_MLP_N_PARAMS) +
+                               " parameters, got " + std::to_string(n_params));
+  for (int32_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(params[i])) return fail(GR_EINVAL, "gr_ctx_set_policy: non-finite parameter");
+  DeviceGuard dg(ctx->device);
+  float* d = nullptr;
+  GR_TRY(pool_typed(ctx, S_MLP, GR_MLP_N_PARAMS, &d));
+  GR_HIP(hipMemcpy(d, params, sizeof(float) * GR_MLP_N_PARAMS, hipMemcpyHostToDevice));
+  ctx->policy_loaded = true;
+  return GR_OK;
+}
+
+// ============================================================================
+// selector network training / inference (device buffers)
+// ============================================================================
+
+extern "C" gr_status gr_mlp_forward(gr_ctx* ctx, const float* params, const float* X, int32_t n,
+                                    float* Y, void* stream) {
+  if (!ctx || !params || (n > 0 && (!X || !Y))) return fail(GR_EINVAL, "gr_mlp_forward: NULL argument");
+  if (n < 0) return fail(GR_EINVAL, "gr_mlp_forward: n < 0");
+  DeviceGuard dg(ctx->device);
+  GR_HIP(launch_mlp_forward(params, X, n, Y, static_cast<hipStream_t>(stream)));
+  return GR_OK;
+}
+
+extern "C" gr_status gr_mlp_loss_grad(gr_ctx* ctx, const float* params, const float* X,
+                                      const float* T, const float* M, int32_t n, float* grad,
+                                      float* loss, void* stream) {
+  if (!ctx || !params || !grad || (n > 0 && (!X || !T || !M)))
+    return fail(GR_EINVAL, "gr_mlp_loss_grad: NULL argument");
+  if (n < 0) return fail(GR_EINVAL, "gr_mlp_loss_grad: n < 0");
+  DeviceGuard dg(ctx->device);
+  const int64_t tiles = (std::max<int64_t>(n, 1) + mlp_tile() - 1) / mlp_tile();
+  float* partial = nullptr;
+  GR_TRY(pool_typed(ctx, S_MLP_WS, (size_t)tiles * (GR_MLP_N_PARAMS + 2), &partial));
+  GR_HIP(launch_mlp_loss_grad(params, X, T, M, n, partial, grad, loss,
+                              static_cast<hipStream_t>(stream)));
+  return GR_OK;
+}
+
+extern "C" gr_status gr_mlp_adam(gr_ctx* ctx, float* params, const float* grad, float* m, float* v,
+                                 int32_t step, float lr, float beta1, float beta2, float eps,
+                                 void* stream) {
+  if (!ctx || !params || !grad || !m || !v) return fail(GR_EINVAL, "gr_mlp_adam: NULL argument");
+  if (step < 1) return fail(GR_EINVAL, "gr_mlp_adam: step must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f && lr > 0.f))
+    return fail(GR_EINVAL, "gr_mlp_adam: need lr > 0, 0 <= beta < 1, eps > 0");
+  DeviceGuard dg(ctx->device);
+  const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+  GR_HIP(launch_adam(params, grad, m, v, GR_MLP_N_PARAMS, lr, beta1, beta2, eps, c1, c2,
+                     static_cast<hipStream_t>(stream)));
+  return GR_OK;
 }
 
 // ============================================================================

@@ -40,7 +40,9 @@ struct DevBuf {
 enum Slot : int {
   S_BM = 0,        // visited bitmaps, interleaved word pairs (old/live)
   S_Q_A,           // vertex frontier queue (ping)
-  S_Q_B,           // vertex frontier queue (pong)
+  S_Q_B,           // vertex frontier queue (second)
+  S_Q_C,           // vertex frontier queue (third; device-predicated levels rotate three)
+  S_DLOG,          // per-level log of a device-predicated block (n_f, m_f, max degree)
   S_U_A,           // unvisited frontier (ping)
   S_U_B,           // unvisited frontier (pong)
   S_OFFSETS,       // exclusive scan of frontier degrees [n_f + 1]
@@ -56,6 +58,7 @@ enum Slot : int {
   S_TMP0,          // small per-call staging (source lists)
   S_CHUNKS,        // LB chunk -> first frontier segment map
   S_MARKS,         // one byte per vertex, all zero between uses
+  S_MLP_WS,        // selector gradient partial sums
   S_NSLOTS
 };
 
@@ -63,8 +66,9 @@ enum Slot : int {
 // 64-bit.  Frontier statistics use two slots selected by the parity of the
 // statistics call, so each call can clear the slot the next one accumulates in.
 struct Ctrl {
-  uint32_t q_count[2];      // frontier queue lengths (ping/pong)
+  uint32_t q_count[3];      // frontier queue lengths (three rotating queues)
   uint32_t u_count[2];      // unvisited frontier lengths (ping/pong)
+  uint32_t pad1;
   int64_t m_f[2];           // sum of frontier degrees
   int64_t max_deg[2];       // largest frontier degree
   int64_t n_f[2];           // frontier size as seen by the statistics kernel
@@ -73,6 +77,12 @@ struct Ctrl {
   int32_t action;           // action chosen on the device (learned policy)
   int32_t pad0;
   int64_t misc[4];
+  // device-predicated level blocks (iteration control without host round trips)
+  int32_t dl_levels;        // levels of the current block that ran
+  int32_t dl_stop;          // a level of the block declined to run
+  int64_t dl_m[3];          // degree sum of the frontier held in queue k
+  int64_t dl_vm[2];         // degree sum of the vertices reached before the current frontier
+  int64_t dl_vn[2];         // number of vertices reached before the current frontier
 };
 
 }  // namespace gr
@@ -163,6 +173,70 @@ hipError_t launch_bfs_pull(bool lb, const int32_t* unvisited, int64_t n_u, const
                            int64_t* inspected, hipStream_t st);
 // live |= old (live = depth <= d + 1 after level d)
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
+
+// multi-source BFS (64-bit source masks per vertex)
+hipError_t launch_ms_seed(const int32_t* src_dev, int32_t k, unsigned long long* visit,
+                          unsigned long long* front, int32_t* depth, int64_t V, hipStream_t st);
+hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offsets,
+                          const int32_t* rstart, const int32_t* chunk_start, int64_t n_a,
+                          int64_t m_a, const int32_t* R, const int32_t* C,
+                          const unsigned long long* front, const unsigned long long* visit,
+                          unsigned long long* next, int32_t* touched, uint32_t* n_touched,
+                          int chunk, hipStream_t st);
+hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C,
+                          const unsigned long long* front, const unsigned long long* visit,
+                          unsigned long long full, unsigned long long* next, int32_t* touched,
+                          uint32_t* n_touched, hipStream_t st);
+hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched, int64_t max_n,
+                              const int32_t* R, const int32_t* C, const unsigned long long* front,
+                              unsigned long long* front_next, unsigned long long* visit,
+                              unsigned long long* next, int32_t* depth, int32_t* parent, int64_t V,
+                              int32_t next_depth, hipStream_t st);
+hipError_t launch_ms_clear(const int32_t* list, const uint32_t* n, int64_t max_n,
+                           unsigned long long* front, hipStream_t st);
+hipError_t launch_ms_teps(const unsigned long long* visit, const int32_t* R, int64_t V, int64_t* out,
+                          hipStream_t st);
+
+// selector network
+int mlp_tile();
+hipError_t launch_mlp_forward(const float* params, const float* X, int32_t n, float* Y,
+                              hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float* params, const float* X, const float* T,
+                                const float* M, int32_t n, float* partial, float* grad,
+                                float* loss, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_select(const float* params, Ctrl* ctrl, int sp, int64_t V, int64_t E,
+                             int64_t n_u_before, int64_t m_u_before, int prev_pull, int allowed,
+                             hipStream_t st);
+
+// Device-predicated level blocks (iteration control): up to kDlMaxLevels
+// push levels are enqueued back to back; each level kernel first decides on
+// the device whether it may run (the previous level ran, the frontier is
+// non-empty and within max_n / max_m, and for BFS the direction heuristic
+// would still push), so the host reads the control block once per block
+// instead of once per level.  Each level appends to q[(cur + 1) % 3] and
+// clears the counters of q[(cur + 2) % 3], which nothing reads during it.
+constexpr int kDlMaxN = 4096;        // frontier vertices staged in LDS per level
+constexpr int kDlMaxLevels = 64;     // levels per block (log capacity)
+struct DlArgs {
+  const int32_t* R;
+  const int32_t* C;
+  const int32_t* q_cur;       // frontier of this level
+  int32_t* q_next;            // appends
+  int32_t cur;                // index of q_cur among the three queues
+  int32_t step;               // level index inside the block
+  int64_t max_n, max_m;       // run only while n_f <= max_n and m_f <= max_m
+  int64_t E;                  // for the push -> pull test
+  double do_a;                // push -> pull when m_f > m_u * do_a (< 0: never)
+  int64_t* log;               // [kDlMaxLevels][3]
+  Ctrl* ctrl;
+};
+hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, hipStream_t st);
+hipError_t launch_bfs_dstep(const DlArgs& a, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
+                            int32_t next_depth, int n_blocks, hipStream_t st);
+hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
+                             int32_t* tags, int32_t next_tag, int n_blocks, hipStream_t st);
 
 // SSSP
 hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int64_t V, Ctrl* ctrl,

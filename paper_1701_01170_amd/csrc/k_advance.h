@@ -2,7 +2,8 @@
 // expansion (Sec. 5.3: functors compiled into the operator kernels, and the
 // filter fused with the advance so that no intermediate edge frontier is
 // written).  A functor provides
-//   int32_t  seg_payload(int32_t u)          per-source value (e.g. dist[u])
+//   pay_t    seg_payload(int32_t u)          per-source value (e.g. dist[u]);
+//                                            pay_t is the functor's payload type
 //   uint32_t edge_value(int64_t e)           per-edge value (e.g. weight)
 //   bool     probe(u, payload, v, ev)        read-only test: may the edge update v?
 //   bool     commit(u, payload, v, ev)       atomic update; true => append v
@@ -35,11 +36,15 @@ constexpr int kAdvBlock = 256;
 constexpr int kLbCap = 2048;  // frontier segments staged in LDS per pass
 
 // Process up to B edges per lane: ok[r] marks a real edge (u[r], pay[r], ce[r]).
-template <class F, int B>
+// With DEG, the degrees of the appended vertices are also summed into
+// *deg_sum (one atomic per wavefront).  All 64 lanes must take part.
+template <class F, int B, bool DEG = false>
 __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict__ C, bool (&ok)[B],
-                                           const int32_t (&u)[B], const int32_t (&pay)[B],
+                                           const int32_t (&u)[B], const typename F::pay_t (&pay)[B],
                                            const int32_t (&ce)[B], int32_t* __restrict__ out_q,
-                                           uint32_t* __restrict__ out_count) {
+                                           uint32_t* __restrict__ out_count,
+                                           const int32_t* __restrict__ R = nullptr,
+                                           unsigned long long* deg_sum = nullptr) {
   int32_t v[B];
   uint32_t ev[B];
 #pragma unroll
@@ -65,6 +70,14 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
 #pragma unroll
   for (int r = 0; r < B; ++r)
     if (ok[r]) out_q[base++] = v[r];
+  if (DEG) {
+    unsigned long long ds = 0;
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      if (ok[r]) ds += (unsigned long long)(R[v[r] + 1] - R[v[r]]);
+    ds = wave_sum(ds);
+    if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
+  }
 }
 
 // One workgroup per chunk of NB * EPT * 256 edges of the output frontier.  The
@@ -85,7 +98,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
   __shared__ int32_t s_off[kLbCap + 1];
   __shared__ int32_t s_u[kLbCap];
   __shared__ int32_t s_rb[kLbCap];
-  __shared__ int32_t s_pay[kLbCap];
+  __shared__ typename F::pay_t s_pay[kLbCap];
   __shared__ int32_t s_tmp[kAdvBlock / kWave + 1];
   const int c = blockIdx.x;
   const int64_t e0 = (int64_t)c * N;
@@ -145,7 +158,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
     for (int b = 0; b < NB; ++b) {
       if (lo + (int64_t)b * BATCH >= hi) break;
       bool ok[EPT];
-      int32_t u[EPT], pay[EPT];
+      int32_t u[EPT];
+      typename F::pay_t pay[EPT];
       int32_t ce[EPT];
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
@@ -172,10 +186,11 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_light(
   __shared__ int32_t s_off[kAdvBlock];
   __shared__ int32_t s_u[kAdvBlock];
   __shared__ int32_t s_rb[kAdvBlock];
-  __shared__ int32_t s_pay[kAdvBlock];
+  __shared__ typename F::pay_t s_pay[kAdvBlock];
   __shared__ int64_t s_tot[kAdvBlock / kWave + 1];
   const int64_t i = (int64_t)blockIdx.x * kAdvBlock + threadIdx.x;
-  int32_t u0 = 0, rb = 0, d = 0, pay0 = 0;
+  int32_t u0 = 0, rb = 0, d = 0;
+  typename F::pay_t pay0 = 0;
   if (i < n_f) {
     u0 = frontier[i];
     rb = R[u0];
@@ -191,7 +206,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_light(
   __syncthreads();
   for (int64_t base = 0; base < total; base += (int64_t)kAdvBlock * B) {
     bool ok[B];
-    int32_t u[B], pay[B];
+    int32_t u[B];
+    typename F::pay_t pay[B];
     int32_t ce[B];
 #pragma unroll
     for (int r = 0; r < B; ++r) {
@@ -214,14 +230,16 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
   constexpr int NW = kAdvBlock / kWave;
   constexpr int B = 4;
   __shared__ int32_t s_claim;
-  __shared__ int32_t s_cu, s_crb, s_cd, s_cpay;
+  __shared__ int32_t s_cu, s_crb, s_cd;
+  __shared__ typename F::pay_t s_cpay;
   __shared__ int32_t s_woff[NW][kWave];
   __shared__ int32_t s_wu[NW][kWave];
   __shared__ int32_t s_wrb[NW][kWave];
-  __shared__ int32_t s_wpay[NW][kWave];
+  __shared__ typename F::pay_t s_wpay[NW][kWave];
   const int64_t i = (int64_t)blockIdx.x * kAdvBlock + threadIdx.x;
   const int w = threadIdx.x / kWave;
-  int32_t u0 = 0, rb = 0, d = 0, pay0 = 0;
+  int32_t u0 = 0, rb = 0, d = 0;
+  typename F::pay_t pay0 = 0;
   if (i < n_f) {
     u0 = frontier[i];
     rb = R[u0];
@@ -245,10 +263,12 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
       big = false;
     }
     __syncthreads();
-    const int32_t cu = s_cu, crb = s_crb, cd = s_cd, cpay = s_cpay;
+    const int32_t cu = s_cu, crb = s_crb, cd = s_cd;
+    const typename F::pay_t cpay = s_cpay;
     for (int base = 0; base < cd; base += kAdvBlock * B) {
       bool ok[B];
-      int32_t u[B], pay[B];
+      int32_t u[B];
+    typename F::pay_t pay[B];
       int32_t ce[B];
 #pragma unroll
       for (int r = 0; r < B; ++r) {
@@ -267,9 +287,11 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
   while (med) {
     const int l = __ffsll((unsigned long long)med) - 1;
     med &= med - 1;
-    const int32_t cu = __shfl(u0, l), crb = __shfl(rb, l), cd = __shfl(d, l), cpay = __shfl(pay0, l);
+    const int32_t cu = __shfl(u0, l), crb = __shfl(rb, l), cd = __shfl(d, l);
+    const typename F::pay_t cpay = __shfl(pay0, l);
     bool ok[B];
-    int32_t u[B], pay[B];
+    int32_t u[B];
+    typename F::pay_t pay[B];
     int32_t ce[B];
 #pragma unroll
     for (int r = 0; r < B; ++r) {
@@ -293,7 +315,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   for (int base = 0; base < tot; base += kWave * B) {
     bool ok[B];
-    int32_t u[B], pay[B];
+    int32_t u[B];
+    typename F::pay_t pay[B];
     int32_t ce[B];
 #pragma unroll
     for (int r = 0; r < B; ++r) {

@@ -19,6 +19,7 @@
 //  * pull: each unvisited v scans its ascending adjacency and stops at the
 //    first frontier neighbour, which is therefore the smallest-id parent.
 #include "k_advance.h"
+#include "k_dloop.h"
 
 namespace gr {
 
@@ -36,6 +37,7 @@ struct BfsVisit {
   int32_t next_depth;
   int32_t p;  // parity: old word = 2w + p
 
+  using pay_t = int32_t;
   __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
@@ -57,6 +59,13 @@ struct BfsVisit {
     depth[v] = next_depth;
     return true;
   }
+  // Device-predicated steps have no merge pass: each frontier vertex joins
+  // live during its own level instead.  Push probes only test old, and
+  // frontier vertices are in old, so this changes no decision of the level;
+  // at its end live = depth <= d + 1, exactly what the merge would give.
+  __device__ __forceinline__ void frontier_vertex(int32_t u) const {
+    atomicOr(&bm[2 * (u >> 5) + 1 - p], 1u << (u & 31));
+  }
 };
 
 // Push without atomics (for levels that discover many vertices): every edge
@@ -68,6 +77,7 @@ struct BfsMark {
   uint8_t* __restrict__ marks;
   int32_t p;
 
+  using pay_t = int32_t;
   __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
@@ -397,6 +407,13 @@ hipError_t launch_bfs_pull(bool lb, const int32_t* unvisited, int64_t n_u, const
         unvisited, (int32_t)n_u, R, C, bm, p, depth, parent, next_depth, out_active,
         out_active_count, out_unvisited, out_unvisited_count, inspected);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_dstep(const DlArgs& a, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
+                            int32_t next_depth, int n_blocks, hipStream_t st) {
+  const BfsVisit<true> f{bm, depth, parent, next_depth, p};
+  k_dstep<BfsVisit<true>><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
   return hipGetLastError();
 }
 

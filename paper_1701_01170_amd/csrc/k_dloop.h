@@ -1,0 +1,129 @@
+// Device-predicated level step: one push level of BFS or SSSP for a small
+// frontier, written so that many levels can be enqueued back to back with no
+// host round trip in between (the per-iteration termination check of the
+// bulk-synchronous loop, Sec. 4 and Sec. 5.2, moved onto the device).
+//
+// Every workgroup first reads the same control values, all written by earlier
+// kernels, and so takes the same decision: the level runs only if no earlier
+// level of the block declined, the frontier is non-empty, it fits the LDS
+// staging (kDlMaxN vertices) and the caller's edge bound, and (BFS) the
+// direction heuristic of Sec. 5.1 would still push.  A declining level sets
+// dl_stop, so the rest of the block does nothing.
+//
+// A running level is output-balanced like LB (Sec. 5.1): each workgroup stages
+// the whole frontier in LDS, scans its degrees, and expands one equal slice
+// of the level's edges.  The degrees of appended vertices are summed on the
+// fly, which gives the next level its m_f without a statistics pass.
+#pragma once
+
+#include "k_advance.h"
+
+namespace gr {
+
+constexpr int kDlPerThread = kDlMaxN / kAdvBlock;
+static_assert(kDlMaxN % kAdvBlock == 0, "frontier staging assumes whole rows");
+
+template <class F>
+__global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
+  using pay_t = typename F::pay_t;
+  constexpr int B = 4;
+  __shared__ int32_t s_u[kDlMaxN];
+  __shared__ int32_t s_rb[kDlMaxN];
+  __shared__ int32_t s_off[kDlMaxN + 1];
+  __shared__ pay_t s_pay[kDlMaxN];
+  __shared__ int64_t s_tot[kAdvBlock / kWave + 1];
+  __shared__ int64_t s_max[kAdvBlock / kWave];
+  Ctrl* ctrl = a.ctrl;
+  if (ctrl->dl_stop) return;
+  const int64_t n_f = ctrl->q_count[a.cur];
+  const int64_t m_f = ctrl->dl_m[a.cur];
+  const int64_t vm = ctrl->dl_vm[a.step & 1];
+  const int64_t vn = ctrl->dl_vn[a.step & 1];
+  bool run = n_f > 0 && n_f <= a.max_n && n_f <= kDlMaxN && m_f <= a.max_m;
+  if (run && a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a) run = false;
+  if (!run) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->dl_stop = 1;
+    return;
+  }
+  const int next = (a.cur + 1) % 3, prev = (a.cur + 2) % 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // none of these is read by this kernel: the counters of the previous
+    // frontier become the append targets of the next level
+    ctrl->dl_levels = a.step + 1;
+    ctrl->q_count[prev] = 0;
+    ctrl->dl_m[prev] = 0;
+    ctrl->dl_vm[(a.step + 1) & 1] = vm + m_f;
+    ctrl->dl_vn[(a.step + 1) & 1] = vn + n_f;
+  }
+  const int nf = (int)n_f;
+  for (int j = threadIdx.x; j < nf; j += kAdvBlock) s_u[j] = a.q_cur[j];
+  __syncthreads();
+  for (int j = blockIdx.x * kAdvBlock + threadIdx.x; j < nf; j += gridDim.x * kAdvBlock)
+    f.frontier_vertex(s_u[j]);
+  // equal edge slices (at least one row of the workgroup each); workgroups
+  // past the last slice have nothing more to do
+  const int64_t G = gridDim.x;
+  int64_t per = (m_f + G - 1) / G;
+  if (per < kAdvBlock) per = kAdvBlock;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  if (lo >= m_f && blockIdx.x != 0) return;
+  // degrees and their exclusive scan, kDlPerThread consecutive entries per thread
+  const int j0 = threadIdx.x * kDlPerThread;
+  int32_t d[kDlPerThread];
+  int64_t sum = 0, mx = 0;
+#pragma unroll
+  for (int r = 0; r < kDlPerThread; ++r) {
+    const int j = j0 + r;
+    d[r] = 0;
+    if (j < nf) {
+      const int32_t u = s_u[j];
+      const int32_t rb = a.R[u];
+      d[r] = a.R[u + 1] - rb;
+      s_rb[j] = rb;
+      s_pay[j] = f.seg_payload(u);
+      sum += d[r];
+      mx = d[r] > mx ? d[r] : mx;
+    }
+  }
+  int64_t total;
+  int64_t ex = block_excl_scan<kAdvBlock>(sum, s_tot, &total);
+#pragma unroll
+  for (int r = 0; r < kDlPerThread; ++r) {
+    const int j = j0 + r;
+    if (j < nf) {
+      s_off[j] = (int32_t)ex;
+      ex += d[r];
+    }
+  }
+  if (threadIdx.x == 0) s_off[nf] = (int32_t)total;
+  mx = wave_max(mx);
+  if (lane() == 0) s_max[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.log) {
+    int64_t m = 0;
+    for (int i = 0; i < kAdvBlock / kWave; ++i) m = s_max[i] > m ? s_max[i] : m;
+    a.log[3 * a.step + 0] = n_f;
+    a.log[3 * a.step + 1] = m_f;
+    a.log[3 * a.step + 2] = m;
+  }
+  const int64_t hi = lo + per < total ? lo + per : total;
+  for (int64_t base = lo; base < hi; base += (int64_t)kAdvBlock * B) {
+    bool ok[B];
+    int32_t u[B];
+    pay_t pay[B];
+    int32_t ce[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int64_t e = base + r * kAdvBlock + threadIdx.x;
+      ok[r] = e < hi;
+      const int k = ok[r] ? upper_index(s_off, 0, nf - 1, (int32_t)e) : 0;
+      u[r] = s_u[k];
+      pay[r] = s_pay[k];
+      ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
+    }
+    edge_batch<F, B, true>(f, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
+                           reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]));
+  }
+}
+
+}  // namespace gr

@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
     queue[0] = source;
     ctrl->q_count[0] = 1;
     ctrl->q_count[1] = 0;
+    ctrl->q_count[2] = 0;
     ctrl->u_count[0] = 0;
     ctrl->u_count[1] = 0;
     ctrl->m_f[0] = ctrl->m_f[1] = 0;
@@ -167,6 +168,18 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
   if (i < n) p[i] = value;
 }
 
+// Start of a device-predicated block: the current frontier (queue cur) has
+// the degree sum the statistics kernel left in slot sp.
+__global__ void k_dl_begin(Ctrl* __restrict__ ctrl, int cur, int sp, int64_t vm, int64_t vn) {
+  ctrl->dl_levels = 0;
+  ctrl->dl_stop = 0;
+  ctrl->dl_m[cur] = ctrl->m_f[sp];
+  ctrl->dl_m[(cur + 1) % 3] = 0;
+  ctrl->q_count[(cur + 1) % 3] = 0;
+  ctrl->dl_vm[0] = vm;
+  ctrl->dl_vn[0] = vn;
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -210,6 +223,11 @@ hipError_t launch_gen_unvisited(const uint32_t* bm, int p, const int32_t* R, int
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st) {
   if (n_words <= 0) return hipSuccess;
   k_bitmap_merge<<<blocks_for(n_words, 256), 256, 0, st>>>(bm, p, n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, hipStream_t st) {
+  k_dl_begin<<<1, 1, 0, st>>>(ctrl, cur, sp, vm, vn);
   return hipGetLastError();
 }
 

@@ -1,0 +1,289 @@
+// Strategy-selector network: 8 inputs -> 32 -> 32 -> 4 outputs, ReLU on the
+// hidden layers, fp32.  Parameters are one flat array (row-major):
+//   W1[32][8], b1[32], W2[32][32], b2[32], W3[4][32], b3[4]   (1476 floats).
+// Outputs are predicted log2 step times of the four advance actions; the
+// selector takes the argmin over the actions the traversal allows.
+//
+// Kernels: batched forward; masked squared-error loss with its gradient
+// (per-tile partial sums, then a fixed-order reduction: deterministic); Adam;
+// and the fused inference kernel the traversal launches each iteration, which
+// builds the eight features from the frontier statistics on the device.
+#include "gr_internal.h"
+#include "k_common.h"
+
+namespace gr {
+
+namespace {
+
+constexpr int kIn = 8, kH = 32, kOut = 4;
+constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH,
+              oW3 = oB2 + kH, oB3 = oW3 + kOut * kH, kNP = oB3 + kOut;
+static_assert(kNP == GR_MLP_N_PARAMS, "parameter count");
+constexpr int kTile = 64;  // samples per workgroup in the gradient kernel
+
+__device__ __forceinline__ void load_params(const float* __restrict__ params, float* s_p) {
+  for (int i = threadIdx.x; i < kNP; i += blockDim.x) s_p[i] = params[i];
+}
+
+// Forward pass of one sample; h1/h2 receive the post-ReLU activations.
+__device__ __forceinline__ void forward1(const float* p, const float* x, float* h1, float* h2,
+                                         float* y) {
+  for (int j = 0; j < kH; ++j) {
+    float z = p[oB1 + j];
+    for (int i = 0; i < kIn; ++i) z += p[oW1 + j * kIn + i] * x[i];
+    h1[j] = z > 0.f ? z : 0.f;
+  }
+  for (int j = 0; j < kH; ++j) {
+    float z = p[oB2 + j];
+    for (int i = 0; i < kH; ++i) z += p[oW2 + j * kH + i] * h1[i];
+    h2[j] = z > 0.f ? z : 0.f;
+  }
+  for (int o = 0; o < kOut; ++o) {
+    float z = p[oB3 + o];
+    for (int j = 0; j < kH; ++j) z += p[oW3 + o * kH + j] * h2[j];
+    y[o] = z;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ params,
+                                                     const float* __restrict__ X, int32_t n,
+                                                     float* __restrict__ Y) {
+  __shared__ float s_p[kNP];
+  load_params(params, s_p);
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  float x[kIn], h1[kH], h2[kH], y[kOut];
+  for (int i = 0; i < kIn; ++i) x[i] = X[s * kIn + i];
+  forward1(s_p, x, h1, h2, y);
+  for (int o = 0; o < kOut; ++o) Y[s * kOut + o] = y[o];
+}
+
+// Per tile of 64 samples: forward and backward per sample (threads 0..63),
+// then every parameter's contribution summed over the tile in sample order.
+// partial[tile][kNP + 0] = sum of masked squared errors, [kNP + 1] = mask sum.
+// The gradient of sum(M * (Y - T)^2) is accumulated here; the reduction
+// divides by max(1, sum M).
+__global__ __launch_bounds__(256) void k_mlp_grad_tiles(const float* __restrict__ params,
+                                                        const float* __restrict__ X,
+                                                        const float* __restrict__ T,
+                                                        const float* __restrict__ M, int32_t n,
+                                                        float* __restrict__ partial) {
+  __shared__ float s_p[kNP];
+  __shared__ float s_x[kTile][kIn];
+  __shared__ float s_h1[kTile][kH];
+  __shared__ float s_h2[kTile][kH];
+  __shared__ float s_dz1[kTile][kH];
+  __shared__ float s_dz2[kTile][kH];
+  __shared__ float s_dy[kTile][kOut];
+  __shared__ float s_l[kTile], s_m[kTile];
+  load_params(params, s_p);
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kTile) {
+    const int64_t s = (int64_t)blockIdx.x * kTile + t;
+    float x[kIn], h1[kH], h2[kH], y[kOut];
+    float l = 0.f, msum = 0.f;
+    if (s < n) {
+      for (int i = 0; i < kIn; ++i) x[i] = X[s * kIn + i];
+      forward1(s_p, x, h1, h2, y);
+      float dy[kOut];
+      for (int o = 0; o < kOut; ++o) {
+        const float m = M[s * kOut + o];
+        const float e = y[o] - T[s * kOut + o];
+        dy[o] = 2.f * m * e;
+        l += m * e * e;
+        msum += m;
+      }
+      float dz2[kH];
+      for (int j = 0; j < kH; ++j) {
+        float g = 0.f;
+        for (int o = 0; o < kOut; ++o) g += dy[o] * s_p[oW3 + o * kH + j];
+        dz2[j] = h2[j] > 0.f ? g : 0.f;
+      }
+      for (int i = 0; i < kH; ++i) {
+        float g = 0.f;
+        for (int j = 0; j < kH; ++j) g += dz2[j] * s_p[oW2 + j * kH + i];
+        s_dz1[t][i] = h1[i] > 0.f ? g : 0.f;
+      }
+      for (int i = 0; i < kIn; ++i) s_x[t][i] = x[i];
+      for (int j = 0; j < kH; ++j) {
+        s_h1[t][j] = h1[j];
+        s_h2[t][j] = h2[j];
+        s_dz2[t][j] = dz2[j];
+      }
+      for (int o = 0; o < kOut; ++o) s_dy[t][o] = dy[o];
+    } else {
+      for (int i = 0; i < kIn; ++i) s_x[t][i] = 0.f;
+      for (int j = 0; j < kH; ++j) s_h1[t][j] = s_h2[t][j] = s_dz1[t][j] = s_dz2[t][j] = 0.f;
+      for (int o = 0; o < kOut; ++o) s_dy[t][o] = 0.f;
+    }
+    s_l[t] = l;
+    s_m[t] = msum;
+  }
+  __syncthreads();
+  float* out = partial + (int64_t)blockIdx.x * (kNP + 2);
+  for (int q = t; q < kNP; q += blockDim.x) {
+    float acc = 0.f;
+    if (q < oB1) {
+      const int j = (q - oW1) / kIn, i = (q - oW1) % kIn;
+      for (int s = 0; s < kTile; ++s) acc += s_dz1[s][j] * s_x[s][i];
+    } else if (q < oW2) {
+      const int j = q - oB1;
+      for (int s = 0; s < kTile; ++s) acc += s_dz1[s][j];
+    } else if (q < oB2) {
+      const int j = (q - oW2) / kH, i = (q - oW2) % kH;
+      for (int s = 0; s < kTile; ++s) acc += s_dz2[s][j] * s_h1[s][i];
+    } else if (q < oW3) {
+      const int j = q - oB2;
+      for (int s = 0; s < kTile; ++s) acc += s_dz2[s][j];
+    } else if (q < oB3) {
+      const int o = (q - oW3) / kH, j = (q - oW3) % kH;
+      for (int s = 0; s < kTile; ++s) acc += s_dy[s][o] * s_h2[s][j];
+    } else {
+      const int o = q - oB3;
+      for (int s = 0; s < kTile; ++s) acc += s_dy[s][o];
+    }
+    out[q] = acc;
+  }
+  if (t == 0) {
+    float l = 0.f, m = 0.f;
+    for (int s = 0; s < kTile; ++s) {
+      l += s_l[s];
+      m += s_m[s];
+    }
+    out[kNP] = l;
+    out[kNP + 1] = m;
+  }
+}
+
+// Sum the tiles in tile order and scale by 1 / max(1, sum M).
+__global__ __launch_bounds__(256) void k_mlp_grad_reduce(const float* __restrict__ partial,
+                                                         int32_t n_tiles, float* __restrict__ grad,
+                                                         float* __restrict__ loss) {
+  __shared__ float s_den;
+  if (threadIdx.x == 0) {
+    float m = 0.f;
+    for (int b = 0; b < n_tiles; ++b) m += partial[(int64_t)b * (kNP + 2) + kNP + 1];
+    s_den = m > 1.f ? m : 1.f;
+  }
+  __syncthreads();
+  const float inv = 1.f / s_den;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < kNP) {
+    float acc = 0.f;
+    for (int b = 0; b < n_tiles; ++b) acc += partial[(int64_t)b * (kNP + 2) + q];
+    grad[q] = acc * inv;
+  } else if (q == kNP && loss) {
+    float acc = 0.f;
+    for (int b = 0; b < n_tiles; ++b) acc += partial[(int64_t)b * (kNP + 2) + kNP];
+    *loss = acc * inv;
+  }
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// p -= lr * (m / c1) / (sqrt(v / c2) + eps) with c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int n,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__device__ __forceinline__ float feat(double x) {
+  return (float)(log2(1.0 + (x > 0 ? x : 0.0)) / 32.0);
+}
+
+// One wavefront: features of the current iteration (the frontier statistics
+// of slot `sp` plus host-known totals), forward pass, argmin over the allowed
+// actions (bit a of allowed) -> ctrl->action.  n_u_before / m_u_before are the
+// unvisited counts before this frontier was visited (BFS), 0 for SSSP.
+__global__ __launch_bounds__(64) void k_mlp_select(const float* __restrict__ params,
+                                                   Ctrl* __restrict__ ctrl, int sp, int64_t V,
+                                                   int64_t E, int64_t n_u_before,
+                                                   int64_t m_u_before, int prev_pull, int allowed) {
+  __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
+  const int t = threadIdx.x;
+  if (t == 0) {
+    const int64_t n_f = ctrl->n_f[sp], m_f = ctrl->m_f[sp];
+    const int64_t n_u = n_u_before > 0 ? n_u_before - n_f : 0;
+    const int64_t m_u = m_u_before > 0 ? m_u_before - m_f : 0;
+    s_x[0] = feat((double)n_f);
+    s_x[1] = feat((double)m_f);
+    s_x[2] = feat((double)n_u);
+    s_x[3] = feat((double)m_u);
+    s_x[4] = feat((double)ctrl->max_deg[sp]);
+    s_x[5] = feat((double)V);
+    s_x[6] = feat((double)E);
+    s_x[7] = feat(prev_pull ? 0.0 : (double)V);
+  }
+  __syncthreads();
+  if (t < kH) {
+    float z = params[oB1 + t];
+    for (int i = 0; i < kIn; ++i) z += params[oW1 + t * kIn + i] * s_x[i];
+    s_h1[t] = z > 0.f ? z : 0.f;
+  }
+  __syncthreads();
+  if (t < kH) {
+    float z = params[oB2 + t];
+    for (int i = 0; i < kH; ++i) z += params[oW2 + t * kH + i] * s_h1[i];
+    s_h2[t] = z > 0.f ? z : 0.f;
+  }
+  __syncthreads();
+  if (t < kOut) {
+    float z = params[oB3 + t];
+    for (int j = 0; j < kH; ++j) z += params[oW3 + t * kH + j] * s_h2[j];
+    s_y[t] = z;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int best = -1;
+    for (int a = 0; a < kOut; ++a)
+      if (((allowed >> a) & 1) && (best < 0 || s_y[a] < s_y[best])) best = a;
+    ctrl->action = best;
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+int mlp_tile() { return kTile; }
+
+hipError_t launch_mlp_forward(const float* params, const float* X, int32_t n, float* Y,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_mlp_forward<<<blocks_for(n, 256), 256, 0, st>>>(params, X, n, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss_grad(const float* params, const float* X, const float* T,
+                                const float* M, int32_t n, float* partial, float* grad,
+                                float* loss, hipStream_t st) {
+  const int tiles = (int)blocks_for(n > 0 ? n : 1, kTile);
+  k_mlp_grad_tiles<<<tiles, 256, 0, st>>>(params, X, T, M, n, partial);
+  k_mlp_grad_reduce<<<blocks_for(kNP + 1, 256), 256, 0, st>>>(partial, tiles, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st) {
+  k_adam<<<blocks_for(n, 256), 256, 0, st>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_select(const float* params, Ctrl* ctrl, int sp, int64_t V, int64_t E,
+                             int64_t n_u_before, int64_t m_u_before, int prev_pull, int allowed,
+                             hipStream_t st) {
+  k_mlp_select<<<1, 64, 0, st>>>(params, ctrl, sp, V, E, n_u_before, m_u_before, prev_pull, allowed);
+  return hipGetLastError();
+}
+
+}  // namespace gr

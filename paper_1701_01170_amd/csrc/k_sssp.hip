@@ -11,6 +11,7 @@
 // key holds the true distance and the smallest-id predecessor among all tight
 // in-edges.  Unreached vertices keep ~0 (distance UINT32_MAX, predecessor -1).
 #include "k_advance.h"
+#include "k_dloop.h"
 
 namespace gr {
 
@@ -22,6 +23,7 @@ struct SsspVisit {
   int32_t* __restrict__ tags;
   int32_t next_tag;
 
+  using pay_t = int32_t;
   __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
     return (int32_t)(uint32_t)(keys[u] >> 32);
   }
@@ -39,6 +41,7 @@ struct SsspVisit {
     if (cand >= (old >> 32)) return false;     // no distance improvement (at most a better pred)
     return atomicExch(&tags[v], next_tag) != next_tag;
   }
+  __device__ __forceinline__ void frontier_vertex(int32_t) const {}
 };
 
 __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restrict__ keys,
@@ -51,6 +54,7 @@ __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restric
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->q_count[1] = 0;
+    ctrl->q_count[2] = 0;
     ctrl->u_count[0] = 0;
     ctrl->u_count[1] = 0;
     ctrl->inspected = 0;
@@ -140,6 +144,13 @@ hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R
   if (g > 4096) g = 4096;
   k_sssp_finalize<<<g, 256, 0, st>>>(keys, R, V, dist, pred, reached_edges);
   if (pred) k_sssp_source_pred<<<blocks_for(n_src, 256), 256, 0, st>>>(src_dev, n_src, pred);
+  return hipGetLastError();
+}
+
+hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
+                             int32_t* tags, int32_t next_tag, int n_blocks, hipStream_t st) {
+  const SsspVisit f{W, keys, tags, next_tag};
+  k_dstep<SsspVisit><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
   return hipGetLastError();
 }
 

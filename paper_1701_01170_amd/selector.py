@@ -1,0 +1,197 @@
+"""Training and evaluation of the learned strategy selector.
+
+Traces: the traversals themselves record, for every iteration, the eight
+selector features, the action taken and its event-timed step time
+(gr_level_trace).  Because the filter is exact, the frontier of every level is
+the same whatever actions were taken, so runs with each fixed action and with
+seeded random actions observe every action's time at the same levels (with
+both "previous step pushed" and "previous step pulled" states).  Each record
+becomes one training sample whose target is log2(step time in us) for the
+action taken, with the other three outputs masked out.
+
+Training runs on the GPU with the library's own kernels (gr_mlp_loss_grad,
+gr_mlp_adam); evaluation compares event-timed traversal time with the
+heuristic and with the network on held-out sources.
+
+CLI:  python -m paper_1701_01170_amd.selector [--quick] [--epochs N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import (MLP_N_PARAMS, POLICY_FIXED, POLICY_HEURISTIC, POLICY_LEARNED, POLICY_RANDOM,
+               Context, Graph, LevelTrace, bfs, default_opts, mlp_adam, mlp_loss_grad, sssp)
+from . import graphgen as gg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "tuning", "selector_gfx950.npy")
+REPORT = os.path.join(HERE, "tuning", "selector_gfx950.json")
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-style initialisation in the documented flat layout."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal((32, 8)) * np.sqrt(2 / 8), np.zeros(32),
+             rng.standard_normal((32, 32)) * np.sqrt(2 / 32), np.zeros(32),
+             rng.standard_normal((4, 32)) * np.sqrt(1 / 32), np.full(4, 6.0)]
+    flat = np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+    assert flat.shape[0] == MLP_N_PARAMS
+    return flat
+
+
+def _records(buf, count):
+    out = []
+    for t in buf[:count]:
+        if t.step_us > 0:
+            out.append((list(t.features), t.action, float(t.step_us)))
+    return out
+
+
+def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 2, sssp_too: bool = True,
+            log=print):
+    """Trace samples X[n][8], T[n][4], M[n][4] from fixed- and random-action runs."""
+    cap = 1 << 15
+    buf = (LevelTrace * cap)()
+    X, T, M = [], [], []
+
+    def add(recs):
+        for f, a, us in recs:
+            X.append(f)
+            t = np.zeros(4, np.float32)
+            m = np.zeros(4, np.float32)
+            t[a] = np.log2(us)
+            m[a] = 1.0
+            T.append(t)
+            M.append(m)
+
+    for name, hg in graphs:
+        t0 = time.time()
+        g = Graph.from_host(ctx, hg, symmetric=True)
+        srcs = gg.sources(hg, n_sources, seed=3000)
+        pols = [dict(policy=POLICY_FIXED, fixed_action=a, lb_light_threshold=0) for a in range(4)]
+        pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r, lb_light_threshold=0)
+                 for r in range(random_runs)]
+        for s in srcs:
+            for kw in pols:
+                o = default_opts(trace=buf, trace_capacity=cap, **kw)
+                bfs(g, int(s), opts=o)
+                add(_records(buf, min(o.trace_count, cap)))
+                if sssp_too and hg.weights is not None and kw["policy"] != POLICY_RANDOM and \
+                        kw.get("fixed_action", 0) < 2:
+                    o = default_opts(trace=buf, trace_capacity=cap, **kw)
+                    sssp(g, [int(s)], opts=o)
+                    add(_records(buf, min(o.trace_count, cap)))
+        g.free()
+        log(f"traced {name}: {len(X)} samples so far ({time.time() - t0:.1f}s)")
+    return (np.asarray(X, np.float32), np.asarray(T, np.float32), np.asarray(M, np.float32))
+
+
+def train(ctx: Context, X, T, M, epochs: int = 400, lr: float = 3e-3, seed: int = 0, log=print):
+    """Full-batch Adam on the GPU kernels; returns float32 parameters."""
+    import torch
+    dX = torch.from_numpy(X).cuda()
+    dT = torch.from_numpy(T).cuda()
+    dM = torch.from_numpy(M).cuda()
+    p = torch.from_numpy(init_params(seed)).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    grad = torch.empty_like(p)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    for step in range(1, epochs + 1):
+        mlp_loss_grad(ctx, p, dX, dT, dM, grad=grad, loss=loss)
+        mlp_adam(ctx, p, grad, m, v, step, lr=lr)
+        if step == 1 or step % 100 == 0 or step == epochs:
+            log(f"step {step}: loss {loss.item():.4f}")
+    return p.cpu().numpy()
+
+
+def evaluate(ctx: Context, graphs, params, n_sources: int = 5, log=print) -> list[dict]:
+    """Median device time of BFS and SSSP under the heuristic (paper defaults
+    and autotuned knobs) and under the network, on held-out sources."""
+    from . import autotune
+    ctx.set_policy(params)
+    rows = []
+    try:
+        for name, hg in graphs:
+            g = Graph.from_host(ctx, hg, symmetric=True)
+            srcs = gg.sources(hg, n_sources, seed=9000)
+            for kind in ("bfs", "sssp"):
+                if kind == "sssp" and hg.weights is None:
+                    continue
+                res = {}
+                cfgs = {"heuristic_paper_knobs": default_opts(),
+                        "heuristic_tuned_knobs": autotune.tuned_opts(g, kind),
+                        "learned": default_opts(policy=POLICY_LEARNED, lb_light_threshold=0)}
+                for label, o in cfgs.items():
+                    times, teps = [], 0
+                    for s in srcs:
+                        best = float("inf")
+                        for _ in range(3):
+                            if kind == "bfs":
+                                st = bfs(g, int(s), opts=o)[2]
+                            else:
+                                st = sssp(g, [int(s)], opts=o)[2]
+                            best = min(best, st["device_ms"])
+                        times.append(best)
+                        teps += st["teps_edges"]
+                    res[label] = dict(ms=float(np.median(times)),
+                                      gteps=teps / (sum(times) * 1e-3) / 1e9)
+                row = dict(graph=name, kind=kind, **res)
+                rows.append(row)
+                log(json.dumps(row))
+            g.free()
+    finally:
+        ctx.set_policy(None)
+    return rows
+
+
+def training_graphs(quick: bool):
+    """Synthetic training set: R-MAT scales 16..22 with a in [0.45, 0.65]
+    (b:c:d kept), Erdos-Renyi average degree 4..64, grids 256^2..2048^2."""
+    gs = []
+    scales = [16, 18] if quick else [16, 18, 20, 22]
+    for s in scales:
+        for a in (0.45, 0.55, 0.65):
+            gs.append((f"rmat_s{s}_a{a}", gg.add_weights(gg.rmat_family(s, 16, a, seed=11 + s), seed=7)))
+    for d in ((4, 64) if quick else (4, 16, 64)):
+        gs.append((f"er_n262144_d{d}", gg.add_weights(gg.erdos_renyi(1 << 18, d, seed=5), seed=7)))
+    for n in ((256, 512) if quick else (256, 512, 1024, 2048)):
+        gs.append((f"grid_{n}", gg.add_weights(gg.grid(n, n), seed=7)))
+    return gs
+
+
+def eval_graphs():
+    """Held-out: the scale-14 R-MAT of the small BFS workload (seed 1, the
+    paper's initiator) plus graphs of the other classes with unseen seeds."""
+    return [("rmat_s14_e16", gg.add_weights(gg.rmat(14, 16, seed=1), seed=101)),
+            ("rmat_s20_e16", gg.add_weights(gg.rmat(20, 16, seed=3), seed=101)),
+            ("er_n262144_d8", gg.add_weights(gg.erdos_renyi(1 << 18, 8, seed=77), seed=101)),
+            ("grid_768", gg.add_weights(gg.grid(768, 768), seed=101))]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--epochs", type=int, default=1500)
+    ap.add_argument("--sources", type=int, default=3)
+    args = ap.parse_args()
+    ctx = Context(0)
+    t0 = time.time()
+    X, T, M = collect(ctx, training_graphs(args.quick), n_sources=args.sources,
+                      log=lambda s: print(s, flush=True))
+    print(f"collected {X.shape[0]} samples in {time.time() - t0:.1f}s", flush=True)
+    params = train(ctx, X, T, M, epochs=args.epochs, log=lambda s: print(s, flush=True))
+    os.makedirs(os.path.dirname(WEIGHTS), exist_ok=True)
+    np.save(WEIGHTS, params.astype(np.float32))
+    rows = evaluate(ctx, eval_graphs(), params, log=lambda s: print(s, flush=True))
+    with open(REPORT, "w") as f:
+        json.dump(dict(samples=int(X.shape[0]), epochs=args.epochs, eval=rows), f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

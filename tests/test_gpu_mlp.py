@@ -1,0 +1,117 @@
+"""GPU selector network: forward, masked-MSE gradient and Adam through the C
+ABI against the float64 oracle (fp32 kernels: rtol 1e-4 on values of order
+1; gradients compared relative to the largest gradient entry), determinism of
+the gradient, and the fused per-iteration inference inside traversals."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1701_01170_amd as gr
+from paper_1701_01170_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gr.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rand_case(seed, n):
+    rng = np.random.default_rng(seed)
+    flat = (rng.standard_normal(oracle.MLP_N_PARAMS) * 0.3).astype(np.float32)
+    X = rng.random((n, 8)).astype(np.float32)
+    T = rng.standard_normal((n, 4)).astype(np.float32)
+    M = (rng.random((n, 4)) < 0.7).astype(np.float32)
+    return flat, X, T, M
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4097])
+def test_forward_matches_oracle(ctx, n):
+    flat, X, _, _ = rand_case(n, n)
+    Y = gr.mlp_forward(ctx, dev(flat), dev(X)).cpu().numpy()
+    ref, _ = oracle.mlp_forward(oracle.mlp_unflatten(flat.astype(np.float64)), X.astype(np.float64))
+    np.testing.assert_allclose(Y, ref, rtol=1e-4, atol=1e-5)
+
+
+@pytest.mark.parametrize("n", [1, 65, 3000])
+def test_loss_grad_matches_oracle(ctx, n):
+    flat, X, T, M = rand_case(100 + n, n)
+    grad, loss = gr.mlp_loss_grad(ctx, dev(flat), dev(X), dev(T), dev(M))
+    ref_loss, ref_g = oracle.mlp_backward(oracle.mlp_unflatten(flat.astype(np.float64)),
+                                          X.astype(np.float64), T.astype(np.float64),
+                                          M.astype(np.float64))
+    ref = oracle.mlp_flatten(ref_g)
+    g = grad.cpu().numpy()
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(g, ref, rtol=1e-4, atol=1e-4 * scale)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * max(1.0, abs(ref_loss))
+    grad2, _ = gr.mlp_loss_grad(ctx, dev(flat), dev(X), dev(T), dev(M))
+    assert torch.equal(grad, grad2), "gradient is not deterministic"
+
+
+def test_adam_matches_oracle(ctx):
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(oracle.MLP_N_PARAMS)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    dp, dm, dv = dev(p), dev(m), dev(v)
+    for t in range(1, 4):
+        g = rng.standard_normal(oracle.MLP_N_PARAMS)
+        p, m, v = oracle.adam_step(p, g, m, v, t, lr=1e-2)
+        gr.mlp_adam(ctx, dp, dev(g), dm, dv, t, lr=1e-2)
+        np.testing.assert_allclose(dp.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_gpu_training_reduces_loss(ctx):
+    flat, X, _, M = rand_case(7, 2048)
+    true = (np.random.default_rng(8).standard_normal(oracle.MLP_N_PARAMS) * 0.5)
+    T, _ = oracle.mlp_forward(oracle.mlp_unflatten(true), X.astype(np.float64))
+    M = np.ones_like(M)
+    dp, dX, dT, dM = dev(flat), dev(X), dev(T), dev(M)
+    m = torch.zeros_like(dp)
+    v = torch.zeros_like(dp)
+    l0 = None
+    for t in range(1, 301):
+        grad, loss = gr.mlp_loss_grad(ctx, dp, dX, dT, dM)
+        if l0 is None:
+            l0 = loss.item()
+        gr.mlp_adam(ctx, dp, grad, m, v, t, lr=1e-2)
+    _, loss = gr.mlp_loss_grad(ctx, dp, dX, dT, dM)
+    assert loss.item() < 0.2 * l0
+
+
+def test_learned_policy_is_exact_and_takes_argmin(ctx, rmat14):
+    g = gr.Graph.from_host(ctx, rmat14)
+    rng = np.random.default_rng(11)
+    flat = (rng.standard_normal(oracle.MLP_N_PARAMS) * 0.5).astype(np.float32)
+    ctx.set_policy(flat)
+    P = oracle.mlp_unflatten(flat.astype(np.float64))
+    cap = 64
+    buf = (gr.LevelTrace * cap)()
+    try:
+        for s in gg.sources(rmat14, 4, seed=1000):
+            o = gr.default_opts(policy=gr.POLICY_LEARNED, trace=buf, trace_capacity=cap)
+            d, p, _ = gr.bfs(g, int(s), opts=o)
+            ed, ep = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, int(s))
+            np.testing.assert_array_equal(d.cpu().numpy(), ed)
+            np.testing.assert_array_equal(p.cpu().numpy(), ep)
+            for t in buf[:o.trace_count]:
+                x = np.array(list(t.features), dtype=np.float64)[None]
+                y, _ = oracle.mlp_forward(P, x)
+                y = y[0]
+                # the device's choice is within fp32 rounding of the argmin
+                assert y[t.action] <= y.min() + 1e-3, (t.level, t.action, y)
+            dist, pred, _ = gr.sssp(g, [int(s)], opts=gr.default_opts(policy=gr.POLICY_LEARNED))
+            edist, epred = oracle.sssp(rmat14.row_offsets, rmat14.col_indices, rmat14.weights, [int(s)])
+            np.testing.assert_array_equal(dist.cpu().numpy().view(np.uint32), edist)
+            np.testing.assert_array_equal(pred.cpu().numpy(), epred)
+    finally:
+        ctx.set_policy(None)
+    with pytest.raises(gr.GrError):
+        ctx.set_policy(np.zeros(10, np.float32))

@@ -29,6 +29,12 @@ POLICIES = [
                        lb_chunk=4096)),
     ("chunk16384", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
                         lb_chunk=16384)),
+    # iteration control: host round trip per level, and device blocks that
+    # stop on a tiny edge bound or run every small push level
+    ("dl_off", dict(device_max_edges=-1)),
+    ("dl_tiny", dict(device_max_edges=64)),
+    ("dl_fixed_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC,
+                          device_max_edges=1 << 24)),
 ]
 
 
@@ -230,17 +236,37 @@ def test_max_iterations_stops_early(ctx, rmat14):
     assert st["iterations"] == 2
 
 
-def test_trace_records(ctx, rmat14):
+@pytest.mark.parametrize("dme", [0, -1, 1 << 24])
+def test_trace_records(ctx, rmat14, dme):
     g = gr.Graph.from_host(ctx, rmat14)
     s = int(gg.sources(rmat14, 1)[0])
     ed, _ = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, s)
     prof = oracle.level_profile(rmat14.row_offsets, ed)
     cap = 64
     buf = (gr.LevelTrace * cap)()
-    o = gr.default_opts(trace=buf, trace_capacity=cap)
+    o = gr.default_opts(trace=buf, trace_capacity=cap, device_max_edges=dme)
     gr.bfs(g, s, opts=o)
     assert o.trace_count == len(prof)
     for t, ref in zip(buf[:o.trace_count], prof):
         assert (t.level, t.n_f, t.m_f, t.n_u, t.m_u, t.max_deg_f) == (
             ref["level"], ref["n_f"], ref["m_f"], ref["n_u"], ref["m_u"], ref["maxdeg_f"])
         assert t.step_us > 0
+    kernels = {t.kernel for t in buf[:o.trace_count]}
+    assert (6 in kernels) == (dme != -1), kernels
+
+
+@pytest.mark.parametrize("max_it", [1, 3, 4, 37, 100])
+def test_device_blocks_respect_max_iterations(ctx, max_it):
+    """Long chains of small levels (a thin grid) run in device blocks of
+    4, 8, 16, ... levels; a level cap that falls inside a block still stops
+    exactly there."""
+    hg = gg.add_weights(gg.grid(7, 301), seed=9)
+    g = gr.Graph.from_host(ctx, hg)
+    ed, _ = oracle.bfs(hg.row_offsets, hg.col_indices, 0)
+    d, _, st = gr.bfs(g, 0, opts=gr.default_opts(max_iterations=max_it))
+    np.testing.assert_array_equal(np_of(d), np.where(ed <= max_it, ed, -1))
+    assert st["iterations"] == min(max_it, int(ed.max()) + 1)
+    dist, _, st = gr.sssp(g, [0], opts=gr.default_opts())
+    edist, _ = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, [0])
+    np.testing.assert_array_equal(np_of(dist).view(np.uint32), edist)
+    g.free()
