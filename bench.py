@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -78,7 +80,90 @@ def parse():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the grid, batched and learned-policy comparisons")
     return ap.parse_args()
+
+
+def _gteps(teps: float, ms: float) -> float | None:
+    return round(teps / (ms * 1e-3) / 1e9, 3) if ms > 0 else None
+
+
+def extras(gr, gg, ctx, torch, log):
+    """Comparison workloads reported next to the headline (device-event time):
+    the 2048 x 2048 grid (high diameter, small frontiers), 64-source batched BFS
+    on R-MAT scale 20 against 64 single-source runs, 256 small R-MAT graphs in
+    one disjoint-union SSSP against 256 separate runs, and (when trained
+    weights are present) the learned selector against the heuristic on the
+    R-MAT scale 22 workload (filled in by the caller)."""
+    from paper_1701_01170_amd import autotune
+    out = {}
+    # grid
+    hg = gg.add_weights(gg.grid(2048, 2048), seed=101)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    s = int(gg.sources(hg, 1, seed=1000)[0])
+    row = {}
+    for label, kw in (("device_blocks", {}), ("host_loop", {"device_max_edges": -1})):
+        ob = autotune.tuned_opts(g, "bfs", **kw)
+        os_ = autotune.tuned_opts(g, "sssp", **kw)
+        gr.bfs(g, s, opts=ob)
+        b = gr.bfs(g, s, opts=ob)[2]
+        t = gr.sssp(g, [s], opts=os_)[2]
+        row[label] = {"bfs_ms": round(b["device_ms"], 3), "bfs_gteps": _gteps(b["teps_edges"], b["device_ms"]),
+                      "bfs_iterations": b["iterations"], "sssp_ms": round(t["device_ms"], 3),
+                      "sssp_gteps": _gteps(t["teps_edges"], t["device_ms"]), "sssp_iterations": t["iterations"]}
+    out["grid_2048x2048"] = row
+    g.free()
+    del hg
+    log("# grid done")
+    # 64-source batched BFS, R-MAT scale 20
+    hg = gg.rmat(20, 16, seed=1)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    srcs = gg.sources(hg, 64, seed=2000).astype(np.int32)
+    ob = autotune.tuned_opts(g, "bfs")
+    V = hg.n_vertices
+    depth = torch.empty((64, V), dtype=torch.int32, device="cuda")
+    parent = torch.empty((64, V), dtype=torch.int32, device="cuda")
+    gr.bfs_multi(g, srcs, out=(depth, parent))
+    m = gr.bfs_multi(g, srcs, out=(depth, parent))[2]
+    d1 = torch.empty(V, dtype=torch.int32, device="cuda")
+    p1 = torch.empty(V, dtype=torch.int32, device="cuda")
+    single_ms = single_teps = 0.0
+    for s in srcs:
+        st = gr.bfs(g, int(s), opts=ob, out=(d1, p1))[2]
+        single_ms += st["device_ms"]
+        single_teps += st["teps_edges"]
+    out["bfs_64_sources_rmat20"] = {
+        "batched_ms": round(m["device_ms"], 3), "batched_gteps": _gteps(m["teps_edges"], m["device_ms"]),
+        "single_source_ms": round(single_ms, 3), "single_source_gteps": _gteps(single_teps, single_ms),
+        "speedup": round(single_ms / m["device_ms"], 3) if m["device_ms"] > 0 else None}
+    del depth, parent
+    g.free()
+    del hg
+    log("# batched bfs done")
+    # 256 small graphs, one union SSSP
+    parts, psrc = gg.small_rmat_batch(256)
+    u, voff = gg.disjoint_union(parts)
+    g = gr.Graph.from_host(ctx, u, symmetric=True)
+    gsrc = (psrc.astype(np.int64) + voff[:-1]).astype(np.int32)
+    ou = autotune.tuned_opts(g, "sssp")
+    gr.sssp(g, gsrc, opts=ou)
+    b = gr.sssp(g, gsrc, opts=ou)[2]
+    g.free()
+    single_ms = single_teps = 0.0
+    for i, p in enumerate(parts):
+        gp = gr.Graph.from_host(ctx, p, symmetric=True)
+        st = gr.sssp(gp, [int(psrc[i])], opts=autotune.tuned_opts(gp, "sssp"))[2]
+        single_ms += st["device_ms"]
+        single_teps += st["teps_edges"]
+        gp.free()
+    out["sssp_256_small_rmat_union"] = {
+        "n_vertices": int(u.n_vertices), "n_edges": int(u.n_edges),
+        "batched_ms": round(b["device_ms"], 3), "batched_gteps": _gteps(b["teps_edges"], b["device_ms"]),
+        "single_graph_ms": round(single_ms, 3), "single_graph_gteps": _gteps(single_teps, single_ms),
+        "speedup": round(single_ms / b["device_ms"], 3) if b["device_ms"] > 0 else None}
+    log("# batched sssp done")
+    return out
 
 
 def main():
@@ -154,6 +239,22 @@ def main():
         paper_ms["bfs"] += gr.bfs(g, s, out=(depth, parent), stream=stream)[2]["device_ms"]
         paper_ms["sssp"] += gr.sssp(g, [s], out=(dist, pred), stream=stream)[2]["device_ms"]
 
+    # the learned selector on the same sources (when trained weights exist)
+    learned = None
+    from paper_1701_01170_amd import selector
+    if not args.no_extras and os.path.exists(selector.WEIGHTS):
+        ctx.set_policy(np.load(selector.WEIGHTS))
+        ol = gr.default_opts(policy=gr.POLICY_LEARNED)
+        lm = {"bfs": 0.0, "sssp": 0.0}
+        for i in range(args.steps):
+            s = int(srcs[args.warmup + i])
+            lm["bfs"] += gr.bfs(g, s, opts=ol, out=(depth, parent), stream=stream)[2]["device_ms"]
+            lm["sssp"] += gr.sssp(g, [s], opts=ol, out=(dist, pred), stream=stream)[2]["device_ms"]
+        ctx.set_policy(None)
+        learned = {"bfs_ms": round(lm["bfs"] / args.steps, 4), "sssp_ms": round(lm["sssp"] / args.steps, 4),
+                   "bfs_gteps_device": _gteps(bfs_teps, lm["bfs"]),
+                   "sssp_gteps_device": _gteps(sssp_teps, lm["sssp"])}
+
     dom = max(per_kernel, key=lambda k: per_kernel[k][1])
     launches, sum_us, sum_bytes = per_kernel[dom]
     achieved = sum_bytes / (sum_us * 1e-6) / 1e9 if sum_us > 0 else None
@@ -209,6 +310,11 @@ def main():
         },
         "cpu_baseline": None,
     }
+
+    out["breakdown"]["learned_selector"] = learned
+    if not args.no_extras:
+        out["breakdown"].update(extras(gr, gg, ctx, torch,
+                                       lambda m: print(m, file=sys.stderr, flush=True)))
 
     if not args.no_cpu_baseline:
         import oracle

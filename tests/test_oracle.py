@@ -377,3 +377,27 @@ def test_level_profile_sums(rmat14):
     assert sum(x["m_f"] for x in prof) == oracle.teps_edges(g.row_offsets, d >= 0)
     for x in prof:
         assert x["n_u"] + sum(y["n_f"] for y in prof if y["level"] <= x["level"]) == g.n_vertices
+
+
+def test_multi_source_on_disjoint_union_is_per_part():
+    """Parts of a block-diagonal union share no edge, so a multi-source run
+    with one source per part must reproduce each part's single-source run
+    (shifted by the part's vertex offset); this pins the multi-source seeding
+    and the source exclusion of the predecessor pass."""
+    parts, srcs = gg.small_rmat_batch(6, scale_lo=3, scale_hi=7, seed=5)
+    u, voff = gg.disjoint_union(parts)
+    gsrc = [int(s + voff[i]) for i, s in enumerate(srcs)]
+    dist, pred = oracle.sssp(u.row_offsets, u.col_indices, u.weights, gsrc)
+    depth_m = oracle.bfs_multi(u.row_offsets, u.col_indices, gsrc)[0]
+    for i, p in enumerate(parts):
+        ed, ep = oracle.sssp(p.row_offsets, p.col_indices, p.weights, [int(srcs[i])])
+        a, b = voff[i], voff[i + 1]
+        assert (dist[a:b] == ed).all()
+        assert (pred[a:b] == np.where(ep >= 0, ep + a, -1)).all()
+        bd, _ = oracle.bfs(p.row_offsets, p.col_indices, int(srcs[i]))
+        # hop counts bound weighted distances from both sides (weights in 1..64)
+        reach = bd >= 0
+        assert ((ed != U32MAX) == reach).all()
+        assert (ed[reach] >= bd[reach]).all() and (ed[reach] <= 64 * bd[reach]).all()
+        assert (depth_m[i][a:b] == bd).all()
+        assert (depth_m[i][:a] == -1).all() and (depth_m[i][b:] == -1).all()
