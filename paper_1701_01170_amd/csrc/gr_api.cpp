@@ -413,6 +413,8 @@ struct DlPlan {
   bool on = false;
   int64_t max_m = 0;
   double do_a = -1.0;   // device push -> pull test (< 0: none)
+  const float* mlp = nullptr;  // device network test (learned policy with pull allowed)
+  int allowed = 0x3;
   int len = kDlFirstLen;
   int blocks = 256;
   int64_t* log = nullptr;
@@ -422,9 +424,11 @@ gr_status dl_plan(gr_ctx* ctx, const gr_opts& o, bool pull_ok, bool learned, boo
                   DlPlan* d) {
   const bool heuristic = o.policy == GR_POLICY_HEURISTIC ||
                          (o.policy == GR_POLICY_LEARNED && !learned);
-  d->on = o.device_max_edges >= 0 && (heuristic || o.policy == GR_POLICY_FIXED);
+  d->on = o.device_max_edges >= 0 && (heuristic || learned || o.policy == GR_POLICY_FIXED);
   d->max_m = o.device_max_edges > 0 ? o.device_max_edges : kDlDefaultMaxEdges;
   d->do_a = heuristic && pull_ok ? (double)o.do_a : -1.0;
+  d->mlp = learned && pull_ok ? static_cast<const float*>(ctx->pool[S_MLP].ptr) : nullptr;
+  d->allowed = pull_ok ? 0xF : 0x3;
   d->len = kDlFirstLen;
   d->blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
   d->log = nullptr;
@@ -550,7 +554,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, dl.do_a,
-                        dl.log, ctrl};
+                        dl.mlp, dl.allowed, V, dl.log, ctrl};
         GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, level + i + 1, dl.blocks, st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
@@ -576,6 +580,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         have_unv = false;
         GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                      &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+        if (learned)
+          GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V - visited_n, E - visited_m, 0, allowed, st));
         GR_TRY(read_ctrl(ctx, ctrl, st));
         if (tracing) {
           int64_t vn = vn0, vm = vm0;
@@ -781,7 +787,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
-                        dl.log, ctrl};
+                        nullptr, 0x3, V, dl.log, ctrl};
         GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, it + i + 1, dl.blocks, st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
@@ -803,6 +809,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         it += k;
         GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                      &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+        if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
         GR_TRY(read_ctrl(ctx, ctrl, st));
         if (tracing) {
           for (int i = 0; i < k; ++i) {

@@ -81,6 +81,7 @@ struct Ctrl {
   int32_t dl_levels;        // levels of the current block that ran
   int32_t dl_stop;          // a level of the block declined to run
   int64_t dl_m[3];          // degree sum of the frontier held in queue k
+  int64_t dl_maxd[3];       // largest degree in the frontier held in queue k
   int64_t dl_vm[2];         // degree sum of the vertices reached before the current frontier
   int64_t dl_vn[2];         // number of vertices reached before the current frontier
 };
@@ -229,6 +230,9 @@ struct DlArgs {
   int64_t max_n, max_m;       // run only while n_f <= max_n and m_f <= max_m
   int64_t E;                  // for the push -> pull test
   double do_a;                // push -> pull when m_f > m_u * do_a (< 0: never)
+  const float* mlp;           // selector network: run only while it picks a push action (nullable)
+  int32_t allowed;            // actions the network may pick (bit a = gr_action a)
+  int64_t V;
   int64_t* log;               // [kDlMaxLevels][3]
   Ctrl* ctrl;
 };

@@ -37,14 +37,16 @@ constexpr int kLbCap = 2048;  // frontier segments staged in LDS per pass
 
 // Process up to B edges per lane: ok[r] marks a real edge (u[r], pay[r], ce[r]).
 // With DEG, the degrees of the appended vertices are also summed into
-// *deg_sum (one atomic per wavefront).  All 64 lanes must take part.
+// *deg_sum and maximised into *deg_max (one atomic each per wavefront).  All
+// 64 lanes must take part.
 template <class F, int B, bool DEG = false>
 __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict__ C, bool (&ok)[B],
                                            const int32_t (&u)[B], const typename F::pay_t (&pay)[B],
                                            const int32_t (&ce)[B], int32_t* __restrict__ out_q,
                                            uint32_t* __restrict__ out_count,
                                            const int32_t* __restrict__ R = nullptr,
-                                           unsigned long long* deg_sum = nullptr) {
+                                           unsigned long long* deg_sum = nullptr,
+                                           unsigned long long* deg_max = nullptr) {
   int32_t v[B];
   uint32_t ev[B];
 #pragma unroll
@@ -71,12 +73,18 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
   for (int r = 0; r < B; ++r)
     if (ok[r]) out_q[base++] = v[r];
   if (DEG) {
-    unsigned long long ds = 0;
+    unsigned long long ds = 0, dm = 0;
 #pragma unroll
     for (int r = 0; r < B; ++r)
-      if (ok[r]) ds += (unsigned long long)(R[v[r] + 1] - R[v[r]]);
+      if (ok[r]) {
+        const unsigned long long d = (unsigned long long)(R[v[r] + 1] - R[v[r]]);
+        ds += d;
+        dm = d > dm ? d : dm;
+      }
     ds = wave_sum(ds);
+    dm = wave_max(dm);
     if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
+    if (lane() == 0 && dm) atomicMax(deg_max, dm);
   }
 }
 

@@ -7,7 +7,9 @@
 // kernels, and so takes the same decision: the level runs only if no earlier
 // level of the block declined, the frontier is non-empty, it fits the LDS
 // staging (kDlMaxN vertices) and the caller's edge bound, and (BFS) the
-// direction heuristic of Sec. 5.1 would still push.  A declining level sets
+// direction heuristic of Sec. 5.1 would still push (or, under the learned
+// policy, the selector network still picks a push action: every workgroup
+// evaluates it on the same features).  A declining level sets
 // dl_stop, so the rest of the block does nothing.
 //
 // A running level is output-balanced like LB (Sec. 5.1): each workgroup stages
@@ -17,6 +19,7 @@
 #pragma once
 
 #include "k_advance.h"
+#include "k_mlp.h"
 
 namespace gr {
 
@@ -41,6 +44,13 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   const int64_t vn = ctrl->dl_vn[a.step & 1];
   bool run = n_f > 0 && n_f <= a.max_n && n_f <= kDlMaxN && m_f <= a.max_m;
   if (run && a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a) run = false;
+  if (run && a.mlp) {
+    __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
+    if (threadIdx.x == 0)
+      mlp_features(s_x, n_f, m_f, a.V - vn - n_f, a.E - vm - m_f, ctrl->dl_maxd[a.cur], a.V, a.E, 0);
+    const int best = mlp_argmin(a.mlp, s_x, s_h1, s_h2, s_y, a.allowed);
+    run = best == GR_PUSH_TWC || best == GR_PUSH_LB;
+  }
   if (!run) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->dl_stop = 1;
     return;
@@ -52,6 +62,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
     ctrl->dl_levels = a.step + 1;
     ctrl->q_count[prev] = 0;
     ctrl->dl_m[prev] = 0;
+    ctrl->dl_maxd[prev] = 0;
     ctrl->dl_vm[(a.step + 1) & 1] = vm + m_f;
     ctrl->dl_vn[(a.step + 1) & 1] = vn + n_f;
   }
@@ -122,7 +133,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
     edge_batch<F, B, true>(f, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
-                           reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]));
+                           reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]),
+                           reinterpret_cast<unsigned long long*>(&ctrl->dl_maxd[next]));
   }
 }
 

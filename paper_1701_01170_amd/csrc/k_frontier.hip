@@ -175,6 +175,8 @@ __global__ void k_dl_begin(Ctrl* __restrict__ ctrl, int cur, int sp, int64_t vm,
   ctrl->dl_stop = 0;
   ctrl->dl_m[cur] = ctrl->m_f[sp];
   ctrl->dl_m[(cur + 1) % 3] = 0;
+  ctrl->dl_maxd[cur] = ctrl->max_deg[sp];
+  ctrl->dl_maxd[(cur + 1) % 3] = 0;
   ctrl->q_count[(cur + 1) % 3] = 0;
   ctrl->dl_vm[0] = vm;
   ctrl->dl_vn[0] = vn;

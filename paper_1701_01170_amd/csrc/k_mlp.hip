@@ -1,8 +1,6 @@
 // Strategy-selector network: 8 inputs -> 32 -> 32 -> 4 outputs, ReLU on the
-// hidden layers, fp32.  Parameters are one flat array (row-major):
-//   W1[32][8], b1[32], W2[32][32], b2[32], W3[4][32], b3[4]   (1476 floats).
-// Outputs are predicted log2 step times of the four advance actions; the
-// selector takes the argmin over the actions the traversal allows.
+// hidden layers, fp32 (parameter layout in k_mlp.h).  The selector takes the
+// argmin of the predicted step times over the actions the traversal allows.
 //
 // Kernels: batched forward; masked squared-error loss with its gradient
 // (per-tile partial sums, then a fixed-order reduction: deterministic); Adam;
@@ -10,15 +8,12 @@
 // builds the eight features from the frontier statistics on the device.
 #include "gr_internal.h"
 #include "k_common.h"
+#include "k_mlp.h"
 
 namespace gr {
 
 namespace {
 
-constexpr int kIn = 8, kH = 32, kOut = 4;
-constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH,
-              oW3 = oB2 + kH, oB3 = oW3 + kOut * kH, kNP = oB3 + kOut;
-static_assert(kNP == GR_MLP_N_PARAMS, "parameter count");
 constexpr int kTile = 64;  // samples per workgroup in the gradient kernel
 
 __device__ __forceinline__ void load_params(const float* __restrict__ params, float* s_p) {
@@ -197,10 +192,6 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-__device__ __forceinline__ float feat(double x) {
-  return (float)(log2(1.0 + (x > 0 ? x : 0.0)) / 32.0);
-}
-
 // One wavefront: features of the current iteration (the frontier statistics
 // of slot `sp` plus host-known totals), forward pass, argmin over the allowed
 // actions (bit a of allowed) -> ctrl->action.  n_u_before / m_u_before are the
@@ -210,45 +201,14 @@ __global__ __launch_bounds__(64) void k_mlp_select(const float* __restrict__ par
                                                    int64_t E, int64_t n_u_before,
                                                    int64_t m_u_before, int prev_pull, int allowed) {
   __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
-  const int t = threadIdx.x;
-  if (t == 0) {
+  if (threadIdx.x == 0) {
     const int64_t n_f = ctrl->n_f[sp], m_f = ctrl->m_f[sp];
     const int64_t n_u = n_u_before > 0 ? n_u_before - n_f : 0;
     const int64_t m_u = m_u_before > 0 ? m_u_before - m_f : 0;
-    s_x[0] = feat((double)n_f);
-    s_x[1] = feat((double)m_f);
-    s_x[2] = feat((double)n_u);
-    s_x[3] = feat((double)m_u);
-    s_x[4] = feat((double)ctrl->max_deg[sp]);
-    s_x[5] = feat((double)V);
-    s_x[6] = feat((double)E);
-    s_x[7] = feat(prev_pull ? 0.0 : (double)V);
+    mlp_features(s_x, n_f, m_f, n_u, m_u, ctrl->max_deg[sp], V, E, prev_pull);
   }
-  __syncthreads();
-  if (t < kH) {
-    float z = params[oB1 + t];
-    for (int i = 0; i < kIn; ++i) z += params[oW1 + t * kIn + i] * s_x[i];
-    s_h1[t] = z > 0.f ? z : 0.f;
-  }
-  __syncthreads();
-  if (t < kH) {
-    float z = params[oB2 + t];
-    for (int i = 0; i < kH; ++i) z += params[oW2 + t * kH + i] * s_h1[i];
-    s_h2[t] = z > 0.f ? z : 0.f;
-  }
-  __syncthreads();
-  if (t < kOut) {
-    float z = params[oB3 + t];
-    for (int j = 0; j < kH; ++j) z += params[oW3 + t * kH + j] * s_h2[j];
-    s_y[t] = z;
-  }
-  __syncthreads();
-  if (t == 0) {
-    int best = -1;
-    for (int a = 0; a < kOut; ++a)
-      if (((allowed >> a) & 1) && (best < 0 || s_y[a] < s_y[best])) best = a;
-    ctrl->action = best;
-  }
+  const int best = mlp_argmin(params, s_x, s_h1, s_h2, s_y, allowed);
+  if (threadIdx.x == 0) ctrl->action = best;
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }

@@ -73,9 +73,12 @@ def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 2, sssp
         t0 = time.time()
         g = Graph.from_host(ctx, hg, symmetric=True)
         srcs = gg.sources(hg, n_sources, seed=3000)
-        pols = [dict(policy=POLICY_FIXED, fixed_action=a, lb_light_threshold=0) for a in range(4)]
-        pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r, lb_light_threshold=0)
-                 for r in range(random_runs)]
+        # one host round trip per level (no device-predicated blocks), so that
+        # every record times exactly one step of the action it names
+        pols = [dict(policy=POLICY_FIXED, fixed_action=a, lb_light_threshold=0, device_max_edges=-1)
+                for a in range(4)]
+        pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r, lb_light_threshold=0,
+                      device_max_edges=-1) for r in range(random_runs)]
         for s in srcs:
             for kw in pols:
                 o = default_opts(trace=buf, trace_capacity=cap, **kw)
@@ -126,6 +129,7 @@ def evaluate(ctx: Context, graphs, params, n_sources: int = 5, log=print) -> lis
                 res = {}
                 cfgs = {"heuristic_paper_knobs": default_opts(),
                         "heuristic_tuned_knobs": autotune.tuned_opts(g, kind),
+                        "heuristic_paper_knobs_host_loop": default_opts(device_max_edges=-1),
                         "learned": default_opts(policy=POLICY_LEARNED, lb_light_threshold=0)}
                 for label, o in cfgs.items():
                     times, teps = [], 0

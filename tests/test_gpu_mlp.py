@@ -105,8 +105,13 @@ def test_learned_policy_is_exact_and_takes_argmin(ctx, rmat14):
                 x = np.array(list(t.features), dtype=np.float64)[None]
                 y, _ = oracle.mlp_forward(P, x)
                 y = y[0]
-                # the device's choice is within fp32 rounding of the argmin
-                assert y[t.action] <= y.min() + 1e-3, (t.level, t.action, y)
+                if t.kernel == 6:
+                    # a device-predicated level: the network (evaluated in the
+                    # level kernel) picked one of the push actions
+                    assert min(y[0], y[1]) <= y.min() + 1e-3, (t.level, y)
+                else:
+                    # the device's choice is within fp32 rounding of the argmin
+                    assert y[t.action] <= y.min() + 1e-3, (t.level, t.action, y)
             dist, pred, _ = gr.sssp(g, [int(s)], opts=gr.default_opts(policy=gr.POLICY_LEARNED))
             edist, epred = oracle.sssp(rmat14.row_offsets, rmat14.col_indices, rmat14.weights, [int(s)])
             np.testing.assert_array_equal(dist.cpu().numpy().view(np.uint32), edist)
