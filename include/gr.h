@@ -215,7 +215,9 @@ gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, in
  * processed 64 per pass, one bit per source in per-vertex 64-bit masks.
  * depth: device int32[k][V] (required), parent: device int32[k][V] or NULL,
  * row s holding the single-source result for sources[s].  Needs GR_SYMMETRIC
- * (parents are found by pulling over in-edges). */
+ * (parents are found by pulling over in-edges).  A level pulls over every
+ * vertex when the vertices active in it carry more than E * opts.do_a edges,
+ * else it pushes from them with the opts' LB / TWC knobs. */
 gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);

@@ -12,6 +12,10 @@ Search (coordinate descent from the paper's defaults):
   2. lb_chunk in {2048, 4096, 8192, 16384}
   3. lb_min_avg_degree in {0 (always LB), 5 (paper), inf (always TWC)}
   4. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8}
+  5. BFS / SSSP: device_max_edges in {off, 2^16, 2^18, 2^20} (edge bound of
+     the device-predicated level blocks)
+Batched BFS ("bfs_multi", 64 sources per call) searches 1, 2 and its
+push -> pull switch do_a in {1/4 .. 1/64}.
 
 The tuned values only change the time taken; results are identical for every
 setting (the GPU tests check every strategy against the oracle).
@@ -28,13 +32,15 @@ import time
 
 import numpy as np
 
-from . import Graph, default_opts, bfs, sssp  # noqa: F401
+from . import Graph, default_opts, bfs, bfs_multi, sssp  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 ARCH = "gfx950"
 
-KNOBS = ("lb_light_threshold", "lb_chunk", "lb_min_avg_degree", "do_a", "do_b")
+KNOBS = ("lb_light_threshold", "lb_chunk", "lb_min_avg_degree", "do_a", "do_b", "device_max_edges")
+DEVICE_MAX_EDGES = [-1, 1 << 16, 1 << 18, 1 << 20]
+MULTI_DO_A = [1 / 4, 1 / 8, 1 / 16, 1 / 32, 1 / 64]
 DO_A = [1 / 2, 1 / 4, 1 / 8, 1 / 14, 1 / 32, 1 / 64, 1 / 256]
 DO_B = [1 / 576, 1 / 64, 1 / 8]
 
@@ -85,6 +91,14 @@ def _time(g: Graph, kind: str, sources, knobs: dict, reps: int = 1) -> float:
     import torch
     total = 0.0
     o = default_opts(**knobs)
+    if kind == "bfs_multi":
+        srcs = np.asarray(sources, dtype=np.int32)
+        best = float("inf")
+        for _ in range(reps + 1):
+            _, _, st = bfs_multi(g, srcs, opts=o)
+            best = min(best, st["device_ms"])
+        torch.cuda.synchronize()
+        return best
     for s in sources:
         best = float("inf")
         for _ in range(reps + 1):
@@ -117,7 +131,11 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
 
     try_set("lb_light_threshold", [0, 1024, 4096])
     try_set("lb_chunk", [2048, 4096, 8192, 16384])
+    if kind == "bfs_multi":
+        try_set("do_a", MULTI_DO_A)
+        return best, best_ms, base_ms
     try_set("lb_min_avg_degree", [0.0, 5.0, 1e9])
+    try_set("device_max_edges", DEVICE_MAX_EDGES)
     if kind == "bfs":
         for a in DO_A:
             for b in DO_B:
@@ -161,8 +179,9 @@ def main():
         g = Graph.from_host(ctx, hg, symmetric=True)
         srcs = gg.sources(hg, args.sources, seed=2000)  # held-out from the bench's sources
         for kind in args.kinds.split(","):
-            knobs, ms, base = tune(g, kind, srcs, log=lambda m: print(f"{name} {m}", flush=True))
-            store(g, kind, knobs, ms, base, name, srcs)
+            ks = gg.sources(hg, 64, seed=2100) if kind == "bfs_multi" else srcs
+            knobs, ms, base = tune(g, kind, ks, log=lambda m: print(f"{name} {m}", flush=True))
+            store(g, kind, knobs, ms, base, name, ks)
             print(f"{name} [{kind}] best {ms:.3f} ms (paper defaults {base:.3f} ms): {knobs}", flush=True)
         g.free()
 

@@ -873,13 +873,6 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
 // multi-source BFS
 // ============================================================================
 
-namespace {
-// The multi-source expansion pulls (every vertex with unreached source bits
-// ORs its neighbours' frontier masks) once the active vertices carry at least
-// E / kMsPullDivisor edges, and pushes from the active vertices before that.
-constexpr int64_t kMsPullDivisor = 16;
-}  // namespace
-
 extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t* sources,
                                   int32_t k, int32_t* depth, int32_t* parent, gr_opts* opts_in,
                                   void* stream, gr_run_stats* stats) {
@@ -953,7 +946,9 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
     GR_TRY(read_ctrl(ctx, ctrl, st));  // also keeps the host source vectors alive for the copies
     int64_t n_a = hc->n_f[sp], m_a = hc->m_f[sp];
     while (n_a > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
-      const bool pull = m_a * kMsPullDivisor >= E;
+      // pull (every vertex with unreached source bits ORs its neighbours'
+      // frontier masks) once the active vertices carry more than E * do_a edges
+      const bool pull = (double)m_a > (double)E * (double)opts.do_a;
       if (pull) {
         GR_HIP(launch_ms_pull(V, g->R, g->C, front[fc], visit, full, next, q[(cur + 1) % 3],
                               &ctrl->q_count[(cur + 1) % 3], st));

@@ -66,8 +66,9 @@ def test_multi_er_policies(ctx):
     hg = gg.erdos_renyi(20000, 12, seed=9)
     g = gr.Graph.from_host(ctx, hg)
     srcs = gg.sources(hg, 64, seed=3)
+    # do_a = 0: every level pulls; do_a huge: every level pushes
     for kw in [dict(), dict(lb_light_threshold=0), dict(lb_min_avg_degree=1e9),
-               dict(lb_light_threshold=1 << 30)]:
+               dict(lb_light_threshold=1 << 30), dict(do_a=0.0), dict(do_a=1e9)]:
         d, p, _ = gr.bfs_multi(g, srcs, opts=gr.default_opts(**kw))
         check_rows(hg, srcs, d, p)
 
