@@ -93,7 +93,8 @@ typedef struct gr_level_trace {
   float kernel_us;     /* device time of the advance kernel alone (event-timed) */
   int32_t kernel;      /* advance kernel: 0 TWC, 1 LB_LIGHT, 2 LB, 3 LB with byte-mark filter,
                           4 pull TWC, 5 pull groups, 6 device-predicated step (step_us and
-                          kernel_us are then the block's time divided by its levels) */
+                          kernel_us are then the block's time divided by its levels),
+                          7 SSSP priority-queue refill (far pile split) */
   int64_t n_next;      /* size of the output frontier */
 } gr_level_trace;
 
@@ -116,7 +117,12 @@ typedef struct gr_opts {
                                 of device-predicated steps with one host round trip per block
                                 (heuristic and fixed push policies only).  0: default 262144;
                                 < 0: off (one host round trip per level); at most 1 << 24 */
-  int32_t reserved[6];
+  int32_t sssp_delta;        /* SSSP two-level priority queue (Sec. 5.1, priority queue): improved
+                                vertices with dist < T form the next frontier, the rest a far pile;
+                                when the frontier empties T grows by sssp_delta and the far pile is
+                                split.  0: off (every improved vertex is in the next frontier).
+                                Results are identical either way. */
+  int32_t reserved[5];
 } gr_opts;
 
 typedef struct gr_run_stats {

@@ -57,7 +57,8 @@ class Opts(ctypes.Structure):
                 ("lb_min_avg_degree", ctypes.c_float), ("max_iterations", ctypes.c_int32),
                 ("lb_chunk", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
                 ("trace", ctypes.POINTER(LevelTrace)), ("trace_count", ctypes.c_int32),
-                ("device_max_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("device_max_edges", ctypes.c_int32), ("sssp_delta", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class RunStats(ctypes.Structure):

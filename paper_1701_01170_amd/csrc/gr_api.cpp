@@ -364,6 +364,7 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->trace is NULL with a positive capacity");
   if (opts->device_max_edges > (1 << 24))
     return fail(GR_EINVAL, "opts->device_max_edges must be at most 1 << 24");
+  if (opts->sssp_delta < 0) return fail(GR_EINVAL, "opts->sssp_delta must be >= 0");
   *local = *opts;
   return GR_OK;
 }
@@ -408,6 +409,7 @@ gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int 
 constexpr int kDlFirstLen = 4;              // levels in the first block; doubles while blocks run whole
 constexpr int64_t kDlDefaultMaxEdges = 1 << 18;
 constexpr int kTraceKernelDstep = 6;
+constexpr int kTraceKernelRefill = 7;
 
 struct DlPlan {
   bool on = false;
@@ -549,7 +551,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       int kmax = dl.len;
       if (opts.max_iterations > 0) kmax = (int)std::min<int64_t>(kmax, opts.max_iterations - level);
       const int64_t vm0 = visited_m - m_f, vn0 = visited_n - n_f;
-      GR_HIP(launch_dl_begin(ctrl, cur, sp, vm0, vn0, st));
+      GR_HIP(launch_dl_begin(ctrl, cur, sp, vm0, vn0, 0u, 0, 0, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
@@ -740,6 +742,16 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
   GR_TRY(pool_typed(ctx, S_TMP0, n_src, &src_dev));
+  // two-level priority queue (near / far piles), when sssp_delta > 0
+  const bool use_pq = opts.sssp_delta > 0;
+  PqState pq{};
+  if (use_pq) {
+    pq.T = (uint32_t)opts.sssp_delta;
+    pq.delta = (uint32_t)opts.sssp_delta;
+    pq.V = V;
+    GR_TRY(pool_typed(ctx, S_FAR, 3 * V, &pq.far_base));
+    GR_TRY(pool_typed(ctx, S_FAR_TAGS, V, &pq.far_tag));
+  }
   Ctrl* hc = ctx->host_ctrl;
   int32_t* q[3] = {qA, qB, qC};
 
@@ -747,7 +759,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
   GR_HIP(hipStreamSynchronize(st));  // the host vector must outlive the copies
   GR_HIP(hipEventRecord(ctx->ev_start, st));
-  GR_HIP(launch_sssp_init(keys, tags, V, ctrl, st));
+  GR_HIP(launch_sssp_init(keys, tags, use_pq ? pq.far_tag : nullptr, V, ctrl, st));
   GR_HIP(launch_sssp_seed(src_dev, n_src, keys, tags, ctrl, st));
   int cur = 0, sp = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
@@ -763,13 +775,23 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   lf.V = V;
   lf.E = E;
   int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], max_deg = hc->max_deg[sp];
+  int64_t far_n = 0;
   int it = 0;
   int64_t inspected = 0;
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
   GR_TRY(dl_plan(ctx, opts, /*pull_ok=*/false, learned, tracing, &dl));
-  while (n_f > 0 && (opts.max_iterations <= 0 || it < opts.max_iterations)) {
+  // after a step that produced the frontier in q[cur]: statistics, selector, read-back
+  auto next_frontier = [&]() -> gr_status {
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                 &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+    if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
+    GR_TRY(read_ctrl(ctx, ctrl, st));
+    if (use_pq) far_n = hc->far_count[pq.fc];
+    return GR_OK;
+  };
+  while ((n_f > 0 || far_n > 0) && (opts.max_iterations <= 0 || it < opts.max_iterations)) {
     lf.level = it;
     lf.n_f = n_f;
     lf.m_f = m_f;
@@ -779,16 +801,18 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     lf.prev_pull = 0;
     const int action = sel.decide(lf, learned ? hc->action : -1);
     if (dl.on && n_f <= kDlMaxN && m_f <= dl.max_m) {
-      // A block of device-predicated relaxation rounds (Alg. 1 iterations).
+      // A block of device-predicated relaxation rounds (Alg. 1 iterations;
+      // with the priority queue also its refill steps).
       int kmax = dl.len;
       if (opts.max_iterations > 0) kmax = std::min(kmax, opts.max_iterations - it);
-      GR_HIP(launch_dl_begin(ctrl, cur, sp, 0, 0, st));
+      GR_HIP(launch_dl_begin(ctrl, cur, sp, 0, 0, pq.T, pq.epoch, pq.fc, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
                         nullptr, 0x3, V, dl.log, ctrl};
-        GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, it + i + 1, dl.blocks, st));
+        if (use_pq) GR_HIP(launch_sssp_pq_dstep(da, g->W, keys, tags, it + i + 1, pq, dl.blocks, st));
+        else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, it + i + 1, dl.blocks, st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
       GR_TRY(read_ctrl(ctx, ctrl, st));
@@ -804,13 +828,15 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
         rs.action_count[action] += k;
         inspected += hc->dl_vm[k & 1];
+        if (use_pq) {
+          pq.T = hc->pq_T[k & 1];
+          pq.epoch = hc->pq_epoch[k & 1];
+          pq.fc = hc->pq_fc[k & 1];
+        }
         cur = (cur + k) % 3;
         sp ^= 1;
         it += k;
-        GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                     &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-        if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
-        GR_TRY(read_ctrl(ctx, ctrl, st));
+        GR_TRY(next_frontier());
         if (tracing) {
           for (int i = 0; i < k; ++i) {
             LevelFeatures li = lf;
@@ -830,25 +856,43 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       }
     }
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
-    const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
-    if (mode == 2)
-      GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
-                                     chunks, chunk, st));
-    if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-    GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W, keys,
-                             tags, it + 1, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], chunk, st));
-    if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+    int kernel = kTraceKernelRefill;
+    if (n_f == 0) {
+      // priority queue: the near frontier ran dry, raise the threshold and
+      // split the far pile
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
+      GR_HIP(launch_sssp_pq_refill(keys, pq, ctrl, far_n, q[(cur + 1) % 3],
+                                   &ctrl->q_count[(cur + 1) % 3], st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+      const uint64_t t1 = (uint64_t)pq.T + pq.delta;
+      pq.T = t1 >= 0xffffffffull ? 0xffffffffu : (uint32_t)t1;
+      pq.epoch += 1;
+      pq.fc = (pq.fc + 1) % 3;
+    } else {
+      const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
+      kernel = mode;
+      if (mode == 2)
+        GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
+                                       chunks, chunk, st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
+      if (use_pq)
+        GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
+                                    g->W, keys, tags, it + 1, pq, ctrl, q[(cur + 1) % 3],
+                                    &ctrl->q_count[(cur + 1) % 3], chunk, st));
+      else
+        GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W,
+                                 keys, tags, it + 1, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
+                                 chunk, st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+      inspected += m_f;
+      rs.action_count[action]++;
+    }
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
-    inspected += m_f;
-    rs.action_count[action]++;
     cur = (cur + 1) % 3;
     sp ^= 1;
     ++it;
-    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                 &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-    if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
-    GR_TRY(read_ctrl(ctx, ctrl, st));
-    if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, mode, hc->n_f[sp]));
+    GR_TRY(next_frontier());
+    if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
     max_deg = hc->max_deg[sp];

@@ -43,6 +43,8 @@ enum Slot : int {
   S_Q_B,           // vertex frontier queue (second)
   S_Q_C,           // vertex frontier queue (third; device-predicated levels rotate three)
   S_DLOG,          // per-level log of a device-predicated block (n_f, m_f, max degree)
+  S_FAR,           // SSSP far piles: three rotating int32[V]
+  S_FAR_TAGS,      // SSSP far-pile generation per vertex
   S_U_A,           // unvisited frontier (ping)
   S_U_B,           // unvisited frontier (pong)
   S_OFFSETS,       // exclusive scan of frontier degrees [n_f + 1]
@@ -84,6 +86,13 @@ struct Ctrl {
   int64_t dl_maxd[3];       // largest degree in the frontier held in queue k
   int64_t dl_vm[2];         // degree sum of the vertices reached before the current frontier
   int64_t dl_vn[2];         // number of vertices reached before the current frontier
+  // SSSP two-level priority queue (near / far piles); [2] slots alternate by
+  // level inside a device-predicated block
+  uint32_t pq_T[2];         // near threshold
+  int32_t pq_epoch[2];      // far-pile generation (dedups far appends)
+  int32_t pq_fc[2];         // far pile in use (of three rotating piles)
+  uint32_t far_count[3];    // far pile lengths
+  uint32_t pad2;
 };
 
 }  // namespace gr
@@ -236,14 +245,39 @@ struct DlArgs {
   int64_t* log;               // [kDlMaxLevels][3]
   Ctrl* ctrl;
 };
-hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, hipStream_t st);
+hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, uint32_t pq_T,
+                           int32_t pq_epoch, int32_t pq_fc, hipStream_t st);
 hipError_t launch_bfs_dstep(const DlArgs& a, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
                             int32_t next_depth, int n_blocks, hipStream_t st);
 hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
                              int32_t* tags, int32_t next_tag, int n_blocks, hipStream_t st);
+// SSSP with the two-level priority queue: improved vertices with dist < T go
+// to the next frontier, the others to far pile `fc` (once per epoch).
+struct PqState {
+  uint32_t T;
+  uint32_t delta;
+  int32_t epoch;
+  int32_t fc;
+  int32_t* far_base;          // three piles of V entries
+  int32_t* far_tag;
+  int64_t V;
+};
+hipError_t launch_sssp_pq_relax(int mode, const int32_t* frontier, const int32_t* offsets,
+                                const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
+                                unsigned long long* keys, int32_t* tags, int32_t next_tag,
+                                const PqState& pq, Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
+                                int chunk, hipStream_t st);
+// Refill: T' = T + delta; far pile fc -> next frontier (T <= dist < T') and
+// far pile (fc + 1) % 3 (dist >= T'); entries with dist < T are stale.
+hipError_t launch_sssp_pq_refill(const unsigned long long* keys, const PqState& pq, Ctrl* ctrl,
+                                 int64_t max_n, int32_t* out_q, uint32_t* out_count, hipStream_t st);
+hipError_t launch_sssp_pq_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
+                                int32_t* tags, int32_t next_tag, const PqState& pq, int n_blocks,
+                                hipStream_t st);
 
 // SSSP
-hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int64_t V, Ctrl* ctrl,
+hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag, int64_t V, Ctrl* ctrl,
                             hipStream_t st);
 hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long long* keys,
                             int32_t* tags, Ctrl* ctrl, hipStream_t st);

@@ -7,6 +7,9 @@
 //   uint32_t edge_value(int64_t e)           per-edge value (e.g. weight)
 //   bool     probe(u, payload, v, ev)        read-only test: may the edge update v?
 //   bool     commit(u, payload, v, ev)       atomic update; true => append v
+//   kFar                                     true for functors whose commit
+//                                            returns 0 / 1 / 2: 2 appends v to
+//                                            a second queue (f.far_q, f.far_count)
 // Edges are handled in batches: every lane first issues all of its
 // column-index loads, then all probe loads, then the atomics of the edges
 // that survive, then one wavefront-aggregated append; independent loads are
@@ -56,11 +59,26 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
   }
 #pragma unroll
   for (int r = 0; r < B; ++r) ok[r] = ok[r] && f.probe(u[r], pay[r], v[r], ev[r]);
-  uint32_t n_app = 0;
+  uint32_t n_app = 0, n_far = 0;
+  bool far[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) {
-    ok[r] = ok[r] && f.commit(u[r], pay[r], v[r], ev[r]);
+    const int c = ok[r] ? (int)f.commit(u[r], pay[r], v[r], ev[r]) : 0;
+    ok[r] = c == 1;
+    far[r] = F::kFar && c == 2;
     n_app += ok[r] ? 1u : 0u;
+    n_far += far[r] ? 1u : 0u;
+  }
+  if constexpr (F::kFar) {
+    if (__ballot(n_far != 0)) {
+      const uint32_t finc = wave_incl_scan(n_far);
+      uint32_t fbase = 0;
+      if (lane() == kWave - 1) fbase = atomicAdd(f.far_count, finc);
+      fbase = __shfl(fbase, kWave - 1) + finc - n_far;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (far[r]) f.far_q[fbase++] = v[r];
+    }
   }
   // wavefront-aggregated append of every lane's survivors
   const uint64_t any = __ballot(n_app != 0);

@@ -38,6 +38,7 @@ struct BfsVisit {
   int32_t p;  // parity: old word = 2w + p
 
   using pay_t = int32_t;
+  static constexpr bool kFar = false;
   __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
@@ -66,6 +67,8 @@ struct BfsVisit {
   __device__ __forceinline__ void frontier_vertex(int32_t u) const {
     atomicOr(&bm[2 * (u >> 5) + 1 - p], 1u << (u & 31));
   }
+  __device__ __forceinline__ BfsVisit prepare(const Ctrl*, int) const { return *this; }
+  __device__ __forceinline__ void advance(Ctrl*, int, bool) const {}
 };
 
 // Push without atomics (for levels that discover many vertices): every edge
@@ -78,6 +81,7 @@ struct BfsMark {
   int32_t p;
 
   using pay_t = int32_t;
+  static constexpr bool kFar = false;
   __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {

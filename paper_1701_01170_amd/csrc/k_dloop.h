@@ -16,6 +16,12 @@
 // the whole frontier in LDS, scans its degrees, and expands one equal slice
 // of the level's edges.  The degrees of appended vertices are summed on the
 // fly, which gives the next level its m_f without a statistics pass.
+//
+// Functors used here also provide prepare(ctrl, step) (the functor of this
+// step, e.g. SSSP's priority-queue threshold read from the control block) and
+// advance(ctrl, step, refill) (the state of the next step, written once).
+// With the SSSP priority queue (kFar), a step whose frontier is empty but
+// whose far pile is not becomes a refill step instead of stopping the block.
 #pragma once
 
 #include "k_advance.h"
@@ -38,6 +44,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   __shared__ int64_t s_max[kAdvBlock / kWave];
   Ctrl* ctrl = a.ctrl;
   if (ctrl->dl_stop) return;
+  const F fs = f.prepare(ctrl, a.step);
   const int64_t n_f = ctrl->q_count[a.cur];
   const int64_t m_f = ctrl->dl_m[a.cur];
   const int64_t vm = ctrl->dl_vm[a.step & 1];
@@ -51,7 +58,9 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
     const int best = mlp_argmin(a.mlp, s_x, s_h1, s_h2, s_y, a.allowed);
     run = best == GR_PUSH_TWC || best == GR_PUSH_LB;
   }
-  if (!run) {
+  bool refill = false;
+  if constexpr (F::kFar) refill = n_f == 0 && fs.far_pending(ctrl);
+  if (!run && !refill) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->dl_stop = 1;
     return;
   }
@@ -65,12 +74,26 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
     ctrl->dl_maxd[prev] = 0;
     ctrl->dl_vm[(a.step + 1) & 1] = vm + m_f;
     ctrl->dl_vn[(a.step + 1) & 1] = vn + n_f;
+    fs.advance(ctrl, a.step, refill);
+    if (refill && a.log) {
+      a.log[3 * a.step + 0] = 0;
+      a.log[3 * a.step + 1] = 0;
+      a.log[3 * a.step + 2] = 0;
+    }
+  }
+  if constexpr (F::kFar) {
+    if (refill) {
+      fs.refill(ctrl, a.q_next, &ctrl->q_count[next], a.R,
+                reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]),
+                reinterpret_cast<unsigned long long*>(&ctrl->dl_maxd[next]));
+      return;
+    }
   }
   const int nf = (int)n_f;
   for (int j = threadIdx.x; j < nf; j += kAdvBlock) s_u[j] = a.q_cur[j];
   __syncthreads();
   for (int j = blockIdx.x * kAdvBlock + threadIdx.x; j < nf; j += gridDim.x * kAdvBlock)
-    f.frontier_vertex(s_u[j]);
+    fs.frontier_vertex(s_u[j]);
   // equal edge slices (at least one row of the workgroup each); workgroups
   // past the last slice have nothing more to do
   const int64_t G = gridDim.x;
@@ -91,7 +114,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
       const int32_t rb = a.R[u];
       d[r] = a.R[u + 1] - rb;
       s_rb[j] = rb;
-      s_pay[j] = f.seg_payload(u);
+      s_pay[j] = fs.seg_payload(u);
       sum += d[r];
       mx = d[r] > mx ? d[r] : mx;
     }
@@ -132,7 +155,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
       pay[r] = s_pay[k];
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
-    edge_batch<F, B, true>(f, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
+    edge_batch<F, B, true>(fs, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
                            reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]),
                            reinterpret_cast<unsigned long long*>(&ctrl->dl_maxd[next]));
   }

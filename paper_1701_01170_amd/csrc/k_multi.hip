@@ -23,6 +23,7 @@ struct MsPush {
   const u64* __restrict__ visit;
   u64* __restrict__ next;
   using pay_t = u64;
+  static constexpr bool kFar = false;
 
   const u64* __restrict__ front;
   __device__ __forceinline__ u64 seg_payload(int32_t u) const { return front[u]; }

@@ -10,6 +10,15 @@
 // relaxes its out-edges at least once with its final distance, hence the final
 // key holds the true distance and the smallest-id predecessor among all tight
 // in-edges.  Unreached vertices keep ~0 (distance UINT32_MAX, predecessor -1).
+//
+// Optional two-level priority queue (Sec. 5.1: the near / far split of the
+// output frontier, a delta-stepping style binning): an improved vertex joins
+// the next frontier only if its distance is below the threshold T; otherwise
+// it goes to a far pile (at most once per far-pile generation).  When the
+// frontier runs dry, T grows by delta and the far pile is split into the new
+// frontier (T <= dist < T + delta), the next far pile (dist >= T + delta) and
+// stale entries (dist < T: already expanded with that distance).  Every vertex
+// is still expanded with its final distance, so results are unchanged.
 #include "k_advance.h"
 #include "k_dloop.h"
 
@@ -24,6 +33,7 @@ struct SsspVisit {
   int32_t next_tag;
 
   using pay_t = int32_t;
+  static constexpr bool kFar = false;
   __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
     return (int32_t)(uint32_t)(keys[u] >> 32);
   }
@@ -42,17 +52,146 @@ struct SsspVisit {
     return atomicExch(&tags[v], next_tag) != next_tag;
   }
   __device__ __forceinline__ void frontier_vertex(int32_t) const {}
+  __device__ __forceinline__ SsspVisit prepare(const Ctrl*, int) const { return *this; }
+  __device__ __forceinline__ void advance(Ctrl*, int, bool) const {}
 };
 
+__device__ __forceinline__ uint32_t pq_next_threshold(uint32_t T, uint32_t delta) {
+  const uint64_t t = (uint64_t)T + delta;
+  return t >= 0xffffffffull ? 0xffffffffu : (uint32_t)t;
+}
+
+// Split far pile fc into the next frontier and far pile (fc + 1) % 3 (see the
+// file comment); grid-stride, every wavefront runs whole iterations.  With
+// deg_sum / deg_max the degrees of the new frontier are accumulated too.
+__device__ __forceinline__ void pq_refill_pass(const unsigned long long* __restrict__ keys,
+                                               uint32_t T, uint32_t delta, int32_t epoch, int32_t fc,
+                                               int32_t* __restrict__ far_base,
+                                               int32_t* __restrict__ far_tag, int64_t V, Ctrl* ctrl,
+                                               int32_t* __restrict__ out_q, uint32_t* out_count,
+                                               const int32_t* __restrict__ R,
+                                               unsigned long long* deg_sum,
+                                               unsigned long long* deg_max) {
+  const uint32_t T1 = pq_next_threshold(T, delta);
+  const int32_t fn = (fc + 1) % 3;
+  const int32_t* __restrict__ in = far_base + (int64_t)fc * V;
+  int32_t* __restrict__ keep_q = far_base + (int64_t)fn * V;
+  const int64_t n = ctrl->far_count[fc];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = i < n ? in[i] : -1;
+    const uint32_t d = v >= 0 ? (uint32_t)(keys[v] >> 32) : 0u;
+    const bool near = v >= 0 && d >= T && d < T1;
+    const bool keep = v >= 0 && d >= T1;
+    if (keep) far_tag[v] = epoch + 1;
+    const uint32_t s1 = wave_append(out_count, near);
+    if (near) out_q[s1] = v;
+    const uint32_t s2 = wave_append(&ctrl->far_count[fn], keep);
+    if (keep) keep_q[s2] = v;
+    if (deg_sum) {
+      const unsigned long long dg = near ? (unsigned long long)(R[v + 1] - R[v]) : 0ull;
+      const unsigned long long ds = wave_sum(dg), dm = wave_max(dg);
+      if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
+      if (lane() == 0 && dm) atomicMax(deg_max, dm);
+    }
+  }
+}
+
+struct SsspPqVisit {
+  const uint32_t* __restrict__ W;
+  unsigned long long* __restrict__ keys;
+  int32_t* __restrict__ tags;
+  int32_t next_tag;
+  uint32_t T;
+  uint32_t delta;
+  int32_t epoch;
+  int32_t fc;
+  int32_t* __restrict__ far_base;
+  int32_t* __restrict__ far_tag;
+  int64_t V;
+  int32_t* __restrict__ far_q;    // far_base + fc * V
+  uint32_t* far_count;            // &ctrl->far_count[fc]
+
+  using pay_t = int32_t;
+  static constexpr bool kFar = true;
+  __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
+    return (int32_t)(uint32_t)(keys[u] >> 32);
+  }
+  __device__ __forceinline__ uint32_t edge_value(int64_t e) const { return W[e]; }
+  __device__ __forceinline__ bool probe(int32_t u, int32_t du, int32_t v, uint32_t w) const {
+    const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
+    if (cand >= 0xffffffffull) return false;
+    const unsigned long long nk = (cand << 32) | (uint32_t)u;
+    return nk < keys[v];
+  }
+  // 1: next frontier, 2: far pile, 0: nothing to append
+  __device__ __forceinline__ int commit(int32_t u, int32_t du, int32_t v, uint32_t w) const {
+    const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
+    const unsigned long long nk = (cand << 32) | (uint32_t)u;
+    const unsigned long long old = atomicMin(&keys[v], nk);
+    if (cand >= (old >> 32)) return 0;
+    if (cand < T) return atomicExch(&tags[v], next_tag) != next_tag ? 1 : 0;
+    return atomicExch(&far_tag[v], epoch) != epoch ? 2 : 0;
+  }
+  __device__ __forceinline__ void frontier_vertex(int32_t) const {}
+  // device-predicated levels read the queue state of their step
+  __device__ __forceinline__ SsspPqVisit prepare(Ctrl* ctrl, int step) const {
+    SsspPqVisit g = *this;
+    const int s = step & 1;
+    g.T = ctrl->pq_T[s];
+    g.epoch = ctrl->pq_epoch[s];
+    g.fc = ctrl->pq_fc[s];
+    g.far_q = far_base + (int64_t)g.fc * V;
+    g.far_count = &ctrl->far_count[g.fc];
+    return g;
+  }
+  __device__ __forceinline__ bool far_pending(const Ctrl* ctrl) const {
+    return ctrl->far_count[fc] > 0;
+  }
+  // queue state of the next step (called once, by one thread)
+  __device__ __forceinline__ void advance(Ctrl* ctrl, int step, bool refill) const {
+    const int s = (step + 1) & 1;
+    if (refill) {
+      ctrl->pq_T[s] = pq_next_threshold(T, delta);
+      ctrl->pq_epoch[s] = epoch + 1;
+      ctrl->pq_fc[s] = (fc + 1) % 3;
+      ctrl->far_count[(fc + 2) % 3] = 0;  // the pile the next refill fills
+    } else {
+      ctrl->pq_T[s] = T;
+      ctrl->pq_epoch[s] = epoch;
+      ctrl->pq_fc[s] = fc;
+    }
+  }
+  __device__ __forceinline__ void refill(Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
+                                         const int32_t* R, unsigned long long* deg_sum,
+                                         unsigned long long* deg_max) const {
+    pq_refill_pass(keys, T, delta, epoch, fc, far_base, far_tag, V, ctrl, out_q, out_count, R,
+                   deg_sum, deg_max);
+  }
+};
+
+__global__ __launch_bounds__(256) void k_sssp_pq_refill(const unsigned long long* __restrict__ keys,
+                                                        PqState pq, Ctrl* __restrict__ ctrl,
+                                                        int32_t* __restrict__ out_q,
+                                                        uint32_t* __restrict__ out_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->far_count[(pq.fc + 2) % 3] = 0;
+  pq_refill_pass(keys, pq.T, pq.delta, pq.epoch, pq.fc, pq.far_base, pq.far_tag, pq.V, ctrl, out_q,
+                 out_count, nullptr, nullptr, nullptr);
+}
+
 __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restrict__ keys,
-                                                   int32_t* __restrict__ tags, int64_t V,
+                                                   int32_t* __restrict__ tags,
+                                                   int32_t* __restrict__ far_tag, int64_t V,
                                                    Ctrl* __restrict__ ctrl) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
     keys[v] = ~0ull;
     tags[v] = -1;
+    if (far_tag) far_tag[v] = -1;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->far_count[0] = ctrl->far_count[1] = ctrl->far_count[2] = 0;
     ctrl->q_count[1] = 0;
     ctrl->q_count[2] = 0;
     ctrl->u_count[0] = 0;
@@ -113,11 +252,11 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
-hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int64_t V, Ctrl* ctrl,
-                            hipStream_t st) {
+hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag, int64_t V,
+                            Ctrl* ctrl, hipStream_t st) {
   unsigned g = blocks_for(V, 256);
   if (g > 4096) g = 4096;
-  k_sssp_init<<<g, 256, 0, st>>>(keys, tags, V, ctrl);
+  k_sssp_init<<<g, 256, 0, st>>>(keys, tags, far_tag, V, ctrl);
   return hipGetLastError();
 }
 
@@ -151,6 +290,41 @@ hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long l
                              int32_t* tags, int32_t next_tag, int n_blocks, hipStream_t st) {
   const SsspVisit f{W, keys, tags, next_tag};
   k_dstep<SsspVisit><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
+  return hipGetLastError();
+}
+
+namespace {
+SsspPqVisit pq_functor(const uint32_t* W, unsigned long long* keys, int32_t* tags, int32_t next_tag,
+                       const PqState& pq, Ctrl* ctrl) {
+  return SsspPqVisit{W, keys, tags, next_tag, pq.T, pq.delta, pq.epoch, pq.fc, pq.far_base,
+                     pq.far_tag, pq.V, pq.far_base + (int64_t)pq.fc * pq.V, &ctrl->far_count[pq.fc]};
+}
+}  // namespace
+
+hipError_t launch_sssp_pq_relax(int mode, const int32_t* frontier, const int32_t* offsets,
+                                const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
+                                unsigned long long* keys, int32_t* tags, int32_t next_tag,
+                                const PqState& pq, Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
+                                int chunk, hipStream_t st) {
+  const SsspPqVisit f = pq_functor(W, keys, tags, next_tag, pq, ctrl);
+  return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
+                       out_count, chunk, st);
+}
+
+hipError_t launch_sssp_pq_refill(const unsigned long long* keys, const PqState& pq, Ctrl* ctrl,
+                                 int64_t max_n, int32_t* out_q, uint32_t* out_count, hipStream_t st) {
+  unsigned g = blocks_for(max_n > 0 ? max_n : 1, 256);
+  if (g > 2048) g = 2048;
+  k_sssp_pq_refill<<<g, 256, 0, st>>>(keys, pq, ctrl, out_q, out_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sssp_pq_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
+                                int32_t* tags, int32_t next_tag, const PqState& pq, int n_blocks,
+                                hipStream_t st) {
+  const SsspPqVisit f = pq_functor(W, keys, tags, next_tag, pq, a.ctrl);
+  k_dstep<SsspPqVisit><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ def test_union_sssp_matches_per_graph_oracle(ctx, n_graphs, lo, hi):
     g = gr.Graph.from_host(ctx, u, symmetric=True)
     gsrc = (srcs.astype(np.int64) + voff[:-1]).astype(np.int32)
     for opts in (gr.default_opts(), gr.default_opts(device_max_edges=-1),
-                 gr.default_opts(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC)):
+                 gr.default_opts(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC),
+                 gr.default_opts(sssp_delta=48)):
         dist, pred, st = gr.sssp(g, gsrc, opts=opts)
         dist = dist.cpu().numpy().view(np.uint32)
         pred = pred.cpu().numpy()

@@ -36,6 +36,18 @@ POLICIES = [
     ("dl_fixed_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC,
                           device_max_edges=1 << 24)),
 ]
+# SSSP also runs with the two-level priority queue: one-distance buckets
+# (delta 1), small and large buckets, refills on the host and inside device
+# blocks, and a threshold beyond every distance
+SSSP_POLICIES = POLICIES + [
+    ("pq1", dict(sssp_delta=1)),
+    ("pq16", dict(sssp_delta=16)),
+    ("pq64_host", dict(sssp_delta=64, device_max_edges=-1)),
+    ("pq64_twc_tiny", dict(sssp_delta=64, policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC,
+                           device_max_edges=64)),
+    ("pq7_light", dict(sssp_delta=7, lb_light_threshold=1 << 30)),
+    ("pq_huge", dict(sssp_delta=1 << 30)),
+]
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +72,7 @@ def run_bfs_all(ctx, hg, sources, symmetric=True, policies=POLICIES):
     g.free()
 
 
-def run_sssp_all(ctx, hg, source_sets, symmetric=True, policies=POLICIES):
+def run_sssp_all(ctx, hg, source_sets, symmetric=True, policies=SSSP_POLICIES):
     g = gr.Graph.from_host(ctx, hg, symmetric=symmetric)
     for srcs in source_sets:
         ed, ep = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, srcs)
@@ -85,7 +97,7 @@ def test_golden(ctx, name):
             np.testing.assert_array_equal(np_of(d), case["depth"], err_msg=pname)
             np.testing.assert_array_equal(np_of(p), case["parent"], err_msg=pname)
     for case in fx["sssp"]:
-        for pname, kw in POLICIES:
+        for pname, kw in SSSP_POLICIES:
             d, p, _ = gr.sssp(g, [case["source"]], opts=gr.default_opts(**kw))
             np.testing.assert_array_equal(np_of(d).view(np.uint32).astype(np.int64), case["dist"],
                                           err_msg=pname)
@@ -266,7 +278,8 @@ def test_device_blocks_respect_max_iterations(ctx, max_it):
     d, _, st = gr.bfs(g, 0, opts=gr.default_opts(max_iterations=max_it))
     np.testing.assert_array_equal(np_of(d), np.where(ed <= max_it, ed, -1))
     assert st["iterations"] == min(max_it, int(ed.max()) + 1)
-    dist, _, st = gr.sssp(g, [0], opts=gr.default_opts())
     edist, _ = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, [0])
-    np.testing.assert_array_equal(np_of(dist).view(np.uint32), edist)
+    for kw in (dict(), dict(sssp_delta=32), dict(sssp_delta=3, device_max_edges=-1)):
+        dist, _, st = gr.sssp(g, [0], opts=gr.default_opts(**kw))
+        np.testing.assert_array_equal(np_of(dist).view(np.uint32), edist, err_msg=str(kw))
     g.free()
