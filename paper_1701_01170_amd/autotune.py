@@ -14,6 +14,7 @@ Search (coordinate descent from the paper's defaults):
   4. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8}
   5. BFS / SSSP: device_max_edges in {off, 2^16, 2^18, 2^20} (edge bound of
      the device-predicated level blocks)
+  6. SSSP only: sssp_delta in {0 (no priority queue), 8, 16, ..., 256}
 Batched BFS ("bfs_multi", 64 sources per call) searches 1, 2 and its
 push -> pull switch do_a in {1/4 .. 1/64}.
 
@@ -38,7 +39,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 ARCH = "gfx950"
 
-KNOBS = ("lb_light_threshold", "lb_chunk", "lb_min_avg_degree", "do_a", "do_b", "device_max_edges")
+KNOBS = ("lb_light_threshold", "lb_chunk", "lb_min_avg_degree", "do_a", "do_b", "device_max_edges",
+         "sssp_delta")
+SSSP_DELTA = [0, 8, 16, 32, 64, 128, 256]
 DEVICE_MAX_EDGES = [-1, 1 << 16, 1 << 18, 1 << 20]
 MULTI_DO_A = [1 / 4, 1 / 8, 1 / 16, 1 / 32, 1 / 64]
 DO_A = [1 / 2, 1 / 4, 1 / 8, 1 / 14, 1 / 32, 1 / 64, 1 / 256]
@@ -135,6 +138,8 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
         try_set("do_a", MULTI_DO_A)
         return best, best_ms, base_ms
     try_set("lb_min_avg_degree", [0.0, 5.0, 1e9])
+    if kind == "sssp":
+        try_set("sssp_delta", SSSP_DELTA)
     try_set("device_max_edges", DEVICE_MAX_EDGES)
     if kind == "bfs":
         for a in DO_A:
