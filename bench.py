@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {
     ("bfs", 0): "k_push_twc<BfsVisit>", ("bfs", 1): "k_push_light<BfsVisit>",
     ("bfs", 2): "k_push_lb<BfsVisit>", ("bfs", 3): "k_push_lb<BfsMark>",
-    ("bfs", 4): "k_bfs_pull_twc", ("bfs", 5): "k_bfs_pull_groups",
+    ("bfs", 4): "k_bfs_pull_bm<1>", ("bfs", 5): "k_bfs_pull_bm<4>",
     ("sssp", 0): "k_push_twc<SsspVisit>", ("sssp", 1): "k_push_light<SsspVisit>",
     ("sssp", 2): "k_push_lb<SsspVisit>",
     ("bfs", 6): "k_dstep<BfsVisit>", ("sssp", 6): "k_dstep<SsspVisit>",

@@ -487,17 +487,13 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
 
   uint32_t* bm;
-  int32_t *qA, *qB, *qC, *uA = nullptr, *uB = nullptr, *offsets, *rstart, *chunks;
+  int32_t *qA, *qB, *qC, *offsets, *rstart, *chunks;
   int64_t* bsums;
   Ctrl* ctrl;
   GR_TRY(pool_typed(ctx, S_BM, 2 * NW, &bm));
   GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
   GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
   GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
-  if (pull_ok) {
-    GR_TRY(pool_typed(ctx, S_U_A, V, &uA));
-    GR_TRY(pool_typed(ctx, S_U_B, V, &uB));
-  }
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
   GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
@@ -506,13 +502,12 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   Ctrl* hc = ctx->host_ctrl;
 
   int32_t* q[3] = {qA, qB, qC};
-  int32_t* ul[2] = {uA, uB};
 
   GR_HIP(hipEventRecord(ctx->ev_start, st));
   GR_HIP(launch_bfs_init(depth, parent, V, bm, NW, source, qA, ctrl, st));
-  int cur = 0, ucur = 0, sp = 0, p = 0;
+  int cur = 0, sp = 0, p = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                               &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+                               &ctrl->q_count[(cur + 1) % 3], nullptr, st));
   const bool learned = opts.policy == GR_POLICY_LEARNED && ctx->policy_loaded;
   const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr);
   const int allowed = pull_ok ? 0xF : 0x3;
@@ -526,8 +521,6 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   lf.E = E;
   int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], max_deg = hc->max_deg[sp];
   int64_t visited_n = n_f, visited_m = m_f;
-  int64_t n_ulist = 0;
-  bool have_unv = false;
   int64_t inspected_push = 0;
   int level = 0;
   gr_run_stats rs{};
@@ -579,9 +572,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         cur = (cur + k) % 3;
         sp ^= 1;
         level += k;
-        have_unv = false;
         GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                     &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+                                     &ctrl->q_count[(cur + 1) % 3], nullptr, st));
         if (learned)
           GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V - visited_n, E - visited_m, 0, allowed, st));
         GR_TRY(read_ctrl(ctx, ctrl, st));
@@ -643,22 +635,12 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
                                        std::min<int64_t>(V - visited_n, m_f), g->R, g->C, bm, p,
                                        parent, st));
       inspected_push += m_f;
-      have_unv = false;
     } else {
-      if (!have_unv) {
-        GR_HIP(launch_fill_u32(&ctrl->u_count[ucur], 1, 0u, st));
-        GR_HIP(launch_gen_unvisited(bm, p, g->R, V, ul[ucur], &ctrl->u_count[ucur], st));
-        GR_TRY(read_ctrl(ctx, ctrl, st));
-        n_ulist = hc->u_count[ucur];
-        have_unv = true;
-      }
       kernel = action == GR_PULL_LB ? 5 : 4;
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, ul[ucur], n_ulist, g->R, g->C, bm, p, depth,
-                             parent, next_depth, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
-                             ul[ucur ^ 1], &ctrl->u_count[ucur ^ 1], &ctrl->inspected, st));
+      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, V, g->R, g->C, bm, p, depth, parent, next_depth,
+                             q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], &ctrl->inspected, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
-      ucur ^= 1;
     }
     GR_HIP(launch_bitmap_merge(bm, p, NW, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
@@ -668,7 +650,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     sp ^= 1;
     ++level;
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                 &ctrl->q_count[(cur + 1) % 3], &ctrl->u_count[ucur ^ 1], st));
+                                 &ctrl->q_count[(cur + 1) % 3], nullptr, st));
     if (learned)
       GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V - visited_n, E - visited_m,
                                sel.mode_pull ? 1 : 0, allowed, st));
@@ -677,7 +659,6 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
     max_deg = hc->max_deg[sp];
-    if (have_unv) n_ulist = hc->u_count[ucur];
     visited_n += n_f;
     visited_m += m_f;
   }

@@ -45,8 +45,6 @@ enum Slot : int {
   S_DLOG,          // per-level log of a device-predicated block (n_f, m_f, max degree)
   S_FAR,           // SSSP far piles: three rotating int32[V]
   S_FAR_TAGS,      // SSSP far-pile generation per vertex
-  S_U_A,           // unvisited frontier (ping)
-  S_U_B,           // unvisited frontier (pong)
   S_OFFSETS,       // exclusive scan of frontier degrees [n_f + 1]
   S_RSTART,        // row start of every frontier vertex [n_f]
   S_BLOCK_SUMS,    // per-block partial sums for the frontier scan
@@ -69,7 +67,6 @@ enum Slot : int {
 // statistics call, so each call can clear the slot the next one accumulates in.
 struct Ctrl {
   uint32_t q_count[3];      // frontier queue lengths (three rotating queues)
-  uint32_t u_count[2];      // unvisited frontier lengths (ping/pong)
   uint32_t pad1;
   int64_t m_f[2];           // sum of frontier degrees
   int64_t max_deg[2];       // largest frontier degree
@@ -174,13 +171,9 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
                                    const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
                                    int32_t* parent, hipStream_t st);
-hipError_t launch_gen_unvisited(const uint32_t* bm, int p, const int32_t* R, int64_t V,
-                                int32_t* out_list, uint32_t* out_count, hipStream_t st);
-hipError_t launch_bfs_pull(bool lb, const int32_t* unvisited, int64_t n_u, const int32_t* R,
-                           const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
-                           int32_t next_depth, int32_t* out_active, uint32_t* out_active_count,
-                           int32_t* out_unvisited, uint32_t* out_unvisited_count,
-                           int64_t* inspected, hipStream_t st);
+hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
+                           int p, int32_t* depth, int32_t* parent, int32_t next_depth,
+                           int32_t* out_q, uint32_t* out_count, int64_t* inspected, hipStream_t st);
 // live |= old (live = depth <= d + 1 after level d)
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
 

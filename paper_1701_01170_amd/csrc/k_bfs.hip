@@ -219,111 +219,144 @@ __device__ __forceinline__ int32_t first_frontier_nbr(bool valid, int32_t rb, in
   return found;
 }
 
-__device__ __forceinline__ void pull_emit(bool valid, int32_t v, int32_t found, uint32_t* bm,
-                                          int p, int32_t* depth, int32_t* parent,
-                                          int32_t next_depth, int32_t* out_a, uint32_t* cnt_a,
-                                          int32_t* out_u, uint32_t* cnt_u) {
-  const bool hit = valid && found >= 0;
-  const bool miss = valid && found < 0;
-  if (hit) {
-    depth[v] = next_depth;
-    if (parent) parent[v] = found;
-    atomicOr(&bm[2 * (v >> 5) + 1 - p], 1u << (v & 31));
-  }
-  const uint32_t sa = wave_append(cnt_a, hit);
-  if (hit) out_a[sa] = v;
-  const uint32_t su = wave_append(cnt_u, miss);
-  if (miss) out_u[su] = v;
-}
+// Pull over the visited bitmap (Alg. 2, with the unvisited set read from the
+// bitmap instead of a generated list): each wavefront owns kPullRuns runs of
+// 64 consecutive vertices, i.e. their bitmap words, which no other wavefront
+// writes during the step.  A vertex outside old scans its ascending
+// adjacency for its first frontier neighbour (the smallest-id parent); the
+// wavefront ORs its hits into live with one plain store per word and the
+// workgroup appends them to the next frontier with a single atomic.
+// GW = 1: one lane per vertex (dynamic grouping: lists longer than 32 go to
+// the whole wavefront); GW > 1: GW lanes per vertex, GW neighbours per step
+// (lists longer than 64 go to the whole wavefront).
+constexpr int kPullRuns = 8;
 
-__device__ __forceinline__ void add_inspected(int64_t* inspected, int64_t scanned) {
-  if (!inspected) return;
-  const int64_t s = wave_sum(scanned);
-  if (lane() == 0 && s) atomicAdd((unsigned long long*)inspected, (unsigned long long)s);
-}
-
-// PULL_TWC: one lane per unvisited vertex, whole wavefront for lists > 32.
-__global__ __launch_bounds__(256) void k_bfs_pull_twc(
-    const int32_t* __restrict__ unv, int32_t n_u, const int32_t* __restrict__ R,
-    const int32_t* __restrict__ C, uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth,
-    int32_t* __restrict__ parent, int32_t next_depth, int32_t* __restrict__ out_a,
-    uint32_t* __restrict__ cnt_a, int32_t* __restrict__ out_u, uint32_t* __restrict__ cnt_u,
-    int64_t* __restrict__ inspected) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n_u;
-  int32_t v = 0, rb = 0, re = 0;
-  if (valid) {
-    v = unv[i];
-    rb = R[v];
-    re = R[v + 1];
-  }
-  int64_t scanned;
-  const int32_t found = first_frontier_nbr<32>(valid, rb, re, C, bm, p, &scanned);
-  pull_emit(valid, v, found, bm, p, depth, parent, next_depth, out_a, cnt_a, out_u, cnt_u);
-  add_inspected(inspected, scanned);
-}
-
-// PULL_LB: fixed-width groups of GW lanes per unvisited vertex, each group
-// checking GW consecutive neighbours per step (the lowest hit lane of the
-// first step with a hit is the smallest-id frontier neighbour); lists longer
-// than 64 neighbours are handed to the whole wavefront.
 template <int GW>
-__global__ __launch_bounds__(256) void k_bfs_pull_groups(
-    const int32_t* __restrict__ unv, int32_t n_u, const int32_t* __restrict__ R,
-    const int32_t* __restrict__ C, uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth,
-    int32_t* __restrict__ parent, int32_t next_depth, int32_t* __restrict__ out_a,
-    uint32_t* __restrict__ cnt_a, int32_t* __restrict__ out_u, uint32_t* __restrict__ cnt_u,
+__global__ __launch_bounds__(256) void k_bfs_pull_bm(
+    int64_t V, const int32_t* __restrict__ R, const int32_t* __restrict__ C,
+    uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth, int32_t* __restrict__ parent,
+    int32_t next_depth, int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count,
     int64_t* __restrict__ inspected) {
-  static_assert(GW > 1 && GW < kWave && (kWave % GW) == 0, "group width");
-  constexpr int GPW = kWave / GW;  // groups (vertices) per wavefront
-  const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int sub = lane() % GW;
-  const int grp = lane() / GW;
-  const int gbase = grp * GW;
-  // lane l < GPW loads the vertex of group l of this wavefront
-  const int64_t mine = wave_id * GPW + lane();
-  int32_t mv = 0, mrb = 0, mre = 0;
-  const bool mvalid = lane() < GPW && mine < n_u;
-  if (mvalid) {
-    mv = unv[mine];
-    mrb = R[mv];
-    mre = R[mv + 1];
-  }
-  const int32_t v = __shfl(mv, grp), rb = __shfl(mrb, grp), re = __shfl(mre, grp);
-  const bool valid = __shfl((int)mvalid, grp) != 0;
-  const bool small = valid && re - rb <= kWave;
-  int32_t found = -1;
+  static_assert(GW >= 1 && GW < kWave && (kWave % GW) == 0, "group width");
+  constexpr int NW = 256 / kWave;
+  constexpr int VPR = kWave / GW;  // vertices per sub-round
+  __shared__ uint32_t s_cnt[NW];
+  __shared__ int64_t s_insp[NW];
+  __shared__ uint32_t s_base;
+  const int w = threadIdx.x / kWave;
+  const int64_t base = ((int64_t)blockIdx.x * NW + w) * kWave * kPullRuns;
+  uint32_t hits = 0;  // bit k: vertex base + 64 k + lane was found
   int64_t scanned = 0;
-  for (int32_t base = rb;; base += GW) {
-    const bool active = small && found < 0 && base < re;
-    if (!__any(active)) break;
-    const int32_t j = base + sub;
-    int32_t u = -1;
-    bool hit = false;
-    if (active && j < re) {
-      u = C[j];
-      hit = in_frontier(bm, p, u);
+  for (int k = 0; k < kPullRuns; ++k) {
+    const int64_t v0 = base + (int64_t)k * kWave;
+    if (v0 >= V) break;  // uniform across the wavefront
+    uint64_t hb = 0;
+    if constexpr (GW == 1) {
+      const int64_t v = v0 + lane();
+      bool cand = false;
+      int32_t rb = 0, re = 0;
+      if (v < V) {
+        const uint2 x = bm_pair(bm, (int32_t)(v >> 5));
+        if (!(((p ? x.y : x.x) >> (v & 31)) & 1u)) {
+          rb = R[v];
+          re = R[v + 1];
+          cand = re > rb;
+        }
+      }
+      int64_t sc = 0;
+      const int32_t found = first_frontier_nbr<32>(cand, rb, re, C, bm, p, &sc);
+      const bool hit = cand && found >= 0;
+      if (hit) {
+        depth[v] = next_depth;
+        if (parent) parent[v] = found;
+      }
+      hb = __ballot(hit);
+      scanned += sc;
+    } else {
+      const int g = lane() / GW, sub = lane() % GW, gbase = g * GW;
+      const bool leader = sub == 0;
+      for (int s = 0; s < GW; ++s) {
+        const int64_t v = v0 + s * VPR + g;
+        bool cand = false;
+        int32_t rb = 0, re = 0;
+        if (v < V) {
+          const uint2 x = bm_pair(bm, (int32_t)(v >> 5));
+          if (!(((p ? x.y : x.x) >> (v & 31)) & 1u)) {
+            rb = R[v];
+            re = R[v + 1];
+            cand = re > rb;
+          }
+        }
+        const bool small = cand && re - rb <= kWave;
+        int32_t found = -1;
+        int64_t sc = 0;
+        for (int32_t b = rb;; b += GW) {
+          const bool active = small && found < 0 && b < re;
+          if (!__any(active)) break;
+          const int32_t j = b + sub;
+          int32_t u = -1;
+          bool h = false;
+          if (active && j < re) {
+            u = C[j];
+            h = in_frontier(bm, p, u);
+          }
+          const uint64_t bb = __ballot(h);
+          const uint64_t gm = (bb >> gbase) & ((1ull << GW) - 1ull);
+          const int src = gm ? gbase + __ffsll((unsigned long long)gm) - 1 : lane();
+          const int32_t cnd = __shfl(u, src);
+          if (active) {
+            sc += (re - b) < GW ? (re - b) : GW;
+            if (gm) found = cnd;
+          }
+        }
+        int64_t scb = 0;
+        const bool big = leader && cand && !small;
+        const int32_t fb = first_frontier_nbr<0>(big, rb, re, C, bm, p, &scb);
+        if (big) {
+          found = fb;
+          sc = scb;
+        }
+        const bool hit = leader && cand && found >= 0;
+        if (hit) {
+          depth[v] = next_depth;
+          if (parent) parent[v] = found;
+        }
+        const uint64_t lb = __ballot(hit);  // bit g * GW for group g
+        uint64_t m = 0;
+        for (int q = 0; q < VPR; ++q) m |= ((lb >> (q * GW)) & 1ull) << q;
+        hb |= m << (s * VPR);
+        if (leader) scanned += sc;
+      }
     }
-    const uint64_t b = __ballot(hit);
-    const uint64_t gm = (b >> gbase) & ((1ull << GW) - 1ull);
-    const int src = gm ? gbase + __ffsll((unsigned long long)gm) - 1 : lane();
-    const int32_t cand = __shfl(u, src);
-    if (active) {
-      scanned += (re - base) < GW ? (re - base) : GW;
-      if (gm) found = cand;
+    // live bits of the run's two words (owned by this wavefront)
+    const int64_t w0 = v0 >> 5;
+    if (lane() == 0 && (uint32_t)hb) bm[2 * w0 + 1 - p] |= (uint32_t)hb;
+    if (lane() == 32 && (uint32_t)(hb >> 32)) bm[2 * (w0 + 1) + 1 - p] |= (uint32_t)(hb >> 32);
+    if ((hb >> lane()) & 1ull) hits |= 1u << k;
+  }
+  // one append (and one inspected-count update) per workgroup
+  const uint32_t n = __popc(hits);
+  const uint32_t inc = wave_incl_scan(n);
+  const int64_t ws = wave_sum(scanned);
+  if (lane() == kWave - 1) s_cnt[w] = inc;
+  if (lane() == 0) s_insp[w] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    int64_t ins = 0;
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t c = s_cnt[i];
+      s_cnt[i] = tot;
+      tot += c;
+      ins += s_insp[i];
     }
+    s_base = tot ? atomicAdd(out_count, tot) : 0u;
+    if (inspected && ins) atomicAdd(reinterpret_cast<unsigned long long*>(inspected), (unsigned long long)ins);
   }
-  // long lists: whole wavefront per vertex (group leaders hold the vertex)
-  const bool leader = sub == 0;
-  int64_t sc_big = 0;
-  const int32_t fb = first_frontier_nbr<0>(leader && valid && !small, rb, re, C, bm, p, &sc_big);
-  if (leader && valid && !small) {
-    found = fb;
-    scanned = sc_big;
-  }
-  pull_emit(valid && leader, v, found, bm, p, depth, parent, next_depth, out_a, cnt_a, out_u,
-            cnt_u);
-  add_inspected(inspected, leader ? scanned : 0);
+  __syncthreads();
+  uint32_t slot = s_base + s_cnt[w] + inc - n;
+  for (int k = 0; k < kPullRuns; ++k)
+    if ((hits >> k) & 1u) out_q[slot++] = (int32_t)(base + (int64_t)k * kWave + lane());
 }
 
 // Parents of the vertices a push step discovered (symmetric graphs): the
@@ -395,22 +428,17 @@ hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, i
   return hipGetLastError();
 }
 
-hipError_t launch_bfs_pull(bool lb, const int32_t* unvisited, int64_t n_u, const int32_t* R,
-                           const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
-                           int32_t next_depth, int32_t* out_active, uint32_t* out_active_count,
-                           int32_t* out_unvisited, uint32_t* out_unvisited_count,
-                           int64_t* inspected, hipStream_t st) {
-  if (n_u <= 0) return hipSuccess;
-  if (lb) {
-    constexpr int GW = 4;
-    k_bfs_pull_groups<GW><<<blocks_for(n_u * GW, 256), 256, 0, st>>>(
-        unvisited, (int32_t)n_u, R, C, bm, p, depth, parent, next_depth, out_active,
-        out_active_count, out_unvisited, out_unvisited_count, inspected);
-  } else {
-    k_bfs_pull_twc<<<blocks_for(n_u, 256), 256, 0, st>>>(
-        unvisited, (int32_t)n_u, R, C, bm, p, depth, parent, next_depth, out_active,
-        out_active_count, out_unvisited, out_unvisited_count, inspected);
-  }
+hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
+                           int p, int32_t* depth, int32_t* parent, int32_t next_depth,
+                           int32_t* out_q, uint32_t* out_count, int64_t* inspected, hipStream_t st) {
+  if (V <= 0) return hipSuccess;
+  const unsigned g = blocks_for(V, 256 * kPullRuns);
+  if (lb)
+    k_bfs_pull_bm<4><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, next_depth, out_q, out_count,
+                                        inspected);
+  else
+    k_bfs_pull_bm<1><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, next_depth, out_q, out_count,
+                                        inspected);
   return hipGetLastError();
 }
 

@@ -1,7 +1,6 @@
 // Frontier bookkeeping kernels: BFS initialisation (Alg. 1, Set_Problem_Data),
 // frontier statistics and the degree prefix-sum that gives advance its scatter
-// offsets (Sec. 4.1, the allocation stage), the unvisited-frontier generation
-// of the pull traversal (Alg. 2), and small bitmap utilities.
+// offsets (Sec. 4.1, the allocation stage), and small bitmap utilities.
 #include "gr_internal.h"
 #include "k_common.h"
 
@@ -33,8 +32,6 @@ __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
     ctrl->q_count[0] = 1;
     ctrl->q_count[1] = 0;
     ctrl->q_count[2] = 0;
-    ctrl->u_count[0] = 0;
-    ctrl->u_count[1] = 0;
     ctrl->m_f[0] = ctrl->m_f[1] = 0;
     ctrl->max_deg[0] = ctrl->max_deg[1] = 0;
     ctrl->inspected = 0;
@@ -137,19 +134,6 @@ __global__ __launch_bounds__(kStatsBlock) void k_frontier_offsets(
   if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n_f] = (int32_t)*total;
 }
 
-// Alg. 2, GenerateUnvisitedFrontier: every vertex not yet visited.  Vertices of
-// degree zero are left out: in a symmetric graph nothing can reach them.
-__global__ __launch_bounds__(256) void k_gen_unvisited(const uint32_t* __restrict__ bm, int p,
-                                                       const int32_t* __restrict__ R, int64_t V,
-                                                       int32_t* __restrict__ out,
-                                                       uint32_t* __restrict__ count) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool keep = false;
-  if (v < V) keep = !((bm[2 * (v >> 5) + p] >> (v & 31)) & 1u) && R[v + 1] > R[v];
-  const uint32_t slot = wave_append(count, keep);
-  if (keep) out[slot] = (int32_t)v;
-}
-
 // live |= old over all word pairs
 __global__ __launch_bounds__(256) void k_bitmap_merge(uint32_t* __restrict__ bm, int p,
                                                       int64_t n_words) {
@@ -216,13 +200,6 @@ hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const i
                                    int32_t chunk, hipStream_t st) {
   k_frontier_offsets<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f, R, block_sums, total,
                                                          offsets, rstart, chunk_start, chunk);
-  return hipGetLastError();
-}
-
-hipError_t launch_gen_unvisited(const uint32_t* bm, int p, const int32_t* R, int64_t V,
-                                int32_t* out_list, uint32_t* out_count, hipStream_t st) {
-  if (V <= 0) return hipSuccess;
-  k_gen_unvisited<<<blocks_for(V, 256), 256, 0, st>>>(bm, p, R, V, out_list, out_count);
   return hipGetLastError();
 }
 

@@ -194,8 +194,6 @@ __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restric
     ctrl->far_count[0] = ctrl->far_count[1] = ctrl->far_count[2] = 0;
     ctrl->q_count[1] = 0;
     ctrl->q_count[2] = 0;
-    ctrl->u_count[0] = 0;
-    ctrl->u_count[1] = 0;
     ctrl->inspected = 0;
     ctrl->reached_edges = 0;
     ctrl->m_f[0] = ctrl->m_f[1] = 0;
