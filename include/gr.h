@@ -74,6 +74,11 @@ typedef enum gr_action {
 /* gr_graph_from_csr flags */
 #define GR_SYMMETRIC 0x1u       /* the CSR holds both (u,v) and (v,u) for every edge: pull may use it */
 #define GR_DEVICE_INPUT 0x2u    /* row_offsets/col_indices/weights are device pointers */
+#define GR_RENUMBER 0x4u        /* renumber vertices by descending degree inside the handle, so the
+                                   per-vertex state of hubs shares cache lines (raises the L2 hit
+                                   rate of SSSP relaxation on scale-free graphs, but clusters the
+                                   long lists of the pull steps); inputs and outputs use the
+                                   caller's ids either way and results are identical */
 
 typedef struct gr_ctx gr_ctx;
 typedef struct gr_graph gr_graph;
@@ -190,8 +195,8 @@ gr_status gr_graph_from_csr(gr_ctx* ctx, int64_t n_vertices, int64_t n_edges,
                             gr_graph** out);
 gr_status gr_graph_free(gr_graph* graph);
 gr_status gr_graph_get_info(const gr_graph* graph, gr_graph_info* out);
-/* Copy the ingested (sorted) CSR back into caller DEVICE buffers
- * (row_offsets[V+1], col_indices[E], weights[E] or NULL). */
+/* Copy the ingested (sorted) CSR, in the caller's vertex ids, back into
+ * caller DEVICE buffers (row_offsets[V+1], col_indices[E], weights[E] or NULL). */
 gr_status gr_graph_export(const gr_graph* graph, int32_t* row_offsets, int32_t* col_indices,
                           uint32_t* weights, void* stream);
 

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "GR_OK", -1: "GR_EINVAL", -2: "GR_ERANGE", -3: "GR_ENOMEM", -
 POLICY_HEURISTIC, POLICY_LEARNED, POLICY_FIXED, POLICY_RANDOM = 0, 1, 2, 3
 PUSH_TWC, PUSH_LB, PULL_TWC, PULL_LB = 0, 1, 2, 3
 ACTION_NAMES = ["PUSH_TWC", "PUSH_LB", "PULL_TWC", "PULL_LB"]
-SYMMETRIC, DEVICE_INPUT = 0x1, 0x2
+SYMMETRIC, DEVICE_INPUT, RENUMBER = 0x1, 0x2, 0x4
 MLP_N_PARAMS = 1476
 
 
@@ -212,10 +212,10 @@ class Graph:
 
     @classmethod
     def from_csr(cls, ctx: Context, row_offsets, col_indices, weights=None,
-                 symmetric: bool = True, stream=None) -> "Graph":
+                 symmetric: bool = True, renumber: bool = False, stream=None) -> "Graph":
         """From host numpy arrays, or from device torch tensors."""
         import torch
-        flags = SYMMETRIC if symmetric else 0
+        flags = (SYMMETRIC if symmetric else 0) | (RENUMBER if renumber else 0)
         if isinstance(row_offsets, torch.Tensor):
             flags |= DEVICE_INPUT
             R, C = row_offsets, col_indices
@@ -242,8 +242,9 @@ class Graph:
         return cls(ctx, h)
 
     @classmethod
-    def from_host(cls, ctx: Context, hg, symmetric: bool = True) -> "Graph":
-        return cls.from_csr(ctx, hg.row_offsets, hg.col_indices, hg.weights, symmetric=symmetric)
+    def from_host(cls, ctx: Context, hg, symmetric: bool = True, renumber: bool = False) -> "Graph":
+        return cls.from_csr(ctx, hg.row_offsets, hg.col_indices, hg.weights, symmetric=symmetric,
+                            renumber=renumber)
 
     def export(self, stream=None):
         """The ingested (sorted) CSR as device tensors (R, C, W or None)."""

@@ -200,9 +200,16 @@ void free_graph_buffers(gr_graph* g) {
   if (g->R) (void)hipFree(g->R);
   if (g->C) (void)hipFree(g->C);
   if (g->W) (void)hipFree(g->W);
+  if (g->perm) (void)hipFree(g->perm);
+  if (g->inv) (void)hipFree(g->inv);
+  if (g->R_orig) (void)hipFree(g->R_orig);
   g->R = nullptr;
   g->C = nullptr;
   g->W = nullptr;
+  g->perm = nullptr;
+  g->inv = nullptr;
+  g->R_orig = nullptr;
+  g->inv_host.clear();
 }
 
 gr_status ingest(gr_ctx* ctx, gr_graph* g, const int32_t* R, const int32_t* C, const uint32_t* W,
@@ -266,6 +273,43 @@ gr_status ingest(gr_ctx* ctx, gr_graph* g, const int32_t* R, const int32_t* C, c
   g->max_degree = host4[1];
   g->max_weight = (uint32_t)host4[2];
   (void)ctx;
+  if (!(g->flags & GR_RENUMBER)) return GR_OK;
+  // renumber by descending degree (see gr_graph)
+  int32_t *perm = nullptr, *inv = nullptr, *R_new = nullptr, *C_new = nullptr;
+  uint32_t* W_new = nullptr;
+  auto undo = [&]() {
+    (void)hipFree(perm);
+    (void)hipFree(inv);
+    (void)hipFree(R_new);
+    (void)hipFree(C_new);
+    (void)hipFree(W_new);
+  };
+  hipError_t e = hipSuccess;
+  if ((e = hipMalloc(&perm, sizeof(int32_t) * V)) == hipSuccess &&
+      (e = hipMalloc(&inv, sizeof(int32_t) * V)) == hipSuccess &&
+      (e = hipMalloc(&R_new, sizeof(int32_t) * (V + 1))) == hipSuccess &&
+      (e = hipMalloc(&C_new, sizeof(int32_t) * std::max<int64_t>(E, 1))) == hipSuccess &&
+      (!g->W || (e = hipMalloc(&W_new, sizeof(uint32_t) * std::max<int64_t>(E, 1))) == hipSuccess))
+    e = relabel_by_degree(g->R, g->C, g->W, V, E, perm, inv, R_new, C_new, W_new, st);
+  if (e != hipSuccess) {
+    undo();
+    return fail(e == hipErrorOutOfMemory ? GR_ENOMEM : GR_EHIP,
+                std::string("vertex renumbering: ") + hipGetErrorString(e));
+  }
+  g->inv_host.resize((size_t)V);
+  e = hipMemcpy(g->inv_host.data(), inv, sizeof(int32_t) * V, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    undo();
+    return fail(GR_EHIP, std::string("vertex renumbering: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(g->C);
+  if (g->W) (void)hipFree(g->W);
+  g->R_orig = g->R;
+  g->R = R_new;
+  g->C = C_new;
+  g->W = W_new;
+  g->perm = perm;
+  g->inv = inv;
   return GR_OK;
 }
 
@@ -276,7 +320,8 @@ extern "C" gr_status gr_graph_from_csr(gr_ctx* ctx, int64_t V, int64_t E, const 
                                        void* stream, gr_graph** out) {
   if (!out) return fail(GR_EINVAL, "gr_graph_from_csr: out is NULL");
   *out = nullptr;
-  if (flags & ~(GR_SYMMETRIC | GR_DEVICE_INPUT)) return fail(GR_EINVAL, "unknown flags");
+  if (flags & ~(GR_SYMMETRIC | GR_DEVICE_INPUT | GR_RENUMBER))
+    return fail(GR_EINVAL, "unknown flags");
   const bool device_input = (flags & GR_DEVICE_INPUT) != 0;
   if (device_input) {
     if (V < 1 || V > (int64_t)INT32_MAX - 1)
@@ -330,10 +375,16 @@ extern "C" gr_status gr_graph_export(const gr_graph* g, int32_t* R, int32_t* C, 
   if (W && !g->W) return fail(GR_EINVAL, "graph has no weights");
   DeviceGuard dg(g->ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  GR_HIP(hipMemcpyAsync(R, g->R, sizeof(int32_t) * (g->V + 1), hipMemcpyDeviceToDevice, st));
-  if (g->E > 0) {
-    GR_HIP(hipMemcpyAsync(C, g->C, sizeof(int32_t) * g->E, hipMemcpyDeviceToDevice, st));
-    if (W) GR_HIP(hipMemcpyAsync(W, g->W, sizeof(uint32_t) * g->E, hipMemcpyDeviceToDevice, st));
+  if (g->perm) {
+    GR_HIP(hipMemcpyAsync(R, g->R_orig, sizeof(int32_t) * (g->V + 1), hipMemcpyDeviceToDevice, st));
+    GR_HIP(launch_unrelabel(g->R_orig, g->perm, g->inv, g->R, g->C, W ? g->W : nullptr, g->V, g->E,
+                            C, W, st));
+  } else {
+    GR_HIP(hipMemcpyAsync(R, g->R, sizeof(int32_t) * (g->V + 1), hipMemcpyDeviceToDevice, st));
+    if (g->E > 0) {
+      GR_HIP(hipMemcpyAsync(C, g->C, sizeof(int32_t) * g->E, hipMemcpyDeviceToDevice, st));
+      if (W) GR_HIP(hipMemcpyAsync(W, g->W, sizeof(uint32_t) * g->E, hipMemcpyDeviceToDevice, st));
+    }
   }
   GR_HIP(hipStreamSynchronize(st));
   return GR_OK;
@@ -500,11 +551,21 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   Ctrl* hc = ctx->host_ctrl;
+  // a renumbered graph traverses into internal arrays indexed by the new
+  // ids (parent values are caller ids already) and scatters them at the end
+  const int32_t* perm = g->perm;
+  int32_t* out_depth = depth;
+  int32_t* out_parent = parent;
+  if (perm) {
+    GR_TRY(pool_typed(ctx, S_DEPTH, V, &depth));
+    if (parent) GR_TRY(pool_typed(ctx, S_PARENT, V, &parent));
+  }
+  const int32_t src = g->to_new(source);
 
   int32_t* q[3] = {qA, qB, qC};
 
   GR_HIP(hipEventRecord(ctx->ev_start, st));
-  GR_HIP(launch_bfs_init(depth, parent, V, bm, NW, source, qA, ctrl, st));
+  GR_HIP(launch_bfs_init(depth, parent, V, bm, NW, src, qA, ctrl, st));
   int cur = 0, sp = 0, p = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                &ctrl->q_count[(cur + 1) % 3], nullptr, st));
@@ -550,7 +611,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, dl.do_a,
                         dl.mlp, dl.allowed, V, dl.log, ctrl};
-        GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, level + i + 1, dl.blocks, st));
+        GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, perm, level + i + 1, dl.blocks,
+                                st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
       GR_TRY(read_ctrl(ctx, ctrl, st));
@@ -626,20 +688,21 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         kernel = mode;
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push(mode, atomic_parent, q[cur], offsets, rstart, chunks, n_f, m_f,
-                               g->R, g->C, bm, p, depth, parent, next_depth, q[(cur + 1) % 3],
+                               g->R, g->C, bm, p, depth, parent, perm, next_depth, q[(cur + 1) % 3],
                                &ctrl->q_count[(cur + 1) % 3], chunk, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
       if (parent && !atomic_parent)
         GR_HIP(launch_bfs_parent_fixup(q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
                                        std::min<int64_t>(V - visited_n, m_f), g->R, g->C, bm, p,
-                                       parent, st));
+                                       parent, perm, st));
       inspected_push += m_f;
     } else {
       kernel = action == GR_PULL_LB ? 5 : 4;
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, V, g->R, g->C, bm, p, depth, parent, next_depth,
-                             q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], &ctrl->inspected, st));
+      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, V, g->R, g->C, bm, p, depth, parent, perm,
+                             next_depth, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
+                             &ctrl->inspected, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
     }
     GR_HIP(launch_bitmap_merge(bm, p, NW, st));
@@ -662,6 +725,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     visited_n += n_f;
     visited_m += m_f;
   }
+  if (perm) GR_HIP(launch_permute_out(perm, V, depth, parent, out_depth, out_parent, st));
   GR_HIP(hipEventRecord(ctx->ev_stop, st));
   GR_HIP(hipEventSynchronize(ctx->ev_stop));
   if (stats) {
@@ -722,10 +786,18 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
-  GR_TRY(pool_typed(ctx, S_TMP0, n_src, &src_dev));
+  // src_dev: the sources in traversal ids, then in caller ids
+  GR_TRY(pool_typed(ctx, S_TMP0, 2 * (size_t)n_src, &src_dev));
+  std::vector<int32_t> src_both(2 * (size_t)n_src);
+  for (int32_t i = 0; i < n_src; ++i) {
+    src_both[i] = g->to_new(uniq[i]);
+    src_both[n_src + i] = uniq[i];
+  }
+  const int32_t* perm = g->perm;
   // two-level priority queue (near / far piles), when sssp_delta > 0
   const bool use_pq = opts.sssp_delta > 0;
   PqState pq{};
+  pq.perm = perm;
   if (use_pq) {
     pq.T = (uint32_t)opts.sssp_delta;
     pq.delta = (uint32_t)opts.sssp_delta;
@@ -736,8 +808,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   Ctrl* hc = ctx->host_ctrl;
   int32_t* q[3] = {qA, qB, qC};
 
-  GR_HIP(hipMemcpyAsync(src_dev, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
-  GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
+  GR_HIP(hipMemcpyAsync(src_dev, src_both.data(), sizeof(int32_t) * 2 * n_src,
+                        hipMemcpyHostToDevice, st));
+  GR_HIP(hipMemcpyAsync(qA, src_both.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
   GR_HIP(hipStreamSynchronize(st));  // the host vector must outlive the copies
   GR_HIP(hipEventRecord(ctx->ev_start, st));
   GR_HIP(launch_sssp_init(keys, tags, use_pq ? pq.far_tag : nullptr, V, ctrl, st));
@@ -793,7 +866,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
                         nullptr, 0x3, V, dl.log, ctrl};
         if (use_pq) GR_HIP(launch_sssp_pq_dstep(da, g->W, keys, tags, it + i + 1, pq, dl.blocks, st));
-        else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, it + i + 1, dl.blocks, st));
+        else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, perm, it + i + 1, dl.blocks, st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
       GR_TRY(read_ctrl(ctx, ctrl, st));
@@ -862,8 +935,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
                                     &ctrl->q_count[(cur + 1) % 3], chunk, st));
       else
         GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W,
-                                 keys, tags, it + 1, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
-                                 chunk, st));
+                                 keys, tags, perm, it + 1, q[(cur + 1) % 3],
+                                 &ctrl->q_count[(cur + 1) % 3], chunk, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       inspected += m_f;
       rs.action_count[action]++;
@@ -879,7 +952,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     max_deg = hc->max_deg[sp];
   }
   int64_t* reached = &ctrl->reached_edges;
-  GR_HIP(launch_sssp_finalize(keys, g->R, V, dist, pred, src_dev, n_src, reached, st));
+  GR_HIP(launch_sssp_finalize(keys, g->R, V, dist, pred, perm, src_dev + n_src, n_src, reached, st));
   GR_HIP(hipEventRecord(ctx->ev_stop, st));
   GR_TRY(read_ctrl(ctx, ctrl, st));
   if (stats) {
@@ -937,7 +1010,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
   GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
-  GR_TRY(pool_typed(ctx, S_TMP0, 64, &src_dev));
+  GR_TRY(pool_typed(ctx, S_TMP0, 128, &src_dev));  // traversal ids, then caller ids
   Ctrl* hc = ctx->host_ctrl;
   int32_t* q[3] = {qA, qB, qC};
 
@@ -954,17 +1027,22 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
     const u64 full = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
     int32_t* dpass = depth + (int64_t)p0 * V;
     int32_t* ppass = parent ? parent + (int64_t)p0 * V : nullptr;
-    std::vector<int32_t> srcs(sources + p0, sources + p0 + kk);
-    std::vector<int32_t> uniq(srcs);
+    // srcs: this pass's sources in traversal ids [kk], then in caller ids [kk]
+    std::vector<int32_t> srcs(2 * (size_t)kk);
+    for (int32_t i = 0; i < kk; ++i) {
+      srcs[i] = g->to_new(sources[p0 + i]);
+      srcs[kk + i] = sources[p0 + i];
+    }
+    std::vector<int32_t> uniq(srcs.begin(), srcs.begin() + kk);
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
     for (u64* m : {visit, front[0], front[1], next})
       GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(m), 2 * V, 0u, st));
-    GR_HIP(hipMemcpyAsync(src_dev, srcs.data(), sizeof(int32_t) * kk, hipMemcpyHostToDevice, st));
+    GR_HIP(hipMemcpyAsync(src_dev, srcs.data(), sizeof(int32_t) * 2 * kk, hipMemcpyHostToDevice, st));
     GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * uniq.size(), hipMemcpyHostToDevice, st));
     GR_HIP(launch_fill_u32(&ctrl->q_count[0], 1, (uint32_t)uniq.size(), st));
     GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
-    GR_HIP(launch_ms_seed(src_dev, kk, visit, front[0], dpass, V, st));
+    GR_HIP(launch_ms_seed(src_dev, src_dev + kk, kk, visit, front[0], dpass, V, st));
     int cur = 0, fc = 0, sp = 0, level = 0;
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[(cur + 1) % 3], nullptr, st));
@@ -990,8 +1068,8 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
       }
       inspected += pull ? E : m_a;
       GR_HIP(launch_ms_finalize(q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], pull ? V : std::min(V, m_a),
-                                g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass, ppass, V,
-                                level + 1, st));
+                                g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass, ppass,
+                                g->perm, V, level + 1, st));
       GR_HIP(launch_ms_clear(q[cur], &ctrl->q_count[cur], n_a, front[fc], st));
       fc ^= 1;
       cur = (cur + 1) % 3;

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 #include <string>
@@ -45,6 +47,8 @@ enum Slot : int {
   S_DLOG,          // per-level log of a device-predicated block (n_f, m_f, max degree)
   S_FAR,           // SSSP far piles: three rotating int32[V]
   S_FAR_TAGS,      // SSSP far-pile generation per vertex
+  S_DEPTH,         // BFS depth / parent in renumbered ids (mapped back at the end)
+  S_PARENT,
   S_OFFSETS,       // exclusive scan of frontier degrees [n_f + 1]
   S_RSTART,        // row start of every frontier vertex [n_f]
   S_BLOCK_SUMS,    // per-block partial sums for the frontier scan
@@ -111,9 +115,19 @@ struct gr_graph {
   uint32_t flags = 0;
   uint32_t max_weight = 0;
   int32_t resorted = 0;
+  // Traversals run on the CSR below.  With GR_RENUMBER its vertices are
+  // renumbered by descending degree (ties by id): row i is the
+  // caller's row perm[i] with every neighbour renamed and kept in the
+  // caller's order (ascending original ids), so "first frontier neighbour"
+  // is still the smallest original id.  Outputs are mapped back.
   int32_t* R = nullptr;   // device row offsets [V+1]
-  int32_t* C = nullptr;   // device column indices [E], each row ascending
+  int32_t* C = nullptr;   // device column indices [E]
   uint32_t* W = nullptr;  // device weights [E] or null
+  int32_t* perm = nullptr;    // new id -> caller id (null: ids kept)
+  int32_t* inv = nullptr;     // caller id -> new id
+  int32_t* R_orig = nullptr;  // caller's row offsets (export)
+  std::vector<int32_t> inv_host;  // caller id -> new id, for host-given sources
+  int32_t to_new(int32_t v) const { return perm ? inv_host[(size_t)v] : v; }
 };
 
 namespace gr {
@@ -129,6 +143,14 @@ hipError_t launch_row_sort(int32_t* R, int32_t* C, uint32_t* W, int64_t V, const
                            int64_t n_rows, uint64_t* scratch, hipStream_t st);
 hipError_t launch_find_unsorted(const int32_t* R, const int32_t* C, const uint32_t* W, int64_t V,
                                 int32_t* rows_out, uint32_t* count, hipStream_t st);
+// Renumber by descending degree (see gr_graph); all outputs preallocated
+// (perm, inv [V], R_new [V+1], C_new, W_new [E]).
+hipError_t relabel_by_degree(const int32_t* R, const int32_t* C, const uint32_t* W, int64_t V,
+                             int64_t E, int32_t* perm, int32_t* inv, int32_t* R_new,
+                             int32_t* C_new, uint32_t* W_new, hipStream_t st);
+hipError_t launch_unrelabel(const int32_t* R_orig, const int32_t* perm, const int32_t* inv,
+                            const int32_t* R_new, const int32_t* C_new, const uint32_t* W_new,
+                            int64_t V, int64_t E, int32_t* C, uint32_t* W, hipStream_t st);
 hipError_t launch_graph_stats(const int32_t* R, const uint32_t* W, int64_t V, int64_t E,
                               int64_t* out2, hipStream_t st);
 
@@ -144,6 +166,10 @@ hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const i
                                    int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
                                    int32_t chunk, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
+// out[perm[i]] = in[i] for the depth and (nullable) parent arrays
+hipError_t launch_permute_out(const int32_t* perm, int64_t V, const int32_t* depth_in,
+                              const int32_t* parent_in, int32_t* depth_out, int32_t* parent_out,
+                              hipStream_t st);
 
 // BFS.  Visited state: one array of word pairs, bm[2w + p] = "old" word w
 // (depth <= d) and bm[2w + 1 - p] = "live" word w, p = level parity.
@@ -151,12 +177,13 @@ hipError_t launch_bfs_init(int32_t* depth, int32_t* parent, int64_t V, uint32_t*
                            int64_t n_words, int32_t source, int32_t* queue, Ctrl* ctrl,
                            hipStream_t st);
 // mode: 0 = TWC, 1 = LB_LIGHT (input balanced), 2 = LB (output balanced)
+// Parent values are caller ids: perm (nullable) maps renumbered ids back.
 hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier,
                            const int32_t* offsets, const int32_t* rstart,
                            const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
                            const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
-                           int32_t next_depth, int32_t* out_q, uint32_t* out_count, int chunk,
-                           hipStream_t st);
+                           const int32_t* perm, int32_t next_depth, int32_t* out_q,
+                           uint32_t* out_count, int chunk, hipStream_t st);
 // Push with the non-atomic filter: byte marks (all zero before and after),
 // then an ordered compaction of the marked vertices.
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
@@ -170,16 +197,19 @@ hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int 
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
                                    const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
-                                   int32_t* parent, hipStream_t st);
+                                   int32_t* parent, const int32_t* perm, hipStream_t st);
 hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
-                           int p, int32_t* depth, int32_t* parent, int32_t next_depth,
-                           int32_t* out_q, uint32_t* out_count, int64_t* inspected, hipStream_t st);
+                           int p, int32_t* depth, int32_t* parent, const int32_t* perm,
+                           int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                           int64_t* inspected, hipStream_t st);
 // live |= old (live = depth <= d + 1 after level d)
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
 
-// multi-source BFS (64-bit source masks per vertex)
-hipError_t launch_ms_seed(const int32_t* src_dev, int32_t k, unsigned long long* visit,
-                          unsigned long long* front, int32_t* depth, int64_t V, hipStream_t st);
+// multi-source BFS (64-bit source masks per vertex); depth / parent are the
+// caller's [k][V] arrays in caller ids (perm nullable)
+hipError_t launch_ms_seed(const int32_t* src_dev, const int32_t* src_orig_dev, int32_t k,
+                          unsigned long long* visit, unsigned long long* front, int32_t* depth,
+                          int64_t V, hipStream_t st);
 hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offsets,
                           const int32_t* rstart, const int32_t* chunk_start, int64_t n_a,
                           int64_t m_a, const int32_t* R, const int32_t* C,
@@ -193,8 +223,8 @@ hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C,
 hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched, int64_t max_n,
                               const int32_t* R, const int32_t* C, const unsigned long long* front,
                               unsigned long long* front_next, unsigned long long* visit,
-                              unsigned long long* next, int32_t* depth, int32_t* parent, int64_t V,
-                              int32_t next_depth, hipStream_t st);
+                              unsigned long long* next, int32_t* depth, int32_t* parent,
+                              const int32_t* perm, int64_t V, int32_t next_depth, hipStream_t st);
 hipError_t launch_ms_clear(const int32_t* list, const uint32_t* n, int64_t max_n,
                            unsigned long long* front, hipStream_t st);
 hipError_t launch_ms_teps(const unsigned long long* visit, const int32_t* R, int64_t V, int64_t* out,
@@ -241,9 +271,10 @@ struct DlArgs {
 hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, uint32_t pq_T,
                            int32_t pq_epoch, int32_t pq_fc, hipStream_t st);
 hipError_t launch_bfs_dstep(const DlArgs& a, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
-                            int32_t next_depth, int n_blocks, hipStream_t st);
+                            const int32_t* perm, int32_t next_depth, int n_blocks, hipStream_t st);
 hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
-                             int32_t* tags, int32_t next_tag, int n_blocks, hipStream_t st);
+                             int32_t* tags, const int32_t* perm, int32_t next_tag, int n_blocks,
+                             hipStream_t st);
 // SSSP with the two-level priority queue: improved vertices with dist < T go
 // to the next frontier, the others to far pile `fc` (once per epoch).
 struct PqState {
@@ -254,6 +285,7 @@ struct PqState {
   int32_t* far_base;          // three piles of V entries
   int32_t* far_tag;
   int64_t V;
+  const int32_t* perm;        // predecessor values in caller ids (nullable)
 };
 hipError_t launch_sssp_pq_relax(int mode, const int32_t* frontier, const int32_t* offsets,
                                 const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
@@ -274,13 +306,17 @@ hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* fa
                             hipStream_t st);
 hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long long* keys,
                             int32_t* tags, Ctrl* ctrl, hipStream_t st);
+// keys hold (dist << 32 | predecessor in caller ids); perm nullable
 hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* offsets,
                              const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                              int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
-                             unsigned long long* keys, int32_t* tags, int32_t next_tag,
-                             int32_t* out_q, uint32_t* out_count, int chunk, hipStream_t st);
+                             unsigned long long* keys, int32_t* tags, const int32_t* perm,
+                             int32_t next_tag, int32_t* out_q, uint32_t* out_count, int chunk,
+                             hipStream_t st);
+// dist / pred written at caller ids; src_orig_dev: the sources in caller ids
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
-                                uint32_t* dist, int32_t* pred, const int32_t* src_dev,
-                                int32_t n_src, int64_t* reached_edges, hipStream_t st);
+                                uint32_t* dist, int32_t* pred, const int32_t* perm,
+                                const int32_t* src_orig_dev, int32_t n_src, int64_t* reached_edges,
+                                hipStream_t st);
 
 }  // namespace gr

@@ -10,6 +10,12 @@
 //   kFar                                     true for functors whose commit
 //                                            returns 0 / 1 / 2: 2 appends v to
 //                                            a second queue (f.far_q, f.far_count)
+//   kBatchCommit                             true for functors that provide
+//                                            commit_batch<B>(u, pay, v, ev, ok, code):
+//                                            the commits of a lane's B edges in
+//                                            phases, so that their atomics are in
+//                                            flight together instead of one
+//                                            round trip after another
 // Edges are handled in batches: every lane first issues all of its
 // column-index loads, then all probe loads, then the atomics of the edges
 // that survive, then one wavefront-aggregated append; independent loads are
@@ -61,9 +67,16 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
   for (int r = 0; r < B; ++r) ok[r] = ok[r] && f.probe(u[r], pay[r], v[r], ev[r]);
   uint32_t n_app = 0, n_far = 0;
   bool far[B];
+  int code[B];
+  if constexpr (F::kBatchCommit) {
+    f.template commit_batch<B>(u, pay, v, ev, ok, code);
+  } else {
+#pragma unroll
+    for (int r = 0; r < B; ++r) code[r] = ok[r] ? (int)f.commit(u[r], pay[r], v[r], ev[r]) : 0;
+  }
 #pragma unroll
   for (int r = 0; r < B; ++r) {
-    const int c = ok[r] ? (int)f.commit(u[r], pay[r], v[r], ev[r]) : 0;
+    const int c = code[r];
     ok[r] = c == 1;
     far[r] = F::kFar && c == 2;
     n_app += ok[r] ? 1u : 0u;

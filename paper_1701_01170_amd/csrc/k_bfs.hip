@@ -29,17 +29,25 @@ __device__ __forceinline__ uint2 bm_pair(const uint32_t* bm, int32_t w) {
   return reinterpret_cast<const uint2*>(bm)[w];
 }
 
+__device__ __forceinline__ int32_t caller_id(const int32_t* perm, int32_t v) {
+  return perm ? perm[v] : v;
+}
+
 template <bool ATOMIC_PARENT>
 struct BfsVisit {
   uint32_t* __restrict__ bm;
   int32_t* __restrict__ depth;
   int32_t* __restrict__ parent;
+  const int32_t* __restrict__ perm;  // renumbered -> caller ids (nullable)
   int32_t next_depth;
   int32_t p;  // parity: old word = 2w + p
 
-  using pay_t = int32_t;
+  using pay_t = int32_t;  // the frontier vertex's caller id (parents compare caller ids)
   static constexpr bool kFar = false;
-  __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
+  static constexpr bool kBatchCommit = true;
+  __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
+    return ATOMIC_PARENT && parent ? caller_id(perm, u) : 0;
+  }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
     const uint2 x = bm_pair(bm, v >> 5);
@@ -48,17 +56,49 @@ struct BfsVisit {
     if (ATOMIC_PARENT) return !(old & bit);
     return !((old | live) & bit);
   }
-  __device__ __forceinline__ bool commit(int32_t u, int32_t, int32_t v, uint32_t) const {
+  __device__ __forceinline__ bool commit(int32_t, int32_t pu, int32_t v, uint32_t) const {
     const uint32_t bit = 1u << (v & 31);
     uint32_t* live = &bm[2 * (v >> 5) + 1 - p];
     if (ATOMIC_PARENT) {
-      if (parent) atomicMin(reinterpret_cast<uint32_t*>(&parent[v]), (uint32_t)u);
+      if (parent) atomicMin(reinterpret_cast<uint32_t*>(&parent[v]), (uint32_t)pu);
       if (*live & bit) return false;
     }
     const uint32_t prev = atomicOr(live, bit);
     if (prev & bit) return false;
     depth[v] = next_depth;
     return true;
+  }
+  // commit() for a lane's B edges in phases: parent minima (no return value
+  // needed), then the live-word reads, then the OR of every still-clear bit,
+  // so no edge waits for another edge's atomic.
+  template <int B>
+  __device__ __forceinline__ void commit_batch(const int32_t (&)[B], const int32_t (&pu)[B],
+                                               const int32_t (&v)[B], const uint32_t (&)[B],
+                                               const bool (&ok)[B], int (&code)[B]) const {
+    uint32_t* live[B];
+    uint32_t bit[B], w[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      bit[r] = 1u << (v[r] & 31);
+      live[r] = &bm[2 * (v[r] >> 5) + 1 - p];
+    }
+    if (ATOMIC_PARENT && parent) {
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (ok[r]) atomicMin(reinterpret_cast<uint32_t*>(&parent[v[r]]), (uint32_t)pu[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) w[r] = (ATOMIC_PARENT && ok[r]) ? *live[r] : 0u;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const bool go = ok[r] && !(w[r] & bit[r]);
+      w[r] = go ? atomicOr(live[r], bit[r]) : bit[r];
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      code[r] = (w[r] & bit[r]) ? 0 : 1;
+      if (code[r]) depth[v[r]] = next_depth;
+    }
   }
   // Device-predicated steps have no merge pass: each frontier vertex joins
   // live during its own level instead.  Push probes only test old, and
@@ -82,6 +122,7 @@ struct BfsMark {
 
   using pay_t = int32_t;
   static constexpr bool kFar = false;
+  static constexpr bool kBatchCommit = false;
   __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
@@ -235,8 +276,8 @@ template <int GW>
 __global__ __launch_bounds__(256) void k_bfs_pull_bm(
     int64_t V, const int32_t* __restrict__ R, const int32_t* __restrict__ C,
     uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth, int32_t* __restrict__ parent,
-    int32_t next_depth, int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count,
-    int64_t* __restrict__ inspected) {
+    const int32_t* __restrict__ perm, int32_t next_depth, int32_t* __restrict__ out_q,
+    uint32_t* __restrict__ out_count, int64_t* __restrict__ inspected) {
   static_assert(GW >= 1 && GW < kWave && (kWave % GW) == 0, "group width");
   constexpr int NW = 256 / kWave;
   constexpr int VPR = kWave / GW;  // vertices per sub-round
@@ -268,7 +309,7 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
       const bool hit = cand && found >= 0;
       if (hit) {
         depth[v] = next_depth;
-        if (parent) parent[v] = found;
+        if (parent) parent[v] = caller_id(perm, found);
       }
       hb = __ballot(hit);
       scanned += sc;
@@ -319,7 +360,7 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
         const bool hit = leader && cand && found >= 0;
         if (hit) {
           depth[v] = next_depth;
-          if (parent) parent[v] = found;
+          if (parent) parent[v] = caller_id(perm, found);
         }
         const uint64_t lb = __ballot(hit);  // bit g * GW for group g
         uint64_t m = 0;
@@ -366,7 +407,8 @@ __global__ __launch_bounds__(256) void k_bfs_parent_fixup(const int32_t* __restr
                                                           const int32_t* __restrict__ R,
                                                           const int32_t* __restrict__ C,
                                                           const uint32_t* __restrict__ bm, int p,
-                                                          int32_t* __restrict__ parent) {
+                                                          int32_t* __restrict__ parent,
+                                                          const int32_t* __restrict__ perm) {
   const int64_t n = *count;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int64_t)blockIdx.x * blockDim.x >= n) return;  // whole block past the end
@@ -379,7 +421,7 @@ __global__ __launch_bounds__(256) void k_bfs_parent_fixup(const int32_t* __restr
   }
   int64_t scanned;
   const int32_t par = first_frontier_nbr<32>(valid, rb, re, C, bm, p, &scanned);
-  if (valid) parent[v] = par;
+  if (valid) parent[v] = caller_id(perm, par);
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -390,14 +432,14 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
                            const int32_t* offsets, const int32_t* rstart,
                            const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
                            const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
-                           int32_t next_depth, int32_t* out_q, uint32_t* out_count, int chunk,
-                           hipStream_t st) {
+                           const int32_t* perm, int32_t next_depth, int32_t* out_q,
+                           uint32_t* out_count, int chunk, hipStream_t st) {
   if (atomic_parent) {
-    BfsVisit<true> f{bm, depth, parent, next_depth, p};
+    BfsVisit<true> f{bm, depth, parent, perm, next_depth, p};
     return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
                          out_count, chunk, st);
   }
-  BfsVisit<false> f{bm, depth, nullptr, next_depth, p};
+  BfsVisit<false> f{bm, depth, nullptr, nullptr, next_depth, p};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
                        out_count, chunk, st);
 }
@@ -422,29 +464,31 @@ hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int 
 
 hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
                                    const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
-                                   int32_t* parent, hipStream_t st) {
+                                   int32_t* parent, const int32_t* perm, hipStream_t st) {
   if (max_count <= 0) return hipSuccess;
-  k_bfs_parent_fixup<<<blocks_for(max_count, 256), 256, 0, st>>>(list, count, R, C, bm, p, parent);
+  k_bfs_parent_fixup<<<blocks_for(max_count, 256), 256, 0, st>>>(list, count, R, C, bm, p, parent,
+                                                                 perm);
   return hipGetLastError();
 }
 
 hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
-                           int p, int32_t* depth, int32_t* parent, int32_t next_depth,
-                           int32_t* out_q, uint32_t* out_count, int64_t* inspected, hipStream_t st) {
+                           int p, int32_t* depth, int32_t* parent, const int32_t* perm,
+                           int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                           int64_t* inspected, hipStream_t st) {
   if (V <= 0) return hipSuccess;
   const unsigned g = blocks_for(V, 256 * kPullRuns);
   if (lb)
-    k_bfs_pull_bm<4><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, next_depth, out_q, out_count,
-                                        inspected);
+    k_bfs_pull_bm<4><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, perm, next_depth, out_q,
+                                        out_count, inspected);
   else
-    k_bfs_pull_bm<1><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, next_depth, out_q, out_count,
-                                        inspected);
+    k_bfs_pull_bm<1><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, perm, next_depth, out_q,
+                                        out_count, inspected);
   return hipGetLastError();
 }
 
 hipError_t launch_bfs_dstep(const DlArgs& a, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
-                            int32_t next_depth, int n_blocks, hipStream_t st) {
-  const BfsVisit<true> f{bm, depth, parent, next_depth, p};
+                            const int32_t* perm, int32_t next_depth, int n_blocks, hipStream_t st) {
+  const BfsVisit<true> f{bm, depth, parent, perm, next_depth, p};
   k_dstep<BfsVisit<true>><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
   return hipGetLastError();
 }

@@ -146,6 +146,19 @@ __global__ __launch_bounds__(256) void k_bitmap_merge(uint32_t* __restrict__ bm,
   }
 }
 
+__global__ __launch_bounds__(256) void k_permute_out(const int32_t* __restrict__ perm, int64_t V,
+                                                     const int32_t* __restrict__ depth_in,
+                                                     const int32_t* __restrict__ parent_in,
+                                                     int32_t* __restrict__ depth_out,
+                                                     int32_t* __restrict__ parent_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < V) {
+    const int32_t o = perm[i];
+    depth_out[o] = depth_in[i];
+    if (parent_out) parent_out[o] = parent_in[i];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n,
                                                   uint32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,6 +225,15 @@ hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t
 hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, uint32_t pq_T,
                            int32_t pq_epoch, int32_t pq_fc, hipStream_t st) {
   k_dl_begin<<<1, 1, 0, st>>>(ctrl, cur, sp, vm, vn, pq_T, pq_epoch, pq_fc);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_out(const int32_t* perm, int64_t V, const int32_t* depth_in,
+                              const int32_t* parent_in, int32_t* depth_out, int32_t* parent_out,
+                              hipStream_t st) {
+  if (V <= 0) return hipSuccess;
+  k_permute_out<<<blocks_for(V, 256), 256, 0, st>>>(perm, V, depth_in, parent_in, depth_out,
+                                                    parent_out);
   return hipGetLastError();
 }
 

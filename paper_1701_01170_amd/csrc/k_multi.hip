@@ -24,6 +24,7 @@ struct MsPush {
   u64* __restrict__ next;
   using pay_t = u64;
   static constexpr bool kFar = false;
+  static constexpr bool kBatchCommit = false;
 
   const u64* __restrict__ front;
   __device__ __forceinline__ u64 seg_payload(int32_t u) const { return front[u]; }
@@ -103,21 +104,24 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
     const int32_t* __restrict__ touched, const uint32_t* __restrict__ n_touched,
     const int32_t* __restrict__ R, const int32_t* __restrict__ C, const u64* __restrict__ front,
     u64* __restrict__ front_next, u64* __restrict__ visit, u64* __restrict__ next,
-    int32_t* __restrict__ depth, int32_t* __restrict__ parent, int64_t V, int32_t next_depth) {
+    int32_t* __restrict__ depth, int32_t* __restrict__ parent, const int32_t* __restrict__ perm,
+    int64_t V, int32_t next_depth) {
   constexpr int U = 8;
   const int64_t n = *n_touched;
   if ((int64_t)blockIdx.x * blockDim.x >= n) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < n;
   int32_t v = 0, rb = 0, re = 0;
+  int64_t vo = 0;  // v's caller id: the output column
   u64 nw = 0;
   if (valid) {
     v = touched[i];
+    vo = perm ? perm[v] : v;
     nw = next[v];
     next[v] = 0;
     visit[v] |= nw;
     front_next[v] = nw;
-    for (u64 b = nw; b; b &= b - 1) depth[(int64_t)(__ffsll(b) - 1) * V + v] = next_depth;
+    for (u64 b = nw; b; b &= b - 1) depth[(int64_t)(__ffsll(b) - 1) * V + vo] = next_depth;
     if (parent) {
       rb = R[v];
       re = R[v + 1];
@@ -138,7 +142,8 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
       for (int r = 0; r < U; ++r) {
         u64 g = f[r] & nw & ~found;
         found |= g;
-        for (; g; g &= g - 1) parent[(int64_t)(__ffsll(g) - 1) * V + v] = u[r];
+        const int32_t uo = g ? (perm ? perm[u[r]] : u[r]) : 0;
+        for (; g; g &= g - 1) parent[(int64_t)(__ffsll(g) - 1) * V + vo] = uo;
       }
     }
   }
@@ -146,7 +151,8 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
   while (big) {
     const int l = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
-    const int32_t vb = __shfl(rb, l), ve = __shfl(re, l), vv = __shfl(v, l);
+    const int32_t vb = __shfl(rb, l), ve = __shfl(re, l);
+    const int64_t vv = __shfl(vo, l);
     const u64 nd = __shfl(nw, l);
     u64 fnd = 0;
     for (int32_t base = vb; base < ve && fnd != nd; base += U * kWave) {
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
           g &= g - 1;
           const uint64_t b = __ballot((f[r] >> s) & 1ull);
           const int32_t pu = __shfl(u[r], __ffsll((unsigned long long)b) - 1);
-          if (lane() == 0) parent[(int64_t)s * V + vv] = pu;
+          if (lane() == 0) parent[(int64_t)s * V + vv] = perm ? perm[pu] : pu;
           fnd |= 1ull << s;
         }
       }
@@ -176,7 +182,8 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
   }
 }
 
-__global__ __launch_bounds__(256) void k_ms_seed(const int32_t* __restrict__ src, int32_t k,
+__global__ __launch_bounds__(256) void k_ms_seed(const int32_t* __restrict__ src,
+                                                 const int32_t* __restrict__ src_orig, int32_t k,
                                                  u64* __restrict__ visit, u64* __restrict__ front,
                                                  int32_t* __restrict__ depth, int64_t V) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(256) void k_ms_seed(const int32_t* __restrict__ src
     const int32_t v = src[s];
     atomicOr(&visit[v], 1ull << s);
     atomicOr(&front[v], 1ull << s);
-    depth[(int64_t)s * V + v] = 0;
+    depth[(int64_t)s * V + src_orig[s]] = 0;
   }
 }
 
@@ -218,9 +225,9 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
-hipError_t launch_ms_seed(const int32_t* src_dev, int32_t k, u64* visit, u64* front,
-                          int32_t* depth, int64_t V, hipStream_t st) {
-  k_ms_seed<<<1, 256, 0, st>>>(src_dev, k, visit, front, depth, V);
+hipError_t launch_ms_seed(const int32_t* src_dev, const int32_t* src_orig_dev, int32_t k,
+                          u64* visit, u64* front, int32_t* depth, int64_t V, hipStream_t st) {
+  k_ms_seed<<<1, 256, 0, st>>>(src_dev, src_orig_dev, k, visit, front, depth, V);
   return hipGetLastError();
 }
 
@@ -245,11 +252,12 @@ hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C, const u
 hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched, int64_t max_n,
                               const int32_t* R, const int32_t* C, const u64* front,
                               u64* front_next, u64* visit, u64* next, int32_t* depth,
-                              int32_t* parent, int64_t V, int32_t next_depth, hipStream_t st) {
+                              int32_t* parent, const int32_t* perm, int64_t V, int32_t next_depth,
+                              hipStream_t st) {
   if (max_n <= 0) return hipSuccess;
   k_ms_finalize<<<blocks_for(max_n, 256), 256, 0, st>>>(touched, n_touched, R, C, front,
-                                                        front_next, visit, next, depth, parent, V,
-                                                        next_depth);
+                                                        front_next, visit, next, depth, parent,
+                                                        perm, V, next_depth);
   return hipGetLastError();
 }
 

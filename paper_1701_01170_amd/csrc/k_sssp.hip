@@ -26,30 +26,60 @@ namespace gr {
 
 namespace {
 
+// Payload of a frontier vertex: its distance.  The predecessor written into
+// a neighbour's key is the vertex's caller id (so ties between predecessors
+// compare caller ids); the probe does not need it: it passes every edge that
+// does not lengthen the distance, and the atomic minimum settles ties.
+__device__ __forceinline__ uint32_t caller_id(const int32_t* perm, int32_t u) {
+  return (uint32_t)(perm ? perm[u] : u);
+}
+
 struct SsspVisit {
   const uint32_t* __restrict__ W;
   unsigned long long* __restrict__ keys;
   int32_t* __restrict__ tags;
+  const int32_t* __restrict__ perm;
   int32_t next_tag;
 
   using pay_t = int32_t;
   static constexpr bool kFar = false;
+  static constexpr bool kBatchCommit = true;
   __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
     return (int32_t)(uint32_t)(keys[u] >> 32);
   }
   __device__ __forceinline__ uint32_t edge_value(int64_t e) const { return W[e]; }
-  __device__ __forceinline__ bool probe(int32_t u, int32_t du, int32_t v, uint32_t w) const {
+  __device__ __forceinline__ bool probe(int32_t, int32_t du, int32_t v, uint32_t w) const {
     const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
     if (cand >= 0xffffffffull) return false;  // cannot be a shortest distance (range checked at entry)
-    const unsigned long long nk = (cand << 32) | (uint32_t)u;
-    return nk < keys[v];                       // keys only decrease: otherwise nothing to gain
+    return cand <= (keys[v] >> 32);            // keys only decrease: otherwise nothing to gain
   }
   __device__ __forceinline__ bool commit(int32_t u, int32_t du, int32_t v, uint32_t w) const {
     const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
-    const unsigned long long nk = (cand << 32) | (uint32_t)u;
+    const unsigned long long nk = (cand << 32) | caller_id(perm, u);
     const unsigned long long old = atomicMin(&keys[v], nk);
     if (cand >= (old >> 32)) return false;     // no distance improvement (at most a better pred)
     return atomicExch(&tags[v], next_tag) != next_tag;
+  }
+  // commit() for a lane's B edges in phases: all atomic minima, then the tag
+  // exchanges of the improved vertices, so no edge waits for another's atomic.
+  template <int B>
+  __device__ __forceinline__ void commit_batch(const int32_t (&u)[B], const int32_t (&du)[B],
+                                               const int32_t (&v)[B], const uint32_t (&w)[B],
+                                               const bool (&ok)[B], int (&code)[B]) const {
+    unsigned long long nk[B];
+    int32_t prev[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      nk[r] = (((uint64_t)(uint32_t)du[r] + (uint64_t)w[r]) << 32) | (ok[r] ? caller_id(perm, u[r]) : 0u);
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const unsigned long long old = ok[r] ? atomicMin(&keys[v[r]], nk[r]) : 0ull;
+      code[r] = ok[r] && (nk[r] >> 32) < (old >> 32);
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) prev[r] = code[r] ? atomicExch(&tags[v[r]], next_tag) : next_tag;
+#pragma unroll
+    for (int r = 0; r < B; ++r) code[r] = prev[r] != next_tag;
   }
   __device__ __forceinline__ void frontier_vertex(int32_t) const {}
   __device__ __forceinline__ SsspVisit prepare(const Ctrl*, int) const { return *this; }
@@ -112,27 +142,51 @@ struct SsspPqVisit {
   int64_t V;
   int32_t* __restrict__ far_q;    // far_base + fc * V
   uint32_t* far_count;            // &ctrl->far_count[fc]
+  const int32_t* __restrict__ perm;
 
   using pay_t = int32_t;
   static constexpr bool kFar = true;
+  static constexpr bool kBatchCommit = true;
   __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
     return (int32_t)(uint32_t)(keys[u] >> 32);
   }
   __device__ __forceinline__ uint32_t edge_value(int64_t e) const { return W[e]; }
-  __device__ __forceinline__ bool probe(int32_t u, int32_t du, int32_t v, uint32_t w) const {
+  __device__ __forceinline__ bool probe(int32_t, int32_t du, int32_t v, uint32_t w) const {
     const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
     if (cand >= 0xffffffffull) return false;
-    const unsigned long long nk = (cand << 32) | (uint32_t)u;
-    return nk < keys[v];
+    return cand <= (keys[v] >> 32);
   }
   // 1: next frontier, 2: far pile, 0: nothing to append
   __device__ __forceinline__ int commit(int32_t u, int32_t du, int32_t v, uint32_t w) const {
     const uint64_t cand = (uint64_t)(uint32_t)du + (uint64_t)w;
-    const unsigned long long nk = (cand << 32) | (uint32_t)u;
+    const unsigned long long nk = (cand << 32) | caller_id(perm, u);
     const unsigned long long old = atomicMin(&keys[v], nk);
     if (cand >= (old >> 32)) return 0;
     if (cand < T) return atomicExch(&tags[v], next_tag) != next_tag ? 1 : 0;
     return atomicExch(&far_tag[v], epoch) != epoch ? 2 : 0;
+  }
+  template <int B>
+  __device__ __forceinline__ void commit_batch(const int32_t (&u)[B], const int32_t (&du)[B],
+                                               const int32_t (&v)[B], const uint32_t (&w)[B],
+                                               const bool (&ok)[B], int (&code)[B]) const {
+    unsigned long long nk[B];
+    int32_t prev[B];
+    bool imp[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      nk[r] = (((uint64_t)(uint32_t)du[r] + (uint64_t)w[r]) << 32) | (ok[r] ? caller_id(perm, u[r]) : 0u);
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const unsigned long long old = ok[r] ? atomicMin(&keys[v[r]], nk[r]) : 0ull;
+      imp[r] = ok[r] && (nk[r] >> 32) < (old >> 32);
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const bool near = (nk[r] >> 32) < T;
+      const int32_t val = near ? next_tag : epoch;
+      prev[r] = imp[r] ? atomicExch(near ? &tags[v[r]] : &far_tag[v[r]], val) : val;
+      code[r] = prev[r] != val ? (near ? 1 : 2) : 0;
+    }
   }
   __device__ __forceinline__ void frontier_vertex(int32_t) const {}
   // device-predicated levels read the queue state of their step
@@ -218,6 +272,7 @@ __global__ __launch_bounds__(256) void k_sssp_finalize(const unsigned long long*
                                                        const int32_t* __restrict__ R, int64_t V,
                                                        uint32_t* __restrict__ dist,
                                                        int32_t* __restrict__ pred,
+                                                       const int32_t* __restrict__ perm,
                                                        int64_t* __restrict__ reached_edges) {
   __shared__ int64_t s[256 / kWave];
   int64_t acc = 0;
@@ -225,8 +280,9 @@ __global__ __launch_bounds__(256) void k_sssp_finalize(const unsigned long long*
        v += (int64_t)gridDim.x * blockDim.x) {
     const unsigned long long k = keys[v];
     const uint32_t d = (uint32_t)(k >> 32);
-    dist[v] = d;
-    if (pred) pred[v] = (int32_t)(uint32_t)(k & 0xffffffffull);
+    const int64_t o = perm ? perm[v] : v;
+    dist[o] = d;
+    if (pred) pred[o] = (int32_t)(uint32_t)(k & 0xffffffffull);
     if (d != 0xffffffffu) acc += (int64_t)R[v + 1] - R[v];
   }
   acc = wave_sum(acc);
@@ -267,26 +323,30 @@ hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long lon
 hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* offsets,
                              const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                              int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
-                             unsigned long long* keys, int32_t* tags, int32_t next_tag,
-                             int32_t* out_q, uint32_t* out_count, int chunk, hipStream_t st) {
-  SsspVisit f{W, keys, tags, next_tag};
+                             unsigned long long* keys, int32_t* tags, const int32_t* perm,
+                             int32_t next_tag, int32_t* out_q, uint32_t* out_count, int chunk,
+                             hipStream_t st) {
+  SsspVisit f{W, keys, tags, perm, next_tag};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
                        out_count, chunk, st);
 }
 
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
-                                uint32_t* dist, int32_t* pred, const int32_t* src_dev,
-                                int32_t n_src, int64_t* reached_edges, hipStream_t st) {
+                                uint32_t* dist, int32_t* pred, const int32_t* perm,
+                                const int32_t* src_orig_dev, int32_t n_src, int64_t* reached_edges,
+                                hipStream_t st) {
   unsigned g = blocks_for(V, 256);
   if (g > 4096) g = 4096;
-  k_sssp_finalize<<<g, 256, 0, st>>>(keys, R, V, dist, pred, reached_edges);
-  if (pred) k_sssp_source_pred<<<blocks_for(n_src, 256), 256, 0, st>>>(src_dev, n_src, pred);
+  k_sssp_finalize<<<g, 256, 0, st>>>(keys, R, V, dist, pred, perm, reached_edges);
+  if (pred)
+    k_sssp_source_pred<<<blocks_for(n_src, 256), 256, 0, st>>>(src_orig_dev, n_src, pred);
   return hipGetLastError();
 }
 
 hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long long* keys,
-                             int32_t* tags, int32_t next_tag, int n_blocks, hipStream_t st) {
-  const SsspVisit f{W, keys, tags, next_tag};
+                             int32_t* tags, const int32_t* perm, int32_t next_tag, int n_blocks,
+                             hipStream_t st) {
+  const SsspVisit f{W, keys, tags, perm, next_tag};
   k_dstep<SsspVisit><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
   return hipGetLastError();
 }
@@ -294,8 +354,10 @@ hipError_t launch_sssp_dstep(const DlArgs& a, const uint32_t* W, unsigned long l
 namespace {
 SsspPqVisit pq_functor(const uint32_t* W, unsigned long long* keys, int32_t* tags, int32_t next_tag,
                        const PqState& pq, Ctrl* ctrl) {
-  return SsspPqVisit{W, keys, tags, next_tag, pq.T, pq.delta, pq.epoch, pq.fc, pq.far_base,
-                     pq.far_tag, pq.V, pq.far_base + (int64_t)pq.fc * pq.V, &ctrl->far_count[pq.fc]};
+  return SsspPqVisit{W,          keys,     tags,          next_tag,
+                     pq.T,       pq.delta, pq.epoch,      pq.fc,
+                     pq.far_base, pq.far_tag, pq.V,     pq.far_base + (int64_t)pq.fc * pq.V,
+                     &ctrl->far_count[pq.fc], pq.perm};
 }
 }  // namespace
 

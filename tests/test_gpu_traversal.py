@@ -59,38 +59,50 @@ def np_of(t):
     return t.cpu().numpy()
 
 
+# every traversal runs in the caller's numbering (the default) and on the
+# degree-renumbered graph
+ORDERS = (False, True)
+
+
 def run_bfs_all(ctx, hg, sources, symmetric=True, policies=POLICIES):
-    g = gr.Graph.from_host(ctx, hg, symmetric=symmetric)
-    for s in sources:
-        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
-        for name, kw in policies:
-            d, p, st = gr.bfs(g, int(s), opts=gr.default_opts(**kw))
-            np.testing.assert_array_equal(np_of(d), ed, err_msg=f"depth src={s} policy={name}")
-            np.testing.assert_array_equal(np_of(p), ep, err_msg=f"parent src={s} policy={name}")
-            assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed >= 0)
-            assert st["iterations"] == int(ed.max()) + 1
-    g.free()
+    for keep in ORDERS:
+        g = gr.Graph.from_host(ctx, hg, symmetric=symmetric, renumber=keep)
+        for s in sources:
+            ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
+            for name, kw in policies:
+                d, p, st = gr.bfs(g, int(s), opts=gr.default_opts(**kw))
+                msg = f"src={s} policy={name} renumber={keep}"
+                np.testing.assert_array_equal(np_of(d), ed, err_msg="depth " + msg)
+                np.testing.assert_array_equal(np_of(p), ep, err_msg="parent " + msg)
+                assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed >= 0)
+                assert st["iterations"] == int(ed.max()) + 1
+        g.free()
 
 
 def run_sssp_all(ctx, hg, source_sets, symmetric=True, policies=SSSP_POLICIES):
-    g = gr.Graph.from_host(ctx, hg, symmetric=symmetric)
-    for srcs in source_sets:
-        ed, ep = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, srcs)
-        for name, kw in policies:
-            d, p, st = gr.sssp(g, srcs, opts=gr.default_opts(**kw))
-            np.testing.assert_array_equal(np_of(d).view(np.uint32), ed,
-                                          err_msg=f"dist srcs={list(srcs)[:4]} policy={name}")
-            np.testing.assert_array_equal(np_of(p), ep,
-                                          err_msg=f"pred srcs={list(srcs)[:4]} policy={name}")
-            assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed != U32MAX)
-    g.free()
+    for keep in ORDERS:
+        g = gr.Graph.from_host(ctx, hg, symmetric=symmetric, renumber=keep)
+        for srcs in source_sets:
+            ed, ep = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, srcs)
+            for name, kw in policies:
+                d, p, st = gr.sssp(g, srcs, opts=gr.default_opts(**kw))
+                msg = f"srcs={list(srcs)[:4]} policy={name} renumber={keep}"
+                np.testing.assert_array_equal(np_of(d).view(np.uint32), ed, err_msg="dist " + msg)
+                np.testing.assert_array_equal(np_of(p), ep, err_msg="pred " + msg)
+                assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed != U32MAX)
+        g.free()
 
 
 @pytest.mark.parametrize("name", ["directed7.txt", "undirected_ties8.txt"])
 def test_golden(ctx, name):
     fx = load_golden(name)
     hg = golden_graph(fx)
-    g = gr.Graph.from_host(ctx, hg, symmetric=fx["undirected"])
+    for keep in ORDERS:
+        run_golden(ctx, fx, hg, keep)
+
+
+def run_golden(ctx, fx, hg, keep):
+    g = gr.Graph.from_host(ctx, hg, symmetric=fx["undirected"], renumber=keep)
     for case in fx["bfs"]:
         for pname, kw in POLICIES:
             d, p, _ = gr.bfs(g, case["source"], opts=gr.default_opts(**kw))
@@ -137,12 +149,15 @@ def test_unsorted_input_is_sorted_on_ingest(ctx, rmat14):
         C[a:b] = C[a:b][perm]
         W[a:b] = W[a:b][perm]
     shuffled = gg.HostGraph(R.copy(), C, W)
-    g = gr.Graph.from_host(ctx, shuffled)
-    assert g.resorted
-    R2, C2, W2 = g.export()
-    np.testing.assert_array_equal(np_of(C2), hg.col_indices)
-    np.testing.assert_array_equal(np_of(W2).view(np.uint32), hg.weights)
-    g.free()
+    for keep in ORDERS:
+        # export gives the sorted CSR in the caller's ids, renumbered or not
+        g = gr.Graph.from_host(ctx, shuffled, renumber=keep)
+        assert g.resorted
+        R2, C2, W2 = g.export()
+        np.testing.assert_array_equal(np_of(R2), hg.row_offsets)
+        np.testing.assert_array_equal(np_of(C2), hg.col_indices)
+        np.testing.assert_array_equal(np_of(W2).view(np.uint32), hg.weights)
+        g.free()
     srcs = gg.sources(hg, 2, seed=9)
     run_bfs_all(ctx, shuffled, srcs)
     run_sssp_all(ctx, shuffled, [[int(srcs[0])]])
