@@ -47,8 +47,11 @@ constexpr int kLbCap = 2048;  // frontier segments staged in LDS per pass
 // Process up to B edges per lane: ok[r] marks a real edge (u[r], pay[r], ce[r]).
 // With DEG, the degrees of the appended vertices are also summed into
 // *deg_sum and maximised into *deg_max (one atomic each per wavefront).  All
-// 64 lanes must take part.
-template <class F, int B, bool DEG = false>
+// 64 lanes must take part.  With AGG the whole workgroup appends with one
+// atomic (every thread of the workgroup must then call it the same number of
+// times): a single queue tail shared by the whole grid serialises its
+// atomics, so fewer of them is the point.
+template <class F, int B, bool DEG = false, bool AGG = false>
 __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict__ C, bool (&ok)[B],
                                            const int32_t (&u)[B], const typename F::pay_t (&pay)[B],
                                            const int32_t (&ce)[B], int32_t* __restrict__ out_q,
@@ -93,16 +96,24 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
         if (far[r]) f.far_q[fbase++] = v[r];
     }
   }
-  // wavefront-aggregated append of every lane's survivors
-  const uint64_t any = __ballot(n_app != 0);
-  if (any == 0) return;
-  const uint32_t inc = wave_incl_scan(n_app);
-  uint32_t base = 0;
-  if (lane() == kWave - 1) base = atomicAdd(out_count, inc);
-  base = __shfl(base, kWave - 1) + inc - n_app;
+  if constexpr (AGG) {
+    uint32_t base = block_append<kAdvBlock>(n_app, out_count);
 #pragma unroll
-  for (int r = 0; r < B; ++r)
-    if (ok[r]) out_q[base++] = v[r];
+    for (int r = 0; r < B; ++r)
+      if (ok[r]) out_q[base++] = v[r];
+    if (__ballot(n_app != 0) == 0) return;
+  } else {
+    // wavefront-aggregated append of every lane's survivors
+    const uint64_t any = __ballot(n_app != 0);
+    if (any == 0) return;
+    const uint32_t inc = wave_incl_scan(n_app);
+    uint32_t base = 0;
+    if (lane() == kWave - 1) base = atomicAdd(out_count, inc);
+    base = __shfl(base, kWave - 1) + inc - n_app;
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      if (ok[r]) out_q[base++] = v[r];
+  }
   if (DEG) {
     unsigned long long ds = 0, dm = 0;
 #pragma unroll
@@ -210,7 +221,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
         pay[r] = s_pay[k];
         ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
       }
-      edge_batch<F, EPT>(f, C, ok, u, pay, ce, out_q, out_count);
+      edge_batch<F, EPT, false, true>(f, C, ok, u, pay, ce, out_q, out_count);
     }
     __syncthreads();
   }
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_light(
       pay[r] = s_pay[k];
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
-    edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
+    edge_batch<F, B, false, true>(f, C, ok, u, pay, ce, out_q, out_count);
   }
 }
 

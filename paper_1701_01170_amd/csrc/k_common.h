@@ -30,6 +30,37 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
 
 // Inclusive prefix sum across the wavefront (all 64 lanes must be active).
 template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x);
+
+// Workgroup-aggregated append: every thread contributes n slots; one atomic
+// per workgroup reserves them all in the queue whose tail is *counter.
+// Returns the thread's first slot.  Every thread of the workgroup must call
+// it (it synchronises the workgroup).
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_append(uint32_t n, uint32_t* counter) {
+  constexpr int NW = BLOCK / kWave;
+  __shared__ uint32_t s_w[NW + 1];
+  const uint32_t inc = wave_incl_scan(n);
+  const int w = threadIdx.x / kWave;
+  if (lane() == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t c = s_w[i];
+      s_w[i] = t;
+      t += c;
+    }
+    s_w[NW] = t ? atomicAdd(counter, t) : 0u;
+  }
+  __syncthreads();
+  const uint32_t base = s_w[NW] + s_w[w] + inc - n;
+  __syncthreads();  // s_w is reused by the next call
+  return base;
+}
+
+// Inclusive prefix sum across the wavefront (all 64 lanes must be active).
+template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
       pay[r] = s_pay[k];
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
-    edge_batch<F, B, true>(fs, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
+    edge_batch<F, B, true, true>(fs, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
                            reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]),
                            reinterpret_cast<unsigned long long*>(&ctrl->dl_maxd[next]));
   }
