@@ -310,12 +310,15 @@ def main():
     from paper_1701_01170_amd import selector
     if not args.no_extras and os.path.exists(selector.WEIGHTS):
         ctx.set_policy(np.load(selector.WEIGHTS))
-        ol = gr.default_opts(policy=gr.POLICY_LEARNED)
+        # the network picks each iteration's action; thresholds and chunk
+        # sizes are the same tuned values as the headline run's
+        olb = autotune.tuned_opts(g, "bfs", policy=gr.POLICY_LEARNED)
+        ols = autotune.tuned_opts(g, "sssp", policy=gr.POLICY_LEARNED)
         lm = {"bfs": 0.0, "sssp": 0.0}
         for i in range(args.steps):
             s = int(srcs[args.warmup + i])
-            lm["bfs"] += gr.bfs(g, s, opts=ol, out=(depth, parent), stream=stream)[2]["device_ms"]
-            lm["sssp"] += gr.sssp(g, [s], opts=ol, out=(dist, pred), stream=stream)[2]["device_ms"]
+            lm["bfs"] += gr.bfs(g, s, opts=olb, out=(depth, parent), stream=stream)[2]["device_ms"]
+            lm["sssp"] += gr.sssp(g, [s], opts=ols, out=(dist, pred), stream=stream)[2]["device_ms"]
         ctx.set_policy(None)
         learned = {"bfs_ms": round(lm["bfs"] / args.steps, 4), "sssp_ms": round(lm["sssp"] / args.steps, 4),
                    "bfs_gteps_device": _gteps(bfs_teps, lm["bfs"]),

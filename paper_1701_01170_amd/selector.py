@@ -7,7 +7,9 @@ the same whatever actions were taken, so runs with each fixed action and with
 seeded random actions observe every action's time at the same levels (with
 both "previous step pushed" and "previous step pulled" states).  Each record
 becomes one training sample whose target is log2(step time in us) for the
-action taken, with the other three outputs masked out.
+action taken, with the other three outputs masked out.  The mask carries a
+sample weight so that every (graph, traversal) pair weighs the same in the
+loss (a 2048 x 2048 grid yields thousands of levels, an R-MAT graph a dozen).
 
 Training runs on the GPU with the library's own kernels (gr_mlp_loss_grad,
 gr_mlp_adam); evaluation compares event-timed traversal time with the
@@ -57,9 +59,9 @@ def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 2, sssp
     """Trace samples X[n][8], T[n][4], M[n][4] from fixed- and random-action runs."""
     cap = 1 << 15
     buf = (LevelTrace * cap)()
-    X, T, M = [], [], []
+    X, T, M, grp = [], [], [], []
 
-    def add(recs):
+    def add(recs, group):
         for f, a, us in recs:
             X.append(f)
             t = np.zeros(4, np.float32)
@@ -68,30 +70,37 @@ def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 2, sssp
             m[a] = 1.0
             T.append(t)
             M.append(m)
+            grp.append(group)
 
+    from . import autotune
     for name, hg in graphs:
         t0 = time.time()
         g = Graph.from_host(ctx, hg, symmetric=True)
-        srcs = gg.sources(hg, n_sources, seed=3000)
-        # one host round trip per level (no device-predicated blocks), so that
+        # R-MAT graphs (the workload the selector serves first) get more sources
+        srcs = gg.sources(hg, 2 * n_sources if name.startswith("rmat") else n_sources, seed=3000)
+        # the tuned chunk sizes and thresholds of this graph's class, and one
+        # host round trip per level (no device-predicated blocks), so that
         # every record times exactly one step of the action it names
-        pols = [dict(policy=POLICY_FIXED, fixed_action=a, lb_light_threshold=0, device_max_edges=-1)
-                for a in range(4)]
-        pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r, lb_light_threshold=0,
-                      device_max_edges=-1) for r in range(random_runs)]
+        pols = [dict(policy=POLICY_FIXED, fixed_action=a, device_max_edges=-1) for a in range(4)]
+        pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r, device_max_edges=-1)
+                 for r in range(random_runs)]
         for s in srcs:
             for kw in pols:
-                o = default_opts(trace=buf, trace_capacity=cap, **kw)
+                o = autotune.tuned_opts(g, "bfs", trace=buf, trace_capacity=cap, **kw)
                 bfs(g, int(s), opts=o)
-                add(_records(buf, min(o.trace_count, cap)))
+                add(_records(buf, min(o.trace_count, cap)), name + "/bfs")
                 if sssp_too and hg.weights is not None and kw["policy"] != POLICY_RANDOM and \
                         kw.get("fixed_action", 0) < 2:
-                    o = default_opts(trace=buf, trace_capacity=cap, **kw)
+                    o = autotune.tuned_opts(g, "sssp", trace=buf, trace_capacity=cap, **kw)
                     sssp(g, [int(s)], opts=o)
-                    add(_records(buf, min(o.trace_count, cap)))
+                    add(_records(buf, min(o.trace_count, cap)), name + "/sssp")
         g.free()
         log(f"traced {name}: {len(X)} samples so far ({time.time() - t0:.1f}s)")
-    return (np.asarray(X, np.float32), np.asarray(T, np.float32), np.asarray(M, np.float32))
+    M = np.asarray(M, np.float32)
+    _, inv, counts = np.unique(np.asarray(grp), return_inverse=True, return_counts=True)
+    w = len(grp) / (len(counts) * counts[inv])
+    M *= w[:, None].astype(np.float32)
+    return (np.asarray(X, np.float32), np.asarray(T, np.float32), M)
 
 
 def train(ctx: Context, X, T, M, epochs: int = 400, lr: float = 3e-3, seed: int = 0, log=print):
@@ -127,12 +136,13 @@ def evaluate(ctx: Context, graphs, params, n_sources: int = 5, log=print) -> lis
                 if kind == "sssp" and hg.weights is None:
                     continue
                 res = {}
+                # the network chooses the action; chunk sizes and thresholds are
+                # the tuned ones in both tuned configurations
                 cfgs = {"heuristic_paper_knobs": default_opts(),
                         "heuristic_tuned_knobs": autotune.tuned_opts(g, kind),
-                        "heuristic_paper_knobs_host_loop": default_opts(device_max_edges=-1),
-                        "learned": default_opts(policy=POLICY_LEARNED, lb_light_threshold=0)}
+                        "learned_tuned_knobs": autotune.tuned_opts(g, kind, policy=POLICY_LEARNED)}
                 for label, o in cfgs.items():
-                    times, teps = [], 0
+                    times, teps = [], []
                     for s in srcs:
                         best = float("inf")
                         for _ in range(3):
@@ -142,9 +152,10 @@ def evaluate(ctx: Context, graphs, params, n_sources: int = 5, log=print) -> lis
                                 st = sssp(g, [int(s)], opts=o)[2]
                             best = min(best, st["device_ms"])
                         times.append(best)
-                        teps += st["teps_edges"]
-                    res[label] = dict(ms=float(np.median(times)),
-                                      gteps=teps / (sum(times) * 1e-3) / 1e9)
+                        teps.append(st["teps_edges"])
+                    # GTEPS of the summed work over the summed best times
+                    res[label] = dict(ms=round(float(np.median(times)), 4),
+                                      gteps=round(sum(teps) / (sum(times) * 1e-3) / 1e9, 3))
                 row = dict(graph=name, kind=kind, **res)
                 rows.append(row)
                 log(json.dumps(row))
