@@ -43,6 +43,9 @@ KERNEL_NAMES = {
     ("sssp", 0): "k_push_twc<SsspVisit>", ("sssp", 1): "k_push_light<SsspVisit>",
     ("sssp", 2): "k_push_lb<SsspVisit>",
     ("bfs", 6): "k_dstep<BfsVisit>", ("sssp", 6): "k_dstep<SsspVisit>",
+    ("sssp", 7): "k_sssp_pq_refill",
+    ("sssp", 8): "k_push_twc<SsspMark>", ("sssp", 9): "k_push_light<SsspMark>",
+    ("sssp", 10): "k_push_lb<SsspMark>",
 }
 
 
@@ -54,7 +57,7 @@ def algorithmic_bytes(kind: str, kernel: int, n_f: int, m_f: int, n_next: int) -
     BFS push: per edge 4 B column (the visited test is one bit, cache
       resident); per frontier vertex 12 B; per new vertex 4 B depth + 4 B
       parent + 4 B queue entry."""
-    if kind == "sssp":
+    if kind == "sssp" and kernel != 7:
         return 16.0 * m_f + 12.0 * n_f + 4.0 * n_next
     if kind == "bfs" and kernel in (0, 1, 2, 3, 6):
         return 4.0 * m_f + 12.0 * n_f + 12.0 * n_next

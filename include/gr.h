@@ -99,7 +99,8 @@ typedef struct gr_level_trace {
   int32_t kernel;      /* advance kernel: 0 TWC, 1 LB_LIGHT, 2 LB, 3 LB with byte-mark filter,
                           4 pull TWC, 5 pull groups, 6 device-predicated step (step_us and
                           kernel_us are then the block's time divided by its levels),
-                          7 SSSP priority-queue refill (far pile split) */
+                          7 SSSP priority-queue refill (far pile split), 8 / 9 / 10 SSSP
+                          TWC / LB_LIGHT / LB relaxation with the byte-mark filter */
   int64_t n_next;      /* size of the output frontier */
 } gr_level_trace;
 
@@ -113,7 +114,8 @@ typedef struct gr_opts {
   float do_b;                /* pull -> push when m_f < m_u * do_b */
   float lb_min_avg_degree;   /* LB when average degree >= this, else TWC (paper: 5) */
   int32_t max_iterations;    /* stop after this many iterations (<= 0: unlimited) */
-  int32_t lb_chunk;          /* edges per workgroup in output-balanced LB: 0 (default 8192), 2048, 4096, 8192, 16384 */
+  int32_t lb_chunk;          /* edges per workgroup in output-balanced LB: 0 (default 8192), 512, 1024,
+                                2048, 4096, 8192, 16384 */
   int32_t trace_capacity;    /* records available in trace */
   gr_level_trace* trace;     /* host array, nullable: per-iteration records */
   int32_t trace_count;       /* out: records written (may exceed capacity; extra are dropped) */

@@ -9,7 +9,7 @@ per (gfx arch, graph class, size bucket, traversal) in `tuning/<arch>.json`.
 
 Search (coordinate descent from the paper's defaults):
   1. lb_light_threshold in {0, 1024, 4096}
-  2. lb_chunk in {2048, 4096, 8192, 16384}
+  2. lb_chunk in {512, 1024, 2048, 4096, 8192, 16384}
   3. lb_min_avg_degree in {0 (always LB), 5 (paper), inf (always TWC)}
   4. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8}
   5. BFS / SSSP: device_max_edges in {off, 2^16, 2^18, 2^20} (edge bound of
@@ -133,7 +133,7 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
                 best, best_ms = cand, ms
 
     try_set("lb_light_threshold", [0, 1024, 4096])
-    try_set("lb_chunk", [2048, 4096, 8192, 16384])
+    try_set("lb_chunk", [512, 1024, 2048, 4096, 8192, 16384])
     if kind == "bfs_multi":
         try_set("do_a", MULTI_DO_A)
         return best, best_ms, base_ms

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -72,9 +73,23 @@ gr_status pool_typed(gr_ctx* ctx, Slot s, size_t count, T** out) {
   return GR_OK;
 }
 
+// The control block after all work queued so far: a publishing kernel copies
+// it to host memory and then bumps a sequence number, which the host polls;
+// every 4096 polls the stream status is checked, so a failed launch or a
+// faulted stream ends the wait with an error instead of a hang.
 gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st) {
-  GR_HIP(hipMemcpyAsync(ctx->host_ctrl, dev, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-  GR_HIP(hipStreamSynchronize(st));
+  const uint32_t seq = ++ctx->publish_seq;
+  GR_HIP(launch_publish(dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
+  for (uint64_t i = 1;; ++i) {
+    if (*ctx->publish_flag == seq) break;
+    if ((i & 4095) == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return fail(GR_EHIP, std::string("stream failed: ") + hipGetErrorString(e));
+      if (*ctx->publish_flag != seq) return fail(GR_EHIP, "control block was not published");
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   return GR_OK;
 }
 
@@ -141,12 +156,25 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
   gr_ctx* c = new gr_ctx();
   c->device = device;
   c->cu_count = prop.multiProcessorCount;
+  // control block mirror + publish flag: coherent, device-mapped pinned memory
   void* hc = nullptr;
-  if (hipHostMalloc(&hc, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+  const size_t mirror_bytes = (sizeof(Ctrl) + 255) / 256 * 256 + 256;
+  if (hipHostMalloc(&hc, mirror_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     delete c;
     return fail(GR_ENOMEM, "pinned host allocation failed");
   }
+  std::memset(hc, 0, mirror_bytes);
+  void* hd = nullptr;
+  if (hipHostGetDevicePointer(&hd, hc, 0) != hipSuccess) {
+    (void)hipHostFree(hc);
+    delete c;
+    return fail(GR_EHIP, "hipHostGetDevicePointer failed");
+  }
   c->host_ctrl = static_cast<Ctrl*>(hc);
+  c->host_ctrl_dev = static_cast<Ctrl*>(hd);
+  const size_t flag_off = mirror_bytes - 256;
+  c->publish_flag = reinterpret_cast<volatile uint32_t*>(static_cast<char*>(hc) + flag_off);
+  c->publish_flag_dev = reinterpret_cast<uint32_t*>(static_cast<char*>(hd) + flag_off);
   if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
       hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess ||
       hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess) {
@@ -408,15 +436,25 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
   if (opts->fixed_action < GR_PUSH_TWC || opts->fixed_action > GR_PULL_LB)
     return fail(GR_EINVAL, "opts->fixed_action out of range");
   if (!(opts->do_a >= 0.0f) || !(opts->do_b >= 0.0f)) return fail(GR_EINVAL, "do_a/do_b must be >= 0");
-  if (opts->lb_chunk != 0 && opts->lb_chunk != 2048 && opts->lb_chunk != 4096 &&
+  if (opts->lb_chunk != 0 && opts->lb_chunk != 512 && opts->lb_chunk != 1024 &&
+      opts->lb_chunk != 2048 && opts->lb_chunk != 4096 &&
       opts->lb_chunk != 8192 && opts->lb_chunk != 16384)
-    return fail(GR_EINVAL, "opts->lb_chunk must be 0 (default), 2048, 4096, 8192 or 16384");
+    return fail(GR_EINVAL, "opts->lb_chunk must be 0 (default), 512, 1024, 2048, 4096, 8192 or 16384");
   if (opts->trace_capacity < 0 || (opts->trace_capacity > 0 && !opts->trace))
     return fail(GR_EINVAL, "opts->trace is NULL with a positive capacity");
   if (opts->device_max_edges > (1 << 24))
     return fail(GR_EINVAL, "opts->device_max_edges must be at most 1 << 24");
   if (opts->sssp_delta < 0) return fail(GR_EINVAL, "opts->sssp_delta must be >= 0");
   *local = *opts;
+  return GR_OK;
+}
+
+// Milliseconds between two recorded events.  The host can observe a
+// published control block before the runtime has retired events recorded
+// ahead of it, so wait for the later event first.
+gr_status elapsed_ms(hipEvent_t a, hipEvent_t b, float* ms) {
+  GR_HIP(hipEventSynchronize(b));
+  GR_HIP(hipEventElapsedTime(ms, a, b));
   return GR_OK;
 }
 
@@ -451,8 +489,8 @@ gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int 
     return GR_OK;
   }
   float step_ms = 0.f, kernel_ms = 0.f;
-  GR_HIP(hipEventElapsedTime(&step_ms, ctx->ev_a, ctx->ev_b));
-  GR_HIP(hipEventElapsedTime(&kernel_ms, ctx->ev_k0, ctx->ev_k1));
+  GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &step_ms));
+  GR_TRY(elapsed_ms(ctx->ev_k0, ctx->ev_k1, &kernel_ms));
   return record_trace_times(opts, lf, action, kernel, n_next, step_ms, kernel_ms);
 }
 
@@ -461,6 +499,10 @@ constexpr int kDlFirstLen = 4;              // levels in the first block; double
 constexpr int64_t kDlDefaultMaxEdges = 1 << 18;
 constexpr int kTraceKernelDstep = 6;
 constexpr int kTraceKernelRefill = 7;
+constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filter: 8 + (0 TWC, 1 LB_LIGHT, 2 LB)
+// SSSP iterations whose frontier has at least V / kSsspMarksDivisor edges use
+// the byte-mark filter.
+constexpr int64_t kSsspMarksDivisor = 4;
 
 struct DlPlan {
   bool on = false;
@@ -547,7 +589,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
-  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   Ctrl* hc = ctx->host_ctrl;
@@ -623,7 +665,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         if (tracing) {
           lg.resize(3 * (size_t)k);
           GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
-          GR_HIP(hipEventElapsedTime(&block_ms, ctx->ev_a, ctx->ev_b));
+          GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         }
         dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
         rs.action_count[action] += k;
@@ -730,7 +772,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   GR_HIP(hipEventSynchronize(ctx->ev_stop));
   if (stats) {
     float ms = 0.f;
-    GR_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    GR_TRY(elapsed_ms(ctx->ev_start, ctx->ev_stop, &ms));
     rs.iterations = level;
     // when stopped early the last frontier is reached but not expanded
     rs.teps_edges = visited_m;
@@ -781,7 +823,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
-  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
@@ -877,7 +919,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         if (tracing) {
           lg.resize(3 * (size_t)k);
           GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
-          GR_HIP(hipEventElapsedTime(&block_ms, ctx->ev_a, ctx->ev_b));
+          GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         }
         dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
         rs.action_count[action] += k;
@@ -929,15 +971,28 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                        chunks, chunk, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      if (use_pq)
+      if (use_pq) {
         GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
                                     g->W, keys, tags, it + 1, pq, ctrl, q[(cur + 1) % 3],
                                     &ctrl->q_count[(cur + 1) % 3], chunk, st));
-      else
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+      } else if (m_f >= V / kSsspMarksDivisor) {
+        // many frontier edges: relax with no returning atomic, then list the
+        // vertices whose distance dropped (byte marks)
+        uint8_t* marks;
+        GR_TRY(marks_buffer(ctx, V, &marks, st));
+        kernel += kTraceMarksOffset;
+        GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
+                                       g->W, keys, perm, marks, chunk, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+        GR_HIP(launch_sssp_mark_compact(marks, V, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
+                                        st));
+      } else {
         GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W,
                                  keys, tags, perm, it + 1, q[(cur + 1) % 3],
                                  &ctrl->q_count[(cur + 1) % 3], chunk, st));
-      if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+      }
       inspected += m_f;
       rs.action_count[action]++;
     }
@@ -957,7 +1012,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(read_ctrl(ctx, ctrl, st));
   if (stats) {
     float ms = 0.f;
-    GR_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    GR_TRY(elapsed_ms(ctx->ev_start, ctx->ev_stop, &ms));
     rs.iterations = it;
     rs.teps_edges = hc->reached_edges;
     rs.inspected_edges = inspected;
@@ -1007,7 +1062,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
   GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
-  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 2048 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_TMP0, 128, &src_dev));  // traversal ids, then caller ids
@@ -1088,7 +1143,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
   GR_TRY(read_ctrl(ctx, ctrl, st));
   if (stats) {
     float ms = 0.f;
-    GR_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    GR_TRY(elapsed_ms(ctx->ev_start, ctx->ev_stop, &ms));
     rs.iterations = max_levels;
     rs.teps_edges = hc->reached_edges;
     rs.inspected_edges = inspected;
@@ -1192,7 +1247,7 @@ extern "C" gr_status gr_copy_bandwidth(gr_ctx* ctx, int64_t bytes, int32_t reps,
   GR_HIP(hipEventRecord(ctx->ev_k1, st));
   GR_HIP(hipEventSynchronize(ctx->ev_k1));
   float ms = 0.f;
-  GR_HIP(hipEventElapsedTime(&ms, ctx->ev_k0, ctx->ev_k1));
+  GR_TRY(elapsed_ms(ctx->ev_k0, ctx->ev_k1, &ms));
   *gbps = (float)(2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9);
   return GR_OK;
 }

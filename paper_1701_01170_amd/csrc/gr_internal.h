@@ -102,7 +102,14 @@ struct gr_ctx {
   int device = 0;
   int cu_count = 256;
   gr::DevBuf pool[gr::S_NSLOTS];
-  gr::Ctrl* host_ctrl = nullptr;   // pinned host mirror of the control block
+  // Host view of the control block: coherent pinned host memory that a small
+  // kernel fills (followed by a sequence number in publish_flag) after each
+  // step, so the host polls memory instead of synchronising the stream.
+  gr::Ctrl* host_ctrl = nullptr;
+  gr::Ctrl* host_ctrl_dev = nullptr;        // the same memory, device address
+  volatile uint32_t* publish_flag = nullptr;
+  uint32_t* publish_flag_dev = nullptr;
+  uint32_t publish_seq = 0;
   bool policy_loaded = false;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_a = nullptr, ev_b = nullptr;
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the advance kernel when tracing
@@ -166,6 +173,9 @@ hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const i
                                    int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
                                    int32_t chunk, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
+// copy *src into host-visible memory, then store seq to *flag (system scope)
+hipError_t launch_publish(const Ctrl* src, Ctrl* host_dst, uint32_t* host_flag, uint32_t seq,
+                          hipStream_t st);
 // out[perm[i]] = in[i] for the depth and (nullable) parent arrays
 hipError_t launch_permute_out(const int32_t* perm, int64_t V, const int32_t* depth_in,
                               const int32_t* parent_in, int32_t* depth_out, int32_t* parent_out,
@@ -313,6 +323,15 @@ hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* o
                              unsigned long long* keys, int32_t* tags, const int32_t* perm,
                              int32_t next_tag, int32_t* out_q, uint32_t* out_count, int chunk,
                              hipStream_t st);
+// Relaxation with the non-atomic filter (byte marks, all zero before and after
+// the pair of calls), then the ordered list of the marked vertices.
+hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int32_t* offsets,
+                                   const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                   int64_t m_f, const int32_t* R, const int32_t* C,
+                                   const uint32_t* W, unsigned long long* keys,
+                                   const int32_t* perm, uint8_t* marks, int chunk, hipStream_t st);
+hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, int32_t* out_q, uint32_t* out_count,
+                                    hipStream_t st);
 // dist / pred written at caller ids; src_orig_dev: the sources in caller ids
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
                                 uint32_t* dist, int32_t* pred, const int32_t* perm,

@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
 inline unsigned adv_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 // mode: 0 = TWC, 1 = LB_LIGHT, 2 = LB with `chunk` edges per workgroup
-// (2048, 4096, 8192 or 16384).
+// (512, 1024, 2048, 4096, 8192 or 16384).
 template <class F>
 inline hipError_t push_dispatch(int mode, const int32_t* frontier, const int32_t* offsets,
                          const int32_t* rstart, const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
@@ -401,6 +401,14 @@ inline hipError_t push_dispatch(int mode, const int32_t* frontier, const int32_t
     if (m_f <= 0) return hipSuccess;
     const unsigned g = adv_blocks(m_f, chunk);
     switch (chunk) {
+      case 512:
+        k_push_lb<F, 2, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
+                                                    (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
+        break;
+      case 1024:
+        k_push_lb<F, 4, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
+                                                    (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
+        break;
       case 2048:
         k_push_lb<F, 8, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);

@@ -159,6 +159,20 @@ __global__ __launch_bounds__(256) void k_permute_out(const int32_t* __restrict__
   }
 }
 
+// Copy the control block to host memory: every thread orders its own stores
+// at system scope before the workgroup barrier, then one thread releases the
+// sequence number the host waits for.
+__global__ __launch_bounds__(128) void k_publish(const uint32_t* __restrict__ src,
+                                                 uint32_t* __restrict__ dst, int n_words,
+                                                 uint32_t* flag, uint32_t seq) {
+  for (int i = threadIdx.x; i < n_words; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n,
                                                   uint32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -234,6 +248,15 @@ hipError_t launch_permute_out(const int32_t* perm, int64_t V, const int32_t* dep
   if (V <= 0) return hipSuccess;
   k_permute_out<<<blocks_for(V, 256), 256, 0, st>>>(perm, V, depth_in, parent_in, depth_out,
                                                     parent_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_publish(const Ctrl* src, Ctrl* host_dst, uint32_t* host_flag, uint32_t seq,
+                          hipStream_t st) {
+  static_assert(sizeof(Ctrl) % 4 == 0, "control block is copied as 32-bit words");
+  k_publish<<<1, 128, 0, st>>>(reinterpret_cast<const uint32_t*>(src),
+                               reinterpret_cast<uint32_t*>(host_dst), (int)(sizeof(Ctrl) / 4),
+                               host_flag, seq);
   return hipGetLastError();
 }
 

@@ -86,6 +86,94 @@ struct SsspVisit {
   __device__ __forceinline__ void advance(Ctrl*, int, bool) const {}
 };
 
+// Relaxation without a returning atomic (for iterations with many frontier
+// edges): each edge that lowers the key issues an atomic minimum whose result
+// nobody waits for, and each edge that lowers the distance seen at its probe
+// stores a one-byte mark (all writers store the same value).  A key only
+// decreases, so a vertex gets a mark exactly when its distance decreased in
+// this iteration, by this edge or by a concurrent one: the marks are the
+// next frontier, which k_sssp_mark_compact lists in ascending order.
+struct SsspMark {
+  const uint32_t* __restrict__ W;
+  unsigned long long* __restrict__ keys;
+  uint8_t* __restrict__ marks;
+  const int32_t* __restrict__ perm;
+
+  using pay_t = int32_t;
+  static constexpr bool kFar = false;
+  static constexpr bool kBatchCommit = true;
+  __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
+    return (int32_t)(uint32_t)(keys[u] >> 32);
+  }
+  __device__ __forceinline__ uint32_t edge_value(int64_t e) const { return W[e]; }
+  // the key test happens in commit_batch, whose loads are batched anyway
+  __device__ __forceinline__ bool probe(int32_t, int32_t du, int32_t, uint32_t w) const {
+    return (uint64_t)(uint32_t)du + (uint64_t)w < 0xffffffffull;
+  }
+  template <int B>
+  __device__ __forceinline__ void commit_batch(const int32_t (&u)[B], const int32_t (&du)[B],
+                                               const int32_t (&v)[B], const uint32_t (&w)[B],
+                                               const bool (&ok)[B], int (&code)[B]) const {
+    unsigned long long k[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) k[r] = ok[r] ? keys[v[r]] : 0ull;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      code[r] = 0;
+      if (!ok[r]) continue;
+      const uint64_t cand = (uint64_t)(uint32_t)du[r] + (uint64_t)w[r];
+      const unsigned long long nk = (cand << 32) | caller_id(perm, u[r]);
+      if (nk < k[r]) atomicMin(&keys[v[r]], nk);
+      if (cand < (k[r] >> 32)) marks[v[r]] = 1;
+    }
+  }
+  __device__ __forceinline__ bool commit(int32_t, int32_t, int32_t, uint32_t) const { return false; }
+};
+
+// One thread per 32 vertices: gather and clear the marks, list the marked
+// vertices (ascending within each wavefront).
+__global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__ marks, int64_t V,
+                                                           int32_t* __restrict__ out_q,
+                                                           uint32_t* __restrict__ out_count) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_words = (V + 31) / 32;
+  uint32_t mask = 0;
+  if (w < n_words) {
+    const int64_t v0 = w * 32;
+    if (v0 + 32 <= V) {
+      const uint4* m4 = reinterpret_cast<const uint4*>(marks + v0);
+      const uint4 a = m4[0], b = m4[1];
+      const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if ((q[i] >> (8 * k)) & 0xffu) mask |= 1u << (4 * i + k);
+      if (mask) {
+        uint4* z = reinterpret_cast<uint4*>(marks + v0);
+        z[0] = make_uint4(0, 0, 0, 0);
+        z[1] = make_uint4(0, 0, 0, 0);
+      }
+    } else {
+      for (int64_t v = v0; v < V; ++v)
+        if (marks[v]) {
+          mask |= 1u << (v - v0);
+          marks[v] = 0;
+        }
+    }
+  }
+  const uint32_t n = __popc(mask);
+  const uint32_t inc = wave_incl_scan(n);
+  uint32_t base = 0;
+  if (lane() == kWave - 1 && inc) base = atomicAdd(out_count, inc);
+  base = __shfl(base, kWave - 1) + inc - n;
+  while (mask) {
+    const int b = __ffs(mask) - 1;
+    mask &= mask - 1;
+    out_q[base++] = (int32_t)(w * 32 + b);
+  }
+}
+
 __device__ __forceinline__ uint32_t pq_next_threshold(uint32_t T, uint32_t delta) {
   const uint64_t t = (uint64_t)T + delta;
   return t >= 0xffffffffull ? 0xffffffffu : (uint32_t)t;
@@ -385,6 +473,24 @@ hipError_t launch_sssp_pq_dstep(const DlArgs& a, const uint32_t* W, unsigned lon
                                 hipStream_t st) {
   const SsspPqVisit f = pq_functor(W, keys, tags, next_tag, pq, a.ctrl);
   k_dstep<SsspPqVisit><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int32_t* offsets,
+                                   const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                   int64_t m_f, const int32_t* R, const int32_t* C,
+                                   const uint32_t* W, unsigned long long* keys,
+                                   const int32_t* perm, uint8_t* marks, int chunk, hipStream_t st) {
+  const SsspMark f{W, keys, marks, perm};
+  return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
+                       nullptr, chunk, st);
+}
+
+hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, int32_t* out_q, uint32_t* out_count,
+                                    hipStream_t st) {
+  const int64_t n_words = (V + 31) / 32;
+  if (n_words <= 0) return hipSuccess;
+  k_sssp_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, out_q, out_count);
   return hipGetLastError();
 }
 

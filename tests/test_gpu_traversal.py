@@ -23,6 +23,10 @@ POLICIES = [
     ("pull_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_LB)),
     ("random1", dict(policy=gr.POLICY_RANDOM, policy_seed=1)),
     ("random2", dict(policy=gr.POLICY_RANDOM, policy_seed=2, lb_light_threshold=0)),
+    ("chunk512", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
+                      lb_chunk=512)),
+    ("chunk1024", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
+                       lb_chunk=1024)),
     ("chunk2048", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
                        lb_chunk=2048)),
     ("chunk4096", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
