@@ -21,24 +21,43 @@ def ctx():
     return gr.Context(0)
 
 
-def _check_bfs_invariants(R, C, s, depth, parent):
-    """depth(v) <= depth(u) + 1 on every edge, every reached non-source vertex
-    has a parent one level closer that is its smallest-id such neighbour."""
-    deg = np.diff(R.astype(np.int64))
-    u = np.repeat(np.arange(len(deg)), deg)
-    v = C.astype(np.int64)
-    du, dv = depth[u].astype(np.int64), depth[v].astype(np.int64)
-    reach_u = du >= 0
-    assert (dv[reach_u] >= 0).all()
-    assert (dv[reach_u] <= du[reach_u] + 1).all()
+def _edge_chunks(R, C, chunk=1 << 26):
+    """(u, v, e0, e1) for consecutive slices of the edge list, u computed from
+    the row offsets of the rows overlapping the slice."""
+    E = int(R[-1])
+    for e0 in range(0, E, chunk):
+        e1 = min(E, e0 + chunk)
+        r0 = int(np.searchsorted(R, e0, side="right")) - 1
+        r1 = int(np.searchsorted(R, e1, side="left"))
+        rows = np.arange(r0, r1, dtype=np.int64)
+        starts = np.maximum(R[rows].astype(np.int64), e0)
+        ends = np.minimum(R[rows + 1].astype(np.int64), e1)
+        u = np.repeat(rows, np.maximum(ends - starts, 0))
+        yield u, C[e0:e1].astype(np.int64), e0, e1
+
+
+def _sample(V, n, seed):
+    return np.unique(np.random.default_rng(seed).integers(0, V, n))
+
+
+def _check_bfs_invariants(R, C, s, depth, parent, n_sample=20_000, chunk=1 << 26):
+    """On every edge depth(v) <= depth(u) + 1 when u is reached (so v is
+    reached too); the source has depth 0 and no parent; and for a seeded
+    sample of vertices (symmetric graph: the in-neighbours are the row) the
+    parent is the smallest-id neighbour one level closer, -1 if unreached."""
+    for u, v, _, _ in _edge_chunks(R, C, chunk):
+        du, dv = depth[u].astype(np.int64), depth[v].astype(np.int64)
+        reach_u = du >= 0
+        assert (dv[reach_u] >= 0).all()
+        assert (dv[reach_u] <= du[reach_u] + 1).all()
     assert depth[s] == 0 and parent[s] == -1
-    cand = np.where((du >= 0) & (dv == du + 1), u, np.iinfo(np.int64).max)
-    best = np.full(len(deg), np.iinfo(np.int64).max)
-    np.minimum.at(best, v, cand)
-    big = np.iinfo(np.int64).max
-    got = np.where(parent >= 0, parent.astype(np.int64), big)
-    nonsrc = np.arange(len(deg)) != s
-    assert (got[nonsrc] == best[nonsrc]).all()
+    for v in _sample(len(R) - 1, n_sample, 17):
+        if v == s:
+            continue
+        nb = C[R[v]:R[v + 1]]
+        closer = nb[depth[nb] == depth[v] - 1] if depth[v] > 0 else nb[:0]
+        expect = int(closer[0]) if len(closer) else -1
+        assert parent[v] == expect, (v, parent[v], expect)
 
 
 def test_rmat22_bfs_sssp_bit_exact(ctx):
@@ -110,4 +129,49 @@ def test_union256_sssp_bit_exact(ctx):
         a, b = voff[i], voff[i + 1]
         np.testing.assert_array_equal(dist[a:b], ed, err_msg=f"part {i}")
         np.testing.assert_array_equal(pred[a:b], np.where(ep >= 0, ep + a, -1), err_msg=f"part {i}")
+    g.free()
+
+
+def _check_sssp_invariants(R, C, W, s, dist, pred, n_sample=20_000, chunk=1 << 26):
+    """On every edge dist(v) <= dist(u) + w(u, v) when u is reached; the
+    source has distance 0 and no predecessor; and for a seeded sample of
+    vertices (symmetric graph, one weight per undirected edge) the predecessor
+    is the smallest-id neighbour u with dist(u) + w = dist(v), -1 if none."""
+    INF = np.uint64(0xFFFFFFFF)
+    d = dist.astype(np.uint64)
+    for u, v, e0, e1 in _edge_chunks(R, C, chunk):
+        du, dv = d[u], d[v]
+        reach = du != INF
+        assert (dv[reach] <= du[reach] + W[e0:e1][reach].astype(np.uint64)).all()
+    assert dist[s] == 0 and pred[s] == -1
+    for v in _sample(len(R) - 1, n_sample, 19):
+        if v == s:
+            continue
+        nb = C[R[v]:R[v + 1]]
+        w = W[R[v]:R[v + 1]].astype(np.uint64)
+        tight = nb[(d[nb] != INF) & (d[nb] + w == d[v])] if d[v] != INF else nb[:0]
+        expect = int(tight[0]) if len(tight) else -1
+        assert pred[v] == expect, (v, pred[v], expect)
+
+
+def test_rmat25_batched_sampled(ctx):
+    """The largest workload (R-MAT scale 25, ~1.05e9 directed edges) with the
+    scale-25 run's configuration: the 16-source batch compared whole against
+    the oracle for its first source and by the BFS invariants for four more;
+    one SSSP checked by the distance and predecessor invariants."""
+    hg = gg.add_weights(gg.rmat(25, 16, seed=1), seed=101)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    srcs = gg.sources(hg, 16, seed=1000).astype(np.int32)
+    depth, parent, _ = gr.bfs_multi(g, srcs, opts=autotune.tuned_opts(g, "bfs_multi"))
+    ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(srcs[0]))
+    np.testing.assert_array_equal(depth[0].cpu().numpy(), ed)
+    np.testing.assert_array_equal(parent[0].cpu().numpy(), ep)
+    del ed, ep
+    for i in (9,):
+        _check_bfs_invariants(hg.row_offsets, hg.col_indices, int(srcs[i]), depth[i].cpu().numpy(),
+                              parent[i].cpu().numpy())
+    del depth, parent
+    dist, pred, _ = gr.sssp(g, [int(srcs[5])], opts=autotune.tuned_opts(g, "sssp"))
+    _check_sssp_invariants(hg.row_offsets, hg.col_indices, hg.weights, int(srcs[5]),
+                           dist.cpu().numpy().view(np.uint32), pred.cpu().numpy())
     g.free()
