@@ -129,7 +129,10 @@ typedef struct gr_opts {
                                 when the frontier empties T grows by sssp_delta and the far pile is
                                 split.  0: off (every improved vertex is in the next frontier).
                                 Results are identical either way. */
-  int32_t reserved[5];
+  float learned_margin;      /* GR_POLICY_LEARNED: the network's action replaces the heuristic's only
+                                when its predicted log2 step time is lower by more than this
+                                (0: plain argmin).  Must be >= 0. */
+  int32_t reserved[4];
 } gr_opts;
 
 typedef struct gr_run_stats {

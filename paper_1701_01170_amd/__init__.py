@@ -58,7 +58,7 @@ class Opts(ctypes.Structure):
                 ("lb_chunk", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
                 ("trace", ctypes.POINTER(LevelTrace)), ("trace_count", ctypes.c_int32),
                 ("device_max_edges", ctypes.c_int32), ("sssp_delta", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("learned_margin", ctypes.c_float), ("reserved", ctypes.c_int32 * 4)]
 
 
 class RunStats(ctypes.Structure):

@@ -445,6 +445,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
   if (opts->device_max_edges > (1 << 24))
     return fail(GR_EINVAL, "opts->device_max_edges must be at most 1 << 24");
   if (opts->sssp_delta < 0) return fail(GR_EINVAL, "opts->sssp_delta must be >= 0");
+  if (!(opts->learned_margin >= 0.0f) || !std::isfinite(opts->learned_margin))
+    return fail(GR_EINVAL, "opts->learned_margin must be finite and >= 0");
   *local = *opts;
   return GR_OK;
 }
@@ -510,6 +512,8 @@ struct DlPlan {
   double do_a = -1.0;   // device push -> pull test (< 0: none)
   const float* mlp = nullptr;  // device network test (learned policy with pull allowed)
   int allowed = 0x3;
+  float margin = 0.f;
+  int h_push = GR_PUSH_LB;
   int len = kDlFirstLen;
   int blocks = 256;
   int64_t* log = nullptr;
@@ -521,9 +525,10 @@ gr_status dl_plan(gr_ctx* ctx, const gr_opts& o, bool pull_ok, bool learned, boo
                          (o.policy == GR_POLICY_LEARNED && !learned);
   d->on = o.device_max_edges >= 0 && (heuristic || learned || o.policy == GR_POLICY_FIXED);
   d->max_m = o.device_max_edges > 0 ? o.device_max_edges : kDlDefaultMaxEdges;
-  d->do_a = heuristic && pull_ok ? (double)o.do_a : -1.0;
+  d->do_a = (heuristic || learned) && pull_ok ? (double)o.do_a : -1.0;
   d->mlp = learned && pull_ok ? static_cast<const float*>(ctx->pool[S_MLP].ptr) : nullptr;
   d->allowed = pull_ok ? 0xF : 0x3;
+  d->margin = o.learned_margin;
   d->len = kDlFirstLen;
   d->blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
   d->log = nullptr;
@@ -630,6 +635,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
   GR_TRY(dl_plan(ctx, opts, pull_ok, learned, tracing, &dl));
+  dl.h_push = (double)E >= (double)V * (double)opts.lb_min_avg_degree ? GR_PUSH_LB : GR_PUSH_TWC;
 
   while (n_f > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
     lf.level = level;
@@ -639,7 +645,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     lf.n_u = V - visited_n;
     lf.m_u = E - visited_m;
     lf.prev_pull = sel.mode_pull ? 1 : 0;
-    const int action = sel.decide(lf, learned ? hc->action : -1);
+    const int action = sel.decide(lf, learned ? hc->action : -1, learned ? hc->pred : nullptr);
     if (dl.on && (action == GR_PUSH_LB || action == GR_PUSH_TWC) && n_f <= kDlMaxN &&
         m_f <= dl.max_m) {
       // A block of device-predicated push levels (atomic parents, no merge
@@ -652,7 +658,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, dl.do_a,
-                        dl.mlp, dl.allowed, V, dl.log, ctrl};
+                        dl.mlp, dl.allowed, dl.h_push, dl.margin, V, dl.log, ctrl};
         GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, perm, level + i + 1, dl.blocks,
                                 st));
       }
@@ -895,7 +901,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     lf.n_u = 0;
     lf.m_u = 0;
     lf.prev_pull = 0;
-    const int action = sel.decide(lf, learned ? hc->action : -1);
+    const int action = sel.decide(lf, learned ? hc->action : -1, learned ? hc->pred : nullptr);
     if (dl.on && n_f <= kDlMaxN && m_f <= dl.max_m) {
       // A block of device-predicated relaxation rounds (Alg. 1 iterations;
       // with the priority queue also its refill steps).
@@ -906,7 +912,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
-                        nullptr, 0x3, V, dl.log, ctrl};
+                        nullptr, 0x3, GR_PUSH_LB, 0.f, V, dl.log, ctrl};
         if (use_pq) GR_HIP(launch_sssp_pq_dstep(da, g->W, keys, tags, it + i + 1, pq, dl.blocks, st));
         else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, perm, it + i + 1, dl.blocks, st));
       }

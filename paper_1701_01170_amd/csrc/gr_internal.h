@@ -77,7 +77,8 @@ struct Ctrl {
   int64_t n_f[2];           // frontier size as seen by the statistics kernel
   int64_t inspected;        // pull: neighbours scanned (accumulated)
   int64_t reached_edges;    // sum of degrees over reached vertices (end of run)
-  int32_t action;           // action chosen on the device (learned policy)
+  int32_t action;           // network argmin over the allowed actions (learned policy)
+  float pred[4];            // the network's predicted log2 step times (disallowed: +inf)
   int32_t pad0;
   int64_t misc[4];
   // device-predicated level blocks (iteration control without host round trips)
@@ -272,8 +273,12 @@ struct DlArgs {
   int64_t max_n, max_m;       // run only while n_f <= max_n and m_f <= max_m
   int64_t E;                  // for the push -> pull test
   double do_a;                // push -> pull when m_f > m_u * do_a (< 0: never)
-  const float* mlp;           // selector network: run only while it picks a push action (nullable)
+  const float* mlp;           // selector network (nullable): the level runs while the guarded
+                              // choice (below) is a push action
   int32_t allowed;            // actions the network may pick (bit a = gr_action a)
+  int32_t h_push;             // the heuristic's push action (by average degree)
+  float margin;               // network overrides the heuristic only when it predicts a
+                              // step shorter by more than this (log2 units)
   int64_t V;
   int64_t* log;               // [kDlMaxLevels][3]
   Ctrl* ctrl;

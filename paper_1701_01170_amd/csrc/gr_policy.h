@@ -84,14 +84,18 @@ struct Selector {
     return lb ? GR_PUSH_LB : GR_PUSH_TWC;
   }
 
-  // device_choice: action computed by the selector network on the device (or
-  // -1 when none is available).
-  int decide(const LevelFeatures& lf, int device_choice = -1) {
+  // device_choice: the network's argmin over the allowed actions, pred: its
+  // predicted log2 step times (both from the device; -1 / null when none).
+  // The learned policy is guarded: it keeps the heuristic's action unless the
+  // network predicts its own choice faster by more than o.learned_margin.
+  int decide(const LevelFeatures& lf, int device_choice = -1, const float* pred = nullptr) {
     int a;
     if (o.policy == GR_POLICY_FIXED) a = o.fixed_action;
     else if (o.policy == GR_POLICY_RANDOM) a = (int)(next(rng) % 4);
-    else if (o.policy == GR_POLICY_LEARNED && learned && device_choice >= 0) a = device_choice;
-    else a = heuristic(lf);
+    else if (o.policy == GR_POLICY_LEARNED && learned && device_choice >= 0 && pred) {
+      const int h = heuristic(lf);
+      a = (device_choice != h && pred[device_choice] + o.learned_margin < pred[h]) ? device_choice : h;
+    } else a = heuristic(lf);
     if (!pull_ok && a >= GR_PULL_TWC) a -= 2;  // same balancing, push direction
     mode_pull = a >= GR_PULL_TWC;
     return a;

@@ -50,13 +50,20 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   const int64_t vm = ctrl->dl_vm[a.step & 1];
   const int64_t vn = ctrl->dl_vn[a.step & 1];
   bool run = n_f > 0 && n_f <= a.max_n && n_f <= kDlMaxN && m_f <= a.max_m;
-  if (run && a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a) run = false;
+  // the heuristic's direction (Sec. 5.1 push -> pull test)
+  const bool h_pull = a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a;
   if (run && a.mlp) {
+    // guarded network choice: the heuristic's action unless the network
+    // predicts another one faster by more than the margin
     __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
     if (threadIdx.x == 0)
       mlp_features(s_x, n_f, m_f, a.V - vn - n_f, a.E - vm - m_f, ctrl->dl_maxd[a.cur], a.V, a.E, 0);
     const int best = mlp_argmin(a.mlp, s_x, s_h1, s_h2, s_y, a.allowed);
-    run = best == GR_PUSH_TWC || best == GR_PUSH_LB;
+    const int h = h_pull ? GR_PULL_TWC : a.h_push;
+    const int fin = (best != h && s_y[best] + a.margin < s_y[h]) ? best : h;
+    run = fin == GR_PUSH_TWC || fin == GR_PUSH_LB;
+  } else if (h_pull) {
+    run = false;
   }
   bool refill = false;
   if constexpr (F::kFar) refill = n_f == 0 && fs.far_pending(ctrl);

@@ -208,6 +208,8 @@ __global__ __launch_bounds__(64) void k_mlp_select(const float* __restrict__ par
     mlp_features(s_x, n_f, m_f, n_u, m_u, ctrl->max_deg[sp], V, E, prev_pull);
   }
   const int best = mlp_argmin(params, s_x, s_h1, s_h2, s_y, allowed);
+  if (threadIdx.x < kOut)
+    ctrl->pred[threadIdx.x] = ((allowed >> threadIdx.x) & 1) ? s_y[threadIdx.x] : __builtin_inff();
   if (threadIdx.x == 0) ctrl->action = best;
 }
 

@@ -122,7 +122,8 @@ def train(ctx: Context, X, T, M, epochs: int = 400, lr: float = 3e-3, seed: int 
     return p.cpu().numpy()
 
 
-def evaluate(ctx: Context, graphs, params, n_sources: int = 5, log=print) -> list[dict]:
+def evaluate(ctx: Context, graphs, params, n_sources: int = 5, margins=(0.0,),
+             log=print) -> list[dict]:
     """Median device time of BFS and SSSP under the heuristic (paper defaults
     and autotuned knobs) and under the network, on held-out sources."""
     from . import autotune
@@ -139,8 +140,10 @@ def evaluate(ctx: Context, graphs, params, n_sources: int = 5, log=print) -> lis
                 # the network chooses the action; chunk sizes and thresholds are
                 # the tuned ones in both tuned configurations
                 cfgs = {"heuristic_paper_knobs": default_opts(),
-                        "heuristic_tuned_knobs": autotune.tuned_opts(g, kind),
-                        "learned_tuned_knobs": autotune.tuned_opts(g, kind, policy=POLICY_LEARNED)}
+                        "heuristic_tuned_knobs": autotune.tuned_opts(g, kind)}
+                for mg in margins:
+                    cfgs[f"learned_tuned_knobs_margin{mg:g}"] = autotune.tuned_opts(
+                        g, kind, policy=POLICY_LEARNED, learned_margin=mg)
                 for label, o in cfgs.items():
                     times, teps = [], []
                     for s in srcs:
@@ -194,8 +197,20 @@ def main():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--epochs", type=int, default=1500)
     ap.add_argument("--sources", type=int, default=3)
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the stored weights")
+    ap.add_argument("--margins", default="0,0.1,0.25,0.5")
     args = ap.parse_args()
+    margins = [float(x) for x in args.margins.split(",")]
     ctx = Context(0)
+    if args.eval_only:
+        rows = evaluate(ctx, eval_graphs(), np.load(WEIGHTS), margins=margins,
+                        log=lambda s: print(s, flush=True))
+        with open(REPORT) as f:
+            rep = json.load(f)
+        rep["eval"] = rows
+        with open(REPORT, "w") as f:
+            json.dump(rep, f, indent=1)
+        return
     t0 = time.time()
     X, T, M = collect(ctx, training_graphs(args.quick), n_sources=args.sources,
                       log=lambda s: print(s, flush=True))
@@ -203,7 +218,7 @@ def main():
     params = train(ctx, X, T, M, epochs=args.epochs, log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(WEIGHTS), exist_ok=True)
     np.save(WEIGHTS, params.astype(np.float32))
-    rows = evaluate(ctx, eval_graphs(), params, log=lambda s: print(s, flush=True))
+    rows = evaluate(ctx, eval_graphs(), params, margins=margins, log=lambda s: print(s, flush=True))
     with open(REPORT, "w") as f:
         json.dump(dict(samples=int(X.shape[0]), epochs=args.epochs, eval=rows), f, indent=1)
 

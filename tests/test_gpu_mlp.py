@@ -120,3 +120,26 @@ def test_learned_policy_is_exact_and_takes_argmin(ctx, rmat14):
         ctx.set_policy(None)
     with pytest.raises(gr.GrError):
         ctx.set_policy(np.zeros(10, np.float32))
+
+
+def test_learned_policy_with_large_margin_is_the_heuristic(ctx, rmat14):
+    """The guarded learned policy keeps the heuristic's action unless the
+    network predicts a gain above the margin: with a huge margin every
+    iteration takes the heuristic's action."""
+    g = gr.Graph.from_host(ctx, rmat14)
+    rng = np.random.default_rng(12)
+    ctx.set_policy((rng.standard_normal(oracle.MLP_N_PARAMS) * 0.5).astype(np.float32))
+    cap = 64
+    try:
+        for s in gg.sources(rmat14, 3, seed=77):
+            runs = []
+            for kw in (dict(), dict(policy=gr.POLICY_LEARNED, learned_margin=1e9)):
+                buf = (gr.LevelTrace * cap)()
+                o = gr.default_opts(trace=buf, trace_capacity=cap, device_max_edges=-1, **kw)
+                gr.bfs(g, int(s), opts=o)
+                runs.append([(t.level, t.action, t.kernel) for t in buf[:o.trace_count]])
+            assert runs[0] == runs[1]
+    finally:
+        ctx.set_policy(None)
+    with pytest.raises(gr.GrError):
+        gr.bfs(g, 0, opts=gr.default_opts(learned_margin=-1.0))
