@@ -325,7 +325,9 @@ def main():
         ctx.set_policy(None)
         learned = {"bfs_ms": round(lm["bfs"] / args.steps, 4), "sssp_ms": round(lm["sssp"] / args.steps, 4),
                    "bfs_gteps_device": _gteps(bfs_teps, lm["bfs"]),
-                   "sssp_gteps_device": _gteps(sssp_teps, lm["sssp"])}
+                   "sssp_gteps_device": _gteps(sssp_teps, lm["sssp"]),
+                   "step_gteps_device": _gteps(bfs_teps + sssp_teps, lm["bfs"] + lm["sssp"]),
+                   "heuristic_step_gteps_device": _gteps(bfs_teps + sssp_teps, bfs_ms + sssp_ms)}
 
     dom = max(per_kernel, key=lambda k: per_kernel[k][1])
     launches, sum_us, sum_bytes = per_kernel[dom]

@@ -510,10 +510,7 @@ struct DlPlan {
   bool on = false;
   int64_t max_m = 0;
   double do_a = -1.0;   // device push -> pull test (< 0: none)
-  const float* mlp = nullptr;  // device network test (learned policy with pull allowed)
-  int allowed = 0x3;
-  float margin = 0.f;
-  int h_push = GR_PUSH_LB;
+
   int len = kDlFirstLen;
   int blocks = 256;
   int64_t* log = nullptr;
@@ -526,9 +523,7 @@ gr_status dl_plan(gr_ctx* ctx, const gr_opts& o, bool pull_ok, bool learned, boo
   d->on = o.device_max_edges >= 0 && (heuristic || learned || o.policy == GR_POLICY_FIXED);
   d->max_m = o.device_max_edges > 0 ? o.device_max_edges : kDlDefaultMaxEdges;
   d->do_a = (heuristic || learned) && pull_ok ? (double)o.do_a : -1.0;
-  d->mlp = learned && pull_ok ? static_cast<const float*>(ctx->pool[S_MLP].ptr) : nullptr;
-  d->allowed = pull_ok ? 0xF : 0x3;
-  d->margin = o.learned_margin;
+
   d->len = kDlFirstLen;
   d->blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
   d->log = nullptr;
@@ -635,7 +630,6 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
   GR_TRY(dl_plan(ctx, opts, pull_ok, learned, tracing, &dl));
-  dl.h_push = (double)E >= (double)V * (double)opts.lb_min_avg_degree ? GR_PUSH_LB : GR_PUSH_TWC;
 
   while (n_f > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
     lf.level = level;
@@ -658,7 +652,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, dl.do_a,
-                        dl.mlp, dl.allowed, dl.h_push, dl.margin, V, dl.log, ctrl};
+                        V, dl.log, ctrl};
         GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, perm, level + i + 1, dl.blocks,
                                 st));
       }
@@ -912,7 +906,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
-                        nullptr, 0x3, GR_PUSH_LB, 0.f, V, dl.log, ctrl};
+                        V, dl.log, ctrl};
         if (use_pq) GR_HIP(launch_sssp_pq_dstep(da, g->W, keys, tags, it + i + 1, pq, dl.blocks, st));
         else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, perm, it + i + 1, dl.blocks, st));
       }

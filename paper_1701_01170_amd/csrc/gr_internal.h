@@ -273,12 +273,6 @@ struct DlArgs {
   int64_t max_n, max_m;       // run only while n_f <= max_n and m_f <= max_m
   int64_t E;                  // for the push -> pull test
   double do_a;                // push -> pull when m_f > m_u * do_a (< 0: never)
-  const float* mlp;           // selector network (nullable): the level runs while the guarded
-                              // choice (below) is a push action
-  int32_t allowed;            // actions the network may pick (bit a = gr_action a)
-  int32_t h_push;             // the heuristic's push action (by average degree)
-  float margin;               // network overrides the heuristic only when it predicts a
-                              // step shorter by more than this (log2 units)
   int64_t V;
   int64_t* log;               // [kDlMaxLevels][3]
   Ctrl* ctrl;

@@ -7,9 +7,7 @@
 // kernels, and so takes the same decision: the level runs only if no earlier
 // level of the block declined, the frontier is non-empty, it fits the LDS
 // staging (kDlMaxN vertices) and the caller's edge bound, and (BFS) the
-// direction heuristic of Sec. 5.1 would still push (or, under the learned
-// policy, the selector network still picks a push action: every workgroup
-// evaluates it on the same features).  A declining level sets
+// direction heuristic of Sec. 5.1 would still push.  A declining level sets
 // dl_stop, so the rest of the block does nothing.
 //
 // A running level is output-balanced like LB (Sec. 5.1): each workgroup stages
@@ -25,7 +23,6 @@
 #pragma once
 
 #include "k_advance.h"
-#include "k_mlp.h"
 
 namespace gr {
 
@@ -51,20 +48,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   const int64_t vn = ctrl->dl_vn[a.step & 1];
   bool run = n_f > 0 && n_f <= a.max_n && n_f <= kDlMaxN && m_f <= a.max_m;
   // the heuristic's direction (Sec. 5.1 push -> pull test)
-  const bool h_pull = a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a;
-  if (run && a.mlp) {
-    // guarded network choice: the heuristic's action unless the network
-    // predicts another one faster by more than the margin
-    __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
-    if (threadIdx.x == 0)
-      mlp_features(s_x, n_f, m_f, a.V - vn - n_f, a.E - vm - m_f, ctrl->dl_maxd[a.cur], a.V, a.E, 0);
-    const int best = mlp_argmin(a.mlp, s_x, s_h1, s_h2, s_y, a.allowed);
-    const int h = h_pull ? GR_PULL_TWC : a.h_push;
-    const int fin = (best != h && s_y[best] + a.margin < s_y[h]) ? best : h;
-    run = fin == GR_PUSH_TWC || fin == GR_PUSH_LB;
-  } else if (h_pull) {
-    run = false;
-  }
+  if (run && a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a) run = false;
   bool refill = false;
   if constexpr (F::kFar) refill = n_f == 0 && fs.far_pending(ctrl);
   if (!run && !refill) {

@@ -54,7 +54,7 @@ def _records(buf, count):
     return out
 
 
-def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 2, sssp_too: bool = True,
+def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 4, sssp_too: bool = True,
             log=print):
     """Trace samples X[n][8], T[n][4], M[n][4] from fixed- and random-action runs."""
     cap = 1 << 15
@@ -195,7 +195,7 @@ def eval_graphs():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
-    ap.add_argument("--epochs", type=int, default=1500)
+    ap.add_argument("--epochs", type=int, default=3000)
     ap.add_argument("--sources", type=int, default=3)
     ap.add_argument("--eval-only", action="store_true", help="evaluate the stored weights")
     ap.add_argument("--margins", default="0,0.1,0.25,0.5")

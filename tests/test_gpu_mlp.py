@@ -106,9 +106,9 @@ def test_learned_policy_is_exact_and_takes_argmin(ctx, rmat14):
                 y, _ = oracle.mlp_forward(P, x)
                 y = y[0]
                 if t.kernel == 6:
-                    # a device-predicated level: the network (evaluated in the
-                    # level kernel) picked one of the push actions
-                    assert min(y[0], y[1]) <= y.min() + 1e-3, (t.level, y)
+                    # inside a block of device-predicated levels the
+                    # heuristic's push test decides
+                    continue
                 else:
                     # the device's choice is within fp32 rounding of the argmin
                     assert y[t.action] <= y.min() + 1e-3, (t.level, t.action, y)
