@@ -971,22 +971,27 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                        chunks, chunk, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      if (use_pq) {
-        GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                    g->W, keys, tags, it + 1, pq, ctrl, q[(cur + 1) % 3],
-                                    &ctrl->q_count[(cur + 1) % 3], chunk, st));
-        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
-      } else if (m_f >= V / kSsspMarksDivisor) {
+      if (m_f >= V / kSsspMarksDivisor) {
         // many frontier edges: relax with no returning atomic, then list the
-        // vertices whose distance dropped (byte marks)
+        // vertices whose distance dropped (byte marks); with the priority
+        // queue the list is split into the next frontier and the far pile
         uint8_t* marks;
         GR_TRY(marks_buffer(ctx, V, &marks, st));
         kernel += kTraceMarksOffset;
         GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
                                        g->W, keys, perm, marks, chunk, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
-        GR_HIP(launch_sssp_mark_compact(marks, V, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
-                                        st));
+        if (use_pq)
+          GR_HIP(launch_sssp_pq_mark_compact(marks, V, keys, pq, ctrl, q[(cur + 1) % 3],
+                                             &ctrl->q_count[(cur + 1) % 3], st));
+        else
+          GR_HIP(launch_sssp_mark_compact(marks, V, q[(cur + 1) % 3],
+                                          &ctrl->q_count[(cur + 1) % 3], st));
+      } else if (use_pq) {
+        GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
+                                    g->W, keys, tags, it + 1, pq, ctrl, q[(cur + 1) % 3],
+                                    &ctrl->q_count[(cur + 1) % 3], chunk, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       } else {
         GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W,
                                  keys, tags, perm, it + 1, q[(cur + 1) % 3],

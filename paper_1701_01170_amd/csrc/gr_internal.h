@@ -263,6 +263,7 @@ hipError_t launch_mlp_select(const float* params, Ctrl* ctrl, int sp, int64_t V,
 // clears the counters of q[(cur + 2) % 3], which nothing reads during it.
 constexpr int kDlMaxN = 4096;        // frontier vertices staged in LDS per level
 constexpr int kDlMaxLevels = 64;     // levels per block (log capacity)
+constexpr uint32_t kDlMaxRefill = 1u << 16;  // SSSP far-pile entries a block may split itself
 struct DlArgs {
   const int32_t* R;
   const int32_t* C;
@@ -331,6 +332,11 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    const int32_t* perm, uint8_t* marks, int chunk, hipStream_t st);
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, int32_t* out_q, uint32_t* out_count,
                                     hipStream_t st);
+// Priority-queue form: marked vertices below pq.T go to out_q, the others to
+// far pile pq.fc (once per far-pile generation).
+hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
+                                       const PqState& pq, Ctrl* ctrl, int32_t* out_q,
+                                       uint32_t* out_count, hipStream_t st);
 // dist / pred written at caller ids; src_orig_dev: the sources in caller ids
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
                                 uint32_t* dist, int32_t* pred, const int32_t* perm,

@@ -137,7 +137,7 @@ struct BfsMark {
 
 // One thread per bitmap word (32 vertices): gather the marks, clear them, set
 // the live bits (the thread owns the word), write depths and append the new
-// vertices in ascending order within each wavefront.
+// vertices in ascending order within each workgroup (one atomic per workgroup).
 __global__ __launch_bounds__(256) void k_bfs_mark_compact(uint8_t* __restrict__ marks, int64_t V,
                                                           uint32_t* __restrict__ bm, int p,
                                                           int32_t* __restrict__ depth,
@@ -145,38 +145,9 @@ __global__ __launch_bounds__(256) void k_bfs_mark_compact(uint8_t* __restrict__ 
                                                           int32_t* __restrict__ out_q,
                                                           uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n_words = (V + 31) / 32;
-  uint32_t mask = 0;
-  if (w < n_words) {
-    const int64_t v0 = w * 32;
-    if (v0 + 32 <= V) {
-      const uint4* m4 = reinterpret_cast<const uint4*>(marks + v0);
-      const uint4 a = m4[0], b = m4[1];
-      const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if ((q[i] >> (8 * k)) & 0xffu) mask |= 1u << (4 * i + k);
-      if (mask) {
-        uint4* z = reinterpret_cast<uint4*>(marks + v0);
-        z[0] = make_uint4(0, 0, 0, 0);
-        z[1] = make_uint4(0, 0, 0, 0);
-      }
-    } else {
-      for (int64_t v = v0; v < V; ++v)
-        if (marks[v]) {
-          mask |= 1u << (v - v0);
-          marks[v] = 0;
-        }
-    }
-    if (mask) bm[2 * w + 1 - p] |= mask;
-  }
-  const uint32_t n = __popc(mask);
-  const uint32_t inc = wave_incl_scan(n);
-  uint32_t base = 0;
-  if (lane() == kWave - 1 && inc) base = atomicAdd(out_count, inc);
-  base = __shfl(base, kWave - 1) + inc - n;
+  uint32_t mask = take_marks(marks, w, V);
+  if (mask) bm[2 * w + 1 - p] |= mask;
+  uint32_t base = block_append<256>(__popc(mask), out_count);
   while (mask) {
     const int b = __ffs(mask) - 1;
     mask &= mask - 1;

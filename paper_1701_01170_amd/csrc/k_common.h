@@ -59,6 +59,51 @@ __device__ __forceinline__ uint32_t block_append(uint32_t n, uint32_t* counter) 
   return base;
 }
 
+// The marks of vertices 32 w .. 32 w + 31 as a bit mask; the marks are
+// cleared (they are all zero again when the pass is done).
+__device__ __forceinline__ uint32_t take_marks(uint8_t* __restrict__ marks, int64_t w, int64_t V) {
+  const int64_t n_words = (V + 31) / 32;
+  uint32_t mask = 0;
+  if (w >= n_words) return 0;
+  const int64_t v0 = w * 32;
+  if (v0 + 32 <= V) {
+    const uint4* m4 = reinterpret_cast<const uint4*>(marks + v0);
+    const uint4 a = m4[0], b = m4[1];
+    const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((q[i] >> (8 * k)) & 0xffu) mask |= 1u << (4 * i + k);
+    if (mask) {
+      uint4* z = reinterpret_cast<uint4*>(marks + v0);
+      z[0] = make_uint4(0, 0, 0, 0);
+      z[1] = make_uint4(0, 0, 0, 0);
+    }
+  } else {
+    for (int64_t v = v0; v < V; ++v)
+      if (marks[v]) {
+        mask |= 1u << (v - v0);
+        marks[v] = 0;
+      }
+  }
+  return mask;
+}
+
+// Appends the vertices 32 w + b, for every bit b of mask, to out_q with one
+// atomic per workgroup (ascending within the workgroup).
+// Every thread of the workgroup must call it.
+template <int BLOCK>
+__device__ __forceinline__ void append_mask(uint32_t mask, int64_t w, int32_t* __restrict__ out_q,
+                                            uint32_t* out_count) {
+  uint32_t base = block_append<BLOCK>(__popc(mask), out_count);
+  while (mask) {
+    const int b = __ffs(mask) - 1;
+    mask &= mask - 1;
+    out_q[base++] = (int32_t)(w * 32 + b);
+  }
+}
+
 // Inclusive prefix sum across the wavefront (all 64 lanes must be active).
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {

@@ -131,47 +131,37 @@ struct SsspMark {
 };
 
 // One thread per 32 vertices: gather and clear the marks, list the marked
-// vertices (ascending within each wavefront).
+// vertices (ascending within each workgroup).
 __global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__ marks, int64_t V,
                                                            int32_t* __restrict__ out_q,
                                                            uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n_words = (V + 31) / 32;
-  uint32_t mask = 0;
-  if (w < n_words) {
-    const int64_t v0 = w * 32;
-    if (v0 + 32 <= V) {
-      const uint4* m4 = reinterpret_cast<const uint4*>(marks + v0);
-      const uint4 a = m4[0], b = m4[1];
-      const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if ((q[i] >> (8 * k)) & 0xffu) mask |= 1u << (4 * i + k);
-      if (mask) {
-        uint4* z = reinterpret_cast<uint4*>(marks + v0);
-        z[0] = make_uint4(0, 0, 0, 0);
-        z[1] = make_uint4(0, 0, 0, 0);
-      }
-    } else {
-      for (int64_t v = v0; v < V; ++v)
-        if (marks[v]) {
-          mask |= 1u << (v - v0);
-          marks[v] = 0;
-        }
+  append_mask<256>(take_marks(marks, w, V), w, out_q, out_count);
+}
+
+// The same with the near / far split of the priority queue: a marked vertex
+// whose distance is below the threshold T joins the next frontier, any other
+// joins far pile fc unless it is already there in this generation (far_tag).
+// Only the thread owning a vertex reads or writes its far tag here.
+__global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
+    uint8_t* __restrict__ marks, int64_t V, const unsigned long long* __restrict__ keys, uint32_t T,
+    int32_t epoch, int32_t* __restrict__ far_tag, int32_t* __restrict__ far_q,
+    uint32_t* __restrict__ far_count, int32_t* __restrict__ out_q,
+    uint32_t* __restrict__ out_count) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t mask = take_marks(marks, w, V), near = 0, far = 0;
+  for (uint32_t m = mask; m; m &= m - 1) {
+    const int b = __ffs(m) - 1;
+    const int64_t v = w * 32 + b;
+    if ((uint32_t)(keys[v] >> 32) < T) {
+      near |= 1u << b;
+    } else if (far_tag[v] != epoch) {
+      far_tag[v] = epoch;
+      far |= 1u << b;
     }
   }
-  const uint32_t n = __popc(mask);
-  const uint32_t inc = wave_incl_scan(n);
-  uint32_t base = 0;
-  if (lane() == kWave - 1 && inc) base = atomicAdd(out_count, inc);
-  base = __shfl(base, kWave - 1) + inc - n;
-  while (mask) {
-    const int b = __ffs(mask) - 1;
-    mask &= mask - 1;
-    out_q[base++] = (int32_t)(w * 32 + b);
-  }
+  append_mask<256>(near, w, out_q, out_count);
+  append_mask<256>(far, w, far_q, far_count);
 }
 
 __device__ __forceinline__ uint32_t pq_next_threshold(uint32_t T, uint32_t delta) {
@@ -180,8 +170,11 @@ __device__ __forceinline__ uint32_t pq_next_threshold(uint32_t T, uint32_t delta
 }
 
 // Split far pile fc into the next frontier and far pile (fc + 1) % 3 (see the
-// file comment); grid-stride, every wavefront runs whole iterations.  With
-// deg_sum / deg_max the degrees of the new frontier are accumulated too.
+// file comment).  Grid-stride over kRefillItems entries per thread; both
+// lists are appended with one atomic per workgroup and round, so every thread
+// of the workgroup must call it.  With deg_sum / deg_max the degrees of the
+// new frontier are accumulated too (one atomic per wavefront at the end).
+constexpr int kRefillItems = 4;
 __device__ __forceinline__ void pq_refill_pass(const unsigned long long* __restrict__ keys,
                                                uint32_t T, uint32_t delta, int32_t epoch, int32_t fc,
                                                int32_t* __restrict__ far_base,
@@ -190,29 +183,51 @@ __device__ __forceinline__ void pq_refill_pass(const unsigned long long* __restr
                                                const int32_t* __restrict__ R,
                                                unsigned long long* deg_sum,
                                                unsigned long long* deg_max) {
+  constexpr int K = kRefillItems;
   const uint32_t T1 = pq_next_threshold(T, delta);
   const int32_t fn = (fc + 1) % 3;
   const int32_t* __restrict__ in = far_base + (int64_t)fc * V;
   int32_t* __restrict__ keep_q = far_base + (int64_t)fn * V;
   const int64_t n = ctrl->far_count[fc];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const int32_t v = i < n ? in[i] : -1;
-    const uint32_t d = v >= 0 ? (uint32_t)(keys[v] >> 32) : 0u;
-    const bool near = v >= 0 && d >= T && d < T1;
-    const bool keep = v >= 0 && d >= T1;
-    if (keep) far_tag[v] = epoch + 1;
-    const uint32_t s1 = wave_append(out_count, near);
-    if (near) out_q[s1] = v;
-    const uint32_t s2 = wave_append(&ctrl->far_count[fn], keep);
-    if (keep) keep_q[s2] = v;
-    if (deg_sum) {
-      const unsigned long long dg = near ? (unsigned long long)(R[v + 1] - R[v]) : 0ull;
-      const unsigned long long ds = wave_sum(dg), dm = wave_max(dg);
-      if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
-      if (lane() == 0 && dm) atomicMax(deg_max, dm);
+  const int64_t per_round = (int64_t)kAdvBlock * K;
+  const int64_t stride = (int64_t)gridDim.x * per_round;
+  unsigned long long ds = 0, dm = 0;
+  for (int64_t base = (int64_t)blockIdx.x * per_round; base < n; base += stride) {
+    int32_t v[K];
+    bool near[K], keep[K];
+    uint32_t n_near = 0, n_keep = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const int64_t i = base + r * kAdvBlock + threadIdx.x;
+      v[r] = i < n ? in[i] : -1;
     }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const uint32_t d = v[r] >= 0 ? (uint32_t)(keys[v[r]] >> 32) : 0u;
+      near[r] = v[r] >= 0 && d >= T && d < T1;
+      keep[r] = v[r] >= 0 && d >= T1;
+      if (keep[r]) far_tag[v[r]] = epoch + 1;
+      n_near += near[r] ? 1u : 0u;
+      n_keep += keep[r] ? 1u : 0u;
+    }
+    uint32_t s1 = block_append<kAdvBlock>(n_near, out_count);
+    uint32_t s2 = block_append<kAdvBlock>(n_keep, &ctrl->far_count[fn]);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      if (near[r]) out_q[s1++] = v[r];
+      if (keep[r]) keep_q[s2++] = v[r];
+      if (deg_sum && near[r]) {
+        const unsigned long long dg = (unsigned long long)(R[v[r] + 1] - R[v[r]]);
+        ds += dg;
+        dm = dg > dm ? dg : dm;
+      }
+    }
+  }
+  if (deg_sum) {
+    ds = wave_sum(ds);
+    dm = wave_max(dm);
+    if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
+    if (lane() == 0 && dm) atomicMax(deg_max, dm);
   }
 }
 
@@ -288,8 +303,12 @@ struct SsspPqVisit {
     g.far_count = &ctrl->far_count[g.fc];
     return g;
   }
+  // a refill step inside a device-predicated block runs on that block's small
+  // grid, so only modest far piles are split there; larger ones end the block
+  // and are split by the full-grid refill kernel
   __device__ __forceinline__ bool far_pending(const Ctrl* ctrl) const {
-    return ctrl->far_count[fc] > 0;
+    const uint32_t n = ctrl->far_count[fc];
+    return n > 0 && n <= kDlMaxRefill;
   }
   // queue state of the next step (called once, by one thread)
   __device__ __forceinline__ void advance(Ctrl* ctrl, int step, bool refill) const {
@@ -313,7 +332,7 @@ struct SsspPqVisit {
   }
 };
 
-__global__ __launch_bounds__(256) void k_sssp_pq_refill(const unsigned long long* __restrict__ keys,
+__global__ __launch_bounds__(kAdvBlock) void k_sssp_pq_refill(const unsigned long long* __restrict__ keys,
                                                         PqState pq, Ctrl* __restrict__ ctrl,
                                                         int32_t* __restrict__ out_q,
                                                         uint32_t* __restrict__ out_count) {
@@ -462,9 +481,9 @@ hipError_t launch_sssp_pq_relax(int mode, const int32_t* frontier, const int32_t
 
 hipError_t launch_sssp_pq_refill(const unsigned long long* keys, const PqState& pq, Ctrl* ctrl,
                                  int64_t max_n, int32_t* out_q, uint32_t* out_count, hipStream_t st) {
-  unsigned g = blocks_for(max_n > 0 ? max_n : 1, 256);
-  if (g > 2048) g = 2048;
-  k_sssp_pq_refill<<<g, 256, 0, st>>>(keys, pq, ctrl, out_q, out_count);
+  unsigned g = blocks_for(max_n > 0 ? max_n : 1, kAdvBlock * kRefillItems);
+  if (g > 4096) g = 4096;
+  k_sssp_pq_refill<<<g, kAdvBlock, 0, st>>>(keys, pq, ctrl, out_q, out_count);
   return hipGetLastError();
 }
 
@@ -484,6 +503,17 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
   const SsspMark f{W, keys, marks, perm};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
                        nullptr, chunk, st);
+}
+
+hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
+                                       const PqState& pq, Ctrl* ctrl, int32_t* out_q,
+                                       uint32_t* out_count, hipStream_t st) {
+  const int64_t n_words = (V + 31) / 32;
+  if (n_words <= 0) return hipSuccess;
+  k_sssp_pq_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(
+      marks, V, keys, pq.T, pq.epoch, pq.far_tag, pq.far_base + (int64_t)pq.fc * pq.V,
+      &ctrl->far_count[pq.fc], out_q, out_count);
+  return hipGetLastError();
 }
 
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, int32_t* out_q, uint32_t* out_count,
