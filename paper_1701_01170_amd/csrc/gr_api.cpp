@@ -505,6 +505,11 @@ constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filt
 // SSSP iterations whose frontier has at least V / kSsspMarksDivisor edges use
 // the byte-mark filter.
 constexpr int64_t kSsspMarksDivisor = 4;
+// ... and screen their edges with the 16-bit distance mirror once the
+// frontiers so far, this one included, sum to at least V / kSsspMirrorDivisor
+// vertices (an upper bound of the vertices reached): before that most edges
+// reach unvisited vertices, pass the screen anyway and pay for both gathers.
+constexpr int64_t kSsspMirrorDivisor = 2;
 
 struct DlPlan {
   bool on = false;
@@ -828,6 +833,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
+  uint16_t* mirror;
+  GR_TRY(pool_typed(ctx, S_MIRROR, V, &mirror));
   // src_dev: the sources in traversal ids, then in caller ids
   GR_TRY(pool_typed(ctx, S_TMP0, 2 * (size_t)n_src, &src_dev));
   std::vector<int32_t> src_both(2 * (size_t)n_src);
@@ -855,7 +862,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_HIP(hipMemcpyAsync(qA, src_both.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
   GR_HIP(hipStreamSynchronize(st));  // the host vector must outlive the copies
   GR_HIP(hipEventRecord(ctx->ev_start, st));
-  GR_HIP(launch_sssp_init(keys, tags, use_pq ? pq.far_tag : nullptr, V, ctrl, st));
+  GR_HIP(launch_sssp_init(keys, tags, use_pq ? pq.far_tag : nullptr, mirror, V, ctrl, st));
   GR_HIP(launch_sssp_seed(src_dev, n_src, keys, tags, ctrl, st));
   int cur = 0, sp = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
@@ -874,6 +881,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   int64_t far_n = 0;
   int it = 0;
   int64_t inspected = 0;
+  int64_t expanded = 0;  // sum of the frontier sizes so far
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
@@ -924,6 +932,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
         rs.action_count[action] += k;
         inspected += hc->dl_vm[k & 1];
+        expanded += hc->dl_vn[k & 1];
         if (use_pq) {
           pq.T = hc->pq_T[k & 1];
           pq.epoch = hc->pq_epoch[k & 1];
@@ -978,14 +987,15 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         uint8_t* marks;
         GR_TRY(marks_buffer(ctx, V, &marks, st));
         kernel += kTraceMarksOffset;
+        const bool screen = expanded + n_f >= V / kSsspMirrorDivisor;
         GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                       g->W, keys, perm, marks, chunk, st));
+                                       g->W, keys, perm, marks, mirror, screen, chunk, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
         if (use_pq)
-          GR_HIP(launch_sssp_pq_mark_compact(marks, V, keys, pq, ctrl, q[(cur + 1) % 3],
+          GR_HIP(launch_sssp_pq_mark_compact(marks, V, keys, mirror, pq, ctrl, q[(cur + 1) % 3],
                                              &ctrl->q_count[(cur + 1) % 3], st));
         else
-          GR_HIP(launch_sssp_mark_compact(marks, V, q[(cur + 1) % 3],
+          GR_HIP(launch_sssp_mark_compact(marks, V, keys, mirror, q[(cur + 1) % 3],
                                           &ctrl->q_count[(cur + 1) % 3], st));
       } else if (use_pq) {
         GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
@@ -999,6 +1009,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
       inspected += m_f;
+      expanded += n_f;
       rs.action_count[action]++;
     }
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));

@@ -63,6 +63,7 @@ enum Slot : int {
   S_CHUNKS,        // LB chunk -> first frontier segment map
   S_MARKS,         // one byte per vertex, all zero between uses
   S_MLP_WS,        // selector gradient partial sums
+  S_MIRROR,        // shortest-path 16-bit distance mirror [V]
   S_NSLOTS
 };
 
@@ -312,8 +313,8 @@ hipError_t launch_sssp_pq_dstep(const DlArgs& a, const uint32_t* W, unsigned lon
                                 hipStream_t st);
 
 // SSSP
-hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag, int64_t V, Ctrl* ctrl,
-                            hipStream_t st);
+hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag,
+                            uint16_t* mirror, int64_t V, Ctrl* ctrl, hipStream_t st);
 hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long long* keys,
                             int32_t* tags, Ctrl* ctrl, hipStream_t st);
 // keys hold (dist << 32 | predecessor in caller ids); perm nullable
@@ -324,19 +325,23 @@ hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* o
                              int32_t next_tag, int32_t* out_q, uint32_t* out_count, int chunk,
                              hipStream_t st);
 // Relaxation with the non-atomic filter (byte marks, all zero before and after
-// the pair of calls), then the ordered list of the marked vertices.
+// the pair of calls), then the ordered list of the marked vertices.  With
+// filter, the 16-bit distance mirror screens the edges before the key gather;
+// the compaction refreshes the mirror of every marked vertex.
 hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                    const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
-                                   const int32_t* perm, uint8_t* marks, int chunk, hipStream_t st);
-hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, int32_t* out_q, uint32_t* out_count,
+                                   const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
+                                   bool filter, int chunk, hipStream_t st);
+hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
+                                    uint16_t* mirror, int32_t* out_q, uint32_t* out_count,
                                     hipStream_t st);
 // Priority-queue form: marked vertices below pq.T go to out_q, the others to
 // far pile pq.fc (once per far-pile generation).
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                       const PqState& pq, Ctrl* ctrl, int32_t* out_q,
-                                       uint32_t* out_count, hipStream_t st);
+                                       uint16_t* mirror, const PqState& pq, Ctrl* ctrl,
+                                       int32_t* out_q, uint32_t* out_count, hipStream_t st);
 // dist / pred written at caller ids; src_orig_dev: the sources in caller ids
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
                                 uint32_t* dist, int32_t* pred, const int32_t* perm,

@@ -42,7 +42,12 @@
 namespace gr {
 
 constexpr int kAdvBlock = 256;
-constexpr int kLbCap = 2048;  // frontier segments staged in LDS per pass
+// Frontier segments a workgroup stages in LDS per pass: half the chunk's
+// edges (at most 2048).  A chunk whose rows average fewer than two edges takes
+// more than one pass; a smaller stage leaves LDS for more resident workgroups.
+constexpr int lb_cap(int chunk_edges) {
+  return chunk_edges / 2 < 256 ? 256 : (chunk_edges / 2 > 2048 ? 2048 : chunk_edges / 2);
+}
 
 // Process up to B edges per lane: ok[r] marks a real edge (u[r], pay[r], ce[r]).
 // With DEG, the degrees of the appended vertices are also summed into
@@ -131,7 +136,7 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
 }
 
 // One workgroup per chunk of NB * EPT * 256 edges of the output frontier.  The
-// frontier segments overlapping the chunk are staged in LDS (kLbCap per pass);
+// frontier segments overlapping the chunk are staged in LDS (lb_cap per pass);
 // a 16-bit segment index per edge slot comes from scattering segment starts and
 // a max-scan; the edges are then processed in NB batches of EPT per thread
 // (EPT independent loads in flight per lane).
@@ -144,11 +149,12 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
   constexpr int BATCH = kAdvBlock * EPT;
   constexpr int N = BATCH * NB;
   constexpr int SPT = N / kAdvBlock;  // segment-map slots per thread
+  constexpr int CAP = lb_cap(N);
   __shared__ uint16_t s_seg[N];
-  __shared__ int32_t s_off[kLbCap + 1];
-  __shared__ int32_t s_u[kLbCap];
-  __shared__ int32_t s_rb[kLbCap];
-  __shared__ typename F::pay_t s_pay[kLbCap];
+  __shared__ int32_t s_off[CAP + 1];
+  __shared__ int32_t s_u[CAP];
+  __shared__ int32_t s_rb[CAP];
+  __shared__ typename F::pay_t s_pay[CAP];
   __shared__ int32_t s_tmp[kAdvBlock / kWave + 1];
   const int c = blockIdx.x;
   const int64_t e0 = (int64_t)c * N;
@@ -156,8 +162,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
   const int nchunks = (int)(((int64_t)m_f + N - 1) / N);
   const int sb = chunk_start[c];
   const int se = c + 1 < nchunks ? chunk_start[c + 1] : n_f - 1;
-  for (int pb = sb; pb <= se; pb += kLbCap) {
-    const int cnt = (se - pb + 1) < kLbCap ? (se - pb + 1) : kLbCap;
+  for (int pb = sb; pb <= se; pb += CAP) {
+    const int cnt = (se - pb + 1) < CAP ? (se - pb + 1) : CAP;
     for (int i = threadIdx.x; i < cnt; i += kAdvBlock) {
       const int s = pb + i;
       const int32_t u = frontier[s];

@@ -93,11 +93,23 @@ struct SsspVisit {
 // decreases, so a vertex gets a mark exactly when its distance decreased in
 // this iteration, by this edge or by a concurrent one: the marks are the
 // next frontier, which k_sssp_mark_compact lists in ascending order.
+//
+// With FILTER, a 16-bit distance mirror (min(dist, 0xffff) of an earlier
+// moment, refreshed by the compaction for every marked vertex) screens the
+// edges first.  Distances only decrease, so a mirror value below 0xffff is an
+// upper bound of the current distance: an edge whose candidate exceeds it can
+// neither shorten the distance nor tie it, and skips the 8-byte key gather.
+// The mirror is a quarter of the keys' size, so its gathers hit the caches
+// more often; the filter pays off once most vertices have been reached.
+constexpr uint32_t kMirrorNone = 0xffffu;
+
+template <bool FILTER>
 struct SsspMark {
   const uint32_t* __restrict__ W;
   unsigned long long* __restrict__ keys;
   uint8_t* __restrict__ marks;
   const int32_t* __restrict__ perm;
+  const uint16_t* __restrict__ mirror;
 
   using pay_t = int32_t;
   static constexpr bool kFar = false;
@@ -114,13 +126,25 @@ struct SsspMark {
   __device__ __forceinline__ void commit_batch(const int32_t (&u)[B], const int32_t (&du)[B],
                                                const int32_t (&v)[B], const uint32_t (&w)[B],
                                                const bool (&ok)[B], int (&code)[B]) const {
+    bool pass[B];
+    if constexpr (FILTER) {
+      uint32_t m[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r) m[r] = ok[r] ? (uint32_t)mirror[v[r]] : 0u;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        pass[r] = ok[r] && (m[r] == kMirrorNone || (uint64_t)(uint32_t)du[r] + w[r] <= m[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < B; ++r) pass[r] = ok[r];
+    }
     unsigned long long k[B];
 #pragma unroll
-    for (int r = 0; r < B; ++r) k[r] = ok[r] ? keys[v[r]] : 0ull;
+    for (int r = 0; r < B; ++r) k[r] = pass[r] ? keys[v[r]] : 0ull;
 #pragma unroll
     for (int r = 0; r < B; ++r) {
       code[r] = 0;
-      if (!ok[r]) continue;
+      if (!pass[r]) continue;
       const uint64_t cand = (uint64_t)(uint32_t)du[r] + (uint64_t)w[r];
       const unsigned long long nk = (cand << 32) | caller_id(perm, u[r]);
       if (nk < k[r]) atomicMin(&keys[v[r]], nk);
@@ -130,22 +154,37 @@ struct SsspMark {
   __device__ __forceinline__ bool commit(int32_t, int32_t, int32_t, uint32_t) const { return false; }
 };
 
+__device__ __forceinline__ uint16_t mirror_of(unsigned long long key) {
+  const uint32_t d = (uint32_t)(key >> 32);
+  return (uint16_t)(d < kMirrorNone ? d : kMirrorNone);
+}
+
 // One thread per 32 vertices: gather and clear the marks, list the marked
 // vertices (ascending within each workgroup).
+// The distance mirror of every marked vertex is refreshed on the way.
 __global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__ marks, int64_t V,
+                                                           const unsigned long long* __restrict__ keys,
+                                                           uint16_t* __restrict__ mirror,
                                                            int32_t* __restrict__ out_q,
                                                            uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  append_mask<256>(take_marks(marks, w, V), w, out_q, out_count);
+  const uint32_t mask = take_marks(marks, w, V);
+  for (uint32_t m = mask; m; m &= m - 1) {
+    const int64_t v = w * 32 + __ffs(m) - 1;
+    mirror[v] = mirror_of(keys[v]);
+  }
+  append_mask<256>(mask, w, out_q, out_count);
 }
 
 // The same with the near / far split of the priority queue: a marked vertex
 // whose distance is below the threshold T joins the next frontier, any other
 // joins far pile fc unless it is already there in this generation (far_tag).
-// Only the thread owning a vertex reads or writes its far tag here.
+// Only the thread owning a vertex reads or writes its far tag here; the
+// distance mirror is refreshed as in k_sssp_mark_compact.
 __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
-    uint8_t* __restrict__ marks, int64_t V, const unsigned long long* __restrict__ keys, uint32_t T,
-    int32_t epoch, int32_t* __restrict__ far_tag, int32_t* __restrict__ far_q,
+    uint8_t* __restrict__ marks, int64_t V, const unsigned long long* __restrict__ keys,
+    uint16_t* __restrict__ mirror, uint32_t T, int32_t epoch, int32_t* __restrict__ far_tag,
+    int32_t* __restrict__ far_q,
     uint32_t* __restrict__ far_count, int32_t* __restrict__ out_q,
     uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,7 +192,9 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
   for (uint32_t m = mask; m; m &= m - 1) {
     const int b = __ffs(m) - 1;
     const int64_t v = w * 32 + b;
-    if ((uint32_t)(keys[v] >> 32) < T) {
+    const unsigned long long key = keys[v];
+    mirror[v] = mirror_of(key);
+    if ((uint32_t)(key >> 32) < T) {
       near |= 1u << b;
     } else if (far_tag[v] != epoch) {
       far_tag[v] = epoch;
@@ -343,13 +384,15 @@ __global__ __launch_bounds__(kAdvBlock) void k_sssp_pq_refill(const unsigned lon
 
 __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restrict__ keys,
                                                    int32_t* __restrict__ tags,
-                                                   int32_t* __restrict__ far_tag, int64_t V,
+                                                   int32_t* __restrict__ far_tag,
+                                                   uint16_t* __restrict__ mirror, int64_t V,
                                                    Ctrl* __restrict__ ctrl) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
     keys[v] = ~0ull;
     tags[v] = -1;
     if (far_tag) far_tag[v] = -1;
+    mirror[v] = (uint16_t)kMirrorNone;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->far_count[0] = ctrl->far_count[1] = ctrl->far_count[2] = 0;
@@ -413,11 +456,11 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
-hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag, int64_t V,
-                            Ctrl* ctrl, hipStream_t st) {
+hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag,
+                            uint16_t* mirror, int64_t V, Ctrl* ctrl, hipStream_t st) {
   unsigned g = blocks_for(V, 256);
   if (g > 4096) g = 4096;
-  k_sssp_init<<<g, 256, 0, st>>>(keys, tags, far_tag, V, ctrl);
+  k_sssp_init<<<g, 256, 0, st>>>(keys, tags, far_tag, mirror, V, ctrl);
   return hipGetLastError();
 }
 
@@ -499,28 +542,36 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
-                                   const int32_t* perm, uint8_t* marks, int chunk, hipStream_t st) {
-  const SsspMark f{W, keys, marks, perm};
+                                   const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
+                                   bool filter, int chunk, hipStream_t st) {
+  if (filter) {
+    const SsspMark<true> f{W, keys, marks, perm, mirror};
+    return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
+                         nullptr, chunk, st);
+  }
+  const SsspMark<false> f{W, keys, marks, perm, mirror};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
                        nullptr, chunk, st);
 }
 
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                       const PqState& pq, Ctrl* ctrl, int32_t* out_q,
-                                       uint32_t* out_count, hipStream_t st) {
+                                       uint16_t* mirror, const PqState& pq, Ctrl* ctrl,
+                                       int32_t* out_q, uint32_t* out_count, hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   if (n_words <= 0) return hipSuccess;
   k_sssp_pq_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(
-      marks, V, keys, pq.T, pq.epoch, pq.far_tag, pq.far_base + (int64_t)pq.fc * pq.V,
+      marks, V, keys, mirror, pq.T, pq.epoch, pq.far_tag, pq.far_base + (int64_t)pq.fc * pq.V,
       &ctrl->far_count[pq.fc], out_q, out_count);
   return hipGetLastError();
 }
 
-hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, int32_t* out_q, uint32_t* out_count,
+hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
+                                    uint16_t* mirror, int32_t* out_q, uint32_t* out_count,
                                     hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   if (n_words <= 0) return hipSuccess;
-  k_sssp_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, out_q, out_count);
+  k_sssp_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, keys, mirror, out_q,
+                                                                out_count);
   return hipGetLastError();
 }
 

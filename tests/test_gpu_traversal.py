@@ -141,6 +141,16 @@ def test_er_bfs_sssp(ctx):
     run_sssp_all(ctx, hg, [[int(s)] for s in gg.sources(hg, 2, seed=4)])
 
 
+@pytest.mark.parametrize("lo,hi", [(1, 2), (30000, 140000)])
+def test_sssp_distance_mirror(ctx, lo, hi):
+    # large frontiers relax through the byte-mark filter, screened by the
+    # 16-bit distance mirror once most vertices are reached: weights 1..2
+    # make tight in-edges (predecessor ties) common, weights 30000..140000
+    # push distances across the mirror's saturation value 0xffff
+    hg = gg.add_weights(gg.erdos_renyi(30001, 8, seed=11), seed=12, lo=lo, hi=hi)
+    run_sssp_all(ctx, hg, [[int(s)] for s in gg.sources(hg, 2, seed=13)])
+
+
 def test_unsorted_input_is_sorted_on_ingest(ctx, rmat14):
     hg = rmat14
     rng = np.random.default_rng(0)
