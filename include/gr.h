@@ -243,7 +243,11 @@ gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* source
  * A small MLP predicts, from eight per-iteration features, the log2 step time
  * of each of the four gr_action strategies; GR_POLICY_LEARNED runs the fused
  * inference kernel on the device every iteration and takes the fastest allowed
- * action.  The choice can only change the time taken: every action computes
+ * action, guarded by learned_margin.  Where an iteration is small enough for a
+ * block of device-predicated push levels (see device_max_edges) the network
+ * may turn the heuristic's pull into a push but not a push into a pull, and
+ * the levels inside such a block follow the heuristic.  The choice can only
+ * change the time taken: every action computes
  * the exact same results.  (The paper picks strategies by fixed thresholds on
  * the degree distribution, Sec. 5.1, and notes in Sec. 7 that the same
  * parameters do not suit every graph; the network replaces the thresholds.)

@@ -77,9 +77,14 @@ gr_status pool_typed(gr_ctx* ctx, Slot s, size_t count, T** out) {
 // it to host memory and then bumps a sequence number, which the host polls;
 // every 4096 polls the stream status is checked, so a failed launch or a
 // faulted stream ends the wait with an error instead of a hang.
-gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st) {
+// With sel, the selector network decides on the device in the same kernel
+// that publishes the control block.
+gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st, const MlpSelect* sel = nullptr) {
   const uint32_t seq = ++ctx->publish_seq;
-  GR_HIP(launch_publish(dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
+  if (sel)
+    GR_HIP(launch_publish_select(*sel, dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
+  else
+    GR_HIP(launch_publish(dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
   for (uint64_t i = 1;; ++i) {
     if (*ctx->publish_flag == seq) break;
     if ((i & 4095) == 0) {
@@ -497,7 +502,7 @@ gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int 
 }
 
 // ---- iteration control: device-predicated blocks of push levels ----------
-constexpr int kDlFirstLen = 4;              // levels in the first block; doubles while blocks run whole
+constexpr int kDlFirstLen = 4;              // levels in the first block (then adapted per block)
 constexpr int64_t kDlDefaultMaxEdges = 1 << 18;
 constexpr int kTraceKernelDstep = 6;
 constexpr int kTraceKernelRefill = 7;
@@ -619,8 +624,12 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const bool learned = opts.policy == GR_POLICY_LEARNED && ctx->policy_loaded;
   const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr);
   const int allowed = pull_ok ? 0xF : 0x3;
-  if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V, E, 0, allowed, st));
-  GR_TRY(read_ctrl(ctx, ctrl, st));
+  // the selector's inputs at the current statistics slot (learned policy only)
+  auto select_at = [&](int slot, int64_t n_u, int64_t m_u, int prev_pull) {
+    return MlpSelect{mlp, slot, V, E, n_u, m_u, prev_pull, allowed};
+  };
+  MlpSelect msel = select_at(sp, V, E, 0);
+  GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
 
   Selector sel;
   sel.init(opts, g->V, g->E, pull_ok, /*is_sssp=*/false, ctx->policy_loaded);
@@ -644,19 +653,23 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     lf.n_u = V - visited_n;
     lf.m_u = E - visited_m;
     lf.prev_pull = sel.mode_pull ? 1 : 0;
-    const int action = sel.decide(lf, learned ? hc->action : -1, learned ? hc->pred : nullptr);
-    if (dl.on && (action == GR_PUSH_LB || action == GR_PUSH_TWC) && n_f <= kDlMaxN &&
-        m_f <= dl.max_m) {
+    const bool dl_fits = dl.on && n_f <= kDlMaxN && m_f <= dl.max_m;
+    const int action = sel.decide(lf, learned ? hc->action : -1, learned ? hc->pred : nullptr,
+                                  dl_fits);
+    if (dl_fits && (action == GR_PUSH_LB || action == GR_PUSH_TWC)) {
       // A block of device-predicated push levels (atomic parents, no merge
       // pass); its first level is the one just decided on the host.
       int kmax = dl.len;
       if (opts.max_iterations > 0) kmax = (int)std::min<int64_t>(kmax, opts.max_iterations - level);
       const int64_t vm0 = visited_m - m_f, vn0 = visited_n - n_f;
+      // the network pushing where the heuristic would pull: the block keeps
+      // pushing (its device-side direction test would stop it at once)
+      const double blk_do_a = sel.last_heuristic >= GR_PULL_TWC ? -1.0 : dl.do_a;
       GR_HIP(launch_dl_begin(ctrl, cur, sp, vm0, vn0, 0u, 0, 0, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
-        const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, dl.do_a,
+        const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, blk_do_a,
                         V, dl.log, ctrl};
         GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, perm, level + i + 1, dl.blocks,
                                 st));
@@ -672,7 +685,9 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
           GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
           GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         }
-        dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
+        // full blocks double the next one; blocks that stop early halve it
+        if (k == kmax) dl.len = std::min(2 * dl.len, kDlMaxLevels);
+        else if (2 * k < kmax) dl.len = std::max(dl.len / 2, kDlFirstLen);
         rs.action_count[action] += k;
         inspected_push += hc->dl_vm[k & 1] - vm0;
         visited_n = hc->dl_vn[k & 1];
@@ -683,9 +698,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         level += k;
         GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                      &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-        if (learned)
-          GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V - visited_n, E - visited_m, 0, allowed, st));
-        GR_TRY(read_ctrl(ctx, ctrl, st));
+        msel = select_at(sp, V - visited_n, E - visited_m, 0);
+        GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
         if (tracing) {
           int64_t vn = vn0, vm = vm0;
           for (int i = 0; i < k; ++i) {
@@ -761,10 +775,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     ++level;
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-    if (learned)
-      GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, V - visited_n, E - visited_m,
-                               sel.mode_pull ? 1 : 0, allowed, st));
-    GR_TRY(read_ctrl(ctx, ctrl, st));
+    msel = select_at(sp, V - visited_n, E - visited_m, sel.mode_pull ? 1 : 0);
+    GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
     if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
@@ -869,8 +881,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
                                &ctrl->q_count[(cur + 1) % 3], nullptr, st));
   const bool learned = opts.policy == GR_POLICY_LEARNED && ctx->policy_loaded;
   const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr);
-  if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
-  GR_TRY(read_ctrl(ctx, ctrl, st));
+  MlpSelect msel{mlp, sp, V, E, 0, 0, 0, 0x3};
+  GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
 
   Selector sel;
   sel.init(opts, V, E, /*pull_ok=*/false, /*is_sssp=*/true, ctx->policy_loaded);
@@ -890,8 +902,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   auto next_frontier = [&]() -> gr_status {
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-    if (learned) GR_HIP(launch_mlp_select(mlp, ctrl, sp, V, E, 0, 0, 0, 0x3, st));
-    GR_TRY(read_ctrl(ctx, ctrl, st));
+    msel.sp = sp;
+    GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
     if (use_pq) far_n = hc->far_count[pq.fc];
     return GR_OK;
   };
@@ -903,8 +915,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     lf.n_u = 0;
     lf.m_u = 0;
     lf.prev_pull = 0;
+    const bool dl_fits = dl.on && n_f <= kDlMaxN && m_f <= dl.max_m;
     const int action = sel.decide(lf, learned ? hc->action : -1, learned ? hc->pred : nullptr);
-    if (dl.on && n_f <= kDlMaxN && m_f <= dl.max_m) {
+    if (dl_fits) {
       // A block of device-predicated relaxation rounds (Alg. 1 iterations;
       // with the priority queue also its refill steps).
       int kmax = dl.len;
@@ -929,7 +942,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
           GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
           GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         }
-        dl.len = k == kmax ? std::min(2 * dl.len, kDlMaxLevels) : dl.len;
+        // full blocks double the next one; blocks that stop early halve it
+        if (k == kmax) dl.len = std::min(2 * dl.len, kDlMaxLevels);
+        else if (2 * k < kmax) dl.len = std::max(dl.len / 2, kDlFirstLen);
         rs.action_count[action] += k;
         inspected += hc->dl_vm[k & 1];
         expanded += hc->dl_vn[k & 1];

@@ -251,9 +251,21 @@ hipError_t launch_mlp_loss_grad(const float* params, const float* X, const float
                                 float* loss, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t st);
-hipError_t launch_mlp_select(const float* params, Ctrl* ctrl, int sp, int64_t V, int64_t E,
-                             int64_t n_u_before, int64_t m_u_before, int prev_pull, int allowed,
-                             hipStream_t st);
+// Inputs of one selector decision besides the frontier statistics in slot sp
+// of the control block: n_u / m_u are the unvisited counts before this
+// frontier (0 when not tracked), allowed has bit a set for each allowed action.
+struct MlpSelect {
+  const float* params;
+  int sp;
+  int64_t V, E, n_u_before, m_u_before;
+  int prev_pull;
+  int allowed;
+};
+// The network's predicted log2 step times (pred, +inf where not allowed) and
+// its argmin (action) written into the control block, which is then published
+// to host memory as launch_publish does; one kernel for both.
+hipError_t launch_publish_select(const MlpSelect& m, Ctrl* ctrl, Ctrl* host_dst,
+                                 uint32_t* host_flag, uint32_t seq, hipStream_t st);
 
 // Device-predicated level blocks (iteration control): up to kDlMaxLevels
 // push levels are enqueued back to back; each level kernel first decides on

@@ -47,6 +47,7 @@ struct Selector {
   bool sssp = false;
   bool learned = false;
   bool mode_pull = false;
+  int last_heuristic = -1;  // the heuristic's action at the last decide() (learned policy)
   uint64_t rng = 0;
   double avg_degree = 0.0;
 
@@ -88,14 +89,24 @@ struct Selector {
   // predicted log2 step times (both from the device; -1 / null when none).
   // The learned policy is guarded: it keeps the heuristic's action unless the
   // network predicts its own choice faster by more than o.learned_margin.
-  int decide(const LevelFeatures& lf, int device_choice = -1, const float* pred = nullptr) {
+  // keep_push: the level fits a block of device-predicated push levels, which
+  // makes pushing it far cheaper than the one-round-trip levels the network
+  // was trained on; the network may then turn the heuristic's pull into a
+  // push, but not a push into a pull.
+  int decide(const LevelFeatures& lf, int device_choice = -1, const float* pred = nullptr,
+             bool keep_push = false) {
     int a;
     if (o.policy == GR_POLICY_FIXED) a = o.fixed_action;
     else if (o.policy == GR_POLICY_RANDOM) a = (int)(next(rng) % 4);
     else if (o.policy == GR_POLICY_LEARNED && learned && device_choice >= 0 && pred) {
       const int h = heuristic(lf);
       a = (device_choice != h && pred[device_choice] + o.learned_margin < pred[h]) ? device_choice : h;
-    } else a = heuristic(lf);
+      if (keep_push && h < GR_PULL_TWC && a >= GR_PULL_TWC) a = h;
+      last_heuristic = h;
+    } else {
+      a = heuristic(lf);
+      last_heuristic = a;
+    }
     if (!pull_ok && a >= GR_PULL_TWC) a -= 2;  // same balancing, push direction
     mode_pull = a >= GR_PULL_TWC;
     return a;

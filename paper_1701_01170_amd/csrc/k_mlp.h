@@ -19,20 +19,25 @@ __device__ __forceinline__ float mlp_feat(double x) {
   return (float)(log2(1.0 + (x > 0 ? x : 0.0)) / 32.0);
 }
 
-// The eight selector inputs of one iteration, written to s_x by the caller's
-// thread: n_f, m_f, n_u, m_u, largest frontier degree, V, E, and the
-// unvisited-list size a pull step would need (V after a push, 0 after a pull).
-__device__ __forceinline__ void mlp_features(float* s_x, int64_t n_f, int64_t m_f, int64_t n_u,
+// Selector input i of one iteration (0..7): n_f, m_f, n_u, m_u, largest
+// frontier degree, V, E, and the unvisited-list size a pull step would need
+// (V after a push, 0 after a pull), each log2(1 + x) / 32.  Eight threads
+// compute the eight inputs side by side.
+__device__ __forceinline__ float mlp_feature(int i, int64_t n_f, int64_t m_f, int64_t n_u,
                                              int64_t m_u, int64_t max_deg, int64_t V, int64_t E,
                                              int prev_pull) {
-  s_x[0] = mlp_feat((double)n_f);
-  s_x[1] = mlp_feat((double)m_f);
-  s_x[2] = mlp_feat((double)n_u);
-  s_x[3] = mlp_feat((double)m_u);
-  s_x[4] = mlp_feat((double)max_deg);
-  s_x[5] = mlp_feat((double)V);
-  s_x[6] = mlp_feat((double)E);
-  s_x[7] = mlp_feat(prev_pull ? 0.0 : (double)V);
+  int64_t x;
+  switch (i) {
+    case 0: x = n_f; break;
+    case 1: x = m_f; break;
+    case 2: x = n_u; break;
+    case 3: x = m_u; break;
+    case 4: x = max_deg; break;
+    case 5: x = V; break;
+    case 6: x = E; break;
+    default: x = prev_pull ? 0 : V; break;
+  }
+  return mlp_feat((double)x);
 }
 
 // Forward pass on the features in s_x and argmin over the allowed actions

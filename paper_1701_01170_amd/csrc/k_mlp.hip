@@ -196,21 +196,51 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 // of slot `sp` plus host-known totals), forward pass, argmin over the allowed
 // actions (bit a of allowed) -> ctrl->action.  n_u_before / m_u_before are the
 // unvisited counts before this frontier was visited (BFS), 0 for SSSP.
-__global__ __launch_bounds__(64) void k_mlp_select(const float* __restrict__ params,
-                                                   Ctrl* __restrict__ ctrl, int sp, int64_t V,
-                                                   int64_t E, int64_t n_u_before,
-                                                   int64_t m_u_before, int prev_pull, int allowed) {
+// Selector decision fused into the publication of the control block: the
+// network runs first (its outputs go to the device control block and, taken
+// from LDS, into the host copy), then every word is copied to host memory,
+// ordered at system scope, and one thread releases the sequence number.
+__global__ __launch_bounds__(128) void k_publish_select(MlpSelect m, Ctrl* __restrict__ ctrl,
+                                                        uint32_t* __restrict__ dst, uint32_t* flag,
+                                                        uint32_t seq) {
+  __shared__ float s_p[kNP];
   __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
-  if (threadIdx.x == 0) {
-    const int64_t n_f = ctrl->n_f[sp], m_f = ctrl->m_f[sp];
-    const int64_t n_u = n_u_before > 0 ? n_u_before - n_f : 0;
-    const int64_t m_u = m_u_before > 0 ? m_u_before - m_f : 0;
-    mlp_features(s_x, n_f, m_f, n_u, m_u, ctrl->max_deg[sp], V, E, prev_pull);
+  __shared__ uint32_t s_dec[kOut + 1];
+  // the parameters are staged in LDS with one coalesced burst: read layer by
+  // layer from memory, each layer would wait for its own round trip
+  for (int i = threadIdx.x; i < kNP; i += blockDim.x) s_p[i] = m.params[i];
+  if (threadIdx.x < kIn) {
+    const int64_t n_f = ctrl->n_f[m.sp], m_f = ctrl->m_f[m.sp];
+    const int64_t n_u = m.n_u_before > 0 ? m.n_u_before - n_f : 0;
+    const int64_t m_u = m.m_u_before > 0 ? m.m_u_before - m_f : 0;
+    s_x[threadIdx.x] = mlp_feature(threadIdx.x, n_f, m_f, n_u, m_u, ctrl->max_deg[m.sp], m.V, m.E,
+                                   m.prev_pull);
   }
-  const int best = mlp_argmin(params, s_x, s_h1, s_h2, s_y, allowed);
-  if (threadIdx.x < kOut)
-    ctrl->pred[threadIdx.x] = ((allowed >> threadIdx.x) & 1) ? s_y[threadIdx.x] : __builtin_inff();
-  if (threadIdx.x == 0) ctrl->action = best;
+  const int best = mlp_argmin(s_p, s_x, s_h1, s_h2, s_y, m.allowed);
+  if (threadIdx.x < kOut) {
+    const float p = ((m.allowed >> threadIdx.x) & 1) ? s_y[threadIdx.x] : __builtin_inff();
+    ctrl->pred[threadIdx.x] = p;
+    s_dec[threadIdx.x] = __float_as_uint(p);
+  }
+  if (threadIdx.x == 0) {
+    ctrl->action = best;
+    s_dec[kOut] = (uint32_t)best;
+  }
+  __syncthreads();
+  constexpr int kWords = (int)(sizeof(Ctrl) / 4);
+  constexpr int kPred = (int)(offsetof(Ctrl, pred) / 4), kAction = (int)(offsetof(Ctrl, action) / 4);
+  static_assert(offsetof(Ctrl, pred) % 4 == 0 && offsetof(Ctrl, action) % 4 == 0, "word offsets");
+  const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(ctrl);
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) {
+    uint32_t w;
+    if (i >= kPred && i < kPred + kOut) w = s_dec[i - kPred];
+    else if (i == kAction) w = s_dec[kOut];
+    else w = src[i];
+    dst[i] = w;
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -241,10 +271,11 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, floa
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_select(const float* params, Ctrl* ctrl, int sp, int64_t V, int64_t E,
-                             int64_t n_u_before, int64_t m_u_before, int prev_pull, int allowed,
-                             hipStream_t st) {
-  k_mlp_select<<<1, 64, 0, st>>>(params, ctrl, sp, V, E, n_u_before, m_u_before, prev_pull, allowed);
+hipError_t launch_publish_select(const MlpSelect& m, Ctrl* ctrl, Ctrl* host_dst,
+                                 uint32_t* host_flag, uint32_t seq, hipStream_t st) {
+  static_assert(sizeof(Ctrl) % 4 == 0, "control block is copied as 32-bit words");
+  k_publish_select<<<1, 128, 0, st>>>(m, ctrl, reinterpret_cast<uint32_t*>(host_dst), host_flag,
+                                      seq);
   return hipGetLastError();
 }
 

@@ -1,12 +1,15 @@
 """Summaries of rocprofv3 output for the committed profiles/ directory.
 
-  python -m paper_1701_01170_amd.rocprof_summary stats <rocpd_dir> <out.md> "<command>"
-      per-kernel call counts and durations (from --kernel-trace --stats runs)
-  python -m paper_1701_01170_amd.rocprof_summary traffic <fetch_dir> <write_dir> <kernel-substring> \
+  python -m paper_1701_01170_amd.rocprof_summary stats <rocpd_dir> <out.md> "<command>" \
+          [<label>=<kernel-regex> ...]
+      per-kernel call counts and durations (from --kernel-trace --stats runs);
+      each label=regex adds a line for all kernels whose name matches
+  python -m paper_1701_01170_amd.rocprof_summary traffic <fetch_dir> <write_dir> <kernel-regex> \
           <copy_bytes> <out.json> "<command>"
-      HBM bytes per launch of one kernel from a FETCH_SIZE run and a WRITE_SIZE
-      run, each scaled by what the same counter reads for the calibration copy
-      kernel (k_copy16, copy_bytes read and copy_bytes written per launch)
+      HBM bytes per launch of the kernels matching the regex, from a FETCH_SIZE
+      run and a WRITE_SIZE run, each scaled by what the same counter reads for
+      the calibration copy kernel (k_copy16, copy_bytes read and copy_bytes
+      written per launch)
 
 rocprofv3 writes a rocpd SQLite database; only its `kernels` and
 `counters_collection` views are read here.
@@ -48,7 +51,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stats(d: str, out: str, command: str) -> None:
+def stats(d: str, out: str, command: str, groups=()) -> None:
     c = _db(d)
     agg = {}
     for name, dur in c.execute("select name, duration from kernels"):
@@ -66,9 +69,18 @@ def stats(d: str, out: str, command: str) -> None:
     for k, (n, tot, mn, mx) in sorted(agg.items(), key=lambda x: -x[1][1]):
         lines.append(f"| `{k}` | {n} | {tot / 1e3:.1f} | {tot / 1e3 / n:.2f} | {mn / 1e3:.2f} | "
                      f"{mx / 1e3:.2f} | {100 * tot / total:.1f} |")
+    if groups:
+        lines += ["", "| group (kernel regex) | calls | total us | avg us |", "|---|---:|---:|---:|"]
+        for g in groups:
+            label, rx = g.split("=", 1)
+            sel = [(n, tot) for k, (n, tot, _, _) in agg.items() if re.search(rx, k)]
+            n = sum(x[0] for x in sel)
+            tot = sum(x[1] for x in sel)
+            if n:
+                lines.append(f"| {label} (`{rx}`) | {n} | {tot / 1e3:.1f} | {tot / 1e3 / n:.2f} |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
-    print("\n".join(lines[:20]))
+    print("\n".join(lines[:20] + lines[-4:]))
 
 
 def _counter_per_dispatch(d: str, counter: str):
@@ -84,7 +96,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, out: s
     for label, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _counter_per_dispatch(d, counter)
         copy = [v for _, n, v in rows if "k_copy16" in n]
-        kern = [v for _, n, v in rows if kernel in n]
+        kern = [v for _, n, v in rows if re.search(kernel, n)]
         if not copy or not kern:
             raise RuntimeError(f"{counter}: no copy-kernel or '{kernel}' dispatches in {d}")
         # counter values are KiB per dispatch; the copy kernel moves copy_bytes each way
@@ -102,7 +114,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, out: s
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+        stats(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7])
     else:

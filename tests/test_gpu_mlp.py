@@ -95,27 +95,31 @@ def test_learned_policy_is_exact_and_takes_argmin(ctx, rmat14):
     cap = 64
     buf = (gr.LevelTrace * cap)()
     try:
+        checked = 0
         for s in gg.sources(rmat14, 4, seed=1000):
-            o = gr.default_opts(policy=gr.POLICY_LEARNED, trace=buf, trace_capacity=cap)
-            d, p, _ = gr.bfs(g, int(s), opts=o)
             ed, ep = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, int(s))
-            np.testing.assert_array_equal(d.cpu().numpy(), ed)
-            np.testing.assert_array_equal(p.cpu().numpy(), ep)
-            for t in buf[:o.trace_count]:
-                x = np.array(list(t.features), dtype=np.float64)[None]
-                y, _ = oracle.mlp_forward(P, x)
-                y = y[0]
-                if t.kernel == 6:
-                    # inside a block of device-predicated levels the
-                    # heuristic's push test decides
+            # with device-predicated blocks on, levels small enough for a block
+            # are the heuristic's; with them off the network decides every level
+            for dme in (0, -1):
+                o = gr.default_opts(policy=gr.POLICY_LEARNED, trace=buf, trace_capacity=cap,
+                                    device_max_edges=dme)
+                d, p, _ = gr.bfs(g, int(s), opts=o)
+                np.testing.assert_array_equal(d.cpu().numpy(), ed)
+                np.testing.assert_array_equal(p.cpu().numpy(), ep)
+                if dme == 0:
                     continue
-                else:
+                for t in buf[:o.trace_count]:
+                    x = np.array(list(t.features), dtype=np.float64)[None]
+                    y, _ = oracle.mlp_forward(P, x)
+                    y = y[0]
                     # the device's choice is within fp32 rounding of the argmin
                     assert y[t.action] <= y.min() + 1e-3, (t.level, t.action, y)
+                    checked += 1
             dist, pred, _ = gr.sssp(g, [int(s)], opts=gr.default_opts(policy=gr.POLICY_LEARNED))
             edist, epred = oracle.sssp(rmat14.row_offsets, rmat14.col_indices, rmat14.weights, [int(s)])
             np.testing.assert_array_equal(dist.cpu().numpy().view(np.uint32), edist)
             np.testing.assert_array_equal(pred.cpu().numpy(), epred)
+        assert checked >= 8
     finally:
         ctx.set_policy(None)
     with pytest.raises(gr.GrError):
