@@ -675,7 +675,15 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
                                 st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
-      GR_TRY(read_ctrl(ctx, ctrl, st));
+      // statistics of the frontier the block leaves (found on the device),
+      // then a single read-back; with k == 0 levels run the frontier is
+      // unchanged and its statistics simply move to the other slot
+      sp ^= 1;
+      GR_HIP(launch_frontier_stats_after_block(Queues3{{qA, qB, qC}}, cur, g->R, bsums, ctrl, sp,
+                                               st));
+      msel = select_at(sp, 0, 0, 0);
+      msel.after_block = 1;
+      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
       const int k = hc->dl_levels;
       if (k > 0) {
         std::vector<int64_t> lg;
@@ -694,12 +702,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
         visited_m = hc->dl_vm[k & 1];
         p ^= k & 1;
         cur = (cur + k) % 3;
-        sp ^= 1;
         level += k;
-        GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                     &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-        msel = select_at(sp, V - visited_n, E - visited_m, 0);
-        GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
         if (tracing) {
           int64_t vn = vn0, vm = vm0;
           for (int i = 0; i < k; ++i) {
@@ -932,8 +935,20 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, perm, it + i + 1, dl.blocks, st));
       }
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
-      GR_TRY(read_ctrl(ctx, ctrl, st));
+      // statistics of the frontier the block leaves, then a single read-back
+      // (with k == 0 levels run the statistics just move to the other slot)
+      sp ^= 1;
+      GR_HIP(launch_frontier_stats_after_block(Queues3{{qA, qB, qC}}, cur, g->R, bsums, ctrl, sp,
+                                               st));
+      msel.sp = sp;
+      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
       const int k = hc->dl_levels;
+      if (use_pq) {
+        pq.T = hc->pq_T[k & 1];
+        pq.epoch = hc->pq_epoch[k & 1];
+        pq.fc = hc->pq_fc[k & 1];
+        far_n = hc->far_count[pq.fc];
+      }
       if (k > 0) {
         std::vector<int64_t> lg;
         float block_ms = 0.f;
@@ -948,15 +963,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         rs.action_count[action] += k;
         inspected += hc->dl_vm[k & 1];
         expanded += hc->dl_vn[k & 1];
-        if (use_pq) {
-          pq.T = hc->pq_T[k & 1];
-          pq.epoch = hc->pq_epoch[k & 1];
-          pq.fc = hc->pq_fc[k & 1];
-        }
         cur = (cur + k) % 3;
-        sp ^= 1;
         it += k;
-        GR_TRY(next_frontier());
         if (tracing) {
           for (int i = 0; i < k; ++i) {
             LevelFeatures li = lf;

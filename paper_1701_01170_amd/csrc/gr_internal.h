@@ -170,6 +170,16 @@ int stats_grid();
 hipError_t launch_frontier_stats(const int32_t* frontier, const uint32_t* n_f_dev, const int32_t* R,
                                  int64_t* block_sums, Ctrl* ctrl, int parity, uint32_t* zero_a,
                                  uint32_t* zero_b, hipStream_t st);
+// The three rotating frontier queues.
+struct Queues3 {
+  int32_t* q[3];
+};
+// launch_frontier_stats for the frontier left by a block of device-predicated
+// levels that started at queue cur0 (the queue is found on the device from
+// the block's level count), so the block needs no read-back of its own.
+hipError_t launch_frontier_stats_after_block(const Queues3& qs, int cur0, const int32_t* R,
+                                             int64_t* block_sums, Ctrl* ctrl, int parity,
+                                             hipStream_t st);
 hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const int32_t* R,
                                    const int64_t* block_sums, const int64_t* total,
                                    int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
@@ -260,6 +270,7 @@ struct MlpSelect {
   int64_t V, E, n_u_before, m_u_before;
   int prev_pull;
   int allowed;
+  int after_block;  // n_u / m_u before the frontier: V / E minus the block's visited counts
 };
 // The network's predicted log2 step times (pred, +inf where not allowed) and
 // its argmin (action) written into the control block, which is then published

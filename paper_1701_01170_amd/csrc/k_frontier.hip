@@ -43,14 +43,14 @@ __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
 // sums go to block_sums[b] (the offsets kernel scans them); totals are
 // accumulated atomically in slot `parity`, which the previous call cleared.
 // Block 0 clears the other slot and the two counters the next step appends to.
-__global__ __launch_bounds__(kStatsBlock) void k_frontier_stats(
-    const int32_t* __restrict__ frontier, const uint32_t* __restrict__ n_f_dev,
-    const int32_t* __restrict__ R, int64_t* __restrict__ block_sums, Ctrl* __restrict__ ctrl,
-    int parity, uint32_t* zero_a, uint32_t* zero_b) {
+__device__ __forceinline__ void frontier_stats(const int32_t* __restrict__ frontier, int64_t n_f,
+                                               const int32_t* __restrict__ R,
+                                               int64_t* __restrict__ block_sums,
+                                               Ctrl* __restrict__ ctrl, int parity,
+                                               uint32_t* zero_a, uint32_t* zero_b) {
   __shared__ int64_t s_sum[kStatsBlock / kWave];
   __shared__ int64_t s_max[kStatsBlock / kWave];
   const int G = gridDim.x;
-  const int64_t n_f = (int64_t)*n_f_dev;
   const int64_t per = (n_f + G - 1) / G;
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = lo + per < n_f ? lo + per : n_f;
@@ -86,6 +86,24 @@ __global__ __launch_bounds__(kStatsBlock) void k_frontier_stats(
       if (zero_b) *zero_b = 0;
     }
   }
+}
+
+__global__ __launch_bounds__(kStatsBlock) void k_frontier_stats(
+    const int32_t* __restrict__ frontier, const uint32_t* __restrict__ n_f_dev,
+    const int32_t* __restrict__ R, int64_t* __restrict__ block_sums, Ctrl* __restrict__ ctrl,
+    int parity, uint32_t* zero_a, uint32_t* zero_b) {
+  frontier_stats(frontier, (int64_t)*n_f_dev, R, block_sums, ctrl, parity, zero_a, zero_b);
+}
+
+// The same for the frontier left by a block of device-predicated levels: the
+// block ran ctrl->dl_levels of them, so its last frontier is queue
+// (cur0 + dl_levels) % 3 and the next appends go to the queue after it.
+__global__ __launch_bounds__(kStatsBlock) void k_frontier_stats_after_block(
+    Queues3 qs, int cur0, const int32_t* __restrict__ R, int64_t* __restrict__ block_sums,
+    Ctrl* __restrict__ ctrl, int parity) {
+  const int cur = (cur0 + ctrl->dl_levels) % 3;
+  frontier_stats(qs.q[cur], (int64_t)ctrl->q_count[cur], R, block_sums, ctrl, parity,
+                 &ctrl->q_count[(cur + 1) % 3], nullptr);
 }
 
 // Exclusive scan of frontier degrees into offsets[0..n_f] (same slicing as
@@ -218,6 +236,14 @@ hipError_t launch_frontier_stats(const int32_t* frontier, const uint32_t* n_f_de
                                  uint32_t* zero_b, hipStream_t st) {
   k_frontier_stats<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f_dev, R, block_sums, ctrl,
                                                        parity, zero_a, zero_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_frontier_stats_after_block(const Queues3& qs, int cur0, const int32_t* R,
+                                             int64_t* block_sums, Ctrl* ctrl, int parity,
+                                             hipStream_t st) {
+  k_frontier_stats_after_block<<<kStatsGrid, kStatsBlock, 0, st>>>(qs, cur0, R, block_sums, ctrl,
+                                                                   parity);
   return hipGetLastError();
 }
 

@@ -211,8 +211,14 @@ __global__ __launch_bounds__(128) void k_publish_select(MlpSelect m, Ctrl* __res
   for (int i = threadIdx.x; i < kNP; i += blockDim.x) s_p[i] = m.params[i];
   if (threadIdx.x < kIn) {
     const int64_t n_f = ctrl->n_f[m.sp], m_f = ctrl->m_f[m.sp];
-    const int64_t n_u = m.n_u_before > 0 ? m.n_u_before - n_f : 0;
-    const int64_t m_u = m.m_u_before > 0 ? m.m_u_before - m_f : 0;
+    int64_t nub = m.n_u_before, mub = m.m_u_before;
+    if (m.after_block) {
+      const int k = ctrl->dl_levels;
+      nub = m.V - ctrl->dl_vn[k & 1];
+      mub = m.E - ctrl->dl_vm[k & 1];
+    }
+    const int64_t n_u = nub > 0 ? nub - n_f : 0;
+    const int64_t m_u = mub > 0 ? mub - m_f : 0;
     s_x[threadIdx.x] = mlp_feature(threadIdx.x, n_f, m_f, n_u, m_u, ctrl->max_deg[m.sp], m.V, m.E,
                                    m.prev_pull);
   }
