@@ -242,6 +242,8 @@ __device__ __forceinline__ int32_t first_frontier_nbr(bool valid, int32_t rb, in
 // the whole wavefront); GW > 1: GW lanes per vertex, GW neighbours per step
 // (lists longer than 64 go to the whole wavefront).
 constexpr int kPullRuns = 8;
+constexpr int kPullBatch = 4;  // runs whose first neighbours are probed together
+static_assert(kPullRuns % kPullBatch == 0, "whole batches");
 
 template <int GW>
 __global__ __launch_bounds__(256) void k_bfs_pull_bm(
@@ -259,24 +261,49 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
   const int64_t base = ((int64_t)blockIdx.x * NW + w) * kWave * kPullRuns;
   uint32_t hits = 0;  // bit k: vertex base + 64 k + lane was found
   int64_t scanned = 0;
+  // GW == 1: the smallest-id neighbour of every candidate of kPullBatch runs
+  // is probed up front, the loads of those runs in flight together (three
+  // dependent rounds per batch instead of three per run).  On a wide pull
+  // level most unvisited vertices find their parent there (a low-id hub in
+  // the frontier); the per-run scan below continues only the others.
+  int32_t prb[kPullBatch], pre[kPullBatch], pu[kPullBatch];
+  bool pc[kPullBatch], ph[kPullBatch];
+#pragma unroll
   for (int k = 0; k < kPullRuns; ++k) {
     const int64_t v0 = base + (int64_t)k * kWave;
     if (v0 >= V) break;  // uniform across the wavefront
+    const int kb = k % kPullBatch;
+    if constexpr (GW == 1) {
+      if (kb == 0) {
+#pragma unroll
+        for (int j = 0; j < kPullBatch; ++j) {
+          const int64_t v = v0 + (int64_t)j * kWave + lane();
+          pc[j] = false;
+          prb[j] = pre[j] = 0;
+          if (v < V) {
+            const uint2 x = bm_pair(bm, (int32_t)(v >> 5));
+            if (!(((p ? x.y : x.x) >> (v & 31)) & 1u)) {
+              prb[j] = R[v];
+              pre[j] = R[v + 1];
+              pc[j] = pre[j] > prb[j];
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kPullBatch; ++j) pu[j] = pc[j] ? C[prb[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < kPullBatch; ++j) ph[j] = pc[j] && in_frontier(bm, p, pu[j]);
+      }
+    }
     uint64_t hb = 0;
     if constexpr (GW == 1) {
       const int64_t v = v0 + lane();
-      bool cand = false;
-      int32_t rb = 0, re = 0;
-      if (v < V) {
-        const uint2 x = bm_pair(bm, (int32_t)(v >> 5));
-        if (!(((p ? x.y : x.x) >> (v & 31)) & 1u)) {
-          rb = R[v];
-          re = R[v + 1];
-          cand = re > rb;
-        }
-      }
+      const bool cand = pc[kb], first = cand && ph[kb];
       int64_t sc = 0;
-      const int32_t found = first_frontier_nbr<32>(cand, rb, re, C, bm, p, &sc);
+      const int32_t rest = first_frontier_nbr<32>(cand && !first, prb[kb] + 1, pre[kb], C, bm, p,
+                                                  &sc);
+      const int32_t found = first ? pu[kb] : rest;
+      if (cand) sc += 1;
       const bool hit = cand && found >= 0;
       if (hit) {
         depth[v] = next_depth;
