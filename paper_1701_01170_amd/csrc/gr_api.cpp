@@ -1148,7 +1148,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
       const bool pull = (double)m_a > (double)E * (double)opts.do_a;
       if (pull) {
         GR_HIP(launch_ms_pull(V, g->R, g->C, front[fc], visit, full, next, q[(cur + 1) % 3],
-                              &ctrl->q_count[(cur + 1) % 3], st));
+                              &ctrl->q_count[(cur + 1) % 3], ppass, g->perm, st));
         rs.action_count[GR_PULL_TWC]++;
       } else {
         const int mode = !use_lb ? 0 : (n_a < opts.lb_light_threshold ? 1 : 2);
@@ -1161,9 +1161,10 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
         rs.action_count[use_lb ? GR_PUSH_LB : GR_PUSH_TWC]++;
       }
       inspected += pull ? E : m_a;
+      // a pull level has written its parents already
       GR_HIP(launch_ms_finalize(q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], pull ? V : std::min(V, m_a),
-                                g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass, ppass,
-                                g->perm, V, level + 1, st));
+                                g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass,
+                                pull ? nullptr : ppass, g->perm, V, level + 1, st));
       GR_HIP(launch_ms_clear(q[cur], &ctrl->q_count[cur], n_a, front[fc], st));
       fc ^= 1;
       cur = (cur + 1) % 3;

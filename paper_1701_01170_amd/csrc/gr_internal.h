@@ -238,10 +238,13 @@ hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offset
                           const unsigned long long* front, const unsigned long long* visit,
                           unsigned long long* next, int32_t* touched, uint32_t* n_touched,
                           int chunk, hipStream_t st);
+// pull with parent nullable: when given, the pull writes the parents of the
+// vertices it reaches (the finalize of that level then gets parent = nullptr)
 hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C,
                           const unsigned long long* front, const unsigned long long* visit,
                           unsigned long long full, unsigned long long* next, int32_t* touched,
-                          uint32_t* n_touched, hipStream_t st);
+                          uint32_t* n_touched, int32_t* parent, const int32_t* perm,
+                          hipStream_t st);
 hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched, int64_t max_n,
                               const int32_t* R, const int32_t* C, const unsigned long long* front,
                               unsigned long long* front_next, unsigned long long* visit,

@@ -45,34 +45,50 @@ __device__ __forceinline__ u64 wave_or(u64 x) {
 }
 
 // Pull expansion over all vertices: lane per vertex for short lists, whole
-// wavefront for long ones.
+// wavefront for long ones.  The scan is ascending with an early exit once all
+// unreached bits appear, so the neighbour where a bit first appears is that
+// source's smallest-id parent; with `parent` it is written here and the
+// finalize pass skips its own parent search for this level.
 __global__ __launch_bounds__(256) void k_ms_pull(int64_t V, const int32_t* __restrict__ R,
                                                  const int32_t* __restrict__ C,
                                                  const u64* __restrict__ front,
                                                  const u64* __restrict__ visit, u64 full,
                                                  u64* __restrict__ next, int32_t* __restrict__ touched,
-                                                 uint32_t* __restrict__ n_touched) {
+                                                 uint32_t* __restrict__ n_touched,
+                                                 int32_t* __restrict__ parent,
+                                                 const int32_t* __restrict__ perm) {
   constexpr int U = 8;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = v < V;
   u64 need = 0;
   int32_t rb = 0, re = 0;
+  int64_t vo = 0;  // v's caller id: the output column
   if (valid) {
     need = full & ~visit[v];
     if (need) {
       rb = R[v];
       re = R[v + 1];
+      vo = perm ? perm[v] : v;
     }
   }
   u64 acc = 0;
   if (need && re - rb <= 64) {
     for (int32_t j0 = rb; j0 < re && (acc & need) != need; j0 += U) {
       int32_t u[U];
+      u64 f[U];
 #pragma unroll
       for (int r = 0; r < U; ++r) u[r] = j0 + r < re ? C[j0 + r] : -1;
 #pragma unroll
-      for (int r = 0; r < U; ++r)
-        if (u[r] >= 0) acc |= front[u[r]];
+      for (int r = 0; r < U; ++r) f[r] = u[r] >= 0 ? front[u[r]] : 0ull;
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        u64 g = f[r] & need & ~acc;
+        acc |= f[r];
+        if (parent && g) {
+          const int32_t uo = perm ? perm[u[r]] : u[r];
+          for (; g; g &= g - 1) parent[(int64_t)(__ffsll(g) - 1) * V + vo] = uo;
+        }
+      }
     }
   }
   uint64_t big = __ballot(need != 0 && re - rb > 64);
@@ -80,18 +96,36 @@ __global__ __launch_bounds__(256) void k_ms_pull(int64_t V, const int32_t* __res
     const int l = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
     const int32_t vb = __shfl(rb, l), ve = __shfl(re, l);
+    const int64_t vv = __shfl(vo, l);
     const u64 nd = __shfl(need, l);
-    u64 a = 0;
-    for (int32_t base = vb; base < ve; base += U * kWave) {
+    u64 fnd = 0;  // bits of nd found so far
+    for (int32_t base = vb; base < ve && fnd != nd; base += U * kWave) {
+      int32_t u[U];
+      u64 f[U];
 #pragma unroll
       for (int r = 0; r < U; ++r) {
         const int32_t j = base + r * kWave + lane();
-        if (j < ve) a |= front[C[j]];
+        u[r] = j < ve ? C[j] : -1;
       }
-      if ((wave_or(a) & nd) == nd) break;
+#pragma unroll
+      for (int r = 0; r < U; ++r) f[r] = u[r] >= 0 ? (front[u[r]] & nd) : 0ull;
+      // ascending neighbour order inside the step: r-major, then lane
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        u64 g = wave_or(f[r]) & ~fnd;
+        fnd |= g;
+        if (parent) {
+          while (g) {
+            const int sb = __ffsll(g) - 1;
+            g &= g - 1;
+            const uint64_t b = __ballot((f[r] >> sb) & 1ull);
+            const int32_t pu = __shfl(u[r], __ffsll((unsigned long long)b) - 1);
+            if (lane() == 0) parent[(int64_t)sb * V + vv] = perm ? perm[pu] : pu;
+          }
+        }
+      }
     }
-    a = wave_or(a);
-    if (lane() == l) acc = a;
+    if (lane() == l) acc = fnd;
   }
   const u64 m = acc & need;
   if (m) next[v] = m;
@@ -99,7 +133,8 @@ __global__ __launch_bounds__(256) void k_ms_pull(int64_t V, const int32_t* __res
   if (m) touched[slot] = (int32_t)v;
 }
 
-// Finalise the touched vertices: masks, depths, parents.
+// Finalise the touched vertices: masks, depths, and (when the expansion did
+// not find them) parents.
 __global__ __launch_bounds__(256) void k_ms_finalize(
     const int32_t* __restrict__ touched, const uint32_t* __restrict__ n_touched,
     const int32_t* __restrict__ R, const int32_t* __restrict__ C, const u64* __restrict__ front,
@@ -243,9 +278,10 @@ hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offset
 
 hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C, const u64* front,
                           const u64* visit, u64 full, u64* next, int32_t* touched,
-                          uint32_t* n_touched, hipStream_t st) {
+                          uint32_t* n_touched, int32_t* parent, const int32_t* perm,
+                          hipStream_t st) {
   k_ms_pull<<<blocks_for(V, 256), 256, 0, st>>>(V, R, C, front, visit, full, next, touched,
-                                                n_touched);
+                                                n_touched, parent, perm);
   return hipGetLastError();
 }
 
