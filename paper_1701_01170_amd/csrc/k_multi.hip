@@ -307,7 +307,7 @@ hipError_t launch_ms_clear(const int32_t* list, const uint32_t* n, int64_t max_n
 hipError_t launch_ms_teps(const u64* visit, const int32_t* R, int64_t V, int64_t* out,
                           hipStream_t st) {
   unsigned g = blocks_for(V, 256);
-  if (g > 2048) g = 2048;
+  if (g > 1024) g = 1024;  // one atomic per workgroup, all on one address
   k_ms_teps<<<g, 256, 0, st>>>(visit, R, V, out);
   return hipGetLastError();
 }

@@ -485,8 +485,10 @@ hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R
                                 uint32_t* dist, int32_t* pred, const int32_t* perm,
                                 const int32_t* src_orig_dev, int32_t n_src, int64_t* reached_edges,
                                 hipStream_t st) {
+  // grid-stride, one atomic per workgroup for the reached-edge sum: a modest
+  // grid keeps those atomics (all on one address) few
   unsigned g = blocks_for(V, 256);
-  if (g > 4096) g = 4096;
+  if (g > 1024) g = 1024;
   k_sssp_finalize<<<g, 256, 0, st>>>(keys, R, V, dist, pred, perm, reached_edges);
   if (pred)
     k_sssp_source_pred<<<blocks_for(n_src, 256), 256, 0, st>>>(src_orig_dev, n_src, pred);
