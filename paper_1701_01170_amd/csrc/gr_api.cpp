@@ -557,6 +557,10 @@ constexpr int64_t kAtomicParentMaxEdges = 1 << 20;
 // non-atomic filter (byte marks + one ordered compaction pass over all V);
 // smaller ones cull with atomics on the visited bitmap.
 constexpr int64_t kMarksFilterDivisor = 4;
+// A pull level reads the unvisited list the previous pull level left when it
+// has at most V / kPullListDivisor entries; a longer list is slower to scan
+// lane by lane than the bitmap (whose runs probe first neighbours together).
+constexpr int64_t kPullListDivisor = 16;
 
 // The byte-mark buffer is all zero between uses (the compaction clears what it
 // reads); a fresh allocation is cleared once here.
@@ -615,6 +619,16 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   const int32_t src = g->to_new(source);
 
   int32_t* q[3] = {qA, qB, qC};
+  // pull levels after the first work from the list of still-unvisited
+  // vertices the previous pull level left (two lists, ping-pong)
+  int32_t* ul[2] = {nullptr, nullptr};
+  if (pull_ok) {
+    GR_TRY(pool_typed(ctx, S_UL_A, V, &ul[0]));
+    GR_TRY(pool_typed(ctx, S_UL_B, V, &ul[1]));
+  }
+  int ulc = 0;            // the list the next pull level reads
+  bool list_ok = false;   // it holds every unvisited vertex with neighbours
+  int64_t list_n = 0;
 
   GR_HIP(hipEventRecord(ctx->ev_start, st));
   GR_HIP(launch_bfs_init(depth, parent, V, bm, NW, src, qA, ctrl, st));
@@ -656,6 +670,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     const bool dl_fits = dl.on && n_f <= kDlMaxN && m_f <= dl.max_m;
     const int action = sel.decide(lf, learned ? hc->action : -1, learned ? hc->pred : nullptr,
                                   dl_fits);
+    if (action == GR_PUSH_LB || action == GR_PUSH_TWC) list_ok = false;
     if (dl_fits && (action == GR_PUSH_LB || action == GR_PUSH_TWC)) {
       // A block of device-predicated push levels (atomic parents, no merge
       // pass); its first level is the one just decided on the host.
@@ -763,11 +778,23 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       inspected_push += m_f;
     } else {
       kernel = action == GR_PULL_LB ? 5 : 4;
+      // the lane-per-vertex pull lists the vertices it leaves unvisited, and
+      // reads such a list instead of the bitmap when the previous level did
+      const bool lane_pull = action == GR_PULL_TWC;
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      GR_HIP(launch_bfs_pull(action == GR_PULL_LB, V, g->R, g->C, bm, p, depth, parent, perm,
-                             next_depth, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
-                             &ctrl->inspected, st));
+      if (lane_pull && list_ok && list_n <= V / kPullListDivisor)
+        GR_HIP(launch_bfs_pull_list(ul[ulc], &ctrl->ul_count[ulc], list_n, g->R, g->C, bm, p,
+                                    depth, parent, perm, next_depth, q[(cur + 1) % 3],
+                                    &ctrl->q_count[(cur + 1) % 3], &ctrl->inspected, ul[ulc ^ 1],
+                                    &ctrl->ul_count[ulc ^ 1], st));
+      else
+        GR_HIP(launch_bfs_pull(action == GR_PULL_LB, V, g->R, g->C, bm, p, depth, parent, perm,
+                               next_depth, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
+                               &ctrl->inspected, lane_pull ? ul[ulc ^ 1] : nullptr,
+                               &ctrl->ul_count[ulc ^ 1], st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+      if (lane_pull) ulc ^= 1;
+      list_ok = lane_pull;
     }
     GR_HIP(launch_bitmap_merge(bm, p, NW, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
@@ -776,10 +803,12 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     cur = (cur + 1) % 3;
     sp ^= 1;
     ++level;
+    // (the list the next pull level appends to starts empty)
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                 &ctrl->q_count[(cur + 1) % 3], nullptr, st));
+                                 &ctrl->q_count[(cur + 1) % 3], &ctrl->ul_count[ulc ^ 1], st));
     msel = select_at(sp, V - visited_n, E - visited_m, sel.mode_pull ? 1 : 0);
     GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
+    list_n = hc->ul_count[ulc];
     if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];

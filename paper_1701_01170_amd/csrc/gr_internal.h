@@ -64,6 +64,8 @@ enum Slot : int {
   S_MARKS,         // one byte per vertex, all zero between uses
   S_MLP_WS,        // selector gradient partial sums
   S_MIRROR,        // shortest-path 16-bit distance mirror [V]
+  S_UL_A,          // BFS pull: unvisited vertices with neighbours (two lists, ping-pong)
+  S_UL_B,
   S_NSLOTS
 };
 
@@ -81,7 +83,8 @@ struct Ctrl {
   int32_t action;           // network argmin over the allowed actions (learned policy)
   float pred[4];            // the network's predicted log2 step times (disallowed: +inf)
   int32_t pad0;
-  int64_t misc[4];
+  uint32_t ul_count[2];     // BFS pull: lengths of the two unvisited lists
+  uint32_t pad3[6];
   // device-predicated level blocks (iteration control without host round trips)
   int32_t dl_levels;        // levels of the current block that ran
   int32_t dl_stop;          // a level of the block declined to run
@@ -220,10 +223,21 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
                                    const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
                                    int32_t* parent, const int32_t* perm, hipStream_t st);
+// Pull over the bitmap; with rem_q (lane-per-vertex form only, lb false) the
+// vertices that keep unvisited with neighbours are listed for the next level.
 hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
                            int p, int32_t* depth, int32_t* parent, const int32_t* perm,
                            int32_t next_depth, int32_t* out_q, uint32_t* out_count,
-                           int64_t* inspected, hipStream_t st);
+                           int64_t* inspected, int32_t* rem_q, uint32_t* rem_count,
+                           hipStream_t st);
+// Pull over such a list (*n_list entries, at most max_n), listing the vertices
+// that stay unvisited again.
+hipError_t launch_bfs_pull_list(const int32_t* list, const uint32_t* n_list, int64_t max_n,
+                                const int32_t* R, const int32_t* C, uint32_t* bm, int p,
+                                int32_t* depth, int32_t* parent, const int32_t* perm,
+                                int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                int64_t* inspected, int32_t* rem_q, uint32_t* rem_count,
+                                hipStream_t st);
 // live |= old (live = depth <= d + 1 after level d)
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
 

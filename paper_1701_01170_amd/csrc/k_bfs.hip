@@ -250,7 +250,8 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
     int64_t V, const int32_t* __restrict__ R, const int32_t* __restrict__ C,
     uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth, int32_t* __restrict__ parent,
     const int32_t* __restrict__ perm, int32_t next_depth, int32_t* __restrict__ out_q,
-    uint32_t* __restrict__ out_count, int64_t* __restrict__ inspected) {
+    uint32_t* __restrict__ out_count, int64_t* __restrict__ inspected,
+    int32_t* __restrict__ rem_q, uint32_t* __restrict__ rem_count) {
   static_assert(GW >= 1 && GW < kWave && (kWave % GW) == 0, "group width");
   constexpr int NW = 256 / kWave;
   constexpr int VPR = kWave / GW;  // vertices per sub-round
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
   const int w = threadIdx.x / kWave;
   const int64_t base = ((int64_t)blockIdx.x * NW + w) * kWave * kPullRuns;
   uint32_t hits = 0;  // bit k: vertex base + 64 k + lane was found
+  uint32_t rems = 0;  // bit k: that vertex has neighbours and stays unvisited (GW == 1)
   int64_t scanned = 0;
   // GW == 1: the smallest-id neighbour of every candidate of kPullBatch runs
   // is probed up front, the loads of those runs in flight together (three
@@ -305,6 +307,7 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
       const int32_t found = first ? pu[kb] : rest;
       if (cand) sc += 1;
       const bool hit = cand && found >= 0;
+      if (cand && !hit) rems |= 1u << k;
       if (hit) {
         depth[v] = next_depth;
         if (parent) parent[v] = caller_id(perm, found);
@@ -396,6 +399,62 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
   uint32_t slot = s_base + s_cnt[w] + inc - n;
   for (int k = 0; k < kPullRuns; ++k)
     if ((hits >> k) & 1u) out_q[slot++] = (int32_t)(base + (int64_t)k * kWave + lane());
+  // the vertices still unvisited (and not isolated): the next pull level's list
+  if (rem_q) {
+    uint32_t rs = block_append<256>(__popc(rems), rem_count);
+    for (int k = 0; k < kPullRuns; ++k)
+      if ((rems >> k) & 1u) rem_q[rs++] = (int32_t)(base + (int64_t)k * kWave + lane());
+  }
+}
+
+// Pull over a list of unvisited vertices (those the previous pull level left,
+// all with neighbours): lane per vertex, the same smallest-id parent scan as
+// the bitmap pull.  Bitmap words are shared by the lanes of different
+// workgroups here, so live bits are set with an atomic OR.  Vertices that
+// stay unvisited form the next list.
+__global__ __launch_bounds__(256) void k_bfs_pull_list(
+    const int32_t* __restrict__ list, const uint32_t* __restrict__ n_list,
+    const int32_t* __restrict__ R, const int32_t* __restrict__ C, uint32_t* __restrict__ bm, int p,
+    int32_t* __restrict__ depth, int32_t* __restrict__ parent, const int32_t* __restrict__ perm,
+    int32_t next_depth, int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count,
+    int64_t* __restrict__ inspected, int32_t* __restrict__ rem_q,
+    uint32_t* __restrict__ rem_count) {
+  __shared__ int64_t s_insp[256 / kWave];
+  const int64_t n = *n_list;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  int32_t v = 0, rb = 0, re = 0;
+  bool cand = false;
+  if (valid) {
+    v = list[i];
+    // a list entry reached since the list was made is dropped
+    const uint2 x = bm_pair(bm, v >> 5);
+    cand = !(((x.x | x.y) >> (v & 31)) & 1u);
+    if (cand) {
+      rb = R[v];
+      re = R[v + 1];
+    }
+  }
+  int64_t sc = 0;
+  const int32_t found = first_frontier_nbr<32>(cand, rb, re, C, bm, p, &sc);
+  const bool hit = cand && found >= 0;
+  if (hit) {
+    depth[v] = next_depth;
+    if (parent) parent[v] = caller_id(perm, found);
+    atomicOr(&bm[2 * (v >> 5) + 1 - p], 1u << (v & 31));
+  }
+  const uint32_t a = block_append<256>(hit ? 1u : 0u, out_count);
+  if (hit) out_q[a] = v;
+  const uint32_t b = block_append<256>(cand && !hit ? 1u : 0u, rem_count);
+  if (cand && !hit) rem_q[b] = v;
+  const int64_t ws = wave_sum(sc);
+  if (lane() == 0) s_insp[threadIdx.x / kWave] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0 && inspected) {
+    int64_t t = 0;
+    for (int k = 0; k < 256 / kWave; ++k) t += s_insp[k];
+    if (t) atomicAdd(reinterpret_cast<unsigned long long*>(inspected), (unsigned long long)t);
+  }
 }
 
 // Parents of the vertices a push step discovered (symmetric graphs): the
@@ -472,15 +531,29 @@ hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, i
 hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
                            int p, int32_t* depth, int32_t* parent, const int32_t* perm,
                            int32_t next_depth, int32_t* out_q, uint32_t* out_count,
-                           int64_t* inspected, hipStream_t st) {
+                           int64_t* inspected, int32_t* rem_q, uint32_t* rem_count,
+                           hipStream_t st) {
   if (V <= 0) return hipSuccess;
   const unsigned g = blocks_for(V, 256 * kPullRuns);
   if (lb)
     k_bfs_pull_bm<4><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, perm, next_depth, out_q,
-                                        out_count, inspected);
+                                        out_count, inspected, nullptr, nullptr);
   else
     k_bfs_pull_bm<1><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, perm, next_depth, out_q,
-                                        out_count, inspected);
+                                        out_count, inspected, rem_q, rem_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_pull_list(const int32_t* list, const uint32_t* n_list, int64_t max_n,
+                                const int32_t* R, const int32_t* C, uint32_t* bm, int p,
+                                int32_t* depth, int32_t* parent, const int32_t* perm,
+                                int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                int64_t* inspected, int32_t* rem_q, uint32_t* rem_count,
+                                hipStream_t st) {
+  if (max_n <= 0) return hipSuccess;
+  k_bfs_pull_list<<<blocks_for(max_n, 256), 256, 0, st>>>(list, n_list, R, C, bm, p, depth,
+                                                          parent, perm, next_depth, out_q,
+                                                          out_count, inspected, rem_q, rem_count);
   return hipGetLastError();
 }
 

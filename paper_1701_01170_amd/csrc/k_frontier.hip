@@ -36,6 +36,7 @@ __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
     ctrl->max_deg[0] = ctrl->max_deg[1] = 0;
     ctrl->inspected = 0;
     ctrl->reached_edges = 0;
+    ctrl->ul_count[0] = ctrl->ul_count[1] = 0;
   }
 }
 
