@@ -50,7 +50,7 @@ KERNEL_NAMES = {
 
 
 def algorithmic_bytes(kind: str, kernel: int, n_f: int, m_f: int, n_next: int) -> float | None:
-    """Bytes the method must move for one advance launch (see DESIGN.md):
+    """Bytes the method must move for one advance launch:
     SSSP relax: per edge 4 B column + 4 B weight + 8 B packed atomic-min of the
       target's (dist, pred) key; per frontier vertex 4 B id + 8 B row offsets;
       per output vertex 4 B queue entry.
@@ -235,7 +235,7 @@ def extras(gr, gg, ctx, torch, log):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; this build has no multi-GPU path (got --gpus {args.gpus})",
+        print(f"bench.py measures one GPU; the library has no multi-GPU path (got --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -52,7 +52,7 @@ typedef enum gr_status {
   GR_ENOMEM = -3,         /* device or host allocation failed */
   GR_EHIP = -4,           /* a HIP runtime call failed (message holds the HIP error) */
   GR_ENODEV = -5,         /* no usable gfx950 device */
-  GR_EUNSUPPORTED = -6    /* valid request this build cannot serve */
+  GR_EUNSUPPORTED = -6    /* valid request the library cannot serve */
 } gr_status;
 
 /* How the per-iteration strategy is chosen (Sec. 5.1 heuristics). */

@@ -156,7 +156,7 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
   hipDeviceProp_t prop;
   GR_HIP(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(GR_ENODEV, std::string("device is ") + prop.gcnArchName + ", this build targets gfx950");
+    return fail(GR_ENODEV, std::string("device is ") + prop.gcnArchName + ", the library is compiled for gfx950 only");
   DeviceGuard g(device);
   gr_ctx* c = new gr_ctx();
   c->device = device;
