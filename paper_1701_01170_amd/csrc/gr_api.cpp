@@ -680,7 +680,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       // the network pushing where the heuristic would pull: the block keeps
       // pushing (its device-side direction test would stop it at once)
       const double blk_do_a = sel.last_heuristic >= GR_PULL_TWC ? -1.0 : dl.do_a;
-      GR_HIP(launch_dl_begin(ctrl, cur, sp, vm0, vn0, 0u, 0, 0, st));
+      GR_HIP(launch_dl_begin(ctrl, cur, vm0, vn0, 0u, 0, 0, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
@@ -954,7 +954,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       // with the priority queue also its refill steps).
       int kmax = dl.len;
       if (opts.max_iterations > 0) kmax = std::min(kmax, opts.max_iterations - it);
-      GR_HIP(launch_dl_begin(ctrl, cur, sp, 0, 0, pq.T, pq.epoch, pq.fc, st));
+      GR_HIP(launch_dl_begin(ctrl, cur, 0, 0, pq.T, pq.epoch, pq.fc, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;

@@ -88,8 +88,6 @@ struct Ctrl {
   // device-predicated level blocks (iteration control without host round trips)
   int32_t dl_levels;        // levels of the current block that ran
   int32_t dl_stop;          // a level of the block declined to run
-  int64_t dl_m[3];          // degree sum of the frontier held in queue k
-  int64_t dl_maxd[3];       // largest degree in the frontier held in queue k
   int64_t dl_vm[2];         // degree sum of the vertices reached before the current frontier
   int64_t dl_vn[2];         // number of vertices reached before the current frontier
   // SSSP two-level priority queue (near / far piles); [2] slots alternate by
@@ -319,7 +317,7 @@ struct DlArgs {
   int64_t* log;               // [kDlMaxLevels][3]
   Ctrl* ctrl;
 };
-hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, uint32_t pq_T,
+hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int64_t vm, int64_t vn, uint32_t pq_T,
                            int32_t pq_epoch, int32_t pq_fc, hipStream_t st);
 hipError_t launch_bfs_dstep(const DlArgs& a, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
                             const int32_t* perm, int32_t next_depth, int n_blocks, hipStream_t st);

@@ -50,20 +50,15 @@ constexpr int lb_cap(int chunk_edges) {
 }
 
 // Process up to B edges per lane: ok[r] marks a real edge (u[r], pay[r], ce[r]).
-// With DEG, the degrees of the appended vertices are also summed into
-// *deg_sum and maximised into *deg_max (one atomic each per wavefront).  All
-// 64 lanes must take part.  With AGG the whole workgroup appends with one
+// All 64 lanes must take part.  With AGG the whole workgroup appends with one
 // atomic (every thread of the workgroup must then call it the same number of
 // times): a single queue tail shared by the whole grid serialises its
 // atomics, so fewer of them is the point.
-template <class F, int B, bool DEG = false, bool AGG = false>
+template <class F, int B, bool AGG = false>
 __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict__ C, bool (&ok)[B],
                                            const int32_t (&u)[B], const typename F::pay_t (&pay)[B],
                                            const int32_t (&ce)[B], int32_t* __restrict__ out_q,
-                                           uint32_t* __restrict__ out_count,
-                                           const int32_t* __restrict__ R = nullptr,
-                                           unsigned long long* deg_sum = nullptr,
-                                           unsigned long long* deg_max = nullptr) {
+                                           uint32_t* __restrict__ out_count) {
   int32_t v[B];
   uint32_t ev[B];
 #pragma unroll
@@ -106,7 +101,6 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
 #pragma unroll
     for (int r = 0; r < B; ++r)
       if (ok[r]) out_q[base++] = v[r];
-    if (__ballot(n_app != 0) == 0) return;
   } else {
     // wavefront-aggregated append of every lane's survivors
     const uint64_t any = __ballot(n_app != 0);
@@ -118,20 +112,6 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
 #pragma unroll
     for (int r = 0; r < B; ++r)
       if (ok[r]) out_q[base++] = v[r];
-  }
-  if (DEG) {
-    unsigned long long ds = 0, dm = 0;
-#pragma unroll
-    for (int r = 0; r < B; ++r)
-      if (ok[r]) {
-        const unsigned long long d = (unsigned long long)(R[v[r] + 1] - R[v[r]]);
-        ds += d;
-        dm = d > dm ? d : dm;
-      }
-    ds = wave_sum(ds);
-    dm = wave_max(dm);
-    if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
-    if (lane() == 0 && dm) atomicMax(deg_max, dm);
   }
 }
 
@@ -227,7 +207,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
         pay[r] = s_pay[k];
         ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
       }
-      edge_batch<F, EPT, false, true>(f, C, ok, u, pay, ce, out_q, out_count);
+      edge_batch<F, EPT, true>(f, C, ok, u, pay, ce, out_q, out_count);
     }
     __syncthreads();
   }
@@ -274,7 +254,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_light(
       pay[r] = s_pay[k];
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
-    edge_batch<F, B, false, true>(f, C, ok, u, pay, ce, out_q, out_count);
+    edge_batch<F, B, true>(f, C, ok, u, pay, ce, out_q, out_count);
   }
 }
 

@@ -3,17 +3,16 @@
 // host round trip in between (the per-iteration termination check of the
 // bulk-synchronous loop, Sec. 4 and Sec. 5.2, moved onto the device).
 //
-// Every workgroup first reads the same control values, all written by earlier
-// kernels, and so takes the same decision: the level runs only if no earlier
-// level of the block declined, the frontier is non-empty, it fits the LDS
-// staging (kDlMaxN vertices) and the caller's edge bound, and (BFS) the
-// direction heuristic of Sec. 5.1 would still push.  A declining level sets
-// dl_stop, so the rest of the block does nothing.
+// Every workgroup reads the same control values, all written by earlier
+// kernels, and stages the same frontier, so all take the same decision: the
+// level runs only if no earlier level of the block declined, the frontier is
+// non-empty, it fits the LDS staging (kDlMaxN vertices) and the caller's edge
+// bound, and (BFS) the direction heuristic of Sec. 5.1 would still push.  A
+// declining level sets dl_stop, so the rest of the block does nothing.
 //
 // A running level is output-balanced like LB (Sec. 5.1): each workgroup stages
-// the whole frontier in LDS, scans its degrees, and expands one equal slice
-// of the level's edges.  The degrees of appended vertices are summed on the
-// fly, which gives the next level its m_f without a statistics pass.
+// the whole frontier in LDS, scans its degrees (which gives the level its m_f
+// without a statistics pass), and expands one equal slice of the edges.
 //
 // Functors used here also provide prepare(ctrl, step) (the functor of this
 // step, e.g. SSSP's priority-queue threshold read from the control block) and
@@ -43,56 +42,41 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   if (ctrl->dl_stop) return;
   const F fs = f.prepare(ctrl, a.step);
   const int64_t n_f = ctrl->q_count[a.cur];
-  const int64_t m_f = ctrl->dl_m[a.cur];
   const int64_t vm = ctrl->dl_vm[a.step & 1];
   const int64_t vn = ctrl->dl_vn[a.step & 1];
-  bool run = n_f > 0 && n_f <= a.max_n && n_f <= kDlMaxN && m_f <= a.max_m;
-  // the heuristic's direction (Sec. 5.1 push -> pull test)
-  if (run && a.do_a >= 0.0 && (double)m_f > (double)(a.E - vm - m_f) * a.do_a) run = false;
+  const int next = (a.cur + 1) % 3, prev = (a.cur + 2) % 3;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   bool refill = false;
   if constexpr (F::kFar) refill = n_f == 0 && fs.far_pending(ctrl);
-  if (!run && !refill) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->dl_stop = 1;
+  if (!refill && !(n_f > 0 && n_f <= a.max_n && n_f <= kDlMaxN)) {
+    if (lead) ctrl->dl_stop = 1;
     return;
-  }
-  const int next = (a.cur + 1) % 3, prev = (a.cur + 2) % 3;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    // none of these is read by this kernel: the counters of the previous
-    // frontier become the append targets of the next level
-    ctrl->dl_levels = a.step + 1;
-    ctrl->q_count[prev] = 0;
-    ctrl->dl_m[prev] = 0;
-    ctrl->dl_maxd[prev] = 0;
-    ctrl->dl_vm[(a.step + 1) & 1] = vm + m_f;
-    ctrl->dl_vn[(a.step + 1) & 1] = vn + n_f;
-    fs.advance(ctrl, a.step, refill);
-    if (refill && a.log) {
-      a.log[3 * a.step + 0] = 0;
-      a.log[3 * a.step + 1] = 0;
-      a.log[3 * a.step + 2] = 0;
-    }
   }
   if constexpr (F::kFar) {
     if (refill) {
-      fs.refill(ctrl, a.q_next, &ctrl->q_count[next], a.R,
-                reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]),
-                reinterpret_cast<unsigned long long*>(&ctrl->dl_maxd[next]));
+      if (lead) {
+        // none of these is read by this kernel
+        ctrl->dl_levels = a.step + 1;
+        ctrl->q_count[prev] = 0;
+        ctrl->dl_vm[(a.step + 1) & 1] = vm;
+        ctrl->dl_vn[(a.step + 1) & 1] = vn;
+        fs.advance(ctrl, a.step, true);
+        if (a.log) {
+          a.log[3 * a.step + 0] = 0;
+          a.log[3 * a.step + 1] = 0;
+          a.log[3 * a.step + 2] = 0;
+        }
+      }
+      fs.refill(ctrl, a.q_next, &ctrl->q_count[next]);
       return;
     }
   }
+  // every workgroup stages the whole frontier and scans its degrees
+  // (kDlPerThread consecutive entries per thread); the scan total is the
+  // level's frontier edge count m_f
   const int nf = (int)n_f;
   for (int j = threadIdx.x; j < nf; j += kAdvBlock) s_u[j] = a.q_cur[j];
   __syncthreads();
-  for (int j = blockIdx.x * kAdvBlock + threadIdx.x; j < nf; j += gridDim.x * kAdvBlock)
-    fs.frontier_vertex(s_u[j]);
-  // equal edge slices (at least one row of the workgroup each); workgroups
-  // past the last slice have nothing more to do
-  const int64_t G = gridDim.x;
-  int64_t per = (m_f + G - 1) / G;
-  if (per < kAdvBlock) per = kAdvBlock;
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  if (lo >= m_f && blockIdx.x != 0) return;
-  // degrees and their exclusive scan, kDlPerThread consecutive entries per thread
   const int j0 = threadIdx.x * kDlPerThread;
   int32_t d[kDlPerThread];
   int64_t sum = 0, mx = 0;
@@ -124,13 +108,40 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   mx = wave_max(mx);
   if (lane() == 0) s_max[threadIdx.x / kWave] = mx;
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.log) {
-    int64_t m = 0;
-    for (int i = 0; i < kAdvBlock / kWave; ++i) m = s_max[i] > m ? s_max[i] : m;
-    a.log[3 * a.step + 0] = n_f;
-    a.log[3 * a.step + 1] = m_f;
-    a.log[3 * a.step + 2] = m;
+  // the level runs only within the caller's edge bound and, under the
+  // heuristic, while its push test holds (Sec. 5.1 push -> pull); every
+  // workgroup computes the same total, so all take the same decision
+  bool run = total <= a.max_m;
+  if (run && a.do_a >= 0.0 && (double)total > (double)(a.E - vm - total) * a.do_a) run = false;
+  if (!run) {
+    if (lead) ctrl->dl_stop = 1;
+    return;
   }
+  if (lead) {
+    // none of these is read by this kernel: the counter of the previous
+    // frontier becomes the append target of the next level
+    ctrl->dl_levels = a.step + 1;
+    ctrl->q_count[prev] = 0;
+    ctrl->dl_vm[(a.step + 1) & 1] = vm + total;
+    ctrl->dl_vn[(a.step + 1) & 1] = vn + n_f;
+    fs.advance(ctrl, a.step, false);
+    if (a.log) {
+      int64_t m = 0;
+      for (int i = 0; i < kAdvBlock / kWave; ++i) m = s_max[i] > m ? s_max[i] : m;
+      a.log[3 * a.step + 0] = n_f;
+      a.log[3 * a.step + 1] = total;
+      a.log[3 * a.step + 2] = m;
+    }
+  }
+  for (int j = blockIdx.x * kAdvBlock + threadIdx.x; j < nf; j += gridDim.x * kAdvBlock)
+    fs.frontier_vertex(s_u[j]);
+  // equal edge slices (at least one row of the workgroup each); workgroups
+  // past the last slice have nothing more to do
+  const int64_t G = gridDim.x;
+  int64_t per = (total + G - 1) / G;
+  if (per < kAdvBlock) per = kAdvBlock;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  if (lo >= total) return;
   const int64_t hi = lo + per < total ? lo + per : total;
   for (int64_t base = lo; base < hi; base += (int64_t)kAdvBlock * B) {
     bool ok[B];
@@ -146,9 +157,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
       pay[r] = s_pay[k];
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
-    edge_batch<F, B, true, true>(fs, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next], a.R,
-                           reinterpret_cast<unsigned long long*>(&ctrl->dl_m[next]),
-                           reinterpret_cast<unsigned long long*>(&ctrl->dl_maxd[next]));
+    edge_batch<F, B, true>(fs, a.C, ok, u, pay, ce, a.q_next, &ctrl->q_count[next]);
   }
 }
 

@@ -198,16 +198,13 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
   if (i < n) p[i] = value;
 }
 
-// Start of a device-predicated block: the current frontier (queue cur) has
-// the degree sum the statistics kernel left in slot sp.
-__global__ void k_dl_begin(Ctrl* __restrict__ ctrl, int cur, int sp, int64_t vm, int64_t vn,
+// Start of a device-predicated block whose first frontier is queue cur: the
+// block counters, the visited counts before that frontier and the priority
+// queue state of its first step.
+__global__ void k_dl_begin(Ctrl* __restrict__ ctrl, int cur, int64_t vm, int64_t vn,
                            uint32_t pq_T, int32_t pq_epoch, int32_t pq_fc) {
   ctrl->dl_levels = 0;
   ctrl->dl_stop = 0;
-  ctrl->dl_m[cur] = ctrl->m_f[sp];
-  ctrl->dl_m[(cur + 1) % 3] = 0;
-  ctrl->dl_maxd[cur] = ctrl->max_deg[sp];
-  ctrl->dl_maxd[(cur + 1) % 3] = 0;
   ctrl->q_count[(cur + 1) % 3] = 0;
   ctrl->dl_vm[0] = vm;
   ctrl->dl_vn[0] = vn;
@@ -263,9 +260,9 @@ hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int sp, int64_t vm, int64_t vn, uint32_t pq_T,
+hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int64_t vm, int64_t vn, uint32_t pq_T,
                            int32_t pq_epoch, int32_t pq_fc, hipStream_t st) {
-  k_dl_begin<<<1, 1, 0, st>>>(ctrl, cur, sp, vm, vn, pq_T, pq_epoch, pq_fc);
+  k_dl_begin<<<1, 1, 0, st>>>(ctrl, cur, vm, vn, pq_T, pq_epoch, pq_fc);
   return hipGetLastError();
 }
 

@@ -213,17 +213,13 @@ __device__ __forceinline__ uint32_t pq_next_threshold(uint32_t T, uint32_t delta
 // Split far pile fc into the next frontier and far pile (fc + 1) % 3 (see the
 // file comment).  Grid-stride over kRefillItems entries per thread; both
 // lists are appended with one atomic per workgroup and round, so every thread
-// of the workgroup must call it.  With deg_sum / deg_max the degrees of the
-// new frontier are accumulated too (one atomic per wavefront at the end).
+// of the workgroup must call it.
 constexpr int kRefillItems = 4;
 __device__ __forceinline__ void pq_refill_pass(const unsigned long long* __restrict__ keys,
                                                uint32_t T, uint32_t delta, int32_t epoch, int32_t fc,
                                                int32_t* __restrict__ far_base,
                                                int32_t* __restrict__ far_tag, int64_t V, Ctrl* ctrl,
-                                               int32_t* __restrict__ out_q, uint32_t* out_count,
-                                               const int32_t* __restrict__ R,
-                                               unsigned long long* deg_sum,
-                                               unsigned long long* deg_max) {
+                                               int32_t* __restrict__ out_q, uint32_t* out_count) {
   constexpr int K = kRefillItems;
   const uint32_t T1 = pq_next_threshold(T, delta);
   const int32_t fn = (fc + 1) % 3;
@@ -232,7 +228,6 @@ __device__ __forceinline__ void pq_refill_pass(const unsigned long long* __restr
   const int64_t n = ctrl->far_count[fc];
   const int64_t per_round = (int64_t)kAdvBlock * K;
   const int64_t stride = (int64_t)gridDim.x * per_round;
-  unsigned long long ds = 0, dm = 0;
   for (int64_t base = (int64_t)blockIdx.x * per_round; base < n; base += stride) {
     int32_t v[K];
     bool near[K], keep[K];
@@ -257,18 +252,7 @@ __device__ __forceinline__ void pq_refill_pass(const unsigned long long* __restr
     for (int r = 0; r < K; ++r) {
       if (near[r]) out_q[s1++] = v[r];
       if (keep[r]) keep_q[s2++] = v[r];
-      if (deg_sum && near[r]) {
-        const unsigned long long dg = (unsigned long long)(R[v[r] + 1] - R[v[r]]);
-        ds += dg;
-        dm = dg > dm ? dg : dm;
-      }
     }
-  }
-  if (deg_sum) {
-    ds = wave_sum(ds);
-    dm = wave_max(dm);
-    if (lane() == 0 && ds) atomicAdd(deg_sum, ds);
-    if (lane() == 0 && dm) atomicMax(deg_max, dm);
   }
 }
 
@@ -365,11 +349,8 @@ struct SsspPqVisit {
       ctrl->pq_fc[s] = fc;
     }
   }
-  __device__ __forceinline__ void refill(Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
-                                         const int32_t* R, unsigned long long* deg_sum,
-                                         unsigned long long* deg_max) const {
-    pq_refill_pass(keys, T, delta, epoch, fc, far_base, far_tag, V, ctrl, out_q, out_count, R,
-                   deg_sum, deg_max);
+  __device__ __forceinline__ void refill(Ctrl* ctrl, int32_t* out_q, uint32_t* out_count) const {
+    pq_refill_pass(keys, T, delta, epoch, fc, far_base, far_tag, V, ctrl, out_q, out_count);
   }
 };
 
@@ -379,7 +360,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_sssp_pq_refill(const unsigned lon
                                                         uint32_t* __restrict__ out_count) {
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->far_count[(pq.fc + 2) % 3] = 0;
   pq_refill_pass(keys, pq.T, pq.delta, pq.epoch, pq.fc, pq.far_base, pq.far_tag, pq.V, ctrl, out_q,
-                 out_count, nullptr, nullptr, nullptr);
+                 out_count);
 }
 
 __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restrict__ keys,
