@@ -778,11 +778,10 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       inspected_push += m_f;
     } else {
       kernel = action == GR_PULL_LB ? 5 : 4;
-      // the lane-per-vertex pull lists the vertices it leaves unvisited, and
-      // reads such a list instead of the bitmap when the previous level did
-      const bool lane_pull = action == GR_PULL_TWC;
+      // every pull lists the vertices it leaves unvisited, and the next pull
+      // level reads that list instead of the bitmap once it is short
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      if (lane_pull && list_ok && list_n <= V / kPullListDivisor)
+      if (list_ok && list_n <= V / kPullListDivisor)
         GR_HIP(launch_bfs_pull_list(ul[ulc], &ctrl->ul_count[ulc], list_n, g->R, g->C, bm, p,
                                     depth, parent, perm, next_depth, q[(cur + 1) % 3],
                                     &ctrl->q_count[(cur + 1) % 3], &ctrl->inspected, ul[ulc ^ 1],
@@ -790,11 +789,10 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       else
         GR_HIP(launch_bfs_pull(action == GR_PULL_LB, V, g->R, g->C, bm, p, depth, parent, perm,
                                next_depth, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3],
-                               &ctrl->inspected, lane_pull ? ul[ulc ^ 1] : nullptr,
-                               &ctrl->ul_count[ulc ^ 1], st));
+                               &ctrl->inspected, ul[ulc ^ 1], &ctrl->ul_count[ulc ^ 1], st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
-      if (lane_pull) ulc ^= 1;
-      list_ok = lane_pull;
+      ulc ^= 1;
+      list_ok = true;
     }
     GR_HIP(launch_bitmap_merge(bm, p, NW, st));
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));

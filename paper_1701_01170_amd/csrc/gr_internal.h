@@ -221,8 +221,8 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 hipError_t launch_bfs_parent_fixup(const int32_t* list, const uint32_t* count, int64_t max_count,
                                    const int32_t* R, const int32_t* C, const uint32_t* bm, int p,
                                    int32_t* parent, const int32_t* perm, hipStream_t st);
-// Pull over the bitmap; with rem_q (lane-per-vertex form only, lb false) the
-// vertices that keep unvisited with neighbours are listed for the next level.
+// Pull over the bitmap; with rem_q the vertices that stay unvisited with
+// neighbours are listed for the next level.
 hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* C, uint32_t* bm,
                            int p, int32_t* depth, int32_t* parent, const int32_t* perm,
                            int32_t next_depth, int32_t* out_q, uint32_t* out_count,

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
   const int w = threadIdx.x / kWave;
   const int64_t base = ((int64_t)blockIdx.x * NW + w) * kWave * kPullRuns;
   uint32_t hits = 0;  // bit k: vertex base + 64 k + lane was found
-  uint32_t rems = 0;  // bit k: that vertex has neighbours and stays unvisited (GW == 1)
+  uint32_t rems = 0;  // bit k: that vertex has neighbours and stays unvisited
   int64_t scanned = 0;
   // GW == 1: the smallest-id neighbour of every candidate of kPullBatch runs
   // is probed up front, the loads of those runs in flight together (three
@@ -317,6 +317,7 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
     } else {
       const int g = lane() / GW, sub = lane() % GW, gbase = g * GW;
       const bool leader = sub == 0;
+      uint64_t rb_all = 0;  // the run's vertices that stay unvisited with neighbours
       for (int s = 0; s < GW; ++s) {
         const int64_t v = v0 + s * VPR + g;
         bool cand = false;
@@ -364,11 +365,17 @@ __global__ __launch_bounds__(256) void k_bfs_pull_bm(
           if (parent) parent[v] = caller_id(perm, found);
         }
         const uint64_t lb = __ballot(hit);  // bit g * GW for group g
-        uint64_t m = 0;
-        for (int q = 0; q < VPR; ++q) m |= ((lb >> (q * GW)) & 1ull) << q;
+        const uint64_t lr = __ballot(leader && cand && !hit);
+        uint64_t m = 0, mr = 0;
+        for (int q = 0; q < VPR; ++q) {
+          m |= ((lb >> (q * GW)) & 1ull) << q;
+          mr |= ((lr >> (q * GW)) & 1ull) << q;
+        }
         hb |= m << (s * VPR);
+        rb_all |= mr << (s * VPR);
         if (leader) scanned += sc;
       }
+      if ((rb_all >> lane()) & 1ull) rems |= 1u << k;
     }
     // live bits of the run's two words (owned by this wavefront)
     const int64_t w0 = v0 >> 5;
@@ -537,7 +544,7 @@ hipError_t launch_bfs_pull(bool lb, int64_t V, const int32_t* R, const int32_t* 
   const unsigned g = blocks_for(V, 256 * kPullRuns);
   if (lb)
     k_bfs_pull_bm<4><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, perm, next_depth, out_q,
-                                        out_count, inspected, nullptr, nullptr);
+                                        out_count, inspected, rem_q, rem_count);
   else
     k_bfs_pull_bm<1><<<g, 256, 0, st>>>(V, R, C, bm, p, depth, parent, perm, next_depth, out_q,
                                         out_count, inspected, rem_q, rem_count);
