@@ -97,7 +97,9 @@ typedef struct gr_level_trace {
   float step_us;       /* device time of the whole iteration (advance, filter, bookkeeping) */
   float kernel_us;     /* device time of the advance kernel alone (event-timed) */
   int32_t kernel;      /* advance kernel: 0 TWC, 1 LB_LIGHT, 2 LB, 3 LB with byte-mark filter,
-                          4 pull TWC, 5 pull groups, 6 device-predicated step (step_us and
+                          4 pull TWC, 5 pull groups (either over the bitmap, or over the
+                          short list of still-unvisited vertices the previous pull level
+                          left), 6 device-predicated step (step_us and
                           kernel_us are then the block's time divided by its levels),
                           7 SSSP priority-queue refill (far pile split), 8 / 9 / 10 SSSP
                           TWC / LB_LIGHT / LB relaxation with the byte-mark filter */
