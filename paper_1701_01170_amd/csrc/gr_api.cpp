@@ -511,9 +511,10 @@ constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filt
 // the byte-mark filter.
 constexpr int64_t kSsspMarksDivisor = 4;
 // ... and screen their edges with the 16-bit distance mirror once the
-// frontiers so far, this one included, sum to at least V / kSsspMirrorDivisor
-// vertices (an upper bound of the vertices reached): before that most edges
-// reach unvisited vertices, pass the screen anyway and pay for both gathers.
+// frontiers so far, this one included, and the far pile of the priority queue
+// sum to at least V / kSsspMirrorDivisor vertices (an estimate of the vertices
+// reached): before that most edges reach unvisited vertices, pass the screen
+// anyway and pay for both gathers.
 constexpr int64_t kSsspMirrorDivisor = 2;
 
 struct DlPlan {
@@ -1037,7 +1038,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         uint8_t* marks;
         GR_TRY(marks_buffer(ctx, V, &marks, st));
         kernel += kTraceMarksOffset;
-        const bool screen = expanded + n_f >= V / kSsspMirrorDivisor;
+        const bool screen = expanded + n_f + far_n >= V / kSsspMirrorDivisor;
         GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
                                        g->W, keys, perm, marks, mirror, screen, chunk, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
