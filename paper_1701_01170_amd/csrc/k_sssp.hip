@@ -159,6 +159,21 @@ __device__ __forceinline__ uint16_t mirror_of(unsigned long long key) {
   return (uint16_t)(d < kMirrorNone ? d : kMirrorNone);
 }
 
+// Keys of the 32 consecutive vertices v0 .. v0 + 31 (v0 a multiple of 32, all
+// below V), two per 16-byte load.  All loads are issued before any is used:
+// loading only the marked ones (a loop over the set bits, or one branch per
+// load) makes each wait for the previous one.
+__device__ __forceinline__ void word_keys(const unsigned long long* __restrict__ keys, int64_t v0,
+                                          unsigned long long (&k)[32]) {
+  const ulonglong2* __restrict__ k2 = reinterpret_cast<const ulonglong2*>(keys + v0);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const ulonglong2 x = k2[j];
+    k[2 * j] = x.x;
+    k[2 * j + 1] = x.y;
+  }
+}
+
 // One thread per 32 vertices: gather and clear the marks, list the marked
 // vertices (ascending within each workgroup).
 // The distance mirror of every marked vertex is refreshed on the way.
@@ -169,9 +184,18 @@ __global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__
                                                            uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t mask = take_marks(marks, w, V);
-  for (uint32_t m = mask; m; m &= m - 1) {
-    const int64_t v = w * 32 + __ffs(m) - 1;
-    mirror[v] = mirror_of(keys[v]);
+  const int64_t v0 = w * 32;
+  if (mask && v0 + 32 <= V) {
+    unsigned long long k[32];
+    word_keys(keys, v0, k);
+#pragma unroll
+    for (int b = 0; b < 32; ++b)
+      if ((mask >> b) & 1u) mirror[v0 + b] = mirror_of(k[b]);
+  } else {
+    for (uint32_t m = mask; m; m &= m - 1) {
+      const int64_t v = v0 + __ffs(m) - 1;
+      mirror[v] = mirror_of(keys[v]);
+    }
   }
   append_mask<256>(mask, w, out_q, out_count);
 }
@@ -189,16 +213,43 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
     uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t mask = take_marks(marks, w, V), near = 0, far = 0;
-  for (uint32_t m = mask; m; m &= m - 1) {
-    const int b = __ffs(m) - 1;
-    const int64_t v = w * 32 + b;
-    const unsigned long long key = keys[v];
-    mirror[v] = mirror_of(key);
-    if ((uint32_t)(key >> 32) < T) {
-      near |= 1u << b;
-    } else if (far_tag[v] != epoch) {
-      far_tag[v] = epoch;
-      far |= 1u << b;
+  const int64_t v0 = w * 32;
+  if (mask && v0 + 32 <= V) {
+    unsigned long long k[32];
+    word_keys(keys, v0, k);
+    int32_t ft[32];
+    const int4* __restrict__ f4 = reinterpret_cast<const int4*>(far_tag + v0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int4 x = f4[j];
+      ft[4 * j] = x.x;
+      ft[4 * j + 1] = x.y;
+      ft[4 * j + 2] = x.z;
+      ft[4 * j + 3] = x.w;
+    }
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+      if (!((mask >> b) & 1u)) continue;
+      mirror[v0 + b] = mirror_of(k[b]);
+      if ((uint32_t)(k[b] >> 32) < T) {
+        near |= 1u << b;
+      } else if (ft[b] != epoch) {
+        far_tag[v0 + b] = epoch;
+        far |= 1u << b;
+      }
+    }
+  } else {
+    for (uint32_t m = mask; m; m &= m - 1) {
+      const int b = __ffs(m) - 1;
+      const int64_t v = v0 + b;
+      const unsigned long long key = keys[v];
+      mirror[v] = mirror_of(key);
+      if ((uint32_t)(key >> 32) < T) {
+        near |= 1u << b;
+      } else if (far_tag[v] != epoch) {
+        far_tag[v] = epoch;
+        far |= 1u << b;
+      }
     }
   }
   append_mask<256>(near, w, out_q, out_count);
