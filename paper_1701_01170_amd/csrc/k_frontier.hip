@@ -10,6 +10,11 @@ namespace {
 
 constexpr int kStatsBlock = 256;
 constexpr int kStatsGrid = 512;
+// Frontier entries a thread handles per round.  Their loads (queue entry, then
+// two row offsets) are all issued before any result is used, and past the
+// slice end they read the slice's last entry instead of branching: a branch
+// around each load would make every load wait for the one before it.
+constexpr int kStatsItems = 8;
 
 __global__ __launch_bounds__(256) void k_bfs_init(int32_t* __restrict__ depth,
                                                   int32_t* __restrict__ parent, int64_t V,
@@ -56,11 +61,24 @@ __device__ __forceinline__ void frontier_stats(const int32_t* __restrict__ front
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = lo + per < n_f ? lo + per : n_f;
   int64_t sum = 0, mx = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kStatsBlock) {
-    const int32_t u = frontier[i];
-    const int64_t d = (int64_t)R[u + 1] - R[u];
-    sum += d;
-    mx = d > mx ? d : mx;
+  for (int64_t base = lo; base < hi; base += (int64_t)kStatsBlock * kStatsItems) {
+    int32_t u[kStatsItems], a[kStatsItems], b[kStatsItems];
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) {
+      const int64_t i = base + r * kStatsBlock + threadIdx.x;
+      u[r] = frontier[i < hi ? i : hi - 1];
+    }
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) {
+      a[r] = R[u[r]];
+      b[r] = R[u[r] + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) {
+      const int64_t d = base + r * kStatsBlock + threadIdx.x < hi ? (int64_t)b[r] - a[r] : 0;
+      sum += d;
+      mx = d > mx ? d : mx;
+    }
   }
   sum = wave_sum(sum);
   mx = wave_max(mx);
@@ -130,23 +148,35 @@ __global__ __launch_bounds__(kStatsBlock) void k_frontier_offsets(
     block_excl_scan<kStatsBlock>(pre, s_tot, &t);
     pre = t;
   }
+  // kStatsItems consecutive entries per thread and round
   int64_t run = pre;
-  for (int64_t base = lo; base < hi; base += kStatsBlock) {
-    const int64_t i = base + threadIdx.x;
-    int64_t d = 0;
-    int32_t rb = 0;
-    if (i < hi) {
-      const int32_t u = frontier[i];
-      rb = R[u];
-      d = (int64_t)R[u + 1] - rb;
+  for (int64_t base = lo; base < hi; base += (int64_t)kStatsBlock * kStatsItems) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kStatsItems;
+    int32_t u[kStatsItems], a[kStatsItems], b[kStatsItems];
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) u[r] = frontier[i0 + r < hi ? i0 + r : hi - 1];
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) {
+      a[r] = R[u[r]];
+      b[r] = R[u[r] + 1];
+    }
+    int64_t d[kStatsItems], tsum = 0;
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) {
+      d[r] = i0 + r < hi ? (int64_t)b[r] - a[r] : 0;
+      tsum += d[r];
     }
     int64_t tot;
-    const int64_t ex = block_excl_scan<kStatsBlock>(d, s_tot, &tot);
-    if (i < hi) {
-      const int64_t o = run + ex;
-      offsets[i] = (int32_t)o;
-      rstart[i] = rb;
-      for (int64_t c = (o + chunk - 1) / chunk; c * chunk < o + d; ++c) chunk_start[c] = (int32_t)i;
+    int64_t o = run + block_excl_scan<kStatsBlock>(tsum, s_tot, &tot);
+#pragma unroll
+    for (int r = 0; r < kStatsItems; ++r) {
+      const int64_t i = i0 + r;
+      if (i < hi) {
+        offsets[i] = (int32_t)o;
+        rstart[i] = a[r];
+        for (int64_t c = (o + chunk - 1) / chunk; c * chunk < o + d[r]; ++c) chunk_start[c] = (int32_t)i;
+      }
+      o += d[r];
     }
     run += tot;
   }
