@@ -79,12 +79,33 @@ gr_status pool_typed(gr_ctx* ctx, Slot s, size_t count, T** out) {
 // faulted stream ends the wait with an error instead of a hang.
 // With sel, the selector network decides on the device in the same kernel
 // that publishes the control block.
-gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st, const MlpSelect* sel = nullptr) {
+// With pre, the degree scan of the frontier just measured is queued behind the
+// publishing kernel, so it runs while the host waits and decides (the next
+// load-balanced advance needs it; when the next step is something else it
+// only used otherwise idle GPU time).
+struct OffsetsJob {
+  const int32_t* frontier;
+  const uint32_t* n_f_dev;
+  const int32_t* R;
+  const int64_t* block_sums;
+  const int64_t* total;
+  int32_t* offsets;
+  int32_t* rstart;
+  int32_t* chunk_start;
+  int32_t chunk;
+};
+
+gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st, const MlpSelect* sel = nullptr,
+                    const OffsetsJob* pre = nullptr) {
   const uint32_t seq = ++ctx->publish_seq;
   if (sel)
     GR_HIP(launch_publish_select(*sel, dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
   else
     GR_HIP(launch_publish(dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
+  if (pre)
+    GR_HIP(launch_frontier_offsets(pre->frontier, 0, pre->R, pre->block_sums, pre->total,
+                                   pre->offsets, pre->rstart, pre->chunk_start, pre->chunk, st,
+                                   pre->n_f_dev));
   for (uint64_t i = 1;; ++i) {
     if (*ctx->publish_flag == seq) break;
     if ((i & 4095) == 0) {
@@ -930,11 +951,18 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   DlPlan dl;
   GR_TRY(dl_plan(ctx, opts, /*pull_ok=*/false, learned, tracing, &dl));
   // after a step that produced the frontier in q[cur]: statistics, selector, read-back
+  // with load-balanced advance likely (average degree), the degree scan of
+  // each new frontier is queued ahead of the read-back (offsets_ready)
+  const bool lb_likely = (double)E / (double)V >= (double)opts.lb_min_avg_degree;
+  bool offsets_ready = false;
   auto next_frontier = [&]() -> gr_status {
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[(cur + 1) % 3], nullptr, st));
     msel.sp = sp;
-    GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
+    const OffsetsJob pre{q[cur], &ctrl->q_count[cur], g->R, bsums, &ctrl->m_f[sp], offsets,
+                         rstart, chunks, chunk};
+    GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr, lb_likely ? &pre : nullptr));
+    offsets_ready = lb_likely;
     if (use_pq) far_n = hc->far_count[pq.fc];
     return GR_OK;
   };
@@ -951,6 +979,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     if (dl_fits) {
       // A block of device-predicated relaxation rounds (Alg. 1 iterations;
       // with the priority queue also its refill steps).
+      offsets_ready = false;  // the block leaves a frontier the scan has not seen
       int kmax = dl.len;
       if (opts.max_iterations > 0) kmax = std::min(kmax, opts.max_iterations - it);
       GR_HIP(launch_dl_begin(ctrl, cur, 0, 0, pq.T, pq.epoch, pq.fc, st));
@@ -1027,7 +1056,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     } else {
       const int mode = action == GR_PUSH_TWC ? 0 : (n_f < opts.lb_light_threshold ? 1 : 2);
       kernel = mode;
-      if (mode == 2)
+      if (mode == 2 && !offsets_ready)
         GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                        chunks, chunk, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));

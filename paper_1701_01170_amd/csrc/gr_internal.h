@@ -181,10 +181,13 @@ struct Queues3 {
 hipError_t launch_frontier_stats_after_block(const Queues3& qs, int cur0, const int32_t* R,
                                              int64_t* block_sums, Ctrl* ctrl, int parity,
                                              hipStream_t st);
+// n_f_dev, when not null, is the frontier size on the device (n_f is then
+// ignored), so the kernel can be queued before the host knows the size.
 hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const int32_t* R,
                                    const int64_t* block_sums, const int64_t* total,
                                    int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
-                                   int32_t chunk, hipStream_t st);
+                                   int32_t chunk, hipStream_t st,
+                                   const uint32_t* n_f_dev = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
 // copy *src into host-visible memory, then store seq to *flag (system scope)
 hipError_t launch_publish(const Ctrl* src, Ctrl* host_dst, uint32_t* host_flag, uint32_t seq,

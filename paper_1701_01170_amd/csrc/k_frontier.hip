@@ -131,11 +131,12 @@ __global__ __launch_bounds__(kStatsBlock) void k_frontier_stats_after_block(
 // output-balanced LB: chunk_start[c] = the frontier index whose neighbour list
 // holds edge c * chunk (the sorted search of 0, N, 2N, ... in the offsets).
 __global__ __launch_bounds__(kStatsBlock) void k_frontier_offsets(
-    const int32_t* __restrict__ frontier, int64_t n_f, const int32_t* __restrict__ R,
-    const int64_t* __restrict__ block_sums, const int64_t* __restrict__ total,
-    int32_t* __restrict__ offsets, int32_t* __restrict__ rstart, int32_t* __restrict__ chunk_start,
-    int32_t chunk) {
+    const int32_t* __restrict__ frontier, int64_t n_f, const uint32_t* __restrict__ n_f_dev,
+    const int32_t* __restrict__ R, const int64_t* __restrict__ block_sums,
+    const int64_t* __restrict__ total, int32_t* __restrict__ offsets,
+    int32_t* __restrict__ rstart, int32_t* __restrict__ chunk_start, int32_t chunk) {
   __shared__ int64_t s_tot[kStatsBlock / kWave + 1];
+  if (n_f_dev) n_f = *n_f_dev;
   const int G = gridDim.x;
   const int64_t per = (n_f + G - 1) / G;
   const int64_t lo = (int64_t)blockIdx.x * per;
@@ -278,9 +279,10 @@ hipError_t launch_frontier_stats_after_block(const Queues3& qs, int cur0, const 
 hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const int32_t* R,
                                    const int64_t* block_sums, const int64_t* total,
                                    int32_t* offsets, int32_t* rstart, int32_t* chunk_start,
-                                   int32_t chunk, hipStream_t st) {
-  k_frontier_offsets<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f, R, block_sums, total,
-                                                         offsets, rstart, chunk_start, chunk);
+                                   int32_t chunk, hipStream_t st, const uint32_t* n_f_dev) {
+  k_frontier_offsets<<<kStatsGrid, kStatsBlock, 0, st>>>(frontier, n_f, n_f_dev, R, block_sums,
+                                                         total, offsets, rstart, chunk_start,
+                                                         chunk);
   return hipGetLastError();
 }
 
