@@ -242,10 +242,24 @@ __global__ __launch_bounds__(256) void k_ms_teps(const u64* __restrict__ visit,
                                                  const int32_t* __restrict__ R, int64_t V,
                                                  int64_t* __restrict__ out) {
   __shared__ int64_t s[256 / kWave];
+  // four vertices per thread and round, all loaded before any is used
+  constexpr int K = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t acc = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
-       v += (int64_t)gridDim.x * blockDim.x)
-    acc += (int64_t)__popcll(visit[v]) * ((int64_t)R[v + 1] - R[v]);
+  for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < V; v0 += stride * K) {
+    u64 m[K];
+    int32_t a[K], b[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const int64_t v = v0 + r * stride < V ? v0 + r * stride : V - 1;
+      m[r] = visit[v];
+      a[r] = R[v];
+      b[r] = R[v + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+      if (v0 + r * stride < V) acc += (int64_t)__popcll(m[r]) * ((int64_t)b[r] - a[r]);
+  }
   acc = wave_sum(acc);
   if (lane() == 0) s[threadIdx.x / kWave] = acc;
   __syncthreads();

@@ -457,15 +457,31 @@ __global__ __launch_bounds__(256) void k_sssp_finalize(const unsigned long long*
                                                        const int32_t* __restrict__ perm,
                                                        int64_t* __restrict__ reached_edges) {
   __shared__ int64_t s[256 / kWave];
+  // kFinalItems vertices per thread and round, all loaded before any is used
+  // (past V the loads repeat vertex V - 1 and the results are dropped)
+  constexpr int kFinalItems = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t acc = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned long long k = keys[v];
-    const uint32_t d = (uint32_t)(k >> 32);
-    const int64_t o = perm ? perm[v] : v;
-    dist[o] = d;
-    if (pred) pred[o] = (int32_t)(uint32_t)(k & 0xffffffffull);
-    if (d != 0xffffffffu) acc += (int64_t)R[v + 1] - R[v];
+  for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < V;
+       v0 += stride * kFinalItems) {
+    unsigned long long k[kFinalItems];
+    int32_t a[kFinalItems], b[kFinalItems], o[kFinalItems];
+#pragma unroll
+    for (int r = 0; r < kFinalItems; ++r) {
+      const int64_t v = v0 + r * stride < V ? v0 + r * stride : V - 1;
+      k[r] = keys[v];
+      a[r] = R[v];
+      b[r] = R[v + 1];
+      o[r] = perm ? perm[v] : (int32_t)v;
+    }
+#pragma unroll
+    for (int r = 0; r < kFinalItems; ++r) {
+      if (v0 + r * stride >= V) continue;
+      const uint32_t d = (uint32_t)(k[r] >> 32);
+      dist[o[r]] = d;
+      if (pred) pred[o[r]] = (int32_t)(uint32_t)(k[r] & 0xffffffffull);
+      if (d != 0xffffffffu) acc += (int64_t)b[r] - a[r];
+    }
   }
   acc = wave_sum(acc);
   if (lane() == 0) s[threadIdx.x / kWave] = acc;
