@@ -24,7 +24,6 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,6 +33,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_1701_01170_amd.rocprof_summary import kernel_source_hash  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {
@@ -62,17 +63,6 @@ def algorithmic_bytes(kind: str, kernel: int, n_f: int, m_f: int, n_next: int) -
     if kind == "bfs" and kernel in (0, 1, 2, 3, 6):
         return 4.0 * m_f + 12.0 * n_f + 12.0 * n_next
     return None
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1701_01170_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode())
-                h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def parse():

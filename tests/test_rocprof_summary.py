@@ -1,0 +1,104 @@
+"""Host logic of the measurement tooling: the rocprofv3 summaries written to
+profiles/ and the kernel-source hash that ties a traffic summary to the
+kernels it was measured on (CPU only, synthetic rocpd databases)."""
+import json
+import os
+import sqlite3
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_1701_01170_amd import rocprof_summary as rs  # noqa: E402
+
+MANGLED_LB = "void gr::(anonymous namespace)::k_push_lb<gr::SsspMark<true>, 4, 1>(int const*)"
+MANGLED_LB_F = "void gr::(anonymous namespace)::k_push_lb<gr::SsspMark<false>, 4, 1>(int const*)"
+MANGLED_LB_32 = "void gr::(anonymous namespace)::k_push_lb<gr::SsspMark<true>, 32, 1>(int const*)"
+COPY = "void gr::(anonymous namespace)::k_copy16(uint4 const*, uint4*, long)"
+
+
+def _kernels_db(path, rows):
+    os.makedirs(path, exist_ok=True)
+    c = sqlite3.connect(os.path.join(path, "run_results.db"))
+    c.execute("create table kernels (name text, duration integer)")
+    c.executemany("insert into kernels values (?, ?)", rows)
+    c.commit()
+    c.close()
+
+
+def _counters_db(path, counter, rows):
+    os.makedirs(path, exist_ok=True)
+    c = sqlite3.connect(os.path.join(path, "run_results.db"))
+    c.execute("create table counters_collection "
+              "(dispatch_id integer, kernel_name text, counter_name text, value real)")
+    c.executemany("insert into counters_collection values (?, ?, ?, ?)",
+                  [(i, n, counter, v) for i, (n, v) in enumerate(rows)])
+    c.commit()
+    c.close()
+
+
+def test_short_name():
+    assert rs.short_name(MANGLED_LB) == "k_push_lb<SsspMark<true>, 4, 1>"
+    assert rs.short_name(COPY) == "k_copy16"
+
+
+def test_stats_counts_durations_and_groups(tmp_path):
+    d = str(tmp_path / "stats")
+    # durations in ns
+    _kernels_db(d, [(MANGLED_LB, 1000), (MANGLED_LB, 3000), (MANGLED_LB_F, 2000),
+                    (MANGLED_LB_32, 10000), (COPY, 4000)])
+    out = str(tmp_path / "k.md")
+    rs.stats(d, out, "cmd", ["tuned=k_push_lb<SsspMark<\\w+>, 4, 1>"])
+    text = open(out).read()
+    assert "Command: `cmd`" in text
+    assert f"Kernel source hash: `{rs.kernel_source_hash()}`" in text
+    # 2 calls, 4.0 us total, 2.00 us average, min 1.00, max 3.00, 4 / 20 of all time
+    assert "| `k_push_lb<SsspMark<true>, 4, 1>` | 2 | 4.0 | 2.00 | 1.00 | 3.00 | 20.0 |" in text
+    # the most expensive kernel is listed first
+    body = [l for l in text.splitlines() if l.startswith("| `")]
+    assert body[0].startswith("| `k_push_lb<SsspMark<true>, 32, 1>`")
+    # the group takes both 4-edge launches of either filter flavour, not the 32-edge one
+    assert "| tuned (`k_push_lb<SsspMark<\\w+>, 4, 1>`) | 3 | 6.0 | 2.00 |" in text
+
+
+def test_traffic_scales_by_the_copy_kernel(tmp_path):
+    copy_bytes = 1 << 20  # 1024 KiB read and written per copy launch
+    fd, wd = str(tmp_path / "f"), str(tmp_path / "w")
+    # FETCH_SIZE reads half the copied bytes (scale 2), WRITE_SIZE all of them (scale 1)
+    _counters_db(fd, "FETCH_SIZE", [(COPY, 512.0), (COPY, 512.0), (MANGLED_LB, 100.0),
+                                    (MANGLED_LB_F, 300.0), (MANGLED_LB_32, 9999.0)])
+    _counters_db(wd, "WRITE_SIZE", [(COPY, 1024.0), (MANGLED_LB, 10.0), (MANGLED_LB_F, 30.0)])
+    out = str(tmp_path / "t.json")
+    rs.traffic(fd, wd, "k_push_lb<SsspMark<\\w+>, 4, 1>", copy_bytes, out, "cmd")
+    j = json.load(open(out))
+    assert j["fetch"]["scale"] == pytest.approx(2.0)
+    assert j["write"]["scale"] == pytest.approx(1.0)
+    assert j["fetch"]["launches"] == 2 and j["write"]["launches"] == 2
+    # per launch: fetch 200 KiB x 2 + write 20 KiB x 1 = 420 KiB
+    assert j["hbm_bytes_per_launch"] == 420 * 1024
+    assert j["kernel_source_hash"] == rs.kernel_source_hash()
+
+
+def test_traffic_needs_the_copy_kernel(tmp_path):
+    fd, wd = str(tmp_path / "f"), str(tmp_path / "w")
+    _counters_db(fd, "FETCH_SIZE", [(MANGLED_LB, 100.0)])
+    _counters_db(wd, "WRITE_SIZE", [(MANGLED_LB, 10.0)])
+    with pytest.raises(RuntimeError):
+        rs.traffic(fd, wd, "k_push_lb", 1 << 20, str(tmp_path / "t.json"), "cmd")
+
+
+def test_kernel_source_hash_tracks_the_sources():
+    h = rs.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    assert rs.kernel_source_hash() == h
+
+
+def test_committed_traffic_summary_names_its_kernel():
+    # the committed summary carries the fields the benchmark reads
+    p = os.path.join(ROOT, "profiles", "traffic_k_push_lb_sssp_rmat22.json")
+    j = json.load(open(p))
+    assert j["hbm_bytes_per_launch"] > 0
+    assert len(j["kernel_source_hash"]) == 16
+    assert "FETCH_SIZE" in j["command"] and "WRITE_SIZE" in j["command"]
