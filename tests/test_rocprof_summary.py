@@ -102,3 +102,20 @@ def test_committed_traffic_summary_names_its_kernel():
     assert j["hbm_bytes_per_launch"] > 0
     assert len(j["kernel_source_hash"]) == 16
     assert "FETCH_SIZE" in j["command"] and "WRITE_SIZE" in j["command"]
+
+
+def test_algorithmic_bytes_per_launch():
+    import bench
+    # SSSP relaxation (any form but the refill): 16 B per edge, 12 B per
+    # frontier vertex, 4 B per output vertex
+    for k in (0, 1, 2, 6, 8, 9, 10):
+        assert bench.algorithmic_bytes("sssp", k, 10, 1000, 7) == 16000 + 120 + 28
+    assert bench.algorithmic_bytes("sssp", 7, 10, 1000, 7) is None
+    # BFS push: 4 B per edge, 12 B per frontier vertex, 12 B per new vertex
+    for k in (0, 1, 2, 3, 6):
+        assert bench.algorithmic_bytes("bfs", k, 10, 1000, 7) == 4000 + 120 + 84
+    # pull levels scan a data-dependent share of the edges: not priced
+    assert bench.algorithmic_bytes("bfs", 4, 10, 1000, 7) is None
+    assert bench.algorithmic_bytes("bfs", 5, 10, 1000, 7) is None
+    # every trace kernel code the library documents has a kernel name
+    assert {k for (_, k) in bench.KERNEL_NAMES} == set(range(11))
