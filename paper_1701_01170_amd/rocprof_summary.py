@@ -10,6 +10,11 @@
       run and a WRITE_SIZE run, each scaled by what the same counter reads for
       the calibration copy kernel (k_copy16, copy_bytes read and copy_bytes
       written per launch)
+  python -m paper_1701_01170_amd.rocprof_summary counters <out.md> "<command>" \
+          <label>=<kernel-regex> <pmc_dir> [<pmc_dir> ...]
+      per-dispatch averages of every counter found in the --pmc runs, over
+      the dispatches of the kernels matching the regex, plus the ratios the
+      kernel analysis uses (wait share of wave cycles, L2 hit rate)
 
 rocprofv3 writes a rocpd SQLite database; only its `kernels` and
 `counters_collection` views are read here.
@@ -112,10 +117,47 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, out: s
     print(json.dumps(j, indent=1))
 
 
+def counters(out: str, command: str, group: str, dirs) -> None:
+    label, rx = group.split("=", 1)
+    vals = {}
+    for d in dirs:
+        c = _db(d)
+        for kn, name, v in c.execute("select kernel_name, counter_name, value from counters_collection"):
+            if re.search(rx, short_name(kn)):
+                vals.setdefault(name, []).append(v)
+    if not vals:
+        raise RuntimeError(f"no dispatches of '{rx}' in {dirs}")
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    lines = ["# rocprofv3 counters", "", f"Command: `{command}`", "",
+             f"Kernel source hash: `{kernel_source_hash()}`", "",
+             f"Kernels: {label} (`{rx}`)", "",
+             "| counter | dispatches | average per dispatch |", "|---|---:|---:|"]
+    for k in sorted(avg):
+        lines.append(f"| `{k}` | {len(vals[k])} | {avg[k]:.6g} |")
+    ratios = []
+    if "SQ_WAIT_ANY" in avg and avg.get("SQ_WAVE_CYCLES"):
+        ratios.append(("waves waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES)",
+                       avg["SQ_WAIT_ANY"] / avg["SQ_WAVE_CYCLES"]))
+    if avg.get("SQ_WAVE_CYCLES") and avg.get("SQ_WAVES"):
+        ratios.append(("average wave lifetime in cycles (SQ_WAVE_CYCLES / SQ_WAVES)",
+                       avg["SQ_WAVE_CYCLES"] / avg["SQ_WAVES"]))
+    if "TCC_HIT_sum" in avg and "TCC_MISS_sum" in avg and avg["TCC_HIT_sum"] + avg["TCC_MISS_sum"] > 0:
+        ratios.append(("L2 hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum))",
+                       avg["TCC_HIT_sum"] / (avg["TCC_HIT_sum"] + avg["TCC_MISS_sum"])))
+    if ratios:
+        lines += ["", "| ratio | value |", "|---|---:|"]
+        lines += [f"| {n} | {v:.4g} |" for n, v in ratios]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
     else:
         raise SystemExit(__doc__)

@@ -119,3 +119,32 @@ def test_algorithmic_bytes_per_launch():
     assert bench.algorithmic_bytes("bfs", 5, 10, 1000, 7) is None
     # every trace kernel code the library documents has a kernel name
     assert {k for (_, k) in bench.KERNEL_NAMES} == set(range(11))
+
+
+def test_counters_averages_and_ratios(tmp_path):
+    a, b = str(tmp_path / "a"), str(tmp_path / "b")
+    os.makedirs(a)
+    c = sqlite3.connect(os.path.join(a, "run_results.db"))
+    c.execute("create table counters_collection "
+              "(dispatch_id integer, kernel_name text, counter_name text, value real)")
+    c.executemany("insert into counters_collection values (?, ?, ?, ?)", [
+        (0, MANGLED_LB, "SQ_WAVE_CYCLES", 100.0), (0, MANGLED_LB, "SQ_WAIT_ANY", 80.0),
+        (0, MANGLED_LB, "SQ_WAVES", 4.0),
+        (1, MANGLED_LB_F, "SQ_WAVE_CYCLES", 300.0), (1, MANGLED_LB_F, "SQ_WAIT_ANY", 280.0),
+        (1, MANGLED_LB_F, "SQ_WAVES", 4.0),
+        (2, COPY, "SQ_WAVE_CYCLES", 5.0), (2, COPY, "SQ_WAIT_ANY", 0.0), (2, COPY, "SQ_WAVES", 1.0)])
+    c.commit()
+    c.close()
+    _counters_db(b, "TCC_HIT_sum", [(MANGLED_LB, 30.0), (COPY, 1.0)])
+    c = sqlite3.connect(os.path.join(b, "run_results.db"))
+    c.execute("insert into counters_collection values (5, ?, 'TCC_MISS_sum', 90.0)", (MANGLED_LB,))
+    c.commit()
+    c.close()
+    out = str(tmp_path / "c.md")
+    rs.counters(out, "cmd", "relax=k_push_lb<SsspMark<\\w+>, 4, 1>", [a, b])
+    text = open(out).read()
+    assert "| `SQ_WAVE_CYCLES` | 2 | 200 |" in text
+    assert "| `SQ_WAIT_ANY` | 2 | 180 |" in text
+    assert "| waves waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) | 0.9 |" in text
+    assert "| average wave lifetime in cycles (SQ_WAVE_CYCLES / SQ_WAVES) | 50 |" in text
+    assert "| L2 hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)) | 0.25 |" in text
