@@ -241,12 +241,16 @@ __device__ __forceinline__ int32_t first_frontier_nbr(bool valid, int32_t rb, in
 // GW = 1: one lane per vertex (dynamic grouping: lists longer than 32 go to
 // the whole wavefront); GW > 1: GW lanes per vertex, GW neighbours per step
 // (lists longer than 64 go to the whole wavefront).
+// The step is a chain of dependent loads (row bounds, neighbour, frontier
+// bit), so resident waves hide its latency: the kernel asks for 8 waves per
+// SIMD (its scalar registers alone would allow 7; the few that spill go to
+// vector-register lanes, not memory).
 constexpr int kPullRuns = 8;
 constexpr int kPullBatch = 4;  // runs whose first neighbours are probed together
 static_assert(kPullRuns % kPullBatch == 0, "whole batches");
 
 template <int GW>
-__global__ __launch_bounds__(256) void k_bfs_pull_bm(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bfs_pull_bm(
     int64_t V, const int32_t* __restrict__ R, const int32_t* __restrict__ C,
     uint32_t* __restrict__ bm, int p, int32_t* __restrict__ depth, int32_t* __restrict__ parent,
     const int32_t* __restrict__ perm, int32_t next_depth, int32_t* __restrict__ out_q,
