@@ -367,6 +367,56 @@ def test_invariants_rmat14(rmat14):
         check_sssp_invariants(g.row_offsets, g.col_indices, g.weights, [int(s)], dist, pred)
 
 
+PROFILE_KEYS = (("n_f", "level_nf"), ("m_f", "level_mf"), ("maxdeg_f", "level_maxdeg"),
+                ("n_u", "level_nu"), ("m_u", "level_mu"))
+
+
+@pytest.mark.parametrize("name", ["directed7.txt", "undirected_ties8.txt"])
+def test_level_profile_golden(name):
+    """Per-level n_f, m_f, largest frontier degree, n_u and m_u (the inputs of
+    the Sec. 5.1 direction switch and of the selector) against values worked
+    out by hand in the fixture; the undirected case keeps two unreachable
+    vertices in the unvisited set to the last level."""
+    fx = load_golden(name)
+    g = golden_graph(fx)
+    for case in fx["bfs"]:
+        d, _ = oracle.bfs(g.row_offsets, g.col_indices, case["source"])
+        prof = oracle.level_profile(g.row_offsets, d)
+        assert [x["level"] for x in prof] == list(range(len(case["level_nf"])))
+        for key, fkey in PROFILE_KEYS:
+            np.testing.assert_array_equal([x[key] for x in prof], case[fkey], err_msg=key)
+
+
+def test_level_profile_path_closed_form():
+    """Path 0-1-...-(n-1) from vertex 0: level d holds vertex d alone (degree
+    1 at the ends, 2 inside); the unvisited vertices d+1..n-1 have degree sum
+    2 (n - 2 - d) + 1 before the last level and 0 at it."""
+    n = 23
+    g = path_graph(n)
+    d, _ = oracle.bfs(g.row_offsets, g.col_indices, 0)
+    prof = oracle.level_profile(g.row_offsets, d)
+    assert len(prof) == n
+    for x in prof:
+        k = x["level"]
+        deg = 1 if k in (0, n - 1) else 2
+        assert (x["n_f"], x["m_f"], x["maxdeg_f"]) == (1, deg, deg)
+        assert x["n_u"] == n - 1 - k
+        assert x["m_u"] == (2 * (n - 2 - k) + 1 if k < n - 1 else 0)
+
+
+def test_level_profile_star_from_leaf_closed_form():
+    """Star with centre 0 and leaves 1..n, BFS from leaf 3: level 0 is the
+    leaf (degree 1), level 1 the centre (degree n), level 2 the other n - 1
+    leaves (degree 1 each); unvisited degree sums 2n - 1, n - 1, 0.  A sum in
+    place of the largest degree would give n - 1 at level 2."""
+    n = 17
+    g = gg.from_edges(n + 1, [(0, i) for i in range(1, n + 1)], symmetric=True)
+    d, _ = oracle.bfs(g.row_offsets, g.col_indices, 3)
+    prof = oracle.level_profile(g.row_offsets, d)
+    got = [(x["n_f"], x["m_f"], x["maxdeg_f"], x["n_u"], x["m_u"]) for x in prof]
+    assert got == [(1, 1, 1, n, 2 * n - 1), (1, n, n, n - 1, n - 1), (n - 1, n - 1, 1, 0, 0)]
+
+
 def test_level_profile_sums(rmat14):
     g = rmat14
     s = int(gg.sources(g, 1, seed=1000)[0])
