@@ -65,6 +65,20 @@ def algorithmic_bytes(kind: str, kernel: int, n_f: int, m_f: int, n_next: int) -
     return None
 
 
+def headline_opts(gr, g, cap: int = 4096):
+    """The timed configuration of the headline step: the heuristic policy with
+    the knobs the autotuner stored for this graph's class and size (paper
+    defaults when none are stored), and per-iteration tracing into host
+    buffers of `cap` records.  Returns (bfs opts, sssp opts, bfs trace,
+    sssp trace); the trace buffers must outlive the opts."""
+    from paper_1701_01170_amd import autotune
+    tb = (gr.LevelTrace * cap)()
+    ts = (gr.LevelTrace * cap)()
+    ob = autotune.tuned_opts(g, "bfs", trace=tb, trace_capacity=cap)
+    os_ = autotune.tuned_opts(g, "sssp", trace=ts, trace_capacity=cap)
+    return ob, os_, tb, ts
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,13 +264,8 @@ def main():
     dist = torch.empty(V, dtype=torch.int32, device=dev)
     pred = torch.empty(V, dtype=torch.int32, device=dev)
     cap = 4096
-    tb = (gr.LevelTrace * cap)()
-    ts = (gr.LevelTrace * cap)()
-    # the heuristic policy with the knobs the autotuner stored for this graph
-    # class and size (paper defaults when none are stored)
     from paper_1701_01170_amd import autotune
-    ob = autotune.tuned_opts(g, "bfs", trace=tb, trace_capacity=cap)
-    os_ = autotune.tuned_opts(g, "sssp", trace=ts, trace_capacity=cap)
+    ob, os_, tb, ts = headline_opts(gr, g, cap)
     knobs = {k: {"bfs": getattr(ob, k), "sssp": getattr(os_, k)} for k in autotune.KNOBS}
     stream = torch.cuda.current_stream()
 

@@ -33,6 +33,10 @@
  *     smallest vertex id, so results are unique and do not depend on the
  *     traversal strategy, the schedule or the thread count.
  *   - A gr_ctx and its graphs must not be used by two host threads at once.
+ *   - Traversals wait for each step's control block with a wall-clock limit
+ *     (60 s, or GR_WAIT_LIMIT_MS from the environment when the context is
+ *     created); past it they return GR_EHIP, and the context must then be
+ *     destroyed, since its stream may still hold the unfinished work.
  */
 #ifndef GR_H
 #define GR_H

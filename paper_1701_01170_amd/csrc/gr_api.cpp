@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -106,11 +108,18 @@ gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st, const MlpSelect* sel
     GR_HIP(launch_frontier_offsets(pre->frontier, 0, pre->R, pre->block_sums, pre->total,
                                    pre->offsets, pre->rstart, pre->chunk_start, pre->chunk, st,
                                    pre->n_f_dev));
+  const auto t0 = std::chrono::steady_clock::now();
   for (uint64_t i = 1;; ++i) {
     if (*ctx->publish_flag == seq) break;
     if ((i & 4095) == 0) {
       const hipError_t e = hipStreamQuery(st);
-      if (e == hipErrorNotReady) continue;
+      if (e == hipErrorNotReady) {
+        if (std::chrono::steady_clock::now() - t0 > ctx->wait_limit)
+          return fail(GR_EHIP, "the device did not publish the control block within " +
+                                   std::to_string(ctx->wait_limit.count()) +
+                                   " ms; the context's stream still holds unfinished work");
+        continue;
+      }
       if (e != hipSuccess) return fail(GR_EHIP, std::string("stream failed: ") + hipGetErrorString(e));
       if (*ctx->publish_flag != seq) return fail(GR_EHIP, "control block was not published");
     }
@@ -182,6 +191,10 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
   gr_ctx* c = new gr_ctx();
   c->device = device;
   c->cu_count = prop.multiProcessorCount;
+  if (const char* w = std::getenv("GR_WAIT_LIMIT_MS")) {
+    const long long ms = std::atoll(w);
+    if (ms > 0) c->wait_limit = std::chrono::milliseconds(ms);
+  }
   // control block mirror + publish flag: coherent, device-mapped pinned memory
   void* hc = nullptr;
   const size_t mirror_bytes = (sizeof(Ctrl) + 255) / 256 * 256 + 256;

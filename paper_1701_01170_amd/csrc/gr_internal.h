@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <vector>
 #include <stdint.h>
 
@@ -114,6 +115,9 @@ struct gr_ctx {
   uint32_t* publish_flag_dev = nullptr;
   uint32_t publish_seq = 0;
   bool policy_loaded = false;
+  // Longest wait for one published control block before a traversal gives up
+  // with GR_EHIP (environment GR_WAIT_LIMIT_MS at context creation, default 60 s).
+  std::chrono::milliseconds wait_limit{60000};
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_a = nullptr, ev_b = nullptr;
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the advance kernel when tracing
 };

@@ -1,8 +1,7 @@
 """Parity at the benchmark's full sizes, with the knobs and launch
 configuration bench.py times: R-MAT scale 22 BFS + SSSP (whole outputs
 against the oracle), the 2048 x 2048 grid, 64-source batched BFS on R-MAT
-scale 20 (whole outputs for a sample of the sources, the edge invariants
-and tree validity for all), and the 256-graph disjoint-union SSSP (every
+scale 20 (every row's whole output against a single-source oracle run), and the 256-graph disjoint-union SSSP (every
 part against a single-source oracle run on that part)."""
 import numpy as np
 import pytest
@@ -61,19 +60,40 @@ def _check_bfs_invariants(R, C, s, depth, parent, n_sample=20_000, chunk=1 << 26
 
 
 def test_rmat22_bfs_sssp_bit_exact(ctx):
+    """The headline step exactly as bench.py times it (its opts constructor,
+    tuned knobs, per-iteration tracing on, bench's first timed sources and
+    preallocated outputs), whole outputs against the oracle; the traced
+    per-level BFS statistics against the oracle's level profile too."""
+    import bench
     hg = gg.add_weights(gg.rmat(22, 16, seed=1), seed=101)
     g = gr.Graph.from_host(ctx, hg, symmetric=True)
-    ob = autotune.tuned_opts(g, "bfs")
-    os_ = autotune.tuned_opts(g, "sssp")
-    for s in gg.sources(hg, 2, seed=1000):
-        d, p, _ = gr.bfs(g, int(s), opts=ob)
-        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
-        np.testing.assert_array_equal(d.cpu().numpy(), ed)
-        np.testing.assert_array_equal(p.cpu().numpy(), ep)
-        dist, pred, _ = gr.sssp(g, [int(s)], opts=os_)
-        edist, epred = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, [int(s)])
-        np.testing.assert_array_equal(dist.cpu().numpy().view(np.uint32), edist)
-        np.testing.assert_array_equal(pred.cpu().numpy(), epred)
+    ob, os_, tb, ts = bench.headline_opts(gr, g)
+    V = hg.n_vertices
+    out_b = (torch.empty(V, dtype=torch.int32, device="cuda"),
+             torch.empty(V, dtype=torch.int32, device="cuda"))
+    out_s = (torch.empty(V, dtype=torch.int32, device="cuda"),
+             torch.empty(V, dtype=torch.int32, device="cuda"))
+    # the first timed source of bench's default run (2 warm-up steps) and of
+    # the driver's run (5 warm-up steps); the source list is prefix-stable
+    srcs = gg.sources(hg, 10 + 2, seed=1000)
+    for s in (int(srcs[2]), int(srcs[5])):
+        d, p, sb = gr.bfs(g, s, opts=ob, out=out_b)
+        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, s)
+        np.testing.assert_array_equal(d.cpu().numpy(), ed, err_msg=f"depth src={s}")
+        np.testing.assert_array_equal(p.cpu().numpy(), ep, err_msg=f"parent src={s}")
+        assert sb["teps_edges"] == oracle.teps_edges(hg.row_offsets, ed >= 0)
+        prof = oracle.level_profile(hg.row_offsets, ed)
+        assert 0 < ob.trace_count == len(prof) <= ob.trace_capacity
+        for t, ref in zip(tb[:ob.trace_count], prof):
+            assert (t.level, t.n_f, t.m_f, t.n_u, t.m_u, t.max_deg_f) == (
+                ref["level"], ref["n_f"], ref["m_f"], ref["n_u"], ref["m_u"], ref["maxdeg_f"])
+        dist, pred, ss = gr.sssp(g, [s], opts=os_, out=out_s)
+        edist, epred = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, [s])
+        np.testing.assert_array_equal(dist.cpu().numpy().view(np.uint32), edist,
+                                      err_msg=f"dist src={s}")
+        np.testing.assert_array_equal(pred.cpu().numpy(), epred, err_msg=f"pred src={s}")
+        assert ss["teps_edges"] == oracle.teps_edges(hg.row_offsets, edist != 0xFFFFFFFF)
+        assert 0 < os_.trace_count <= os_.trace_capacity
     g.free()
 
 
@@ -97,6 +117,7 @@ def test_grid2048_bfs_sssp_bit_exact(ctx):
 
 
 def test_rmat20_64_source_batch(ctx):
+    """All 64 rows of the batch compared whole with single-source oracle runs."""
     hg = gg.rmat(20, 16, seed=1)
     g = gr.Graph.from_host(ctx, hg, symmetric=True)
     srcs = gg.sources(hg, 64, seed=2000).astype(np.int32)
@@ -105,13 +126,10 @@ def test_rmat20_64_source_batch(ctx):
     parent = parent.cpu().numpy()
     teps = 0
     for i, s in enumerate(srcs):
-        if i % 16 == 0:
-            ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
-            np.testing.assert_array_equal(depth[i], ed, err_msg=f"source {i}")
-            np.testing.assert_array_equal(parent[i], ep, err_msg=f"source {i}")
-        else:
-            _check_bfs_invariants(hg.row_offsets, hg.col_indices, int(s), depth[i], parent[i])
-        teps += oracle.teps_edges(hg.row_offsets, depth[i] >= 0)
+        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
+        np.testing.assert_array_equal(depth[i], ed, err_msg=f"source {i}")
+        np.testing.assert_array_equal(parent[i], ep, err_msg=f"source {i}")
+        teps += oracle.teps_edges(hg.row_offsets, ed >= 0)
     assert st["teps_edges"] == teps
     g.free()
 
@@ -156,21 +174,18 @@ def _check_sssp_invariants(R, C, W, s, dist, pred, n_sample=20_000, chunk=1 << 2
 
 def test_rmat25_batched_sampled(ctx):
     """The largest workload (R-MAT scale 25, ~1.05e9 directed edges) with the
-    scale-25 run's configuration: the 16-source batch compared whole against
-    the oracle for its first source and by the BFS invariants for four more;
+    scale-25 run's configuration: rows 0, 3, 7, 9 and 15 of the 16-source batch
+    compared whole against single-source oracle runs;
     one SSSP checked by the distance and predecessor invariants."""
     hg = gg.add_weights(gg.rmat(25, 16, seed=1), seed=101)
     g = gr.Graph.from_host(ctx, hg, symmetric=True)
     srcs = gg.sources(hg, 16, seed=1000).astype(np.int32)
     depth, parent, _ = gr.bfs_multi(g, srcs, opts=autotune.tuned_opts(g, "bfs_multi"))
-    ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(srcs[0]))
-    np.testing.assert_array_equal(depth[0].cpu().numpy(), ed)
-    np.testing.assert_array_equal(parent[0].cpu().numpy(), ep)
-    del ed, ep
-    for i in (9,):
-        _check_bfs_invariants(hg.row_offsets, hg.col_indices, int(srcs[i]), depth[i].cpu().numpy(),
-                              parent[i].cpu().numpy())
-    del depth, parent
+    for i in (0, 3, 7, 9, 15):
+        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(srcs[i]))
+        np.testing.assert_array_equal(depth[i].cpu().numpy(), ed, err_msg=f"source {i}")
+        np.testing.assert_array_equal(parent[i].cpu().numpy(), ep, err_msg=f"source {i}")
+    del ed, ep, depth, parent
     dist, pred, _ = gr.sssp(g, [int(srcs[5])], opts=autotune.tuned_opts(g, "sssp"))
     _check_sssp_invariants(hg.row_offsets, hg.col_indices, hg.weights, int(srcs[5]),
                            dist.cpu().numpy().view(np.uint32), pred.cpu().numpy())

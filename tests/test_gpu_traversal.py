@@ -286,7 +286,10 @@ def test_trace_records(ctx, rmat14, dme):
     cap = 64
     buf = (gr.LevelTrace * cap)()
     o = gr.default_opts(trace=buf, trace_capacity=cap, device_max_edges=dme)
-    gr.bfs(g, s, opts=o)
+    d, p, _ = gr.bfs(g, s, opts=o)
+    _, ep = oracle.bfs(rmat14.row_offsets, rmat14.col_indices, s)
+    np.testing.assert_array_equal(np_of(d), ed)
+    np.testing.assert_array_equal(np_of(p), ep)
     assert o.trace_count == len(prof)
     for t, ref in zip(buf[:o.trace_count], prof):
         assert (t.level, t.n_f, t.m_f, t.n_u, t.m_u, t.max_deg_f) == (
@@ -294,6 +297,26 @@ def test_trace_records(ctx, rmat14, dme):
         assert t.step_us > 0
     kernels = {t.kernel for t in buf[:o.trace_count]}
     assert (6 in kernels) == (dme != -1), kernels
+
+
+@pytest.mark.parametrize("delta", [0, 16])
+@pytest.mark.parametrize("dme", [0, -1])
+def test_traced_sssp_outputs(ctx, rmat14, dme, delta):
+    """Tracing takes its own paths (event records around every advance
+    kernel, the block logs of device-predicated levels copied back); the
+    traced SSSP must still match the oracle element by element."""
+    g = gr.Graph.from_host(ctx, rmat14)
+    cap = 256
+    buf = (gr.LevelTrace * cap)()
+    for s in gg.sources(rmat14, 2, seed=1000):
+        o = gr.default_opts(trace=buf, trace_capacity=cap, device_max_edges=dme, sssp_delta=delta)
+        d, p, st = gr.sssp(g, [int(s)], opts=o)
+        ed, ep = oracle.sssp(rmat14.row_offsets, rmat14.col_indices, rmat14.weights, [int(s)])
+        np.testing.assert_array_equal(np_of(d).view(np.uint32), ed)
+        np.testing.assert_array_equal(np_of(p), ep)
+        assert 0 < o.trace_count <= cap
+        assert all(t.step_us > 0 for t in buf[:o.trace_count])
+    g.free()
 
 
 @pytest.mark.parametrize("max_it", [1, 3, 4, 37, 100])
