@@ -106,8 +106,14 @@ typedef struct gr_level_trace {
                           left), 6 device-predicated step (step_us and
                           kernel_us are then the block's time divided by its levels),
                           7 SSSP priority-queue refill (far pile split), 8 / 9 / 10 SSSP
-                          TWC / LB_LIGHT / LB relaxation with the byte-mark filter */
+                          TWC / LB_LIGHT / LB relaxation with the byte-mark filter,
+                          11 BFS pull over the list of still-unvisited vertices the
+                          previous pull level left (else 4 / 5 pull over the bitmap) */
   int64_t n_next;      /* size of the output frontier */
+  int64_t n_in;        /* vertices the advance read as input: push the frontier (n_f),
+                          pull over the bitmap the unvisited vertices (n_u), pull over
+                          the list its entries, refill the far-pile entries */
+  int64_t inspected;   /* edges the advance read: push m_f, pull the neighbours scanned */
 } gr_level_trace;
 
 typedef struct gr_opts {

@@ -47,7 +47,8 @@ class LevelTrace(ctypes.Structure):
                 ("n_f", ctypes.c_int64), ("m_f", ctypes.c_int64), ("n_u", ctypes.c_int64),
                 ("m_u", ctypes.c_int64), ("max_deg_f", ctypes.c_int64),
                 ("features", ctypes.c_float * 8), ("step_us", ctypes.c_float),
-                ("kernel_us", ctypes.c_float), ("kernel", ctypes.c_int32), ("n_next", ctypes.c_int64)]
+                ("kernel_us", ctypes.c_float), ("kernel", ctypes.c_int32), ("n_next", ctypes.c_int64),
+                ("n_in", ctypes.c_int64), ("inspected", ctypes.c_int64)]
 
 
 class Opts(ctypes.Structure):

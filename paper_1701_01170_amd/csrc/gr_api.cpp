@@ -75,6 +75,34 @@ gr_status pool_typed(gr_ctx* ctx, Slot s, size_t count, T** out) {
   return GR_OK;
 }
 
+// Where a traversal takes its working arrays: the context's pool (grown on
+// demand), or a fixed device region carved front to back in 256-byte aligned
+// pieces (no allocation; asking for more than the region holds is GR_ERANGE).
+// A slot asked for twice gets the same memory both times.
+struct Arena {
+  gr_ctx* ctx = nullptr;
+  char* base = nullptr;  // fixed region (null: the pool)
+  size_t cap = 0;
+  size_t used = 0;
+  void* got[S_NSLOTS] = {};
+
+  template <typename T>
+  gr_status get(Slot s, size_t count, T** out) {
+    if (!base) return pool_typed(ctx, s, count, out);
+    if (!got[s]) {
+      const size_t off = (used + 255) / 256 * 256;
+      const size_t bytes = std::max<size_t>(count * sizeof(T), 1);
+      if (off + bytes > cap)
+        return fail(GR_ERANGE, "working arrays need more than the " + std::to_string(cap) +
+                                   " bytes of the static device workspace");
+      got[s] = base + off;
+      used = off + bytes;
+    }
+    *out = static_cast<T*>(got[s]);
+    return GR_OK;
+  }
+};
+
 // The control block after all work queued so far: a publishing kernel copies
 // it to host memory and then bumps a sequence number, which the host polls;
 // every 4096 polls the stream status is checked, so a failed launch or a
@@ -500,8 +528,16 @@ gr_status elapsed_ms(hipEvent_t a, hipEvent_t b, float* ms) {
 }
 
 // Trace record of one iteration with the given step and kernel times.
+// Work of one iteration's advance, for its trace record: input vertices read
+// (push: the frontier; pull: the unvisited vertices or list entries scanned)
+// and edges read (push: m_f; pull: neighbours scanned).
+struct StepWork {
+  int64_t n_in;
+  int64_t inspected;
+};
+
 gr_status record_trace_times(gr_opts* opts, const LevelFeatures& lf, int action, int kernel,
-                             int64_t n_next, float step_ms, float kernel_ms) {
+                             int64_t n_next, float step_ms, float kernel_ms, StepWork w) {
   if (!opts || !opts->trace) return GR_OK;
   int i = opts->trace_count++;
   if (i >= opts->trace_capacity) return GR_OK;
@@ -518,13 +554,15 @@ gr_status record_trace_times(gr_opts* opts, const LevelFeatures& lf, int action,
   t.kernel_us = kernel_ms * 1000.0f;
   t.kernel = kernel;
   t.n_next = n_next;
+  t.n_in = w.n_in;
+  t.inspected = w.inspected;
   return GR_OK;
 }
 
 // Event-timed record of one iteration: ev_a..ev_b brackets the whole step,
 // ev_k0..ev_k1 the advance kernel alone.
 gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int action,
-                       int kernel, int64_t n_next) {
+                       int kernel, int64_t n_next, StepWork w) {
   if (!opts || !opts->trace || opts->trace_count >= opts->trace_capacity) {
     if (opts && opts->trace) opts->trace_count++;
     return GR_OK;
@@ -532,7 +570,7 @@ gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int 
   float step_ms = 0.f, kernel_ms = 0.f;
   GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &step_ms));
   GR_TRY(elapsed_ms(ctx->ev_k0, ctx->ev_k1, &kernel_ms));
-  return record_trace_times(opts, lf, action, kernel, n_next, step_ms, kernel_ms);
+  return record_trace_times(opts, lf, action, kernel, n_next, step_ms, kernel_ms, w);
 }
 
 // ---- iteration control: device-predicated blocks of push levels ----------
@@ -540,6 +578,7 @@ constexpr int kDlFirstLen = 4;              // levels in the first block (then a
 constexpr int64_t kDlDefaultMaxEdges = 1 << 18;
 constexpr int kTraceKernelDstep = 6;
 constexpr int kTraceKernelRefill = 7;
+constexpr int kTraceKernelPullList = 11;
 constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filter: 8 + (0 TWC, 1 LB_LIGHT, 2 LB)
 // SSSP iterations whose frontier has at least V / kSsspMarksDivisor edges use
 // the byte-mark filter.
@@ -561,8 +600,8 @@ struct DlPlan {
   int64_t* log = nullptr;
 };
 
-gr_status dl_plan(gr_ctx* ctx, const gr_opts& o, bool pull_ok, bool learned, bool tracing,
-                  DlPlan* d) {
+gr_status dl_plan(gr_ctx* ctx, Arena& ar, const gr_opts& o, bool pull_ok, bool learned,
+                  bool tracing, DlPlan* d) {
   const bool heuristic = o.policy == GR_POLICY_HEURISTIC ||
                          (o.policy == GR_POLICY_LEARNED && !learned);
   d->on = o.device_max_edges >= 0 && (heuristic || learned || o.policy == GR_POLICY_FIXED);
@@ -572,7 +611,7 @@ gr_status dl_plan(gr_ctx* ctx, const gr_opts& o, bool pull_ok, bool learned, boo
   d->len = kDlFirstLen;
   d->blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
   d->log = nullptr;
-  if (d->on && tracing) GR_TRY(pool_typed(ctx, S_DLOG, 3 * kDlMaxLevels, &d->log));
+  if (d->on && tracing) GR_TRY(ar.get(S_DLOG, 3 * kDlMaxLevels, &d->log));
   return GR_OK;
 }
 
@@ -598,9 +637,12 @@ constexpr int64_t kMarksFilterDivisor = 4;
 constexpr int64_t kPullListDivisor = 16;
 
 // The byte-mark buffer is all zero between uses (the compaction clears what it
-// reads); a fresh allocation is cleared once here.
-gr_status marks_buffer(gr_ctx* ctx, int64_t V, uint8_t** out, hipStream_t st) {
+// reads); a fresh allocation is cleared once here.  A fixed arena's marks are
+// cleared at the start of every call instead (see bfs_run), since the region
+// keeps whatever an earlier call, possibly a failed one, left there.
+gr_status marks_buffer(gr_ctx* ctx, Arena& ar, int64_t V, uint8_t** out, hipStream_t st) {
   const size_t bytes = (size_t)((V + 31) / 32) * 32;
+  if (ar.base) return ar.get(S_MARKS, bytes, out);
   const bool fresh = ctx->pool[S_MARKS].bytes < bytes;
   void* p = nullptr;
   GR_TRY(pool_get(ctx, S_MARKS, bytes, &p));
@@ -611,18 +653,23 @@ gr_status marks_buffer(gr_ctx* ctx, int64_t V, uint8_t** out, hipStream_t st) {
 }
 }  // namespace
 
-extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth,
-                            int32_t* parent, gr_opts* opts_in, void* stream, gr_run_stats* stats) {
-  if (!ctx || !g) return fail(GR_EINVAL, "gr_bfs: ctx or graph is NULL");
-  if (g->ctx != ctx) return fail(GR_EINVAL, "gr_bfs: graph belongs to another context");
-  if (!depth) return fail(GR_EINVAL, "gr_bfs: depth is NULL");
+namespace {
+gr_status bfs_check(const char* who, gr_ctx* ctx, const gr_graph* g, int32_t source,
+                    const int32_t* depth) {
+  const std::string w(who);
+  if (!ctx || !g) return fail(GR_EINVAL, w + ": ctx or graph is NULL");
+  if (g->ctx != ctx) return fail(GR_EINVAL, w + ": graph belongs to another context");
+  if (!depth) return fail(GR_EINVAL, w + ": depth is NULL");
   if (source < 0 || (int64_t)source >= g->V)
-    return fail(GR_EINVAL, "gr_bfs: source " + std::to_string(source) + " out of range");
-  gr_opts opts;
-  GR_TRY(check_opts(opts_in, &opts));
-  if (opts_in) opts_in->trace_count = 0;
-  DeviceGuard dg(ctx->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
+    return fail(GR_EINVAL, w + ": source " + std::to_string(source) + " out of range");
+  return GR_OK;
+}
+
+// The BFS enactor; its working arrays come from `ar` (arguments checked by
+// the caller, device current).
+gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth, int32_t* parent,
+                  gr_opts* opts_in, const gr_opts& opts, hipStream_t st, gr_run_stats* stats,
+                  Arena& ar) {
   const int64_t V = g->V, E = g->E, NW = words_for(V);
   const bool pull_ok = (g->flags & GR_SYMMETRIC) != 0;
   const int G = stats_grid();
@@ -632,15 +679,21 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   int32_t *qA, *qB, *qC, *offsets, *rstart, *chunks;
   int64_t* bsums;
   Ctrl* ctrl;
-  GR_TRY(pool_typed(ctx, S_BM, 2 * NW, &bm));
-  GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
-  GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
-  GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
-  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
-  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
-  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
-  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, G + 1, &bsums));
-  GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
+  GR_TRY(ar.get(S_BM, 2 * NW, &bm));
+  GR_TRY(ar.get(S_Q_A, V, &qA));
+  GR_TRY(ar.get(S_Q_B, V, &qB));
+  GR_TRY(ar.get(S_Q_C, V, &qC));
+  GR_TRY(ar.get(S_OFFSETS, V + 1, &offsets));
+  GR_TRY(ar.get(S_RSTART, V, &rstart));
+  GR_TRY(ar.get(S_CHUNKS, E / 512 + 2, &chunks));
+  GR_TRY(ar.get(S_BLOCK_SUMS, G + 1, &bsums));
+  GR_TRY(ar.get(S_CTRL, 1, &ctrl));
+  if (ar.base) {
+    // the fixed region keeps the last call's contents: start from zero marks
+    uint8_t* marks;
+    GR_TRY(marks_buffer(ctx, ar, V, &marks, st));
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(marks), (V + 31) / 32 * 8, 0u, st));
+  }
   Ctrl* hc = ctx->host_ctrl;
   // a renumbered graph traverses into internal arrays indexed by the new
   // ids (parent values are caller ids already) and scatters them at the end
@@ -648,8 +701,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   int32_t* out_depth = depth;
   int32_t* out_parent = parent;
   if (perm) {
-    GR_TRY(pool_typed(ctx, S_DEPTH, V, &depth));
-    if (parent) GR_TRY(pool_typed(ctx, S_PARENT, V, &parent));
+    GR_TRY(ar.get(S_DEPTH, V, &depth));
+    if (parent) GR_TRY(ar.get(S_PARENT, V, &parent));
   }
   const int32_t src = g->to_new(source);
 
@@ -658,8 +711,8 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   // vertices the previous pull level left (two lists, ping-pong)
   int32_t* ul[2] = {nullptr, nullptr};
   if (pull_ok) {
-    GR_TRY(pool_typed(ctx, S_UL_A, V, &ul[0]));
-    GR_TRY(pool_typed(ctx, S_UL_B, V, &ul[1]));
+    GR_TRY(ar.get(S_UL_A, V, &ul[0]));
+    GR_TRY(ar.get(S_UL_B, V, &ul[1]));
   }
   int ulc = 0;            // the list the next pull level reads
   bool list_ok = false;   // it holds every unvisited vertex with neighbours
@@ -688,11 +741,13 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], max_deg = hc->max_deg[sp];
   int64_t visited_n = n_f, visited_m = m_f;
   int64_t inspected_push = 0;
+  int64_t pull_in = 0;     // input vertices of the last pull level (trace)
+  int64_t pull_seen = 0;   // the device's pull neighbour count before this level
   int level = 0;
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
-  GR_TRY(dl_plan(ctx, opts, pull_ok, learned, tracing, &dl));
+  GR_TRY(dl_plan(ctx, ar, opts, pull_ok, learned, tracing, &dl));
 
   while (n_f > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
     lf.level = level;
@@ -768,7 +823,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
             if (i > 0) li.prev_pull = 0;
             const int64_t nn = i + 1 < k ? lg[3 * (i + 1)] : (int64_t)hc->n_f[sp];
             GR_TRY(record_trace_times(opts_in, li, action, kTraceKernelDstep, nn, block_ms / k,
-                                      block_ms / k));
+                                      block_ms / k, StepWork{li.n_f, li.m_f}));
           }
         }
         n_f = hc->n_f[sp];
@@ -790,7 +845,7 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       const bool atomic_parent = parent && (!pull_ok || m_f <= kAtomicParentMaxEdges);
       if (!atomic_parent && m_f >= V / kMarksFilterDivisor) {
         uint8_t* marks;
-        GR_TRY(marks_buffer(ctx, V, &marks, st));
+        GR_TRY(marks_buffer(ctx, ar, V, &marks, st));
         kernel = mode == 2 ? 3 : mode;
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
@@ -813,10 +868,15 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
       inspected_push += m_f;
     } else {
       kernel = action == GR_PULL_LB ? 5 : 4;
+      pull_in = lf.n_u;
       // every pull lists the vertices it leaves unvisited, and the next pull
       // level reads that list instead of the bitmap once it is short
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
-      if (list_ok && list_n <= V / kPullListDivisor)
+      if (list_ok && list_n <= V / kPullListDivisor) {
+        kernel = kTraceKernelPullList;
+        pull_in = list_n;
+      }
+      if (kernel == kTraceKernelPullList)
         GR_HIP(launch_bfs_pull_list(ul[ulc], &ctrl->ul_count[ulc], list_n, g->R, g->C, bm, p,
                                     depth, parent, perm, next_depth, q[(cur + 1) % 3],
                                     &ctrl->q_count[(cur + 1) % 3], &ctrl->inspected, ul[ulc ^ 1],
@@ -842,7 +902,13 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     msel = select_at(sp, V - visited_n, E - visited_m, sel.mode_pull ? 1 : 0);
     GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
     list_n = hc->ul_count[ulc];
-    if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
+    if (tracing) {
+      const bool pulled = kernel >= 4;
+      const StepWork w{pulled ? pull_in : n_f,
+                       pulled ? (int64_t)hc->inspected - pull_seen : m_f};
+      GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp], w));
+    }
+    pull_seen = hc->inspected;
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
     max_deg = hc->max_deg[sp];
@@ -863,6 +929,21 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
     *stats = rs;
   }
   return GR_OK;
+}
+
+}  // namespace
+
+extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth,
+                            int32_t* parent, gr_opts* opts_in, void* stream, gr_run_stats* stats) {
+  GR_TRY(bfs_check("gr_bfs", ctx, g, source, depth));
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  DeviceGuard dg(ctx->device);
+  Arena ar;
+  ar.ctx = ctx;
+  return bfs_run(ctx, g, source, depth, parent, opts_in, opts, static_cast<hipStream_t>(stream),
+                 stats, ar);
 }
 
 // ============================================================================
@@ -962,7 +1043,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   gr_run_stats rs{};
   const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
-  GR_TRY(dl_plan(ctx, opts, /*pull_ok=*/false, learned, tracing, &dl));
+  Arena ar;
+  ar.ctx = ctx;
+  GR_TRY(dl_plan(ctx, ar, opts, /*pull_ok=*/false, learned, tracing, &dl));
   // after a step that produced the frontier in q[cur]: statistics, selector, read-back
   // with load-balanced advance likely (average degree), the degree scan of
   // each new frontier is queued ahead of the read-back (offsets_ready)
@@ -1044,7 +1127,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
             li.max_deg_f = lg[3 * i + 2];
             const int64_t nn = i + 1 < k ? lg[3 * (i + 1)] : (int64_t)hc->n_f[sp];
             GR_TRY(record_trace_times(opts_in, li, action, kTraceKernelDstep, nn, block_ms / k,
-                                      block_ms / k));
+                                      block_ms / k, StepWork{li.n_f, li.m_f}));
           }
         }
         n_f = hc->n_f[sp];
@@ -1055,6 +1138,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     }
     if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
     int kernel = kTraceKernelRefill;
+    const int64_t refill_in = far_n;
     if (n_f == 0) {
       // priority queue: the near frontier ran dry, raise the threshold and
       // split the far pile
@@ -1078,7 +1162,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         // vertices whose distance dropped (byte marks); with the priority
         // queue the list is split into the next frontier and the far pile
         uint8_t* marks;
-        GR_TRY(marks_buffer(ctx, V, &marks, st));
+        GR_TRY(marks_buffer(ctx, ar, V, &marks, st));
         kernel += kTraceMarksOffset;
         const bool screen = expanded + n_f + far_n >= V / kSsspMirrorDivisor;
         GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
@@ -1110,7 +1194,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     sp ^= 1;
     ++it;
     GR_TRY(next_frontier());
-    if (tracing) GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp]));
+    if (tracing)
+      GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp],
+                          kernel == kTraceKernelRefill ? StepWork{refill_in, 0} : StepWork{n_f, m_f}));
     n_f = hc->n_f[sp];
     m_f = hc->m_f[sp];
     max_deg = hc->max_deg[sp];

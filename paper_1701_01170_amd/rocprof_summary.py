@@ -6,10 +6,13 @@
       each label=regex adds a line for all kernels whose name matches
   python -m paper_1701_01170_amd.rocprof_summary traffic <fetch_dir> <write_dir> <kernel-regex> \
           <copy_bytes> <out.json> "<command>"
-      HBM bytes per launch of the kernels matching the regex, from a FETCH_SIZE
-      run and a WRITE_SIZE run, each scaled by what the same counter reads for
-      the calibration copy kernel (k_copy16, copy_bytes read and copy_bytes
-      written per launch)
+      bytes per launch that the kernels matching the regex move between the
+      L2 caches and the memory fabric, from a FETCH_SIZE run and a WRITE_SIZE
+      run, each scaled by what the same counter reads for the calibration copy
+      kernel (k_copy16, copy_bytes read and copy_bytes written per launch).
+      These counters sit at the L2's fabric side: reads the Infinity Cache
+      serves count too, so the figure bounds HBM traffic from above; for a
+      streaming kernel the two agree, for a random gather they need not.
   python -m paper_1701_01170_amd.rocprof_summary counters <out.md> "<command>" \
           <label>=<kernel-regex> <pmc_dir> [<pmc_dir> ...]
       per-dispatch averages of every counter found in the --pmc runs, over
@@ -108,10 +111,15 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, out: s
         scale = (copy_bytes / 1024.0) / (sum(copy) / len(copy))
         res[label] = dict(kib_per_launch=sum(kern) / len(kern), launches=len(kern),
                           copy_kib_per_launch=sum(copy) / len(copy), scale=scale)
-    hbm = 1024.0 * (res["fetch"]["kib_per_launch"] * res["fetch"]["scale"]
-                    + res["write"]["kib_per_launch"] * res["write"]["scale"])
+    fabric = 1024.0 * (res["fetch"]["kib_per_launch"] * res["fetch"]["scale"]
+                       + res["write"]["kib_per_launch"] * res["write"]["scale"])
+    raw = 1024.0 * (res["fetch"]["kib_per_launch"] + res["write"]["kib_per_launch"])
     j = dict(kernel=kernel, command=command, kernel_source_hash=kernel_source_hash(),
-             fetch=res["fetch"], write=res["write"], hbm_bytes_per_launch=round(hbm))
+             fetch=res["fetch"], write=res["write"],
+             l2_fabric_bytes_per_launch=round(fabric), unscaled_bytes_per_launch=round(raw),
+             meaning="L2 <-> fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by "
+                     "its reading for the copy kernel); Infinity Cache hits included, so an "
+                     "upper bound of HBM bytes")
     with open(out, "w") as f:
         json.dump(j, f, indent=1)
     print(json.dumps(j, indent=1))

@@ -77,7 +77,10 @@ def test_traffic_scales_by_the_copy_kernel(tmp_path):
     assert j["write"]["scale"] == pytest.approx(1.0)
     assert j["fetch"]["launches"] == 2 and j["write"]["launches"] == 2
     # per launch: fetch 200 KiB x 2 + write 20 KiB x 1 = 420 KiB
-    assert j["hbm_bytes_per_launch"] == 420 * 1024
+    assert j["l2_fabric_bytes_per_launch"] == 420 * 1024
+    # unscaled: fetch 200 KiB + write 20 KiB
+    assert j["unscaled_bytes_per_launch"] == 220 * 1024
+    assert "upper bound" in j["meaning"]
     assert j["kernel_source_hash"] == rs.kernel_source_hash()
 
 
@@ -99,7 +102,7 @@ def test_committed_traffic_summary_names_its_kernel():
     # the committed summary carries the fields the benchmark reads
     p = os.path.join(ROOT, "profiles", "traffic_k_push_lb_sssp_rmat22.json")
     j = json.load(open(p))
-    assert j["hbm_bytes_per_launch"] > 0
+    assert j["l2_fabric_bytes_per_launch"] > 0
     assert len(j["kernel_source_hash"]) == 16
     assert "FETCH_SIZE" in j["command"] and "WRITE_SIZE" in j["command"]
 
@@ -110,15 +113,41 @@ def test_algorithmic_bytes_per_launch():
     # frontier vertex, 4 B per output vertex
     for k in (0, 1, 2, 6, 8, 9, 10):
         assert bench.algorithmic_bytes("sssp", k, 10, 1000, 7) == 16000 + 120 + 28
-    assert bench.algorithmic_bytes("sssp", 7, 10, 1000, 7) is None
+    # priority-queue refill: 16 B per far-pile entry read
+    assert bench.algorithmic_bytes("sssp", 7, 0, 0, 7, n_in=50) == 800
     # BFS push: 4 B per edge, 12 B per frontier vertex, 12 B per new vertex
     for k in (0, 1, 2, 3, 6):
         assert bench.algorithmic_bytes("bfs", k, 10, 1000, 7) == 4000 + 120 + 84
-    # pull levels scan a data-dependent share of the edges: not priced
-    assert bench.algorithmic_bytes("bfs", 4, 10, 1000, 7) is None
-    assert bench.algorithmic_bytes("bfs", 5, 10, 1000, 7) is None
+    # pull over the bitmap: V / 4 bitmap bytes, 8 B per unvisited vertex,
+    # 4 B per neighbour scanned, 12 B per vertex found
+    for k in (4, 5):
+        assert bench.algorithmic_bytes("bfs", k, 10, 1000, 7, n_in=300, inspected=900,
+                                       V=4096) == 1024 + 2400 + 3600 + 84
+    # pull over the list: 12 B per entry, 4 B per neighbour scanned, 12 B per hit
+    assert bench.algorithmic_bytes("bfs", 11, 10, 1000, 7, n_in=300, inspected=900,
+                                   V=4096) == 3600 + 3600 + 84
     # every trace kernel code the library documents has a kernel name
-    assert {k for (_, k) in bench.KERNEL_NAMES} == set(range(11))
+    assert {k for (_, k) in bench.KERNEL_NAMES} == set(range(12))
+
+
+def test_accumulate_and_roofline():
+    import bench
+
+    class T:
+        def __init__(self, kernel, n_f, m_f, n_next, n_in, inspected, us):
+            self.kernel, self.n_f, self.m_f, self.n_next = kernel, n_f, m_f, n_next
+            self.n_in, self.inspected, self.kernel_us = n_in, inspected, us
+
+    pk = {}
+    buf = [T(2, 10, 1000, 7, 10, 1000, 2.0), T(4, 0, 0, 5, 100, 40, 1.0), T(2, 1, 10, 0, 1, 10, 2.0)]
+    tot = bench.accumulate(pk, "bfs", buf, 3, 64)
+    assert pk[("bfs", 2)] == [2, 4.0, (4000 + 120 + 84) + (40 + 12)]
+    assert pk[("bfs", 4)] == [1, 1.0, 16 + 800 + 160 + 60]
+    assert tot == 4204 + 52 + 1036
+    r = bench.roofline_of(pk, ("bfs", 2))
+    assert r["kernel"] == "k_push_lb<BfsVisit>" and r["launches"] == 2
+    assert r["achieved"] == round(4256 / 4e-6 / 1e9, 1) and r["peak"] == 8000.0
+    assert r["frac"] == round(4256 / 4e-6 / 1e9 / 8000.0, 4)
 
 
 def test_counters_averages_and_ratios(tmp_path):
