@@ -227,6 +227,23 @@ gr_status gr_graph_export(const gr_graph* graph, int32_t* row_offsets, int32_t* 
 gr_status gr_bfs(gr_ctx* ctx, const gr_graph* graph, int32_t source, int32_t* depth,
                  int32_t* parent, gr_opts* opts, void* stream, gr_run_stats* stats);
 
+/* gr_bfs for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, results and statistics as gr_bfs, but every working array (visited
+ * bitmaps, frontier queues, degree scan, unvisited lists, byte marks, control
+ * block) is carved from a static device workspace of
+ * GR_STATIC_WORKSPACE_BYTES that the library holds on each device it runs on
+ * until the process ends; the call makes no hipMalloc / hipFree and no other
+ * allocating call.  Its address is looked up when the context is created.
+ * The workspace needs about 29.25 * V + E / 128 bytes (plus 8 * V for a
+ * GR_RENUMBER graph): a graph that does not fit is rejected with GR_ERANGE
+ * before any device work.  The workspace keeps the last call's contents and
+ * is shared by every call on the device (all contexts, gr_bfs_static only):
+ * calls that overlap on one device race and give undefined results. */
+#define GR_STATIC_WORKSPACE_BYTES (64ll << 20)
+gr_status gr_bfs_static(gr_ctx* ctx, const gr_graph* graph, int32_t source, int32_t* depth,
+                        int32_t* parent, gr_opts* opts, void* stream, gr_run_stats* stats);
+
 /* Shortest paths from n_sources host-given sources (Sec. 6.2, Alg. 1:
  * advance with atomic-min relaxation, filter removing redundant vertices).
  * dist: device uint32[V] (required) = least summed weight from any source;

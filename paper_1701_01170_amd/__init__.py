@@ -100,6 +100,8 @@ _SIGNATURES = {
     "gr_graph_export": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "gr_bfs": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
                               ctypes.POINTER(RunStats)]),
+    "gr_bfs_static": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
+                                     ctypes.POINTER(RunStats)]),
     "gr_sssp": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
                                ctypes.POINTER(RunStats)]),
     "gr_bfs_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
@@ -294,6 +296,20 @@ def bfs(g: Graph, source: int, want_parent: bool = True, opts: Opts | None = Non
     check(lib().gr_bfs(g.ctx.handle, g.handle, int(source), _ptr(depth), _ptr(parent),
                        _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
     return depth, parent, st.as_dict()
+
+
+def bfs_static(g: Graph, source: int, out, opts: Opts | None = None, stream=None):
+    """gr_bfs_static: BFS whose working arrays live in the library's static
+    device workspace (no allocation inside the call).  `out` = (depth,
+    parent or None), caller-allocated int32[V] tensors.  Returns stats."""
+    depth, parent = out
+    st = RunStats()
+    check(lib().gr_bfs_static(g.ctx.handle, g.handle, int(source), _ptr(depth), _ptr(parent),
+                              _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
+    return st.as_dict()
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def sssp(g: Graph, sources, want_pred: bool = True, opts: Opts | None = None, stream=None,

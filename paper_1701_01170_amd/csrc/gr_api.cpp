@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,36 @@ gr_status fail(gr_status code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+
+// The static workspace of gr_bfs_static: one copy per device, held from the
+// time the library's code is loaded on that device until the process ends.
+// Host code never takes its address directly (in host code the name stands for
+// a host-side shadow, not device memory); it uses the device address looked up
+// with hipGetSymbolAddress, which ws_address keeps per device.
+static __device__ __align__(256) char scratch[GR_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_ws_mutex;
+void* g_ws_addr[kMaxDevices] = {};
+
+// The device address of `device`'s workspace (the device must be current).
+gr_status ws_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(GR_EUNSUPPORTED, "static workspace: device index " + std::to_string(device) +
+                                     " beyond the library's table");
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  if (!g_ws_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_ws_addr[device] = p;
+  }
+  *out = g_ws_addr[device];
+  return GR_OK;
+}
+}  // namespace
 
 gr_status pool_get(gr_ctx* ctx, Slot s, size_t bytes, void** out) {
   DevBuf& b = ctx->pool[s];
@@ -78,27 +109,38 @@ gr_status pool_typed(gr_ctx* ctx, Slot s, size_t count, T** out) {
 // Where a traversal takes its working arrays: the context's pool (grown on
 // demand), or a fixed device region carved front to back in 256-byte aligned
 // pieces (no allocation; asking for more than the region holds is GR_ERANGE).
-// A slot asked for twice gets the same memory both times.
+// A slot asked for twice gets the same memory both times (a second request
+// larger than the first is an error).  A measuring arena only adds up the
+// bytes a fixed region would need and hands out null pointers.
 struct Arena {
   gr_ctx* ctx = nullptr;
   char* base = nullptr;  // fixed region (null: the pool)
   size_t cap = 0;
   size_t used = 0;
-  void* got[S_NSLOTS] = {};
+  bool measure = false;
+  bool taken[S_NSLOTS] = {};
+  size_t off_of[S_NSLOTS] = {};
+  size_t bytes_of[S_NSLOTS] = {};
+
+  bool fixed() const { return base != nullptr || measure; }
 
   template <typename T>
   gr_status get(Slot s, size_t count, T** out) {
-    if (!base) return pool_typed(ctx, s, count, out);
-    if (!got[s]) {
+    if (!fixed()) return pool_typed(ctx, s, count, out);
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 1);
+    if (!taken[s]) {
       const size_t off = (used + 255) / 256 * 256;
-      const size_t bytes = std::max<size_t>(count * sizeof(T), 1);
-      if (off + bytes > cap)
+      if (!measure && off + bytes > cap)
         return fail(GR_ERANGE, "working arrays need more than the " + std::to_string(cap) +
                                    " bytes of the static device workspace");
-      got[s] = base + off;
+      taken[s] = true;
+      off_of[s] = off;
+      bytes_of[s] = bytes;
       used = off + bytes;
+    } else if (bytes > bytes_of[s]) {
+      return fail(GR_ERANGE, "working array grew after the static workspace was laid out");
     }
-    *out = static_cast<T*>(got[s]);
+    *out = measure ? nullptr : reinterpret_cast<T*>(base + off_of[s]);
     return GR_OK;
   }
 };
@@ -236,6 +278,11 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
     (void)hipHostFree(hc);
     delete c;
     return fail(GR_EHIP, "hipHostGetDevicePointer failed");
+  }
+  if (gr_status ws = ws_address(device, &c->static_ws); ws != GR_OK) {
+    (void)hipHostFree(hc);
+    delete c;
+    return ws;
   }
   c->host_ctrl = static_cast<Ctrl*>(hc);
   c->host_ctrl_dev = static_cast<Ctrl*>(hd);
@@ -642,7 +689,7 @@ constexpr int64_t kPullListDivisor = 16;
 // keeps whatever an earlier call, possibly a failed one, left there.
 gr_status marks_buffer(gr_ctx* ctx, Arena& ar, int64_t V, uint8_t** out, hipStream_t st) {
   const size_t bytes = (size_t)((V + 31) / 32) * 32;
-  if (ar.base) return ar.get(S_MARKS, bytes, out);
+  if (ar.fixed()) return ar.get(S_MARKS, bytes, out);
   const bool fresh = ctx->pool[S_MARKS].bytes < bytes;
   void* p = nullptr;
   GR_TRY(pool_get(ctx, S_MARKS, bytes, &p));
@@ -665,6 +712,45 @@ gr_status bfs_check(const char* who, gr_ctx* ctx, const gr_graph* g, int32_t sou
   return GR_OK;
 }
 
+// The BFS working arrays.  In a fixed arena every one of them is laid out
+// here, up front, so that measuring this layout gives the bytes a call needs;
+// the pool hands out the byte marks lazily (marks_buffer).
+struct BfsArrays {
+  uint32_t* bm = nullptr;
+  int32_t *qA = nullptr, *qB = nullptr, *qC = nullptr;
+  int32_t *offsets = nullptr, *rstart = nullptr, *chunks = nullptr;
+  int64_t* bsums = nullptr;
+  Ctrl* ctrl = nullptr;
+  uint8_t* marks = nullptr;            // fixed arenas only
+  int32_t *depth = nullptr, *parent = nullptr;  // renumbered graphs only
+  int32_t *ul0 = nullptr, *ul1 = nullptr;       // symmetric graphs only
+  int64_t* dlog = nullptr;             // fixed arenas, traced calls only
+};
+
+gr_status bfs_layout(Arena& ar, int64_t V, int64_t E, bool pull_ok, bool renumbered,
+                     bool want_parent, bool tracing, BfsArrays* a) {
+  GR_TRY(ar.get(S_BM, 2 * words_for(V), &a->bm));
+  GR_TRY(ar.get(S_Q_A, V, &a->qA));
+  GR_TRY(ar.get(S_Q_B, V, &a->qB));
+  GR_TRY(ar.get(S_Q_C, V, &a->qC));
+  GR_TRY(ar.get(S_OFFSETS, V + 1, &a->offsets));
+  GR_TRY(ar.get(S_RSTART, V, &a->rstart));
+  GR_TRY(ar.get(S_CHUNKS, E / 512 + 2, &a->chunks));
+  GR_TRY(ar.get(S_BLOCK_SUMS, stats_grid() + 1, &a->bsums));
+  GR_TRY(ar.get(S_CTRL, 1, &a->ctrl));
+  if (ar.fixed()) GR_TRY(ar.get(S_MARKS, (size_t)((V + 31) / 32) * 32, &a->marks));
+  if (renumbered) {
+    GR_TRY(ar.get(S_DEPTH, V, &a->depth));
+    if (want_parent) GR_TRY(ar.get(S_PARENT, V, &a->parent));
+  }
+  if (pull_ok) {
+    GR_TRY(ar.get(S_UL_A, V, &a->ul0));
+    GR_TRY(ar.get(S_UL_B, V, &a->ul1));
+  }
+  if (ar.fixed() && tracing) GR_TRY(ar.get(S_DLOG, 3 * kDlMaxLevels, &a->dlog));
+  return GR_OK;
+}
+
 // The BFS enactor; its working arrays come from `ar` (arguments checked by
 // the caller, device current).
 gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth, int32_t* parent,
@@ -672,28 +758,19 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
                   Arena& ar) {
   const int64_t V = g->V, E = g->E, NW = words_for(V);
   const bool pull_ok = (g->flags & GR_SYMMETRIC) != 0;
-  const int G = stats_grid();
   const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+  const bool tracing = opts_in && opts_in->trace;
 
-  uint32_t* bm;
-  int32_t *qA, *qB, *qC, *offsets, *rstart, *chunks;
-  int64_t* bsums;
-  Ctrl* ctrl;
-  GR_TRY(ar.get(S_BM, 2 * NW, &bm));
-  GR_TRY(ar.get(S_Q_A, V, &qA));
-  GR_TRY(ar.get(S_Q_B, V, &qB));
-  GR_TRY(ar.get(S_Q_C, V, &qC));
-  GR_TRY(ar.get(S_OFFSETS, V + 1, &offsets));
-  GR_TRY(ar.get(S_RSTART, V, &rstart));
-  GR_TRY(ar.get(S_CHUNKS, E / 512 + 2, &chunks));
-  GR_TRY(ar.get(S_BLOCK_SUMS, G + 1, &bsums));
-  GR_TRY(ar.get(S_CTRL, 1, &ctrl));
-  if (ar.base) {
-    // the fixed region keeps the last call's contents: start from zero marks
-    uint8_t* marks;
-    GR_TRY(marks_buffer(ctx, ar, V, &marks, st));
-    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(marks), (V + 31) / 32 * 8, 0u, st));
-  }
+  BfsArrays a;
+  GR_TRY(bfs_layout(ar, V, E, pull_ok, g->perm != nullptr, parent != nullptr, tracing, &a));
+  uint32_t* bm = a.bm;
+  int32_t *qA = a.qA, *qB = a.qB, *qC = a.qC, *offsets = a.offsets, *rstart = a.rstart,
+          *chunks = a.chunks;
+  int64_t* bsums = a.bsums;
+  Ctrl* ctrl = a.ctrl;
+  // the fixed region keeps the last call's contents: start from zero marks
+  if (a.marks)
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(a.marks), (V + 31) / 32 * 8, 0u, st));
   Ctrl* hc = ctx->host_ctrl;
   // a renumbered graph traverses into internal arrays indexed by the new
   // ids (parent values are caller ids already) and scatters them at the end
@@ -701,19 +778,15 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
   int32_t* out_depth = depth;
   int32_t* out_parent = parent;
   if (perm) {
-    GR_TRY(ar.get(S_DEPTH, V, &depth));
-    if (parent) GR_TRY(ar.get(S_PARENT, V, &parent));
+    depth = a.depth;
+    if (parent) parent = a.parent;
   }
   const int32_t src = g->to_new(source);
 
   int32_t* q[3] = {qA, qB, qC};
   // pull levels after the first work from the list of still-unvisited
   // vertices the previous pull level left (two lists, ping-pong)
-  int32_t* ul[2] = {nullptr, nullptr};
-  if (pull_ok) {
-    GR_TRY(ar.get(S_UL_A, V, &ul[0]));
-    GR_TRY(ar.get(S_UL_B, V, &ul[1]));
-  }
+  int32_t* ul[2] = {a.ul0, a.ul1};
   int ulc = 0;            // the list the next pull level reads
   bool list_ok = false;   // it holds every unvisited vertex with neighbours
   int64_t list_n = 0;
@@ -745,7 +818,6 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
   int64_t pull_seen = 0;   // the device's pull neighbour count before this level
   int level = 0;
   gr_run_stats rs{};
-  const bool tracing = opts_in && opts_in->trace;
   DlPlan dl;
   GR_TRY(dl_plan(ctx, ar, opts, pull_ok, learned, tracing, &dl));
 
@@ -791,11 +863,10 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
       GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
       const int k = hc->dl_levels;
       if (k > 0) {
-        std::vector<int64_t> lg;
+        int64_t lg[3 * kDlMaxLevels];  // the block's level log (host copy)
         float block_ms = 0.f;
         if (tracing) {
-          lg.resize(3 * (size_t)k);
-          GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
+          GR_HIP(hipMemcpy(lg, dl.log, sizeof(int64_t) * 3 * (size_t)k, hipMemcpyDeviceToHost));
           GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         }
         // full blocks double the next one; blocks that stop early halve it
@@ -942,6 +1013,35 @@ extern "C" gr_status gr_bfs(gr_ctx* ctx, const gr_graph* g, int32_t source, int3
   DeviceGuard dg(ctx->device);
   Arena ar;
   ar.ctx = ctx;
+  return bfs_run(ctx, g, source, depth, parent, opts_in, opts, static_cast<hipStream_t>(stream),
+                 stats, ar);
+}
+
+extern "C" gr_status gr_bfs_static(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth,
+                                   int32_t* parent, gr_opts* opts_in, void* stream,
+                                   gr_run_stats* stats) {
+  GR_TRY(bfs_check("gr_bfs_static", ctx, g, source, depth));
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  if (!ctx->static_ws) return fail(GR_EHIP, "gr_bfs_static: the context has no static workspace");
+  // lay the working arrays out without touching the device, and refuse
+  // graphs whose arrays do not fit before any work is enqueued
+  Arena m;
+  m.measure = true;
+  BfsArrays unused;
+  const bool tracing = opts_in && opts_in->trace;
+  GR_TRY(bfs_layout(m, g->V, g->E, (g->flags & GR_SYMMETRIC) != 0, g->perm != nullptr,
+                    parent != nullptr, tracing, &unused));
+  if (m.used > (size_t)GR_STATIC_WORKSPACE_BYTES)
+    return fail(GR_ERANGE, "gr_bfs_static: this graph needs " + std::to_string(m.used) +
+                               " bytes of working arrays, the static workspace holds " +
+                               std::to_string((size_t)GR_STATIC_WORKSPACE_BYTES));
+  DeviceGuard dg(ctx->device);
+  Arena ar;
+  ar.ctx = ctx;
+  ar.base = static_cast<char*>(ctx->static_ws);
+  ar.cap = GR_STATIC_WORKSPACE_BYTES;
   return bfs_run(ctx, g, source, depth, parent, opts_in, opts, static_cast<hipStream_t>(stream),
                  stats, ar);
 }
@@ -1103,11 +1203,10 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         far_n = hc->far_count[pq.fc];
       }
       if (k > 0) {
-        std::vector<int64_t> lg;
+        int64_t lg[3 * kDlMaxLevels];  // the block's level log (host copy)
         float block_ms = 0.f;
         if (tracing) {
-          lg.resize(3 * (size_t)k);
-          GR_HIP(hipMemcpy(lg.data(), dl.log, sizeof(int64_t) * lg.size(), hipMemcpyDeviceToHost));
+          GR_HIP(hipMemcpy(lg, dl.log, sizeof(int64_t) * 3 * (size_t)k, hipMemcpyDeviceToHost));
           GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         }
         // full blocks double the next one; blocks that stop early halve it

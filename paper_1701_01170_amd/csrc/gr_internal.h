@@ -115,6 +115,9 @@ struct gr_ctx {
   uint32_t* publish_flag_dev = nullptr;
   uint32_t publish_seq = 0;
   bool policy_loaded = false;
+  // Device address of this device's copy of the library's static workspace
+  // (gr_bfs_static), looked up once per device when the context is created.
+  void* static_ws = nullptr;
   // Longest wait for one published control block before a traversal gives up
   // with GR_EHIP (environment GR_WAIT_LIMIT_MS at context creation, default 60 s).
   std::chrono::milliseconds wait_limit{60000};
