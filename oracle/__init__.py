@@ -6,6 +6,9 @@ the GPU library (its C part is ``oracle.c``, built by ``oracle/build.py``
 with gcc; the MLP reference below is plain numpy in float64).
 
 Graph results (definitions; see oracle.c for the full statement):
+  * BC   (paper Sec. 6, betweenness centrality, Brandes's two passes):
+    bc(v) = sum over the given sources s != v of the dependency delta_s(v),
+    float64, no halving or normalisation.
   * BFS  (paper Sec. 6.1; labels / predecessors initialised as in Alg. 1,
     Set_Problem_Data): depth = fewest edges from the source (-1 unreached);
     parent = minimum-id in-neighbour one level closer (-1 for the source and
@@ -42,6 +45,9 @@ def lib():
         L.or_sssp.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
         L.or_sssp.restype = ctypes.c_int
+        L.or_bc.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_bc.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -89,6 +95,22 @@ def sssp(row_offsets, col_indices, weights, sources, want_pred: bool = True):
     if rc != 0:
         raise ValueError(f"oracle sssp failed ({rc})")
     return dist, pred
+
+
+def bc(row_offsets, col_indices, sources, want_sigma: bool = False):
+    """Betweenness centrality over the given sources (Brandes, float64; see
+    or_bc in oracle.c for the definition): returns (bc float64[V], sigma of
+    the last source float64[V] or None)."""
+    R, C = _i32(row_offsets), _i32(col_indices)
+    V = R.shape[0] - 1
+    S = _i32(np.asarray(sources).reshape(-1))
+    out = np.empty(V, dtype=np.float64)
+    sig = np.empty(V, dtype=np.float64) if want_sigma else None
+    rc = lib().or_bc(V, R.ctypes.data, C.ctypes.data if C.size else None, S.shape[0],
+                     S.ctypes.data, out.ctypes.data, sig.ctypes.data if want_sigma else None)
+    if rc != 0:
+        raise ValueError(f"oracle bc failed ({rc})")
+    return out, sig
 
 
 def level_profile(row_offsets, depth):

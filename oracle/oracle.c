@@ -174,3 +174,82 @@ int or_sssp(int64_t n_vertices, const int32_t* row_offsets, const int32_t* col_i
   free(dist); free(done); free(is_source); free(heap);
   return rc;
 }
+
+/*
+ * Betweenness centrality (paper Sec. 6, betweenness centrality: Brandes's
+ * formulation, a forward BFS pass that counts shortest paths and a backward
+ * pass over the BFS levels that accumulates dependencies).
+ *
+ * For a source s, with d(v) the hop distance from s:
+ *   sigma_s(s) = 1,  sigma_s(w) = sum of sigma_s(v) over edges (v,w) with
+ *                    d(w) = d(v) + 1          (number of shortest s-w paths);
+ *   delta_s(v) = sum over edges (v,w) with d(w) = d(v) + 1 of
+ *                sigma_s(v) / sigma_s(w) * (1 + delta_s(w))
+ *                (Brandes' recursion for the dependency of s on v, taken in
+ *                decreasing distance, so delta_s(w) is final when used);
+ *   bc(v)      = sum over the given sources s != v of delta_s(v).
+ * No halving for undirected graphs and no normalisation: bc(v) is the sum of
+ * sigma_st(v) / sigma_st over ordered pairs (s, t) with s in the source set,
+ * t != s, v not in {s, t}.  All arithmetic in double precision.
+ * sigma_last (nullable) receives sigma of the last source (0 where unreached).
+ */
+int or_bc(int64_t n_vertices, const int32_t* row_offsets, const int32_t* col_indices,
+          int64_t n_sources, const int32_t* sources, double* bc, double* sigma_last) {
+  if (n_vertices < 1 || n_sources < 1) return OR_EINVAL;
+  for (int64_t i = 0; i < n_sources; ++i)
+    if (sources[i] < 0 || sources[i] >= n_vertices) return OR_EINVAL;
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_vertices);
+  int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_vertices);
+  double* sigma = (double*)malloc(sizeof(double) * (size_t)n_vertices);
+  double* delta = (double*)malloc(sizeof(double) * (size_t)n_vertices);
+  if (!order || !dist || !sigma || !delta) {
+    free(order);
+    free(dist);
+    free(sigma);
+    free(delta);
+    return OR_ENOMEM;
+  }
+  for (int64_t v = 0; v < n_vertices; ++v) bc[v] = 0.0;
+  for (int64_t i = 0; i < n_sources; ++i) {
+    const int32_t s = sources[i];
+    for (int64_t v = 0; v < n_vertices; ++v) {
+      dist[v] = -1;
+      sigma[v] = 0.0;
+      delta[v] = 0.0;
+    }
+    /* forward: FIFO BFS; `order` is the visit order (non-decreasing d) */
+    int64_t head = 0, tail = 0;
+    dist[s] = 0;
+    sigma[s] = 1.0;
+    order[tail++] = s;
+    while (head < tail) {
+      const int32_t v = order[head++];
+      for (int64_t e = row_offsets[v]; e < row_offsets[v + 1]; ++e) {
+        const int32_t w = col_indices[e];
+        if (dist[w] == -1) {
+          dist[w] = dist[v] + 1;
+          order[tail++] = w;
+        }
+        if (dist[w] == dist[v] + 1) sigma[w] += sigma[v];
+      }
+    }
+    /* backward: vertices in reverse visit order */
+    for (int64_t k = tail - 1; k >= 0; --k) {
+      const int32_t v = order[k];
+      double acc = 0.0;
+      for (int64_t e = row_offsets[v]; e < row_offsets[v + 1]; ++e) {
+        const int32_t w = col_indices[e];
+        if (dist[w] == dist[v] + 1) acc += sigma[v] / sigma[w] * (1.0 + delta[w]);
+      }
+      delta[v] = acc;
+      if (v != s) bc[v] += acc;
+    }
+    if (sigma_last && i == n_sources - 1)
+      for (int64_t v = 0; v < n_vertices; ++v) sigma_last[v] = sigma[v];
+  }
+  free(order);
+  free(dist);
+  free(sigma);
+  free(delta);
+  return OR_OK;
+}
