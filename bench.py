@@ -237,6 +237,56 @@ def learned_vs_heuristic(gr, g, ctx, sources, outs=None) -> dict | None:
     return summarize_pair(res, "heuristic", "learned")
 
 
+def filter_ablation(gr, g, sources, outs) -> dict:
+    """BFS under the paper's idempotence x direction-optimisation ablation
+    (Sec. 7, optimisation analysis): the filter of the push levels (auto:
+    atomic culling on small levels, atomic-free byte marks on large ones;
+    atomic: the first atomic OR of a vertex's visited bit appends it on every
+    level, the LB_CULL-style exact filter; idempotent: no atomics in the
+    advance, inexact culling heuristics, then an exact filter pass) with and
+    without the push -> pull switch.  Tuned knobs otherwise, untraced, the
+    variants interleaved per source.  A traced run per variant gives the
+    duplicates the idempotent heuristics let through (candidates / exact new
+    vertices over its idempotent levels)."""
+    import math
+    from paper_1701_01170_amd import autotune
+    variants = {}
+    for fname, fv in (("auto", gr.BFS_FILTER_AUTO), ("atomic", gr.BFS_FILTER_ATOMIC),
+                      ("idempotent", gr.BFS_FILTER_IDEMPOTENT)):
+        for dname, do_kw in (("do", {}), ("no_do", {"do_a": math.inf})):
+            variants[f"{fname}_{dname}"] = autotune.tuned_opts(g, "bfs", bfs_filter=fv, **do_kw)
+    ms = {k: [] for k in variants}
+    teps = []
+    for i, s in enumerate(sources):
+        names = list(variants)
+        if i % 2:
+            names = names[::-1]
+        for k in names:
+            st = gr.bfs(g, int(s), opts=variants[k], out=outs)[2]
+            ms[k].append(st["device_ms"])
+        teps.append(st["teps_edges"])
+    out = {"sources": len(sources)}
+    base = sum(ms["auto_do"])
+    for k in variants:
+        out[k] = {"median_ms": round(statistics.median(ms[k]), 4),
+                  "gteps": _gteps(sum(teps), sum(ms[k])),
+                  "time_over_auto_do": round(sum(ms[k]) / base, 4) if base > 0 else None}
+    cap = 512
+    for k in ("idempotent_do", "idempotent_no_do"):
+        tr = (gr.LevelTrace * cap)()
+        o = autotune.tuned_opts(g, "bfs", bfs_filter=variants[k].bfs_filter, do_a=variants[k].do_a,
+                                trace=tr, trace_capacity=cap)
+        cand = exact = 0
+        for s in sources[:4]:
+            gr.bfs(g, int(s), opts=o, out=outs)
+            for r in tr[:min(o.trace_count, cap)]:
+                if r.kernel >= 12:
+                    cand += r.n_cand
+                    exact += r.n_next
+        out[k]["candidates_over_new_vertices"] = round(cand / exact, 4) if exact else None
+    return out
+
+
 def rmat14(gr, gg, ctx) -> dict:
     """R-MAT scale 14: the single-source BFS (median device us and GTEPS over
     20 seeded sources, tuned heuristic, untraced) and the learned selector
@@ -589,6 +639,9 @@ def main():
             gr, g, ctx, gg.sources(hg, 12, seed=1100),
             outs={"bfs": (depth, parent), "sssp": (dist, pred)})
         log("# learned vs heuristic done")
+        out["breakdown"]["bfs_filter_ablation_rmat22"] = filter_ablation(
+            gr, g, gg.sources(hg, 8, seed=1200), (depth, parent))
+        log("# filter ablation done")
         out["breakdown"]["rmat14"] = rmat14(gr, gg, ctx)
         log("# rmat14 done")
         out["breakdown"].update(extras(gr, gg, ctx, torch, log))

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 1
+#define GR_ABI_VERSION 2
 
 typedef enum gr_status {
   GR_OK = 0,
@@ -108,12 +108,17 @@ typedef struct gr_level_trace {
                           7 SSSP priority-queue refill (far pile split), 8 / 9 / 10 SSSP
                           TWC / LB_LIGHT / LB relaxation with the byte-mark filter,
                           11 BFS pull over the list of still-unvisited vertices the
-                          previous pull level left (else 4 / 5 pull over the bitmap) */
+                          previous pull level left (else 4 / 5 pull over the bitmap),
+                          12 / 13 / 14 idempotent BFS push TWC / LB_LIGHT / LB
+                          (GR_BFS_FILTER_IDEMPOTENT) */
   int64_t n_next;      /* size of the output frontier */
   int64_t n_in;        /* vertices the advance read as input: push the frontier (n_f),
                           pull over the bitmap the unvisited vertices (n_u), pull over
                           the list its entries, refill the far-pile entries */
   int64_t inspected;   /* edges the advance read: push m_f, pull the neighbours scanned */
+  int64_t n_cand;      /* entries the advance emitted before the exact filter: n_next for
+                          the exact filters, more with the idempotent advance (its
+                          surviving duplicates; see gr_opts.bfs_filter) */
 } gr_level_trace;
 
 typedef struct gr_opts {
@@ -144,8 +149,38 @@ typedef struct gr_opts {
   float learned_margin;      /* GR_POLICY_LEARNED: the network's action replaces the heuristic's only
                                 when its predicted log2 step time is lower by more than this
                                 (0: plain argmin).  Must be >= 0. */
-  int32_t reserved[4];
+  int32_t bfs_filter;        /* BFS push levels (outside device-predicated blocks), gr_bfs_filter:
+                                how repeated discoveries of a vertex are removed */
+  int32_t idem_culls_off;    /* GR_BFS_FILTER_IDEMPOTENT: culling heuristics switched off, a bit
+                                set of GR_IDEM_CULL_* (0: all on) */
+  int32_t idem_table_log2;   /* GR_BFS_FILTER_IDEMPOTENT: log2 of the entries of the per-workgroup
+                                history table: 0 (default 10), 8, 10 or 12 */
+  int32_t adv_block;         /* workgroup size of the push advance kernels (TWC, LB_LIGHT, LB):
+                                0 (default 256), 128, 256 or 512 */
+  int32_t twc_wave_min;      /* TWC tiers (Sec. 5.1 dynamic grouping): neighbour lists longer than
+                                this are expanded by one wavefront (0: default 64) ... */
+  int32_t twc_block_min;     /* ... and lists longer than this by the whole workgroup (0: default
+                                adv_block); must be >= twc_wave_min when both are set */
+  int32_t reserved;
 } gr_opts;
+
+/* gr_opts.bfs_filter (Sec. 5.2: idempotent vs. non-idempotent operations).
+ * Results are identical for all three; only the time differs. */
+typedef enum gr_bfs_filter {
+  GR_BFS_FILTER_AUTO = 0,       /* atomic bitmap culling on small levels, atomic-free byte marks plus
+                                   one ordered compaction on levels with >= V/4 frontier edges */
+  GR_BFS_FILTER_ATOMIC = 1,     /* every level: the first atomic OR of a vertex's visited bit
+                                   appends it (the exact filter fused into the advance) */
+  GR_BFS_FILTER_IDEMPOTENT = 2  /* idempotent advance: no atomics; repeated discoveries are culled
+                                   by inexact heuristics (visited bitmap, per-workgroup history
+                                   hash table, per-wavefront hash table, depth label) and the
+                                   survivors (with the duplicates the heuristics missed) go through
+                                   an exact filter pass; symmetric graphs only (elsewhere it acts
+                                   as GR_BFS_FILTER_AUTO) */
+} gr_bfs_filter;
+#define GR_IDEM_CULL_WAVE 0x1u   /* per-wavefront table: one lane per repeated vertex of a batch */
+#define GR_IDEM_CULL_HISTORY 0x2u /* per-workgroup history table in LDS */
+#define GR_IDEM_CULL_LABEL 0x4u  /* depth label already written this level */
 
 typedef struct gr_run_stats {
   int32_t iterations;        /* bulk-synchronous iterations executed */
@@ -266,6 +301,25 @@ gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, in
 gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);
+
+/* Betweenness centrality over n_sources host-given sources (Sec. 6,
+ * betweenness centrality: Brandes's forward pass counting shortest paths and
+ * backward pass accumulating dependencies, both on the advance operator).
+ * bc: device double[V] (required) = for every vertex v, the sum over the
+ * given sources s != v of delta_s(v) = sum over targets t not in {s, v} of
+ * sigma_st(v) / sigma_st, where sigma_st counts shortest s-t paths and
+ * sigma_st(v) those through v (no halving for undirected graphs, no
+ * normalisation).  sigma: device double[V] or NULL; with exactly one source it
+ * receives sigma_sv (the number of shortest paths from the source to v; 0 if
+ * unreached, 1 at the source).  Arithmetic in double precision; sums are
+ * accumulated with atomic adds, so the last bits may vary from run to run.
+ * Each source runs one gr_bfs with `opts` (its policy and knobs; tracing and
+ * max_iterations are ignored), then one push advance per level in each
+ * direction.  Needs GR_SYMMETRIC (GR_EUNSUPPORTED otherwise).  stats:
+ * iterations and teps_edges summed over the sources' BFS runs; device_ms for
+ * the whole call. */
+gr_status gr_bc(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t n_sources,
+                double* bc, double* sigma, gr_opts* opts, void* stream, gr_run_stats* stats);
 
 /* ---- selector network (learned per-iteration strategy) -------------------
  *

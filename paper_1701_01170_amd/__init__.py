@@ -33,6 +33,8 @@ POLICY_HEURISTIC, POLICY_LEARNED, POLICY_FIXED, POLICY_RANDOM = 0, 1, 2, 3
 PUSH_TWC, PUSH_LB, PULL_TWC, PULL_LB = 0, 1, 2, 3
 ACTION_NAMES = ["PUSH_TWC", "PUSH_LB", "PULL_TWC", "PULL_LB"]
 SYMMETRIC, DEVICE_INPUT, RENUMBER = 0x1, 0x2, 0x4
+BFS_FILTER_AUTO, BFS_FILTER_ATOMIC, BFS_FILTER_IDEMPOTENT = 0, 1, 2
+IDEM_CULL_WAVE, IDEM_CULL_HISTORY, IDEM_CULL_LABEL = 0x1, 0x2, 0x4
 MLP_N_PARAMS = 1476
 
 
@@ -48,7 +50,8 @@ class LevelTrace(ctypes.Structure):
                 ("m_u", ctypes.c_int64), ("max_deg_f", ctypes.c_int64),
                 ("features", ctypes.c_float * 8), ("step_us", ctypes.c_float),
                 ("kernel_us", ctypes.c_float), ("kernel", ctypes.c_int32), ("n_next", ctypes.c_int64),
-                ("n_in", ctypes.c_int64), ("inspected", ctypes.c_int64)]
+                ("n_in", ctypes.c_int64), ("inspected", ctypes.c_int64),
+                ("n_cand", ctypes.c_int64)]
 
 
 class Opts(ctypes.Structure):
@@ -59,7 +62,10 @@ class Opts(ctypes.Structure):
                 ("lb_chunk", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
                 ("trace", ctypes.POINTER(LevelTrace)), ("trace_count", ctypes.c_int32),
                 ("device_max_edges", ctypes.c_int32), ("sssp_delta", ctypes.c_int32),
-                ("learned_margin", ctypes.c_float), ("reserved", ctypes.c_int32 * 4)]
+                ("learned_margin", ctypes.c_float), ("bfs_filter", ctypes.c_int32),
+                ("idem_culls_off", ctypes.c_int32), ("idem_table_log2", ctypes.c_int32),
+                ("adv_block", ctypes.c_int32), ("twc_wave_min", ctypes.c_int32),
+                ("twc_block_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -106,6 +112,8 @@ _SIGNATURES = {
                                ctypes.POINTER(RunStats)]),
     "gr_bfs_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
                                     ctypes.POINTER(RunStats)]),
+    "gr_bc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
+                             ctypes.POINTER(RunStats)]),
     "gr_copy_bandwidth": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P,
                                          ctypes.POINTER(ctypes.c_float)]),
     "gr_mlp_forward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P]),
@@ -347,6 +355,24 @@ def bfs_multi(g: Graph, sources, want_parent: bool = True, opts: Opts | None = N
     check(lib().gr_bfs_multi(g.ctx.handle, g.handle, src.ctypes.data, k, _ptr(depth), _ptr(parent),
                              _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
     return depth, parent, st.as_dict()
+
+
+def bc(g: Graph, sources, want_sigma: bool = False, opts: Opts | None = None, stream=None,
+       out=None):
+    """Betweenness centrality summed over `sources` (gr_bc).  Returns (bc
+    float64[V], sigma float64[V] or None (one source only), stats dict)."""
+    import torch
+    src = np.ascontiguousarray(np.asarray(sources).reshape(-1), dtype=np.int32)
+    if out is not None:
+        b, sig = out
+    else:
+        dev = torch.device("cuda", g.ctx.device)
+        b = torch.empty(g.n_vertices, dtype=torch.float64, device=dev)
+        sig = torch.empty(g.n_vertices, dtype=torch.float64, device=dev) if want_sigma else None
+    st = RunStats()
+    check(lib().gr_bc(g.ctx.handle, g.handle, src.ctypes.data, int(src.shape[0]), _ptr(b), _ptr(sig),
+                      _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
+    return b, sig, st.as_dict()
 
 
 def mlp_forward(ctx: Context, params, X, stream=None):

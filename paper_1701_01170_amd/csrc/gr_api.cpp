@@ -200,6 +200,16 @@ gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st, const MlpSelect* sel
 
 constexpr int kDefaultChunk = 8192;
 
+// The push kernels' launch shape from the options (validated by check_opts).
+AdvCfg adv_cfg(const gr_opts& o) {
+  AdvCfg c;
+  c.chunk = o.lb_chunk > 0 ? o.lb_chunk : kDefaultChunk;
+  c.block = o.adv_block > 0 ? o.adv_block : 256;
+  c.twc_wave_min = o.twc_wave_min > 0 ? o.twc_wave_min : -1;
+  c.twc_block_min = o.twc_block_min > 0 ? o.twc_block_min : -1;
+  return c;
+}
+
 }  // namespace
 }  // namespace gr
 
@@ -291,7 +301,8 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
   c->publish_flag_dev = reinterpret_cast<uint32_t*>(static_cast<char*>(hd) + flag_off);
   if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
       hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess ||
-      hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess) {
+      hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
+      hipEventCreate(&c->ev_c0) != hipSuccess || hipEventCreate(&c->ev_c1) != hipSuccess) {
     gr_ctx_destroy(c);
     return fail(GR_EHIP, "hipEventCreate failed");
   }
@@ -305,7 +316,8 @@ extern "C" gr_status gr_ctx_destroy(gr_ctx* c) {
   for (auto& b : c->pool)
     if (b.ptr) (void)hipFree(b.ptr);
   if (c->host_ctrl) (void)hipHostFree(c->host_ctrl);
-  for (hipEvent_t ev : {c->ev_start, c->ev_stop, c->ev_a, c->ev_b, c->ev_k0, c->ev_k1})
+  for (hipEvent_t ev : {c->ev_start, c->ev_stop, c->ev_a, c->ev_b, c->ev_k0, c->ev_k1, c->ev_c0,
+                        c->ev_c1})
     if (ev) (void)hipEventDestroy(ev);
   delete c;
   return GR_OK;
@@ -561,6 +573,20 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
   if (opts->sssp_delta < 0) return fail(GR_EINVAL, "opts->sssp_delta must be >= 0");
   if (!(opts->learned_margin >= 0.0f) || !std::isfinite(opts->learned_margin))
     return fail(GR_EINVAL, "opts->learned_margin must be finite and >= 0");
+  if (opts->adv_block != 0 && opts->adv_block != 128 && opts->adv_block != 256 &&
+      opts->adv_block != 512)
+    return fail(GR_EINVAL, "opts->adv_block must be 0 (default 256), 128, 256 or 512");
+  if (opts->twc_wave_min < 0 || opts->twc_block_min < 0)
+    return fail(GR_EINVAL, "opts->twc_wave_min / twc_block_min must be >= 0");
+  if (opts->twc_wave_min > 0 && opts->twc_block_min > 0 && opts->twc_block_min < opts->twc_wave_min)
+    return fail(GR_EINVAL, "opts->twc_block_min must be >= twc_wave_min");
+  if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
+    return fail(GR_EINVAL, "opts->bfs_filter out of range");
+  if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
+    return fail(GR_EINVAL, "opts->idem_culls_off has unknown bits");
+  if (opts->idem_table_log2 != 0 && opts->idem_table_log2 != 8 && opts->idem_table_log2 != 10 &&
+      opts->idem_table_log2 != 12)
+    return fail(GR_EINVAL, "opts->idem_table_log2 must be 0 (default 10), 8, 10 or 12");
   *local = *opts;
   return GR_OK;
 }
@@ -581,6 +607,7 @@ gr_status elapsed_ms(hipEvent_t a, hipEvent_t b, float* ms) {
 struct StepWork {
   int64_t n_in;
   int64_t inspected;
+  int64_t n_cand = -1;  // entries before the exact filter (< 0: the filter was exact, n_next)
 };
 
 gr_status record_trace_times(gr_opts* opts, const LevelFeatures& lf, int action, int kernel,
@@ -603,6 +630,7 @@ gr_status record_trace_times(gr_opts* opts, const LevelFeatures& lf, int action,
   t.n_next = n_next;
   t.n_in = w.n_in;
   t.inspected = w.inspected;
+  t.n_cand = w.n_cand >= 0 ? w.n_cand : n_next;
   return GR_OK;
 }
 
@@ -626,6 +654,7 @@ constexpr int64_t kDlDefaultMaxEdges = 1 << 18;
 constexpr int kTraceKernelDstep = 6;
 constexpr int kTraceKernelRefill = 7;
 constexpr int kTraceKernelPullList = 11;
+constexpr int kTraceKernelIdem = 12;  // idempotent BFS push: 12 + (0 TWC, 1 LB_LIGHT, 2 LB)
 constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filter: 8 + (0 TWC, 1 LB_LIGHT, 2 LB)
 // SSSP iterations whose frontier has at least V / kSsspMarksDivisor edges use
 // the byte-mark filter.
@@ -725,10 +754,11 @@ struct BfsArrays {
   int32_t *depth = nullptr, *parent = nullptr;  // renumbered graphs only
   int32_t *ul0 = nullptr, *ul1 = nullptr;       // symmetric graphs only
   int64_t* dlog = nullptr;             // fixed arenas, traced calls only
+  int32_t* cand = nullptr;             // idempotent advance only
 };
 
 gr_status bfs_layout(Arena& ar, int64_t V, int64_t E, bool pull_ok, bool renumbered,
-                     bool want_parent, bool tracing, BfsArrays* a) {
+                     bool want_parent, bool tracing, bool idem, BfsArrays* a) {
   GR_TRY(ar.get(S_BM, 2 * words_for(V), &a->bm));
   GR_TRY(ar.get(S_Q_A, V, &a->qA));
   GR_TRY(ar.get(S_Q_B, V, &a->qB));
@@ -748,21 +778,33 @@ gr_status bfs_layout(Arena& ar, int64_t V, int64_t E, bool pull_ok, bool renumbe
     GR_TRY(ar.get(S_UL_B, V, &a->ul1));
   }
   if (ar.fixed() && tracing) GR_TRY(ar.get(S_DLOG, 3 * kDlMaxLevels, &a->dlog));
+  if (idem) GR_TRY(ar.get(S_CAND, V, &a->cand));
   return GR_OK;
+}
+
+// The idempotent advance needs the parent fix-up, which scans out-edges as
+// in-edges: symmetric graphs only.
+bool bfs_idem_on(const gr_opts& o, bool pull_ok) {
+  return o.bfs_filter == GR_BFS_FILTER_IDEMPOTENT && pull_ok;
 }
 
 // The BFS enactor; its working arrays come from `ar` (arguments checked by
 // the caller, device current).
 gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth, int32_t* parent,
                   gr_opts* opts_in, const gr_opts& opts, hipStream_t st, gr_run_stats* stats,
-                  Arena& ar) {
+                  Arena& ar, bool internal_ids = false) {
   const int64_t V = g->V, E = g->E, NW = words_for(V);
   const bool pull_ok = (g->flags & GR_SYMMETRIC) != 0;
-  const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+  const AdvCfg adv = adv_cfg(opts);
+  const int chunk = adv.chunk;
   const bool tracing = opts_in && opts_in->trace;
 
+  const bool idem = bfs_idem_on(opts, pull_ok);
+  const uint32_t idem_culls = (GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL) &
+                              ~(uint32_t)opts.idem_culls_off;
+  const int idem_log_h = opts.idem_table_log2 > 0 ? opts.idem_table_log2 : 10;
   BfsArrays a;
-  GR_TRY(bfs_layout(ar, V, E, pull_ok, g->perm != nullptr, parent != nullptr, tracing, &a));
+  GR_TRY(bfs_layout(ar, V, E, pull_ok, g->perm != nullptr, parent != nullptr, tracing, idem, &a));
   uint32_t* bm = a.bm;
   int32_t *qA = a.qA, *qB = a.qB, *qC = a.qC, *offsets = a.offsets, *rstart = a.rstart,
           *chunks = a.chunks;
@@ -777,7 +819,7 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
   const int32_t* perm = g->perm;
   int32_t* out_depth = depth;
   int32_t* out_parent = parent;
-  if (perm) {
+  if (perm && !internal_ids) {
     depth = a.depth;
     if (parent) parent = a.parent;
   }
@@ -913,14 +955,26 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
       if (mode == 2)
         GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                        chunks, chunk, st));
-      const bool atomic_parent = parent && (!pull_ok || m_f <= kAtomicParentMaxEdges);
-      if (!atomic_parent && m_f >= V / kMarksFilterDivisor) {
+      const bool atomic_parent = !idem && parent && (!pull_ok || m_f <= kAtomicParentMaxEdges);
+      if (idem) {
+        // idempotent advance into the candidate list, then the exact filter
+        kernel = kTraceKernelIdem + mode;
+        GR_HIP(launch_fill_u32(&ctrl->cand_count, 1, 0u, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
+        GR_HIP(launch_bfs_push_idem(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, bm,
+                                    p, depth, next_depth, idem_culls, idem_log_h, a.cand,
+                                    &ctrl->cand_count, V, adv, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
+        GR_HIP(launch_bfs_idem_filter(a.cand, &ctrl->cand_count, V, V, bm, p, depth, next_depth,
+                                      q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], st));
+      } else if (opts.bfs_filter != GR_BFS_FILTER_ATOMIC && !atomic_parent &&
+                 m_f >= V / kMarksFilterDivisor) {
         uint8_t* marks;
         GR_TRY(marks_buffer(ctx, ar, V, &marks, st));
         kernel = mode == 2 ? 3 : mode;
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                     bm, p, marks, chunk, st));
+                                     bm, p, marks, adv, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
         GR_HIP(launch_bfs_mark_compact(marks, V, bm, p, depth, next_depth, q[(cur + 1) % 3],
                                        &ctrl->q_count[(cur + 1) % 3], st));
@@ -929,7 +983,7 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push(mode, atomic_parent, q[cur], offsets, rstart, chunks, n_f, m_f,
                                g->R, g->C, bm, p, depth, parent, perm, next_depth, q[(cur + 1) % 3],
-                               &ctrl->q_count[(cur + 1) % 3], chunk, st));
+                               &ctrl->q_count[(cur + 1) % 3], adv, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
       if (parent && !atomic_parent)
@@ -974,9 +1028,11 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
     GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
     list_n = hc->ul_count[ulc];
     if (tracing) {
-      const bool pulled = kernel >= 4;
+      const bool pulled = kernel >= 4 && kernel <= kTraceKernelPullList;
+      const bool idem_step = kernel >= kTraceKernelIdem;
       const StepWork w{pulled ? pull_in : n_f,
-                       pulled ? (int64_t)hc->inspected - pull_seen : m_f};
+                       pulled ? (int64_t)hc->inspected - pull_seen : m_f,
+                       idem_step ? (int64_t)hc->cand_count : -1};
       GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp], w));
     }
     pull_seen = hc->inspected;
@@ -986,7 +1042,8 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
     visited_n += n_f;
     visited_m += m_f;
   }
-  if (perm) GR_HIP(launch_permute_out(perm, V, depth, parent, out_depth, out_parent, st));
+  if (perm && !internal_ids)
+    GR_HIP(launch_permute_out(perm, V, depth, parent, out_depth, out_parent, st));
   GR_HIP(hipEventRecord(ctx->ev_stop, st));
   GR_HIP(hipEventSynchronize(ctx->ev_stop));
   if (stats) {
@@ -1032,7 +1089,8 @@ extern "C" gr_status gr_bfs_static(gr_ctx* ctx, const gr_graph* g, int32_t sourc
   BfsArrays unused;
   const bool tracing = opts_in && opts_in->trace;
   GR_TRY(bfs_layout(m, g->V, g->E, (g->flags & GR_SYMMETRIC) != 0, g->perm != nullptr,
-                    parent != nullptr, tracing, &unused));
+                    parent != nullptr, tracing, bfs_idem_on(opts, (g->flags & GR_SYMMETRIC) != 0),
+                    &unused));
   if (m.used > (size_t)GR_STATIC_WORKSPACE_BYTES)
     return fail(GR_ERANGE, "gr_bfs_static: this graph needs " + std::to_string(m.used) +
                                " bytes of working arrays, the static workspace holds " +
@@ -1070,7 +1128,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t V = g->V, E = g->E;
   const int G = stats_grid();
-  const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+  const AdvCfg adv = adv_cfg(opts);
+  const int chunk = adv.chunk;
 
   std::vector<int32_t> uniq(sources, sources + n_sources);
   std::sort(uniq.begin(), uniq.end());
@@ -1265,7 +1324,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         kernel += kTraceMarksOffset;
         const bool screen = expanded + n_f + far_n >= V / kSsspMirrorDivisor;
         GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                       g->W, keys, perm, marks, mirror, screen, chunk, st));
+                                       g->W, keys, perm, marks, mirror, screen, adv, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
         if (use_pq)
           GR_HIP(launch_sssp_pq_mark_compact(marks, V, keys, mirror, pq, ctrl, q[(cur + 1) % 3],
@@ -1276,12 +1335,12 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       } else if (use_pq) {
         GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
                                     g->W, keys, tags, it + 1, pq, ctrl, q[(cur + 1) % 3],
-                                    &ctrl->q_count[(cur + 1) % 3], chunk, st));
+                                    &ctrl->q_count[(cur + 1) % 3], adv, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       } else {
         GR_HIP(launch_sssp_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C, g->W,
                                  keys, tags, perm, it + 1, q[(cur + 1) % 3],
-                                 &ctrl->q_count[(cur + 1) % 3], chunk, st));
+                                 &ctrl->q_count[(cur + 1) % 3], adv, st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
       inspected += m_f;
@@ -1339,7 +1398,8 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t V = g->V, E = g->E;
   const int G = stats_grid();
-  const int chunk = opts.lb_chunk > 0 ? opts.lb_chunk : kDefaultChunk;
+  const AdvCfg adv = adv_cfg(opts);
+  const int chunk = adv.chunk;
   const bool use_lb = (double)E / (double)V >= (double)opts.lb_min_avg_degree;
   using u64 = unsigned long long;
 
@@ -1411,7 +1471,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
           GR_HIP(launch_frontier_offsets(q[cur], n_a, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                          chunks, chunk, st));
         GR_HIP(launch_ms_push(mode, q[cur], offsets, rstart, chunks, n_a, m_a, g->R, g->C,
-                              front[fc], visit, next, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], chunk,
+                              front[fc], visit, next, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], adv,
                               st));
         rs.action_count[use_lb ? GR_PUSH_LB : GR_PUSH_TWC]++;
       }
@@ -1442,6 +1502,134 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
     rs.iterations = max_levels;
     rs.teps_edges = hc->reached_edges;
     rs.inspected_edges = inspected;
+    rs.device_ms = ms;
+    *stats = rs;
+  }
+  return GR_OK;
+}
+
+// ============================================================================
+// betweenness centrality (Sec. 6, Brandes's forward and backward passes)
+// ============================================================================
+
+extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* sources,
+                           int32_t n_sources, double* bc, double* sigma, gr_opts* opts_in,
+                           void* stream, gr_run_stats* stats) {
+  if (!ctx || !g) return fail(GR_EINVAL, "gr_bc: ctx or graph is NULL");
+  if (g->ctx != ctx) return fail(GR_EINVAL, "gr_bc: graph belongs to another context");
+  if (!bc) return fail(GR_EINVAL, "gr_bc: bc is NULL");
+  if (!sources || n_sources < 1) return fail(GR_EINVAL, "gr_bc: need at least one source");
+  for (int32_t i = 0; i < n_sources; ++i)
+    if (sources[i] < 0 || (int64_t)sources[i] >= g->V)
+      return fail(GR_EINVAL, "gr_bc: source " + std::to_string(sources[i]) + " out of range");
+  if (sigma && n_sources != 1) return fail(GR_EINVAL, "gr_bc: sigma needs exactly one source");
+  if (!(g->flags & GR_SYMMETRIC))
+    return fail(GR_EUNSUPPORTED, "gr_bc needs a symmetric graph (the backward pass pushes over in-edges)");
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  opts.trace = nullptr;       // the BFS inside is not traced
+  opts.trace_capacity = 0;
+  opts.max_iterations = 0;    // every level is needed
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t V = g->V, E = g->E;
+  const AdvCfg adv = adv_cfg(opts);
+  const int chunk = adv.chunk;
+  const bool lb = (double)E / (double)V >= (double)opts.lb_min_avg_degree;
+
+  int32_t *depth, *levels, *offsets, *rstart, *chunks;
+  double *sig, *acc;
+  uint32_t* lvl_n;
+  unsigned long long* lvl_m;
+  int64_t* bsums;
+  Ctrl* ctrl;
+  GR_TRY(pool_typed(ctx, S_BC_DEPTH, V, &depth));
+  GR_TRY(pool_typed(ctx, S_BC_SIGMA, V, &sig));
+  GR_TRY(pool_typed(ctx, S_BC_ACC, V, &acc));
+  GR_TRY(pool_typed(ctx, S_BC_LEVELS, V, &levels));
+  GR_TRY(pool_typed(ctx, S_BC_LVL_N, 2 * (size_t)(V + 1), &lvl_n));  // counts, then cursors
+  GR_TRY(pool_typed(ctx, S_BC_LVL_M, V + 1, &lvl_m));
+  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
+  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, stats_grid() + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
+
+  GR_HIP(hipEventRecord(ctx->ev_c0, st));
+  GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(bc), 2 * V, 0u, st));
+  Arena ar;
+  ar.ctx = ctx;
+  gr_run_stats rs{};
+  std::vector<uint32_t> hn;
+  std::vector<unsigned long long> hm;
+  std::vector<uint32_t> off;
+  // a level's workload mapping (as the heuristic picks it for a push level),
+  // with the degree scan queued first when it balances edges
+  int sp = 0;
+  auto prepare_level = [&](int64_t n, const int32_t* front, const uint32_t* n_dev,
+                           int* mode) -> gr_status {
+    *mode = !lb ? 0 : (n < opts.lb_light_threshold ? 1 : 2);
+    if (*mode == 2) {
+      GR_HIP(launch_frontier_stats(front, n_dev, g->R, bsums, ctrl, sp, nullptr, nullptr, st));
+      GR_HIP(launch_frontier_offsets(front, n, g->R, bsums, &ctrl->m_f[sp], offsets, rstart, chunks,
+                                     chunk, st));
+      sp ^= 1;
+    }
+    return GR_OK;
+  };
+  for (int32_t i = 0; i < n_sources; ++i) {
+    gr_run_stats bs{};
+    GR_TRY(bfs_run(ctx, g, sources[i], depth, nullptr, nullptr, opts, st, &bs, ar,
+                   /*internal_ids=*/true));
+    const int32_t L = bs.iterations;  // levels 0 .. L - 1 are non-empty
+    const int32_t src = g->to_new(sources[i]);
+    GR_HIP(launch_fill_u32(lvl_n, L, 0u, st));
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(lvl_m), 2 * (int64_t)L, 0u, st));
+    GR_HIP(launch_bc_levels(depth, g->R, V, src, L, lvl_n, lvl_m, sig, acc, st));
+    hn.resize(L);
+    hm.resize(L);
+    off.assign((size_t)L + 1, 0u);
+    GR_HIP(hipMemcpyAsync(hn.data(), lvl_n, sizeof(uint32_t) * L, hipMemcpyDeviceToHost, st));
+    GR_HIP(hipMemcpyAsync(hm.data(), lvl_m, sizeof(unsigned long long) * L, hipMemcpyDeviceToHost,
+                          st));
+    GR_HIP(hipStreamSynchronize(st));
+    for (int32_t d = 0; d < L; ++d) off[d + 1] = off[d] + hn[d];
+    GR_HIP(hipMemcpyAsync(lvl_n + L, off.data(), sizeof(uint32_t) * L, hipMemcpyHostToDevice, st));
+    GR_HIP(launch_bc_scatter(depth, V, L, lvl_n + L, levels, st));
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
+    sp = 0;
+    // forward: sigma of level d + 1 from level d
+    for (int32_t d = 0; d + 1 < L; ++d) {
+      if (hm[d] == 0) continue;
+      const int32_t* front = levels + off[d];
+      int mode = 0;
+      GR_TRY(prepare_level(hn[d], front, lvl_n + d, &mode));
+      GR_HIP(launch_bc_sigma(mode, front, offsets, rstart, chunks, hn[d], (int64_t)hm[d], g->R, g->C,
+                             depth, sig, d + 1, adv, st));
+    }
+    // backward: dependency sums of level d - 1 from level d
+    for (int32_t d = L - 1; d >= 1; --d) {
+      if (hm[d] == 0) continue;
+      const int32_t* front = levels + off[d];
+      int mode = 0;
+      GR_TRY(prepare_level(hn[d], front, lvl_n + d, &mode));
+      GR_HIP(launch_bc_dependency(mode, front, offsets, rstart, chunks, hn[d], (int64_t)hm[d], g->R,
+                                  g->C, depth, sig, acc, d - 1, adv, st));
+    }
+    GR_HIP(launch_bc_finalize(depth, sig, acc, V, src, g->perm, bc, sigma, st));
+    // the host vectors are reused by the next source: finish their copies
+    GR_HIP(hipStreamSynchronize(st));
+    rs.iterations += L;
+    rs.teps_edges += bs.teps_edges;
+    rs.inspected_edges += bs.inspected_edges;
+    for (int a = 0; a < 4; ++a) rs.action_count[a] += bs.action_count[a];
+  }
+  GR_HIP(hipEventRecord(ctx->ev_c1, st));
+  GR_HIP(hipEventSynchronize(ctx->ev_c1));
+  if (stats) {
+    float ms = 0.f;
+    GR_TRY(elapsed_ms(ctx->ev_c0, ctx->ev_c1, &ms));
     rs.device_ms = ms;
     *stats = rs;
   }

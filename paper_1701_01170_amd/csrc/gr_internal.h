@@ -67,6 +67,13 @@ enum Slot : int {
   S_MIRROR,        // shortest-path 16-bit distance mirror [V]
   S_UL_A,          // BFS pull: unvisited vertices with neighbours (two lists, ping-pong)
   S_UL_B,
+  S_CAND,          // BFS idempotent advance: candidate list [V]
+  S_BC_DEPTH,      // betweenness centrality: depths from the current source [V]
+  S_BC_SIGMA,      // shortest-path counts [V] (double)
+  S_BC_ACC,        // dependency sums [V] (double)
+  S_BC_LEVELS,     // vertices grouped by level [V]
+  S_BC_LVL_N,      // vertices per level, then level cursors [L + 1]
+  S_BC_LVL_M,      // degree sum per level [L + 1]
   S_NSLOTS
 };
 
@@ -75,7 +82,7 @@ enum Slot : int {
 // statistics call, so each call can clear the slot the next one accumulates in.
 struct Ctrl {
   uint32_t q_count[3];      // frontier queue lengths (three rotating queues)
-  uint32_t pad1;
+  uint32_t cand_count;      // BFS idempotent advance: candidate list length (may exceed its capacity)
   int64_t m_f[2];           // sum of frontier degrees
   int64_t max_deg[2];       // largest frontier degree
   int64_t n_f[2];           // frontier size as seen by the statistics kernel
@@ -123,6 +130,7 @@ struct gr_ctx {
   std::chrono::milliseconds wait_limit{60000};
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_a = nullptr, ev_b = nullptr;
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the advance kernel when tracing
+  hipEvent_t ev_c0 = nullptr, ev_c1 = nullptr;  // around a whole call that runs BFS inside
 };
 
 struct gr_graph {
@@ -150,6 +158,15 @@ struct gr_graph {
 namespace gr {
 
 gr_status pool_get(gr_ctx* ctx, Slot s, size_t bytes, void** out);
+
+// Launch shape of the push-advance kernels (tuning knobs: the results never
+// depend on them).
+struct AdvCfg {
+  int chunk = 8192;         // LB: edges per workgroup (512 .. 16384, powers of two)
+  int block = 256;          // workgroup size: 128, 256 or 512
+  int twc_wave_min = -1;    // TWC: lists longer than this go to a wavefront (< 0: 64)
+  int twc_block_min = -1;   // TWC: lists longer than this go to the workgroup (< 0: block)
+};
 
 // ---- kernel launchers (defined in the .hip files) -----------------------------
 
@@ -216,13 +233,13 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
                            const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
                            const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
                            const int32_t* perm, int32_t next_depth, int32_t* out_q,
-                           uint32_t* out_count, int chunk, hipStream_t st);
+                           uint32_t* out_count, const AdvCfg& cfg, hipStream_t st);
 // Push with the non-atomic filter: byte marks (all zero before and after),
 // then an ordered compaction of the marked vertices.
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                  const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                  int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
-                                 int p, uint8_t* marks, int chunk, hipStream_t st);
+                                 int p, uint8_t* marks, const AdvCfg& cfg, hipStream_t st);
 hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int p, int32_t* depth,
                                    int32_t next_depth, int32_t* out_q, uint32_t* out_count,
                                    hipStream_t st);
@@ -246,6 +263,39 @@ hipError_t launch_bfs_pull_list(const int32_t* list, const uint32_t* n_list, int
                                 int32_t next_depth, int32_t* out_q, uint32_t* out_count,
                                 int64_t* inspected, int32_t* rem_q, uint32_t* rem_count,
                                 hipStream_t st);
+// Idempotent push (no atomics): survivors of the culling heuristics go to
+// cand (at most cap entries are stored; *cand_count may count more).  culls:
+// the GR_IDEM_CULL_* bits that are on; log_h: history table size (8, 10, 12).
+hipError_t launch_bfs_push_idem(int mode, const int32_t* frontier, const int32_t* offsets,
+                                const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                int64_t m_f, const int32_t* R, const int32_t* C,
+                                const uint32_t* bm, int p, int32_t* depth, int32_t next_depth,
+                                uint32_t culls, int log_h, int32_t* cand, uint32_t* cand_count,
+                                int64_t cap, const AdvCfg& cfg, hipStream_t st);
+// The exact filter after it: live bits set, each new vertex appended once.
+hipError_t launch_bfs_idem_filter(const int32_t* cand, const uint32_t* cand_count, int64_t cap,
+                                  int64_t V, uint32_t* bm, int p, const int32_t* depth,
+                                  int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                  hipStream_t st);
+// betweenness centrality (levels by counting sort of the depths, then push
+// advances per level with fp64 atomic sums; see k_bc.hip)
+hipError_t launch_bc_levels(const int32_t* depth, const int32_t* R, int64_t V, int32_t source,
+                            int32_t n_levels, uint32_t* lvl_n, unsigned long long* lvl_m,
+                            double* sigma, double* acc, hipStream_t st);
+hipError_t launch_bc_scatter(const int32_t* depth, int64_t V, int32_t n_levels, uint32_t* cursor,
+                             int32_t* levels, hipStream_t st);
+hipError_t launch_bc_sigma(int mode, const int32_t* frontier, const int32_t* offsets,
+                           const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                           int64_t m_f, const int32_t* R, const int32_t* C, const int32_t* depth,
+                           double* sigma, int32_t next_depth, const AdvCfg& cfg, hipStream_t st);
+hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t* offsets,
+                                const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                int64_t m_f, const int32_t* R, const int32_t* C,
+                                const int32_t* depth, const double* sigma, double* acc,
+                                int32_t prev_depth, const AdvCfg& cfg, hipStream_t st);
+hipError_t launch_bc_finalize(const int32_t* depth, const double* sigma, const double* acc,
+                              int64_t V, int32_t source, const int32_t* perm, double* bc,
+                              double* sigma_out, hipStream_t st);
 // live |= old (live = depth <= d + 1 after level d)
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
 
@@ -259,7 +309,7 @@ hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offset
                           int64_t m_a, const int32_t* R, const int32_t* C,
                           const unsigned long long* front, const unsigned long long* visit,
                           unsigned long long* next, int32_t* touched, uint32_t* n_touched,
-                          int chunk, hipStream_t st);
+                          const AdvCfg& cfg, hipStream_t st);
 // pull with parent nullable: when given, the pull writes the parents of the
 // vertices it reaches (the finalize of that level then gets parent = nullptr)
 hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C,
@@ -351,7 +401,7 @@ hipError_t launch_sssp_pq_relax(int mode, const int32_t* frontier, const int32_t
                                 int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
                                 unsigned long long* keys, int32_t* tags, int32_t next_tag,
                                 const PqState& pq, Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
-                                int chunk, hipStream_t st);
+                                const AdvCfg& cfg, hipStream_t st);
 // Refill: T' = T + delta; far pile fc -> next frontier (T <= dist < T') and
 // far pile (fc + 1) % 3 (dist >= T'); entries with dist < T are stale.
 hipError_t launch_sssp_pq_refill(const unsigned long long* keys, const PqState& pq, Ctrl* ctrl,
@@ -370,7 +420,7 @@ hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* o
                              const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                              int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
                              unsigned long long* keys, int32_t* tags, const int32_t* perm,
-                             int32_t next_tag, int32_t* out_q, uint32_t* out_count, int chunk,
+                             int32_t next_tag, int32_t* out_q, uint32_t* out_count, const AdvCfg& cfg,
                              hipStream_t st);
 // Relaxation with the non-atomic filter (byte marks, all zero before and after
 // the pair of calls), then the ordered list of the marked vertices.  With
@@ -381,7 +431,7 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
                                    const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
-                                   bool filter, int chunk, hipStream_t st);
+                                   bool filter, const AdvCfg& cfg, hipStream_t st);
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
                                     uint16_t* mirror, int32_t* out_q, uint32_t* out_count,
                                     hipStream_t st);

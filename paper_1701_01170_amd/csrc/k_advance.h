@@ -36,10 +36,46 @@
 //                  scan-based gather.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "gr_internal.h"
 #include "k_common.h"
 
 namespace gr {
+
+// Optional functor members.  block_init(): per-workgroup state (e.g. an LDS
+// table), run once by every thread before the first edge, followed by a
+// workgroup barrier.  out_cap: the output queue holds this many entries;
+// appends beyond it are counted in *out_count but not stored.
+template <class F, class = void>
+struct has_block_init : std::false_type {};
+template <class F>
+struct has_block_init<F, std::void_t<decltype(std::declval<const F&>().block_init())>>
+    : std::true_type {};
+template <class F, class = void>
+struct has_out_cap : std::false_type {};
+template <class F>
+struct has_out_cap<F, std::void_t<decltype(&F::out_cap)>> : std::true_type {};
+
+template <class F>
+__device__ __forceinline__ void functor_block_init(const F& f) {
+  if constexpr (has_block_init<F>::value) {
+    f.block_init();
+    __syncthreads();
+  }
+}
+
+// out_q[slot] = v, unless the functor bounds its queue and slot is past it.
+template <class F>
+__device__ __forceinline__ void put_out(const F& f, int32_t* __restrict__ out_q, uint32_t slot,
+                                        int32_t v) {
+  if constexpr (has_out_cap<F>::value) {
+    if (slot < f.out_cap) out_q[slot] = v;
+  } else {
+    out_q[slot] = v;
+  }
+}
 
 constexpr int kAdvBlock = 256;
 // Frontier segments a workgroup stages in LDS per pass: half the chunk's
@@ -54,7 +90,7 @@ constexpr int lb_cap(int chunk_edges) {
 // atomic (every thread of the workgroup must then call it the same number of
 // times): a single queue tail shared by the whole grid serialises its
 // atomics, so fewer of them is the point.
-template <class F, int B, bool AGG = false>
+template <class F, int B, bool AGG = false, int BLOCK = kAdvBlock>
 __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict__ C, bool (&ok)[B],
                                            const int32_t (&u)[B], const typename F::pay_t (&pay)[B],
                                            const int32_t (&ce)[B], int32_t* __restrict__ out_q,
@@ -97,10 +133,10 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
     }
   }
   if constexpr (AGG) {
-    uint32_t base = block_append<kAdvBlock>(n_app, out_count);
+    uint32_t base = block_append<BLOCK>(n_app, out_count);
 #pragma unroll
     for (int r = 0; r < B; ++r)
-      if (ok[r]) out_q[base++] = v[r];
+      if (ok[r]) put_out(f, out_q, base++, v[r]);
   } else {
     // wavefront-aggregated append of every lane's survivors
     const uint64_t any = __ballot(n_app != 0);
@@ -111,7 +147,7 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
     base = __shfl(base, kWave - 1) + inc - n_app;
 #pragma unroll
     for (int r = 0; r < B; ++r)
-      if (ok[r]) out_q[base++] = v[r];
+      if (ok[r]) put_out(f, out_q, base++, v[r]);
   }
 }
 
@@ -120,22 +156,23 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
 // a 16-bit segment index per edge slot comes from scattering segment starts and
 // a max-scan; the edges are then processed in NB batches of EPT per thread
 // (EPT independent loads in flight per lane).
-template <class F, int EPT, int NB>
-__global__ __launch_bounds__(kAdvBlock) void k_push_lb(
+template <class F, int EPT, int NB, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_push_lb(
     const int32_t* __restrict__ frontier, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ rstart, const int32_t* __restrict__ chunk_start, int32_t n_f,
     int32_t m_f, const int32_t* __restrict__ C, F f,
     int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count) {
-  constexpr int BATCH = kAdvBlock * EPT;
+  constexpr int BATCH = BLOCK * EPT;
   constexpr int N = BATCH * NB;
-  constexpr int SPT = N / kAdvBlock;  // segment-map slots per thread
+  constexpr int SPT = N / BLOCK;  // segment-map slots per thread
   constexpr int CAP = lb_cap(N);
   __shared__ uint16_t s_seg[N];
   __shared__ int32_t s_off[CAP + 1];
   __shared__ int32_t s_u[CAP];
   __shared__ int32_t s_rb[CAP];
   __shared__ typename F::pay_t s_pay[CAP];
-  __shared__ int32_t s_tmp[kAdvBlock / kWave + 1];
+  __shared__ int32_t s_tmp[BLOCK / kWave + 1];
+  functor_block_init(f);
   const int c = blockIdx.x;
   const int64_t e0 = (int64_t)c * N;
   const int64_t e1 = e0 + N < m_f ? e0 + N : m_f;
@@ -144,7 +181,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
   const int se = c + 1 < nchunks ? chunk_start[c + 1] : n_f - 1;
   for (int pb = sb; pb <= se; pb += CAP) {
     const int cnt = (se - pb + 1) < CAP ? (se - pb + 1) : CAP;
-    for (int i = threadIdx.x; i < cnt; i += kAdvBlock) {
+    for (int i = threadIdx.x; i < cnt; i += BLOCK) {
       const int s = pb + i;
       const int32_t u = frontier[s];
       s_off[i] = offsets[s];
@@ -153,13 +190,13 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
       s_pay[i] = f.seg_payload(u);
     }
     if (threadIdx.x == 0) s_off[cnt] = offsets[pb + cnt];
-    for (int j = threadIdx.x; j < N; j += kAdvBlock) s_seg[j] = 0;
+    for (int j = threadIdx.x; j < N; j += BLOCK) s_seg[j] = 0;
     __syncthreads();
     const int64_t lo = e0 > (int64_t)s_off[0] ? e0 : (int64_t)s_off[0];
     const int64_t hi = e1 < (int64_t)s_off[cnt] ? e1 : (int64_t)s_off[cnt];
     // starts of the non-empty segments inside [lo, hi) (exactly one non-empty
     // segment starts at any edge position; empty ones own no edge)
-    for (int k = 1 + threadIdx.x; k < cnt; k += kAdvBlock) {
+    for (int k = 1 + threadIdx.x; k < cnt; k += BLOCK) {
       const int64_t pos = (int64_t)s_off[k] - lo;
       if (pos < hi - lo && s_off[k + 1] > s_off[k]) s_seg[pos] = (uint16_t)k;
     }
@@ -199,7 +236,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
       int32_t ce[EPT];
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
-        const int j = b * BATCH + r * kAdvBlock + threadIdx.x;
+        const int j = b * BATCH + r * BLOCK + threadIdx.x;
         const int64_t e = lo + j;
         ok[r] = e < hi;
         const int k = ok[r] ? (int)s_seg[j] : 0;
@@ -207,24 +244,25 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_lb(
         pay[r] = s_pay[k];
         ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
       }
-      edge_batch<F, EPT, true>(f, C, ok, u, pay, ce, out_q, out_count);
+      edge_batch<F, EPT, true, BLOCK>(f, C, ok, u, pay, ce, out_q, out_count);
     }
     __syncthreads();
   }
 }
 
-template <class F>
-__global__ __launch_bounds__(kAdvBlock) void k_push_light(
+template <class F, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_push_light(
     const int32_t* __restrict__ frontier, int32_t n_f, const int32_t* __restrict__ R,
     const int32_t* __restrict__ C, F f, int32_t* __restrict__ out_q,
     uint32_t* __restrict__ out_count) {
   constexpr int B = 4;
-  __shared__ int32_t s_off[kAdvBlock];
-  __shared__ int32_t s_u[kAdvBlock];
-  __shared__ int32_t s_rb[kAdvBlock];
-  __shared__ typename F::pay_t s_pay[kAdvBlock];
-  __shared__ int64_t s_tot[kAdvBlock / kWave + 1];
-  const int64_t i = (int64_t)blockIdx.x * kAdvBlock + threadIdx.x;
+  __shared__ int32_t s_off[BLOCK];
+  __shared__ int32_t s_u[BLOCK];
+  __shared__ int32_t s_rb[BLOCK];
+  __shared__ typename F::pay_t s_pay[BLOCK];
+  __shared__ int64_t s_tot[BLOCK / kWave + 1];
+  functor_block_init(f);
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   int32_t u0 = 0, rb = 0, d = 0;
   typename F::pay_t pay0 = 0;
   if (i < n_f) {
@@ -234,36 +272,39 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_light(
     pay0 = f.seg_payload(u0);
   }
   int64_t total;
-  const int64_t ex = block_excl_scan<kAdvBlock>((int64_t)d, s_tot, &total);
+  const int64_t ex = block_excl_scan<BLOCK>((int64_t)d, s_tot, &total);
   s_off[threadIdx.x] = (int32_t)ex;
   s_u[threadIdx.x] = u0;
   s_rb[threadIdx.x] = rb;
   s_pay[threadIdx.x] = pay0;
   __syncthreads();
-  for (int64_t base = 0; base < total; base += (int64_t)kAdvBlock * B) {
+  for (int64_t base = 0; base < total; base += (int64_t)BLOCK * B) {
     bool ok[B];
     int32_t u[B];
     typename F::pay_t pay[B];
     int32_t ce[B];
 #pragma unroll
     for (int r = 0; r < B; ++r) {
-      const int64_t e = base + r * kAdvBlock + threadIdx.x;
+      const int64_t e = base + r * BLOCK + threadIdx.x;
       ok[r] = e < total;
-      const int k = ok[r] ? upper_index(s_off, 0, kAdvBlock - 1, e) : 0;
+      const int k = ok[r] ? upper_index(s_off, 0, BLOCK - 1, e) : 0;
       u[r] = s_u[k];
       pay[r] = s_pay[k];
       ce[r] = s_rb[k] + (int32_t)(e - s_off[k]);
     }
-    edge_batch<F, B, true>(f, C, ok, u, pay, ce, out_q, out_count);
+    edge_batch<F, B, true, BLOCK>(f, C, ok, u, pay, ce, out_q, out_count);
   }
 }
 
-template <class F>
-__global__ __launch_bounds__(kAdvBlock) void k_push_twc(
+// TWC tiers: lists longer than block_min are expanded by the whole
+// workgroup, lists longer than wave_min by one wavefront, the rest by the
+// lane-tier gather (0 <= wave_min <= block_min; any split is correct).
+template <class F, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_push_twc(
     const int32_t* __restrict__ frontier, int32_t n_f, const int32_t* __restrict__ R,
     const int32_t* __restrict__ C, F f, int32_t* __restrict__ out_q,
-    uint32_t* __restrict__ out_count) {
-  constexpr int NW = kAdvBlock / kWave;
+    uint32_t* __restrict__ out_count, int32_t wave_min, int32_t block_min) {
+  constexpr int NW = BLOCK / kWave;
   constexpr int B = 4;
   __shared__ int32_t s_claim;
   __shared__ int32_t s_cu, s_crb, s_cd;
@@ -272,7 +313,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
   __shared__ int32_t s_wu[NW][kWave];
   __shared__ int32_t s_wrb[NW][kWave];
   __shared__ typename F::pay_t s_wpay[NW][kWave];
-  const int64_t i = (int64_t)blockIdx.x * kAdvBlock + threadIdx.x;
+  functor_block_init(f);
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int w = threadIdx.x / kWave;
   int32_t u0 = 0, rb = 0, d = 0;
   typename F::pay_t pay0 = 0;
@@ -282,8 +324,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
     d = R[u0 + 1] - rb;
     pay0 = f.seg_payload(u0);
   }
-  // workgroup tier: lists longer than the workgroup
-  bool big = d > kAdvBlock;
+  // workgroup tier
+  bool big = d > block_min;
   for (;;) {
     if (threadIdx.x == 0) s_claim = -1;
     __syncthreads();
@@ -301,14 +343,14 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
     __syncthreads();
     const int32_t cu = s_cu, crb = s_crb, cd = s_cd;
     const typename F::pay_t cpay = s_cpay;
-    for (int base = 0; base < cd; base += kAdvBlock * B) {
+    for (int base = 0; base < cd; base += BLOCK * B) {
       bool ok[B];
       int32_t u[B];
-    typename F::pay_t pay[B];
+      typename F::pay_t pay[B];
       int32_t ce[B];
 #pragma unroll
       for (int r = 0; r < B; ++r) {
-        const int j = base + r * kAdvBlock + threadIdx.x;
+        const int j = base + r * BLOCK + threadIdx.x;
         ok[r] = j < cd;
         u[r] = cu;
         pay[r] = cpay;
@@ -318,29 +360,31 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
     }
     __syncthreads();
   }
-  // wavefront tier: lists longer than a wavefront
-  uint64_t med = __ballot(d > kWave && d <= kAdvBlock);
+  // wavefront tier
+  uint64_t med = __ballot(d > wave_min && d <= block_min);
   while (med) {
     const int l = __ffsll((unsigned long long)med) - 1;
     med &= med - 1;
     const int32_t cu = __shfl(u0, l), crb = __shfl(rb, l), cd = __shfl(d, l);
     const typename F::pay_t cpay = __shfl(pay0, l);
-    bool ok[B];
-    int32_t u[B];
-    typename F::pay_t pay[B];
-    int32_t ce[B];
+    for (int base = 0; base < cd; base += kWave * B) {
+      bool ok[B];
+      int32_t u[B];
+      typename F::pay_t pay[B];
+      int32_t ce[B];
 #pragma unroll
-    for (int r = 0; r < B; ++r) {
-      const int j = r * kWave + lane();
-      ok[r] = j < cd;
-      u[r] = cu;
-      pay[r] = cpay;
-      ce[r] = crb + j;
+      for (int r = 0; r < B; ++r) {
+        const int j = base + r * kWave + lane();
+        ok[r] = j < cd;
+        u[r] = cu;
+        pay[r] = cpay;
+        ce[r] = crb + j;
+      }
+      edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
     }
-    edge_batch<F, B>(f, C, ok, u, pay, ce, out_q, out_count);
   }
   // lane tier: scan-based gather of the short lists across the wavefront
-  const int32_t ds = d <= kWave ? d : 0;
+  const int32_t ds = d <= wave_min ? d : 0;
   const int32_t inc = wave_incl_scan(ds);
   const int32_t tot = __shfl(inc, kWave - 1);
   s_woff[w][lane()] = inc - ds;
@@ -369,51 +413,79 @@ __global__ __launch_bounds__(kAdvBlock) void k_push_twc(
 
 inline unsigned adv_blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// mode: 0 = TWC, 1 = LB_LIGHT, 2 = LB with `chunk` edges per workgroup
-// (512, 1024, 2048, 4096, 8192 or 16384).
-template <class F>
-inline hipError_t push_dispatch(int mode, const int32_t* frontier, const int32_t* offsets,
-                         const int32_t* rstart, const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
-                         const int32_t* C, const F& f, int32_t* out_q, uint32_t* out_count,
-                         int chunk, hipStream_t st) {
-  if (n_f <= 0) return hipSuccess;
+// Output-balanced LB with `chunk` edges per workgroup of BLOCK threads: EPT
+// edges per thread per batch (at most 32 in flight; 16 with 512 threads, whose
+// waves get at most 128 vector registers), NB batches.
+template <class F, int BLOCK>
+inline void launch_lb(int chunk, unsigned g, const int32_t* frontier, const int32_t* offsets,
+                      const int32_t* rstart, const int32_t* chunk_start, int32_t n_f, int32_t m_f,
+                      const int32_t* C, const F& f, int32_t* out_q, uint32_t* out_count,
+                      hipStream_t st) {
+#define GR_LB(CH)                                                                              \
+  case CH: {                                                                                   \
+    constexpr int cap = BLOCK >= 512 ? 16 : 32;                                                \
+    constexpr int ept = (CH / BLOCK) < cap ? (CH / BLOCK) : cap;                               \
+    constexpr int nb = CH / (BLOCK * ept);                                                     \
+    k_push_lb<F, ept, nb, BLOCK><<<g, BLOCK, 0, st>>>(frontier, offsets, rstart, chunk_start,   \
+                                                     n_f, m_f, C, f, out_q, out_count);          \
+    break;                                                                                     \
+  }
+  switch (chunk) {
+    GR_LB(512)
+    GR_LB(1024)
+    GR_LB(2048)
+    GR_LB(4096)
+    GR_LB(16384)
+    default:
+      GR_LB(8192)
+  }
+#undef GR_LB
+}
+
+template <class F, int BLOCK>
+inline hipError_t push_dispatch_block(int mode, const int32_t* frontier, const int32_t* offsets,
+                                      const int32_t* rstart, const int32_t* chunk_start,
+                                      int64_t n_f, int64_t m_f, const int32_t* R,
+                                      const int32_t* C, const F& f, int32_t* out_q,
+                                      uint32_t* out_count, const AdvCfg& cfg, hipStream_t st) {
   if (mode == 0) {
-    k_push_twc<F><<<adv_blocks(n_f, kAdvBlock), kAdvBlock, 0, st>>>(frontier, (int32_t)n_f, R, C, f,
-                                                                   out_q, out_count);
+    int32_t wmin = cfg.twc_wave_min >= 0 ? cfg.twc_wave_min : kWave;
+    int32_t bmin = cfg.twc_block_min >= 0 ? cfg.twc_block_min : BLOCK;
+    if (bmin < wmin) bmin = wmin;
+    k_push_twc<F, BLOCK><<<adv_blocks(n_f, BLOCK), BLOCK, 0, st>>>(
+        frontier, (int32_t)n_f, R, C, f, out_q, out_count, wmin, bmin);
   } else if (mode == 1) {
-    k_push_light<F><<<adv_blocks(n_f, kAdvBlock), kAdvBlock, 0, st>>>(frontier, (int32_t)n_f, R, C,
-                                                                     f, out_q, out_count);
+    k_push_light<F, BLOCK><<<adv_blocks(n_f, BLOCK), BLOCK, 0, st>>>(frontier, (int32_t)n_f, R, C,
+                                                                   f, out_q, out_count);
   } else {
     if (m_f <= 0) return hipSuccess;
-    const unsigned g = adv_blocks(m_f, chunk);
-    switch (chunk) {
-      case 512:
-        k_push_lb<F, 2, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
-                                                    (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
-        break;
-      case 1024:
-        k_push_lb<F, 4, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
-                                                    (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
-        break;
-      case 2048:
-        k_push_lb<F, 8, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
-                                                    (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
-        break;
-      case 4096:
-        k_push_lb<F, 16, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
-                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
-        break;
-      case 16384:
-        k_push_lb<F, 32, 2><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
-                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
-        break;
-      default:
-        k_push_lb<F, 32, 1><<<g, kAdvBlock, 0, st>>>(frontier, offsets, rstart, chunk_start,
-                                                     (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count);
-        break;
-    }
+    launch_lb<F, BLOCK>(cfg.chunk, adv_blocks(m_f, cfg.chunk), frontier, offsets, rstart,
+                        chunk_start, (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count, st);
   }
   return hipGetLastError();
+}
+
+// mode: 0 = TWC, 1 = LB_LIGHT, 2 = LB with cfg.chunk edges per workgroup
+// (512, 1024, 2048, 4096, 8192 or 16384); workgroups of cfg.block threads
+// (128, 256 or 512).
+template <class F>
+inline hipError_t push_dispatch(int mode, const int32_t* frontier, const int32_t* offsets,
+                                const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                int64_t m_f, const int32_t* R, const int32_t* C, const F& f,
+                                int32_t* out_q, uint32_t* out_count, const AdvCfg& cfg,
+                                hipStream_t st) {
+  if (n_f <= 0) return hipSuccess;
+  switch (cfg.block) {
+    case 128:
+      return push_dispatch_block<F, 128>(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R,
+                                         C, f, out_q, out_count, cfg, st);
+    case 512:
+      return push_dispatch_block<F, 512>(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R,
+                                         C, f, out_q, out_count, cfg, st);
+    default:
+      return push_dispatch_block<F, 256>(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R,
+                                         C, f, out_q, out_count, cfg, st);
+  }
 }
 
 }  // namespace gr

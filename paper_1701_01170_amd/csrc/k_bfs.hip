@@ -135,6 +135,165 @@ struct BfsMark {
   }
 };
 
+// Idempotent push (Sec. 5.2, idempotent vs. non-idempotent operations).  The
+// BFS visit is idempotent -- every discoverer of v stores the same depth -- so
+// this advance takes no atomic at all.  Repeated discoveries of a vertex are
+// culled by inexpensive, inexact heuristics (the paper's global bitmask, block
+// level history table and warp level table), in this order:
+//   probe   the visited bitmap (old: depth <= d; one bit, cache resident);
+//   HISTORY a per-workgroup table in LDS, slot = multiplicative hash of v: v
+//           is dropped when its slot holds v;
+//   WAVE    a per-wavefront table of 128 slots: the lanes of one batch write
+//           their v, then those that read their own v back write a tag (lane,
+//           edge); of the lanes holding the same v only the one whose tag
+//           survives keeps it;
+//   LABEL   the depth label: v is dropped when some lane already wrote d + 1.
+// A survivor stores depth d + 1, enters the history table and is appended to
+// the candidate list.  Each heuristic drops v only when some lane keeps v (a
+// table slot holds v only if a lane kept it; a written label was written by a
+// lane that keeps v), so no vertex is lost; races between wavefronts only let
+// duplicates through.  k_bfs_idem_filter removes those exactly.
+constexpr int kIdemWaveSlots = 128;
+
+template <int LOG_H>
+__device__ __forceinline__ int32_t* idem_history() {
+  __shared__ int32_t t[1 << LOG_H];
+  return t;
+}
+
+__device__ __forceinline__ int32_t* idem_wave_table(int which) {
+  __shared__ int32_t t[2][512 / kWave][kIdemWaveSlots];  // up to 512-thread workgroups
+  return t[which][threadIdx.x / kWave];
+}
+
+template <int LOG_H>
+struct BfsIdem {
+  const uint32_t* __restrict__ bm;
+  int32_t* __restrict__ depth;
+  int32_t next_depth;
+  int32_t p;
+  uint32_t culls;    // GR_IDEM_CULL_* bits that are on
+  uint32_t out_cap;  // candidate list capacity
+
+  using pay_t = int32_t;
+  static constexpr bool kFar = false;
+  static constexpr bool kBatchCommit = true;
+  __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
+  __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
+  __device__ __forceinline__ static uint32_t slot(int32_t v) {
+    return ((uint32_t)v * 2654435761u) >> (32 - LOG_H);
+  }
+  __device__ __forceinline__ void block_init() const {
+    int32_t* h = idem_history<LOG_H>();
+    for (int i = threadIdx.x; i < (1 << LOG_H); i += (int)blockDim.x) h[i] = -1;
+  }
+  __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
+    const uint2 x = bm_pair(bm, v >> 5);
+    return !(((p ? x.y : x.x) >> (v & 31)) & 1u);
+  }
+  __device__ __forceinline__ bool commit(int32_t, int32_t, int32_t, uint32_t) const { return false; }
+  template <int B>
+  __device__ __forceinline__ void commit_batch(const int32_t (&)[B], const int32_t (&)[B],
+                                               const int32_t (&v)[B], const uint32_t (&)[B],
+                                               const bool (&ok)[B], int (&code)[B]) const {
+    int32_t* hist = idem_history<LOG_H>();
+    bool keep[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) keep[r] = ok[r];
+    if (culls & GR_IDEM_CULL_HISTORY) {
+#pragma unroll
+      for (int r = 0; r < B; ++r) keep[r] = keep[r] && hist[slot(v[r])] != v[r];
+    }
+    if (culls & GR_IDEM_CULL_WAVE) {
+      // every lane of the wavefront is here (edge_batch's contract)
+      int32_t* vals = idem_wave_table(0);
+      int32_t* tags = idem_wave_table(1);
+      bool mine[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (keep[r]) vals[v[r] & (kIdemWaveSlots - 1)] = v[r];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+      for (int r = 0; r < B; ++r) mine[r] = keep[r] && vals[v[r] & (kIdemWaveSlots - 1)] == v[r];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (mine[r]) tags[v[r] & (kIdemWaveSlots - 1)] = lane() * B + r;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (mine[r]) keep[r] = tags[v[r] & (kIdemWaveSlots - 1)] == lane() * B + r;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    if (culls & GR_IDEM_CULL_LABEL) {
+      int32_t dv[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r) dv[r] = keep[r] ? depth[v[r]] : -1;
+#pragma unroll
+      for (int r = 0; r < B; ++r) keep[r] = keep[r] && dv[r] < 0;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      code[r] = keep[r] ? 1 : 0;
+      if (keep[r]) {
+        depth[v[r]] = next_depth;
+        if (culls & GR_IDEM_CULL_HISTORY) hist[slot(v[r])] = v[r];
+      }
+    }
+  }
+};
+
+// The exact filter after the idempotent advance.  Each candidate's live bit is
+// set with an atomic OR and the lane that set it appends the vertex, so the
+// next frontier holds every new vertex once.  When the candidates outgrew the
+// list (more than cap), the list is incomplete and the pass instead reads the
+// depth labels of all V vertices: every vertex discovered this level has depth
+// d + 1 (its keeper wrote it) and no live bit yet.  Grid-stride; the branch is
+// the same for every workgroup.
+__global__ __launch_bounds__(256) void k_bfs_idem_filter(const int32_t* __restrict__ cand,
+                                                         const uint32_t* __restrict__ n_cand,
+                                                         int64_t cap, int64_t V,
+                                                         uint32_t* __restrict__ bm, int p,
+                                                         const int32_t* __restrict__ depth,
+                                                         int32_t next_depth,
+                                                         int32_t* __restrict__ out_q,
+                                                         uint32_t* __restrict__ out_count) {
+  const int64_t n = *n_cand;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  if (n <= cap) {
+    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < n; b0 += stride) {
+      const int64_t i = b0 + threadIdx.x;
+      bool first = false;
+      int32_t v = 0;
+      if (i < n) {
+        v = cand[i];
+        const uint32_t bit = 1u << (v & 31);
+        first = !(atomicOr(&bm[2 * (v >> 5) + 1 - p], bit) & bit);
+      }
+      const uint32_t a = block_append<256>(first ? 1u : 0u, out_count);
+      if (first) out_q[a] = v;
+    }
+  } else {
+    const int64_t nw = (V + 31) / 32;
+    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < nw; b0 += stride) {
+      const int64_t w = b0 + threadIdx.x;
+      uint32_t mask = 0;
+      if (w < nw) {
+        const int64_t v0 = w * 32;
+        for (int b = 0; b < 32; ++b)
+          if (v0 + b < V && depth[v0 + b] == next_depth) mask |= 1u << b;
+        // this thread is the only writer of the word in this branch
+        if (mask) bm[2 * w + 1 - p] |= mask;
+      }
+      append_mask<256>(mask, w, out_q, out_count);
+    }
+  }
+}
+
 // One thread per bitmap word (32 vertices): gather the marks, clear them, set
 // the live bits (the thread owns the word), write depths and append the new
 // vertices in ascending order within each workgroup (one atomic per workgroup).
@@ -501,24 +660,58 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
                            const int32_t* chunk_start, int64_t n_f, int64_t m_f, const int32_t* R,
                            const int32_t* C, uint32_t* bm, int p, int32_t* depth, int32_t* parent,
                            const int32_t* perm, int32_t next_depth, int32_t* out_q,
-                           uint32_t* out_count, int chunk, hipStream_t st) {
+                           uint32_t* out_count, const AdvCfg& cfg, hipStream_t st) {
   if (atomic_parent) {
     BfsVisit<true> f{bm, depth, parent, perm, next_depth, p};
     return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
-                         out_count, chunk, st);
+                         out_count, cfg, st);
   }
   BfsVisit<false> f{bm, depth, nullptr, nullptr, next_depth, p};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
-                       out_count, chunk, st);
+                       out_count, cfg, st);
 }
 
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                  const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                  int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
-                                 int p, uint8_t* marks, int chunk, hipStream_t st) {
+                                 int p, uint8_t* marks, const AdvCfg& cfg, hipStream_t st) {
   BfsMark f{bm, marks, p};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
-                       nullptr, chunk, st);
+                       nullptr, cfg, st);
+}
+
+hipError_t launch_bfs_push_idem(int mode, const int32_t* frontier, const int32_t* offsets,
+                                const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                                int64_t m_f, const int32_t* R, const int32_t* C,
+                                const uint32_t* bm, int p, int32_t* depth, int32_t next_depth,
+                                uint32_t culls, int log_h, int32_t* cand, uint32_t* cand_count,
+                                int64_t cap, const AdvCfg& cfg, hipStream_t st) {
+  const uint32_t c32 = cap < (int64_t)UINT32_MAX ? (uint32_t)cap : UINT32_MAX;
+  if (log_h == 8) {
+    BfsIdem<8> f{bm, depth, next_depth, p, culls, c32};
+    return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, cand,
+                         cand_count, cfg, st);
+  }
+  if (log_h == 12) {
+    BfsIdem<12> f{bm, depth, next_depth, p, culls, c32};
+    return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, cand,
+                         cand_count, cfg, st);
+  }
+  BfsIdem<10> f{bm, depth, next_depth, p, culls, c32};
+  return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, cand,
+                       cand_count, cfg, st);
+}
+
+hipError_t launch_bfs_idem_filter(const int32_t* cand, const uint32_t* cand_count, int64_t cap,
+                                  int64_t V, uint32_t* bm, int p, const int32_t* depth,
+                                  int32_t next_depth, int32_t* out_q, uint32_t* out_count,
+                                  hipStream_t st) {
+  int64_t g = blocks_for(std::max<int64_t>(cap, (V + 31) / 32), 256);
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  k_bfs_idem_filter<<<(unsigned)g, 256, 0, st>>>(cand, cand_count, cap, V, bm, p, depth,
+                                                 next_depth, out_q, out_count);
+  return hipGetLastError();
 }
 
 hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int p, int32_t* depth,

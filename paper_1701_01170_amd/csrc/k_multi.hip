@@ -284,10 +284,10 @@ hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offset
                           const int32_t* rstart, const int32_t* chunk_start, int64_t n_a,
                           int64_t m_a, const int32_t* R, const int32_t* C, const u64* front,
                           const u64* visit, u64* next, int32_t* touched, uint32_t* n_touched,
-                          int chunk, hipStream_t st) {
+                          const AdvCfg& cfg, hipStream_t st) {
   MsPush f{visit, next, front};
   return push_dispatch(mode, active, offsets, rstart, chunk_start, n_a, m_a, R, C, f, touched,
-                       n_touched, chunk, st);
+                       n_touched, cfg, st);
 }
 
 hipError_t launch_ms_pull(int64_t V, const int32_t* R, const int32_t* C, const u64* front,

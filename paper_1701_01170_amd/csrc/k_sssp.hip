@@ -522,11 +522,11 @@ hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* o
                              const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                              int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
                              unsigned long long* keys, int32_t* tags, const int32_t* perm,
-                             int32_t next_tag, int32_t* out_q, uint32_t* out_count, int chunk,
+                             int32_t next_tag, int32_t* out_q, uint32_t* out_count, const AdvCfg& cfg,
                              hipStream_t st) {
   SsspVisit f{W, keys, tags, perm, next_tag};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
-                       out_count, chunk, st);
+                       out_count, cfg, st);
 }
 
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
@@ -566,10 +566,10 @@ hipError_t launch_sssp_pq_relax(int mode, const int32_t* frontier, const int32_t
                                 int64_t m_f, const int32_t* R, const int32_t* C, const uint32_t* W,
                                 unsigned long long* keys, int32_t* tags, int32_t next_tag,
                                 const PqState& pq, Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
-                                int chunk, hipStream_t st) {
+                                const AdvCfg& cfg, hipStream_t st) {
   const SsspPqVisit f = pq_functor(W, keys, tags, next_tag, pq, ctrl);
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, out_q,
-                       out_count, chunk, st);
+                       out_count, cfg, st);
 }
 
 hipError_t launch_sssp_pq_refill(const unsigned long long* keys, const PqState& pq, Ctrl* ctrl,
@@ -593,15 +593,15 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
                                    const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
-                                   bool filter, int chunk, hipStream_t st) {
+                                   bool filter, const AdvCfg& cfg, hipStream_t st) {
   if (filter) {
     const SsspMark<true> f{W, keys, marks, perm, mirror};
     return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
-                         nullptr, chunk, st);
+                         nullptr, cfg, st);
   }
   const SsspMark<false> f{W, keys, marks, perm, mirror};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
-                       nullptr, chunk, st);
+                       nullptr, cfg, st);
 }
 
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,

@@ -39,6 +39,19 @@ POLICIES = [
     ("dl_tiny", dict(device_max_edges=64)),
     ("dl_fixed_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC,
                           device_max_edges=1 << 24)),
+    # launch shapes the autotuner sweeps: workgroup size and TWC tier cut-offs
+    ("block128_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
+                         adv_block=128, device_max_edges=-1)),
+    ("block512_lb16384", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
+                              adv_block=512, lb_chunk=16384, device_max_edges=-1)),
+    ("block512_light", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB,
+                            lb_light_threshold=1 << 30, adv_block=512, device_max_edges=-1)),
+    ("block128_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC, adv_block=128,
+                          device_max_edges=-1)),
+    ("twc_tiers_small", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC, twc_wave_min=4,
+                             twc_block_min=9, adv_block=512, device_max_edges=-1)),
+    ("twc_tiers_large", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC, twc_wave_min=700,
+                             twc_block_min=100000, device_max_edges=-1)),
 ]
 # SSSP also runs with the two-level priority queue: one-distance buckets
 # (delta 1), small and large buckets, refills on the host and inside device
