@@ -10,12 +10,17 @@ per (gfx arch, graph class, size bucket, traversal) in `tuning/<arch>.json`.
 Search (coordinate descent from the paper's defaults):
   1. lb_light_threshold in {0, 1024, 4096}
   2. lb_chunk in {512, 1024, 2048, 4096, 8192, 16384}
-  3. lb_min_avg_degree in {0 (always LB), 5 (paper), inf (always TWC)}
-  4. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8}
-  5. BFS / SSSP: device_max_edges in {off, 2^16, 2^18, 2^20} (edge bound of
-     the device-predicated level blocks)
+  3. adv_block (workgroup size of the push kernels) in {128, 256, 512}
+  4. lb_min_avg_degree in {0 (always LB), 5 (paper), inf (always TWC)}
+  5. while TWC is in use: its tier cut-offs, twc_wave_min in {16, 32, 64,
+     128, 256} and twc_block_min in {64, ..., 4096} (lists longer than these
+     go to a wavefront / the whole workgroup)
   6. SSSP only: sssp_delta in {0 (no priority queue), 8, 16, ..., 256}
-Batched BFS ("bfs_multi", 64 sources per call) searches 1, 2 and its
+  7. BFS / SSSP: device_max_edges in {off, 2^16, 2^18, 2^20} (edge bound of
+     the device-predicated level blocks)
+  8. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8},
+     then bfs_filter in {auto, atomic, idempotent} (Sec. 5.2)
+Batched BFS ("bfs_multi", 64 sources per call) searches 1, 2, 3 and its
 push -> pull switch do_a in {1/4 .. 1/64}.
 
 The tuned values only change the time taken; results are identical for every
@@ -40,7 +45,10 @@ TUNING_DIR = os.path.join(HERE, "tuning")
 ARCH = "gfx950"
 
 KNOBS = ("lb_light_threshold", "lb_chunk", "lb_min_avg_degree", "do_a", "do_b", "device_max_edges",
-         "sssp_delta")
+         "sssp_delta", "adv_block", "twc_wave_min", "twc_block_min", "bfs_filter")
+ADV_BLOCK = [128, 256, 512]
+TWC_WAVE_MIN = [16, 32, 64, 128, 256]
+TWC_BLOCK_MIN = [64, 128, 256, 512, 1024, 4096]
 SSSP_DELTA = [0, 8, 16, 32, 64, 128, 256]
 DEVICE_MAX_EDGES = [-1, 1 << 16, 1 << 18, 1 << 20]
 MULTI_DO_A = [1 / 4, 1 / 8, 1 / 16, 1 / 32, 1 / 64]
@@ -123,21 +131,31 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
     best_ms = base_ms
     log(f"[{kind}] paper defaults: {base_ms:.3f} ms")
 
-    def try_set(key, values):
+    def try_set(key, values, valid=lambda c: True):
         nonlocal best, best_ms
         for v in values:
             cand = dict(best, **{key: v})
+            if not valid(cand):
+                continue
             ms = _time(g, kind, sources, cand)
             log(f"[{kind}] {key}={v:.6g}: {ms:.3f} ms")
             if ms < best_ms * 0.99:
                 best, best_ms = cand, ms
 
+    def tiers_ok(c):
+        w, b = c.get("twc_wave_min", 0), c.get("twc_block_min", 0)
+        return not (w > 0 and b > 0 and b < w)
+
     try_set("lb_light_threshold", [0, 1024, 4096])
     try_set("lb_chunk", [512, 1024, 2048, 4096, 8192, 16384])
+    try_set("adv_block", ADV_BLOCK)
     if kind == "bfs_multi":
         try_set("do_a", MULTI_DO_A)
         return best, best_ms, base_ms
     try_set("lb_min_avg_degree", [0.0, 5.0, 1e9])
+    if g.n_edges < best["lb_min_avg_degree"] * g.n_vertices:  # TWC expands the push levels
+        try_set("twc_wave_min", TWC_WAVE_MIN, tiers_ok)
+        try_set("twc_block_min", TWC_BLOCK_MIN, tiers_ok)
     if kind == "sssp":
         try_set("sssp_delta", SSSP_DELTA)
     try_set("device_max_edges", DEVICE_MAX_EDGES)
@@ -149,6 +167,7 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
                 log(f"[{kind}] do_a=1/{1 / a:.0f} do_b=1/{1 / b:.0f}: {ms:.3f} ms")
                 if ms < best_ms * 0.99:
                     best, best_ms = cand, ms
+        try_set("bfs_filter", [0, 1, 2])
     return best, best_ms, base_ms
 
 

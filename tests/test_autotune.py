@@ -30,3 +30,25 @@ def test_lookup_nearest_bucket(tmp_path, monkeypatch):
     assert at.lookup(fake(1 << 14, 400_000, 3000), "bfs") == {"lb_chunk": 2048}
     assert at.lookup(g, "sssp") is None
     assert at.lookup(fake(1 << 22, 16_000_000, 4), "bfs") == {"lb_chunk": 4096}
+
+
+def test_tuner_sweeps_every_launch_knob(monkeypatch):
+    """The coordinate search visits the workgroup size, both TWC tier cut-offs
+    (on a graph that expands with TWC) and the BFS filter, and never asks for
+    a tier split the library rejects (block tier below the wave tier)."""
+    seen = []
+
+    def fake_time(g, kind, sources, knobs, reps=1):
+        seen.append(dict(knobs))
+        w, b = knobs.get("twc_wave_min", 0), knobs.get("twc_block_min", 0)
+        assert not (w > 0 and b > 0 and b < w)
+        return 1.0 + 0.01 * (knobs.get("adv_block") == 512) - 0.5 * (knobs.get("twc_wave_min") == 32)
+
+    monkeypatch.setattr(at, "_time", fake_time)
+    g = fake(1 << 20, 4 << 20, 4)  # average degree 4: below the LB cut of 5, so TWC
+    best, best_ms, base = at.tune(g, "bfs", [0], log=lambda m: None)
+    keys = {k for kn in seen for k, v in kn.items() if v}
+    assert {"adv_block", "twc_wave_min", "twc_block_min", "bfs_filter"} <= keys
+    assert {kn.get("adv_block") for kn in seen} >= {128, 256, 512}
+    assert best["twc_wave_min"] == 32 and best_ms == 0.5
+    assert set(best) == set(at.KNOBS)
