@@ -306,6 +306,21 @@ def rmat14(gr, gg, ctx) -> dict:
            "bfs_median_us": round(1e3 * statistics.median(ms), 2),
            "bfs_min_us": round(1e3 * min(ms), 2), "bfs_max_us": round(1e3 * max(ms), 2),
            "bfs_gteps": _gteps(sum(te), sum(ms)), "sources": len(srcs)}
+    # iteration control: per-level cost with device blocks (enqueued, or
+    # recorded as hipGraphs) and with a host round trip per level
+    levels = {}
+    for label, kw in (("device_blocks", {}), ("device_blocks_graph", {"graph_blocks": 1}),
+                      ("host_loop", {"device_max_edges": -1})):
+        o = autotune.tuned_opts(g, "bfs", **kw)
+        gr.bfs(g, int(srcs[0]), opts=o)
+        tot_ms = tot_it = 0
+        for s in srcs:
+            st = gr.bfs(g, int(s), opts=o)[2]
+            tot_ms += st["device_ms"]
+            tot_it += st["iterations"]
+        levels[label] = {"us_per_level": round(1e3 * tot_ms / max(1, tot_it), 2),
+                         "bfs_mean_us": round(1e3 * tot_ms / len(srcs), 2)}
+    out["iteration_control"] = levels
     out["learned_vs_heuristic"] = learned_vs_heuristic(gr, g, ctx, gg.sources(hg, 20, seed=1100))
     g.free()
     return out
@@ -323,7 +338,8 @@ def extras(gr, gg, ctx, torch, log):
     g = gr.Graph.from_host(ctx, hg, symmetric=True)
     s = int(gg.sources(hg, 1, seed=1000)[0])
     row = {}
-    for label, kw in (("device_blocks", {}), ("host_loop", {"device_max_edges": -1})):
+    for label, kw in (("device_blocks", {}), ("device_blocks_graph", {"graph_blocks": 1}),
+                      ("host_loop", {"device_max_edges": -1})):
         ob = autotune.tuned_opts(g, "bfs", **kw)
         os_ = autotune.tuned_opts(g, "sssp", **kw)
         gr.bfs(g, s, opts=ob)

@@ -161,7 +161,11 @@ typedef struct gr_opts {
                                 this are expanded by one wavefront (0: default 64) ... */
   int32_t twc_block_min;     /* ... and lists longer than this by the whole workgroup (0: default
                                 adv_block); must be >= twc_wave_min when both are set */
-  int32_t reserved;
+  int32_t graph_blocks;      /* iteration control: 1 = each block of device-predicated levels (see
+                                device_max_edges) is recorded as a hipGraph and launched as one
+                                graph (the instantiated graph of a block of the same length is
+                                kept in the context and updated); 0 = the block's kernels are
+                                enqueued one by one.  Ignored while tracing and by gr_bfs_static. */
 } gr_opts;
 
 /* gr_opts.bfs_filter (Sec. 5.2: idempotent vs. non-idempotent operations).

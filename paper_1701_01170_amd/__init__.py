@@ -65,7 +65,7 @@ class Opts(ctypes.Structure):
                 ("learned_margin", ctypes.c_float), ("bfs_filter", ctypes.c_int32),
                 ("idem_culls_off", ctypes.c_int32), ("idem_table_log2", ctypes.c_int32),
                 ("adv_block", ctypes.c_int32), ("twc_wave_min", ctypes.c_int32),
-                ("twc_block_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("twc_block_min", ctypes.c_int32), ("graph_blocks", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):

@@ -316,6 +316,8 @@ extern "C" gr_status gr_ctx_destroy(gr_ctx* c) {
   for (auto& b : c->pool)
     if (b.ptr) (void)hipFree(b.ptr);
   if (c->host_ctrl) (void)hipHostFree(c->host_ctrl);
+  for (auto& kv : c->block_graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t ev : {c->ev_start, c->ev_stop, c->ev_a, c->ev_b, c->ev_k0, c->ev_k1, c->ev_c0,
                         c->ev_c1})
     if (ev) (void)hipEventDestroy(ev);
@@ -580,6 +582,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->twc_wave_min / twc_block_min must be >= 0");
   if (opts->twc_wave_min > 0 && opts->twc_block_min > 0 && opts->twc_block_min < opts->twc_wave_min)
     return fail(GR_EINVAL, "opts->twc_block_min must be >= twc_wave_min");
+  if (opts->graph_blocks != 0 && opts->graph_blocks != 1)
+    return fail(GR_EINVAL, "opts->graph_blocks must be 0 or 1");
   if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
     return fail(GR_EINVAL, "opts->bfs_filter out of range");
   if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
@@ -674,7 +678,69 @@ struct DlPlan {
   int len = kDlFirstLen;
   int blocks = 256;
   int64_t* log = nullptr;
+  bool graph = false;   // record each block as a hipGraph
 };
+constexpr int kGraphKeyBfs = 0, kGraphKeySssp = 1, kGraphKeySsspPq = 2;
+
+// hipGraph iteration control.  While a block of device-predicated levels is
+// enqueued, its launches go to the context's capture stream (nothing runs
+// there); the graph is then instantiated -- or, when a block of the same shape
+// ran before, the kept instance is updated with the new arguments -- and
+// launched on the caller's stream.  The guard ends a capture that an error
+// left open.
+struct BlockCapture {
+  gr_ctx* ctx = nullptr;
+  bool active = false;
+  ~BlockCapture() {
+    if (!active) return;
+    hipGraph_t gph = nullptr;
+    (void)hipStreamEndCapture(ctx->cap_stream, &gph);
+    if (gph) (void)hipGraphDestroy(gph);
+    (void)hipGetLastError();
+  }
+};
+
+gr_status block_capture_begin(gr_ctx* ctx, BlockCapture* bc, hipStream_t* enqueue_on) {
+  if (!ctx->cap_stream) GR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  GR_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  bc->ctx = ctx;
+  bc->active = true;
+  *enqueue_on = ctx->cap_stream;
+  return GR_OK;
+}
+
+gr_status block_capture_launch(gr_ctx* ctx, BlockCapture* bc, int key, hipStream_t st) {
+  hipGraph_t gph = nullptr;
+  bc->active = false;
+  GR_HIP(hipStreamEndCapture(ctx->cap_stream, &gph));
+  struct GraphFree {
+    hipGraph_t g;
+    ~GraphFree() {
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gf{gph};
+  auto it = ctx->block_graphs.find(key);
+  bool updated = false;
+  if (it != ctx->block_graphs.end()) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateSuccess;
+    if (hipGraphExecUpdate(it->second, gph, &err_node, &res) == hipSuccess &&
+        res == hipGraphExecUpdateSuccess) {
+      updated = true;
+    } else {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(it->second);
+      ctx->block_graphs.erase(it);
+    }
+  }
+  if (!updated) {
+    hipGraphExec_t exec = nullptr;
+    GR_HIP(hipGraphInstantiate(&exec, gph, nullptr, nullptr, 0));
+    ctx->block_graphs[key] = exec;
+  }
+  GR_HIP(hipGraphLaunch(ctx->block_graphs[key], st));
+  return GR_OK;
+}
 
 gr_status dl_plan(gr_ctx* ctx, Arena& ar, const gr_opts& o, bool pull_ok, bool learned,
                   bool tracing, DlPlan* d) {
@@ -687,6 +753,7 @@ gr_status dl_plan(gr_ctx* ctx, Arena& ar, const gr_opts& o, bool pull_ok, bool l
   d->len = kDlFirstLen;
   d->blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
   d->log = nullptr;
+  d->graph = o.graph_blocks == 1 && !tracing && !ar.fixed();
   if (d->on && tracing) GR_TRY(ar.get(S_DLOG, 3 * kDlMaxLevels, &d->log));
   return GR_OK;
 }
@@ -884,15 +951,19 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
       // the network pushing where the heuristic would pull: the block keeps
       // pushing (its device-side direction test would stop it at once)
       const double blk_do_a = sel.last_heuristic >= GR_PULL_TWC ? -1.0 : dl.do_a;
-      GR_HIP(launch_dl_begin(ctrl, cur, vm0, vn0, 0u, 0, 0, st));
+      BlockCapture capture;
+      hipStream_t es = st;
+      if (dl.graph) GR_TRY(block_capture_begin(ctx, &capture, &es));
+      GR_HIP(launch_dl_begin(ctrl, cur, vm0, vn0, 0u, 0, 0, es));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, blk_do_a,
                         V, dl.log, ctrl};
         GR_HIP(launch_bfs_dstep(da, bm, p ^ (i & 1), depth, parent, perm, level + i + 1, dl.blocks,
-                                st));
+                                es));
       }
+      if (dl.graph) GR_TRY(block_capture_launch(ctx, &capture, (kGraphKeyBfs << 8) | kmax, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
       // statistics of the frontier the block leaves (found on the device),
       // then a single read-back; with k == 0 levels run the frontier is
@@ -1237,15 +1308,21 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       offsets_ready = false;  // the block leaves a frontier the scan has not seen
       int kmax = dl.len;
       if (opts.max_iterations > 0) kmax = std::min(kmax, opts.max_iterations - it);
-      GR_HIP(launch_dl_begin(ctrl, cur, 0, 0, pq.T, pq.epoch, pq.fc, st));
+      BlockCapture capture;
+      hipStream_t es = st;
+      if (dl.graph) GR_TRY(block_capture_begin(ctx, &capture, &es));
+      GR_HIP(launch_dl_begin(ctrl, cur, 0, 0, pq.T, pq.epoch, pq.fc, es));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       for (int i = 0; i < kmax; ++i) {
         const int qc = (cur + i) % 3;
         const DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl.max_m, E, -1.0,
                         V, dl.log, ctrl};
-        if (use_pq) GR_HIP(launch_sssp_pq_dstep(da, g->W, keys, tags, it + i + 1, pq, dl.blocks, st));
-        else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, perm, it + i + 1, dl.blocks, st));
+        if (use_pq) GR_HIP(launch_sssp_pq_dstep(da, g->W, keys, tags, it + i + 1, pq, dl.blocks, es));
+        else GR_HIP(launch_sssp_dstep(da, g->W, keys, tags, perm, it + i + 1, dl.blocks, es));
       }
+      if (dl.graph)
+        GR_TRY(block_capture_launch(ctx, &capture,
+                                    ((use_pq ? kGraphKeySsspPq : kGraphKeySssp) << 8) | kmax, st));
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
       // statistics of the frontier the block leaves, then a single read-back
       // (with k == 0 levels run the statistics just move to the other slot)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <map>
 #include <vector>
 #include <stdint.h>
 
@@ -131,6 +132,11 @@ struct gr_ctx {
   hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_a = nullptr, ev_b = nullptr;
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the advance kernel when tracing
   hipEvent_t ev_c0 = nullptr, ev_c1 = nullptr;  // around a whole call that runs BFS inside
+  // hipGraph iteration control (gr_opts.graph_blocks): a stream nothing runs
+  // on, used only to capture the launches of a block of device-predicated
+  // levels, and the instantiated graph per block shape (traversal, length).
+  hipStream_t cap_stream = nullptr;
+  std::map<int, hipGraphExec_t> block_graphs;
 };
 
 struct gr_graph {

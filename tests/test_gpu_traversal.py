@@ -39,6 +39,10 @@ POLICIES = [
     ("dl_tiny", dict(device_max_edges=64)),
     ("dl_fixed_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC,
                           device_max_edges=1 << 24)),
+    # blocks of device-predicated levels recorded and replayed as hipGraphs
+    ("dl_graph", dict(graph_blocks=1)),
+    ("dl_graph_twc", dict(graph_blocks=1, policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC,
+                          device_max_edges=1 << 24)),
     # launch shapes the autotuner sweeps: workgroup size and TWC tier cut-offs
     ("block128_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB, lb_light_threshold=0,
                          adv_block=128, device_max_edges=-1)),
@@ -64,6 +68,7 @@ SSSP_POLICIES = POLICIES + [
                            device_max_edges=64)),
     ("pq7_light", dict(sssp_delta=7, lb_light_threshold=1 << 30)),
     ("pq_huge", dict(sssp_delta=1 << 30)),
+    ("pq16_graph", dict(sssp_delta=16, graph_blocks=1)),
 ]
 
 
@@ -347,4 +352,26 @@ def test_device_blocks_respect_max_iterations(ctx, max_it):
     for kw in (dict(), dict(sssp_delta=32), dict(sssp_delta=3, device_max_edges=-1)):
         dist, _, st = gr.sssp(g, [0], opts=gr.default_opts(**kw))
         np.testing.assert_array_equal(np_of(dist).view(np.uint32), edist, err_msg=str(kw))
+    g.free()
+
+
+def test_block_graphs_replayed_between_eager_runs(ctx):
+    """Instantiated block graphs are kept in the context and updated with each
+    block's arguments: replays alternate with eager runs (and host
+    synchronisations) and every result must equal the oracle."""
+    import torch
+    hg = gg.add_weights(gg.grid(90, 70), seed=3)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    for rnd, s in enumerate([0, 3150, 6299, 77, 0]):
+        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, s)
+        edist, epred = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, [s])
+        for graph in (1, 0, 1):
+            o = gr.default_opts(graph_blocks=graph)
+            d, p, st = gr.bfs(g, s, opts=o)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(np_of(d), ed, err_msg=f"bfs round {rnd} graph {graph}")
+            np.testing.assert_array_equal(np_of(p), ep, err_msg=f"bfs round {rnd} graph {graph}")
+            dist, pred, _ = gr.sssp(g, [s], opts=gr.default_opts(graph_blocks=graph, sssp_delta=32 * rnd))
+            np.testing.assert_array_equal(np_of(dist).view(np.uint32), edist)
+            np.testing.assert_array_equal(np_of(pred), epred)
     g.free()
