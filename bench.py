@@ -436,11 +436,12 @@ def cpu_baseline(hg, srcs, budget_s: float = 10.0, max_pairs: int = 4) -> dict:
 
 def large(args, gr, gg, torch):
     """R-MAT scale 25 (edge factor 16, ~1.07B directed edges, uint32 weights
-    1..64) resident in HBM: one 16-source batched BFS and 16 single-source SSSP
-    runs back to back, under the learned selector when trained weights exist
-    (else the heuristic; the batched BFS follows its own push / pull rule).
-    The SSSP runs are traced, so the dominant kernel gets a roofline and the
-    SSSP part an achieved GB/s.  Prints its own JSON line."""
+    1..64) resident in HBM: one 16-source batched BFS and one 16-source batched
+    SSSP (gr_sssp_multi) are the timed step.  Next to them, for comparison, 16
+    single-source SSSP runs back to back under the learned selector when
+    trained weights exist (else the heuristic); those runs are traced, so the
+    single-source relaxation kernel gets a roofline and an achieved GB/s.
+    Prints its own JSON line."""
     from paper_1701_01170_amd import autotune, selector
     t0 = time.time()
     hg = gg.add_weights(gg.rmat(25, 16, seed=1), seed=101)
@@ -465,6 +466,17 @@ def large(args, gr, gg, torch):
     torch.cuda.synchronize()
     bfs_wall = time.perf_counter() - t0
     del depth, parent
+    # batched SSSP: the 16 sources in one sweep per iteration
+    dist16 = torch.empty((16, V), dtype=torch.int32, device="cuda")
+    pred16 = torch.empty((16, V), dtype=torch.int32, device="cuda")
+    omsssp = autotune.tuned_opts(g, "sssp_multi")
+    gr.sssp_multi(g, srcs[:2], opts=omsssp, out=(dist16[:2], pred16[:2]))  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms16 = gr.sssp_multi(g, srcs, opts=omsssp, out=(dist16, pred16))[2]
+    torch.cuda.synchronize()
+    msssp_wall = time.perf_counter() - t0
+    del dist16, pred16
     dist = torch.empty(V, dtype=torch.int32, device="cuda")
     pred = torch.empty(V, dtype=torch.int32, device="cuda")
     cap = 4096
@@ -481,24 +493,36 @@ def large(args, gr, gg, torch):
         sssp_bytes += accumulate(per_kernel, "sssp", ts, min(os_.trace_count, cap), V)
     torch.cuda.synchronize()
     sssp_wall = time.perf_counter() - t0
-    teps = mb["teps_edges"] + sum(st["teps_edges"] for st in steps)
-    wall = bfs_wall + sssp_wall
+    teps = mb["teps_edges"] + ms16["teps_edges"]
+    wall = bfs_wall + msssp_wall
     sssp_ms = sum(st["device_ms"] for st in steps)
+    serial_teps = mb["teps_edges"] + sum(st["teps_edges"] for st in steps)
     dom = max(per_kernel, key=lambda k: per_kernel[k][1])
     roof = roofline_of(per_kernel, dom)
     roof["traffic"] = None
     out = {
-        "metric": "GTEPS BFS/SSSP RMAT-25, 16-source batched BFS + 16 SSSP",
+        "metric": "GTEPS BFS/SSSP RMAT-25, 16-source batched BFS + 16-source batched SSSP",
         "value": round(teps / wall / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
         "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "rmat_s25_e16, int32 CSR, uint32 weights 1..64; gr_bfs_multi with 16 "
-                               "sources + 16 gr_sssp runs",
-                   "policy": {"sssp": policy, "bfs_multi": "push / pull by its active-edge rule"},
+                               "sources + gr_sssp_multi with the same 16 sources",
+                   "policy": {"sssp_single_source_comparison": policy,
+                              "bfs_multi": "push / pull by its active-edge rule",
+                              "sssp_multi": "load-balanced push every iteration"},
                    "n_vertices": V, "n_edges": g.n_edges},
         "roofline": roof,
         "breakdown": {"bfs_multi16_ms": round(mb["device_ms"], 3),
                       "bfs_multi16_gteps_device": _gteps(mb["teps_edges"], mb["device_ms"]),
+                      "sssp_multi16_ms": round(ms16["device_ms"], 3),
+                      "sssp_multi16_gteps_device": _gteps(ms16["teps_edges"], ms16["device_ms"]),
+                      "sssp_multi16_iterations": ms16["iterations"],
+                      "sssp_multi16_knobs": {"lb_chunk": omsssp.lb_chunk,
+                                             "sssp_delta": omsssp.sssp_delta},
+                      "sssp_multi16_union_edges": ms16["inspected_edges"],
+                      "sssp_batched_speedup_over_16_single": round(sssp_ms / ms16["device_ms"], 3)
+                      if ms16["device_ms"] > 0 else None,
+                      "step_with_16_single_sssp_gteps": round(serial_teps / (bfs_wall + sssp_wall) / 1e9, 4),
                       "sssp16_ms": round(sssp_ms, 3),
                       "sssp16_gteps_device": _gteps(sum(st["teps_edges"] for st in steps), sssp_ms),
                       "sssp16_algorithmic_gbs": round(sssp_bytes / (sssp_ms * 1e-3) / 1e9, 1),

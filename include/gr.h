@@ -306,6 +306,26 @@ gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* source
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);
 
+/* k single-source shortest-path runs sharing each sweep over the graph (the
+ * paper's future-work task parallelism, Sec. 8, applied to Alg. 1).  Sources
+ * are processed 16 per pass: every vertex keeps one packed (distance,
+ * predecessor) key per source of the pass in one row (4, 8 or 16 slots), the
+ * frontier is the union of the sources' frontiers with a per-vertex mask of
+ * the sources it is active for, and each (frontier edge, active source) pair
+ * is relaxed by one lane, the pairs of an edge on neighbouring lanes.  dist:
+ * device uint32[k][V] (required), pred: device int32[k][V] or NULL; row s
+ * equals gr_sssp with the single source sources[s] (same definitions and
+ * canonical predecessors).  Needs weights; GR_ERANGE as gr_sssp.  opts used:
+ * lb_chunk (512, 1024 (default here) or 2048 edges per workgroup; other
+ * values act as 1024), sssp_delta (> 0: near / far split of the improved
+ * (vertex, source) pairs at one threshold for all sources, raised by delta
+ * when the frontier runs dry; results unchanged) and max_iterations.  stats:
+ * teps_edges summed over the sources; iterations of the longest pass;
+ * inspected_edges = frontier edges swept (each once for all its sources). */
+gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
+                        uint32_t* dist, int32_t* pred, gr_opts* opts, void* stream,
+                        gr_run_stats* stats);
+
 /* Betweenness centrality over n_sources host-given sources (Sec. 6,
  * betweenness centrality: Brandes's forward pass counting shortest paths and
  * backward pass accumulating dependencies, both on the advance operator).

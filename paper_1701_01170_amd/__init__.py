@@ -112,6 +112,8 @@ _SIGNATURES = {
                                ctypes.POINTER(RunStats)]),
     "gr_bfs_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
                                     ctypes.POINTER(RunStats)]),
+    "gr_sssp_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
+                                     ctypes.POINTER(RunStats)]),
     "gr_bc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(Opts), _P,
                              ctypes.POINTER(RunStats)]),
     "gr_copy_bandwidth": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P,
@@ -355,6 +357,25 @@ def bfs_multi(g: Graph, sources, want_parent: bool = True, opts: Opts | None = N
     check(lib().gr_bfs_multi(g.ctx.handle, g.handle, src.ctypes.data, k, _ptr(depth), _ptr(parent),
                              _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
     return depth, parent, st.as_dict()
+
+
+def sssp_multi(g: Graph, sources, want_pred: bool = True, opts: Opts | None = None, stream=None,
+               out=None):
+    """k single-source SSSP runs sharing each sweep (gr_sssp_multi).  Returns
+    (dist int32[k][V] holding uint32 bits, pred int32[k][V] or None, stats)."""
+    import torch
+    src = np.ascontiguousarray(np.asarray(sources).reshape(-1), dtype=np.int32)
+    k = int(src.shape[0])
+    if out is not None:
+        dist, pred = out
+    else:
+        dev = torch.device("cuda", g.ctx.device)
+        dist = torch.empty((k, g.n_vertices), dtype=torch.int32, device=dev)
+        pred = torch.empty((k, g.n_vertices), dtype=torch.int32, device=dev) if want_pred else None
+    st = RunStats()
+    check(lib().gr_sssp_multi(g.ctx.handle, g.handle, src.ctypes.data, k, _ptr(dist), _ptr(pred),
+                              _opts_arg(opts), _stream_handle(stream), ctypes.byref(st)))
+    return dist, pred, st.as_dict()
 
 
 def bc(g: Graph, sources, want_sigma: bool = False, opts: Opts | None = None, stream=None,

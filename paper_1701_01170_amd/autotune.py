@@ -21,7 +21,8 @@ Search (coordinate descent from the paper's defaults):
   8. BFS only: the do_a x do_b grid {1/2 .. 1/256} x {1/576, 1/64, 1/8},
      then bfs_filter in {auto, atomic, idempotent} (Sec. 5.2)
 Batched BFS ("bfs_multi", 64 sources per call) searches 1, 2, 3 and its
-push -> pull switch do_a in {1/4 .. 1/64}.
+push -> pull switch do_a in {1/4 .. 1/64}; batched SSSP ("sssp_multi", 16
+sources per call) its chunk {512, 1024, 2048} and sssp_delta {0, 2, ..., 64}.
 
 The tuned values only change the time taken; results are identical for every
 setting (the GPU tests check every strategy against the oracle).
@@ -38,7 +39,7 @@ import time
 
 import numpy as np
 
-from . import Graph, default_opts, bfs, bfs_multi, sssp  # noqa: F401
+from . import Graph, default_opts, bfs, bfs_multi, sssp, sssp_multi  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
@@ -50,6 +51,7 @@ ADV_BLOCK = [128, 256, 512]
 TWC_WAVE_MIN = [16, 32, 64, 128, 256]
 TWC_BLOCK_MIN = [64, 128, 256, 512, 1024, 4096]
 SSSP_DELTA = [0, 8, 16, 32, 64, 128, 256]
+SSSP_DELTA_MULTI = [2, 4, 8, 16, 32, 64]
 DEVICE_MAX_EDGES = [-1, 1 << 16, 1 << 18, 1 << 20]
 MULTI_DO_A = [1 / 4, 1 / 8, 1 / 16, 1 / 32, 1 / 64]
 DO_A = [1 / 2, 1 / 4, 1 / 8, 1 / 14, 1 / 32, 1 / 64, 1 / 256]
@@ -102,11 +104,12 @@ def _time(g: Graph, kind: str, sources, knobs: dict, reps: int = 1) -> float:
     import torch
     total = 0.0
     o = default_opts(**knobs)
-    if kind == "bfs_multi":
+    if kind in ("bfs_multi", "sssp_multi"):
         srcs = np.asarray(sources, dtype=np.int32)
+        run = bfs_multi if kind == "bfs_multi" else sssp_multi
         best = float("inf")
         for _ in range(reps + 1):
-            _, _, st = bfs_multi(g, srcs, opts=o)
+            _, _, st = run(g, srcs, opts=o)
             best = min(best, st["device_ms"])
         torch.cuda.synchronize()
         return best
@@ -146,6 +149,10 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
         w, b = c.get("twc_wave_min", 0), c.get("twc_block_min", 0)
         return not (w > 0 and b > 0 and b < w)
 
+    if kind == "sssp_multi":
+        try_set("lb_chunk", [512, 1024, 2048])
+        try_set("sssp_delta", [0] + SSSP_DELTA_MULTI)
+        return best, best_ms, base_ms
     try_set("lb_light_threshold", [0, 1024, 4096])
     try_set("lb_chunk", [512, 1024, 2048, 4096, 8192, 16384])
     try_set("adv_block", ADV_BLOCK)
@@ -203,7 +210,8 @@ def main():
         g = Graph.from_host(ctx, hg, symmetric=True)
         srcs = gg.sources(hg, args.sources, seed=2000)  # held-out from the bench's sources
         for kind in args.kinds.split(","):
-            ks = gg.sources(hg, 64, seed=2100) if kind == "bfs_multi" else srcs
+            ks = (gg.sources(hg, 64, seed=2100) if kind == "bfs_multi" else
+                  gg.sources(hg, 16, seed=2200) if kind == "sssp_multi" else srcs)
             knobs, ms, base = tune(g, kind, ks, log=lambda m: print(f"{name} {m}", flush=True))
             store(g, kind, knobs, ms, base, name, ks)
             print(f"{name} [{kind}] best {ms:.3f} ms (paper defaults {base:.3f} ms): {knobs}", flush=True)

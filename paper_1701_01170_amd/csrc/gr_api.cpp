@@ -1586,6 +1586,139 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
 }
 
 // ============================================================================
+// batched shortest paths (Sec. 8 task parallelism applied to Alg. 1)
+// ============================================================================
+
+extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t* sources,
+                                   int32_t k, uint32_t* dist, int32_t* pred, gr_opts* opts_in,
+                                   void* stream, gr_run_stats* stats) {
+  if (!ctx || !g) return fail(GR_EINVAL, "gr_sssp_multi: ctx or graph is NULL");
+  if (g->ctx != ctx) return fail(GR_EINVAL, "gr_sssp_multi: graph belongs to another context");
+  if (!dist) return fail(GR_EINVAL, "gr_sssp_multi: dist is NULL");
+  if (!sources || k < 1) return fail(GR_EINVAL, "gr_sssp_multi: need at least one source");
+  if (!g->W) return fail(GR_EINVAL, "gr_sssp_multi: graph has no weights");
+  for (int32_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || (int64_t)sources[i] >= g->V)
+      return fail(GR_EINVAL, "gr_sssp_multi: source " + std::to_string(sources[i]) + " out of range");
+  if ((uint64_t)g->max_weight * (uint64_t)(g->V - 1) >= 0xffffffffull)
+    return fail(GR_ERANGE, "gr_sssp_multi: max_weight * (V - 1) >= 2^32 - 1, distances may not fit uint32");
+  gr_opts opts;
+  GR_TRY(check_opts(opts_in, &opts));
+  if (opts_in) opts_in->trace_count = 0;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t V = g->V, E = g->E;
+  const int chunk = msssp_chunk(opts.lb_chunk > 0 ? opts.lb_chunk : 1024);
+  constexpr int kPass = 16;
+  const int KSmax = msssp_row(std::min<int32_t>(k, kPass));
+
+  unsigned long long* keys;
+  uint32_t *amask, *nmask, *fmask = nullptr;
+  int32_t *qA, *qB, *offsets, *rstart, *chunks, *src_dev, *piles = nullptr;
+  int64_t* bsums;
+  Ctrl* ctrl;
+  GR_TRY(pool_typed(ctx, S_MS_KEYS, (size_t)V * KSmax, &keys));
+  GR_TRY(pool_typed(ctx, S_MS_AMASK, V, &amask));
+  GR_TRY(pool_typed(ctx, S_MS_NMASK, V, &nmask));
+  // near / far split (sssp_delta > 0): far-pair masks and two far piles
+  const bool use_pq = opts.sssp_delta > 0;
+  GR_TRY(pool_typed(ctx, S_MS_FMASK, V, &fmask));
+  if (use_pq) GR_TRY(pool_typed(ctx, S_FAR, 2 * (size_t)V, &piles));
+  GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
+  GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
+  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
+  GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, stats_grid() + 1, &bsums));
+  GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
+  GR_TRY(pool_typed(ctx, S_TMP0, 2 * kPass, &src_dev));
+  Ctrl* hc = ctx->host_ctrl;
+  int32_t* q[2] = {qA, qB};
+
+  GR_HIP(hipEventRecord(ctx->ev_start, st));
+  GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->reached_edges), 2, 0u, st));
+  gr_run_stats rs{};
+  int max_it = 0;
+  std::vector<int32_t> srcs, uniq;
+  for (int32_t p0 = 0; p0 < k; p0 += kPass) {
+    const int32_t kk = std::min<int32_t>(kPass, k - p0);
+    const int KS = msssp_row(kk);
+    // src_dev: the pass's sources in traversal ids, then in caller ids
+    srcs.resize(2 * (size_t)kk);
+    for (int32_t i = 0; i < kk; ++i) {
+      srcs[i] = g->to_new(sources[p0 + i]);
+      srcs[kk + i] = sources[p0 + i];
+    }
+    uniq.assign(srcs.begin(), srcs.begin() + kk);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    GR_HIP(hipMemcpyAsync(src_dev, srcs.data(), sizeof(int32_t) * 2 * kk, hipMemcpyHostToDevice, st));
+    GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * uniq.size(), hipMemcpyHostToDevice, st));
+    GR_HIP(launch_fill_u32(&ctrl->q_count[0], 1, (uint32_t)uniq.size(), st));
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
+    GR_HIP(launch_msssp_init(keys, KS, amask, nmask, fmask, V, src_dev, kk, st));
+    GR_HIP(launch_fill_u32(&ctrl->far_count[0], 2, 0u, st));
+    int cur = 0, sp = 0, it = 0, pile = 0;
+    uint32_t T = (uint32_t)opts.sssp_delta;
+    GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                 &ctrl->q_count[cur ^ 1], nullptr, st));
+    GR_TRY(read_ctrl(ctx, ctrl, st));  // also keeps the host source vectors alive for the copies
+    int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], far_n = 0;
+    while ((n_f > 0 || far_n > 0) && (opts.max_iterations <= 0 || it < opts.max_iterations)) {
+      if (n_f == 0) {
+        // the frontier ran dry: raise the threshold and split the far pile
+        // into the frontier (appended to the empty queue q[cur])
+        const uint64_t t1 = (uint64_t)T + (uint64_t)opts.sssp_delta;
+        const uint32_t T1 = t1 >= 0xffffffffull ? 0xffffffffu : (uint32_t)t1;
+        GR_HIP(launch_fill_u32(&ctrl->far_count[pile ^ 1], 1, 0u, st));
+        GR_HIP(launch_msssp_refill(piles + (int64_t)pile * V, &ctrl->far_count[pile], far_n,
+                                   piles + (int64_t)(pile ^ 1) * V, &ctrl->far_count[pile ^ 1], keys,
+                                   KS, fmask, amask, T, T1, q[cur], &ctrl->q_count[cur], st));
+        T = T1;
+        pile ^= 1;
+      } else {
+        GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
+                                       chunks, chunk, st));
+        const MsFar far{fmask, use_pq ? piles + (int64_t)pile * V : nullptr, &ctrl->far_count[pile],
+                        T};
+        GR_HIP(launch_msssp_relax(KS, chunk, q[cur], offsets, rstart, chunks, n_f, m_f, g->C, g->W,
+                                  keys, amask, nmask, use_pq ? &far : nullptr, g->perm, q[cur ^ 1],
+                                  &ctrl->q_count[cur ^ 1], st));
+        GR_HIP(launch_msssp_rotate(q[cur], &ctrl->q_count[cur], n_f, q[cur ^ 1],
+                                   &ctrl->q_count[cur ^ 1], std::min<int64_t>(V, m_f), amask, nmask,
+                                   st));
+        rs.inspected_edges += m_f;
+        rs.action_count[GR_PUSH_LB]++;
+        cur ^= 1;
+        sp ^= 1;
+      }
+      ++it;
+      GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
+                                   &ctrl->q_count[cur ^ 1], nullptr, st));
+      GR_TRY(read_ctrl(ctx, ctrl, st));
+      n_f = hc->n_f[sp];
+      m_f = hc->m_f[sp];
+      far_n = use_pq ? hc->far_count[pile] : 0;
+    }
+    max_it = std::max(max_it, it);
+    GR_HIP(launch_msssp_finalize(keys, KS, kk, g->R, V, dist + (int64_t)p0 * V,
+                                 pred ? pred + (int64_t)p0 * V : nullptr, g->perm, src_dev + kk,
+                                 &ctrl->reached_edges, st));
+  }
+  GR_HIP(hipEventRecord(ctx->ev_stop, st));
+  GR_TRY(read_ctrl(ctx, ctrl, st));
+  if (stats) {
+    float ms = 0.f;
+    GR_TRY(elapsed_ms(ctx->ev_start, ctx->ev_stop, &ms));
+    rs.iterations = max_it;
+    rs.teps_edges = hc->reached_edges;
+    rs.device_ms = ms;
+    *stats = rs;
+  }
+  return GR_OK;
+}
+
+// ============================================================================
 // betweenness centrality (Sec. 6, Brandes's forward and backward passes)
 // ============================================================================
 

@@ -75,6 +75,10 @@ enum Slot : int {
   S_BC_LEVELS,     // vertices grouped by level [V]
   S_BC_LVL_N,      // vertices per level, then level cursors [L + 1]
   S_BC_LVL_M,      // degree sum per level [L + 1]
+  S_MS_KEYS,       // batched SSSP: packed keys, KS per vertex [V * KS]
+  S_MS_AMASK,      // batched SSSP: sources a frontier vertex is active for [V]
+  S_MS_NMASK,      // batched SSSP: sources whose distance dropped this iteration [V]
+  S_MS_FMASK,      // batched SSSP: pairs waiting on the far pile [V]
   S_NSLOTS
 };
 
@@ -302,6 +306,40 @@ hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t
 hipError_t launch_bc_finalize(const int32_t* depth, const double* sigma, const double* acc,
                               int64_t V, int32_t source, const int32_t* perm, double* bc,
                               double* sigma_out, hipStream_t st);
+// batched SSSP (up to 16 sources per pass; see k_msssp.hip): keys per
+// vertex in a row of KS = msssp_row(k) slots; relaxation chunks of
+// msssp_chunk(chunk) edges
+int msssp_row(int k);
+int msssp_chunk(int chunk);
+// the near / far split: pairs improved to a distance >= T go to fmask and the
+// far pile
+struct MsFar {
+  uint32_t* fmask;
+  int32_t* pile;
+  uint32_t* pile_count;
+  uint32_t T;
+};
+hipError_t launch_msssp_init(unsigned long long* keys, int KS, uint32_t* amask, uint32_t* nmask,
+                             uint32_t* fmask, int64_t V, const int32_t* src_dev, int32_t k,
+                             hipStream_t st);
+hipError_t launch_msssp_relax(int KS, int chunk, const int32_t* frontier, const int32_t* offsets,
+                              const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                              int64_t m_f, const int32_t* C, const uint32_t* W,
+                              unsigned long long* keys, const uint32_t* amask, uint32_t* nmask,
+                              const MsFar* far, const int32_t* perm, int32_t* out_q,
+                              uint32_t* out_count, hipStream_t st);
+hipError_t launch_msssp_refill(const int32_t* pile, const uint32_t* n_pile, int64_t max_pile,
+                               int32_t* pile_next, uint32_t* n_pile_next,
+                               const unsigned long long* keys, int KS, uint32_t* fmask,
+                               uint32_t* amask, uint32_t T0, uint32_t T1, int32_t* out_q,
+                               uint32_t* out_count, hipStream_t st);
+hipError_t launch_msssp_rotate(const int32_t* cur_q, const uint32_t* cur_n, int64_t max_cur,
+                               const int32_t* next_q, const uint32_t* next_n, int64_t max_next,
+                               uint32_t* amask, uint32_t* nmask, hipStream_t st);
+hipError_t launch_msssp_finalize(const unsigned long long* keys, int KS, int32_t k,
+                                 const int32_t* R, int64_t V, uint32_t* dist, int32_t* pred,
+                                 const int32_t* perm, const int32_t* src_orig_dev,
+                                 int64_t* reached_edges, hipStream_t st);
 // live |= old (live = depth <= d + 1 after level d)
 hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t st);
 
