@@ -229,7 +229,7 @@ def learned_vs_heuristic(gr, g, ctx, sources, outs=None) -> dict | None:
     from paper_1701_01170_amd import autotune, selector
     if not os.path.exists(selector.WEIGHTS):
         return None
-    ctx.set_policy(np.load(selector.WEIGHTS))
+    selector.load_policy(ctx)
     oh = {k: autotune.tuned_opts(g, k) for k in ("bfs", "sssp")}
     ol = {k: autotune.tuned_opts(g, k, policy=gr.POLICY_LEARNED) for k in ("bfs", "sssp")}
     res = compare_policies(gr, g, sources, oh, ol, outs=outs)
@@ -378,6 +378,25 @@ def extras(gr, gg, ctx, torch, log):
         "batched_iterations": m["iterations"],
         "single_source_ms": round(single_ms, 3), "single_source_gteps": _gteps(single_teps, single_ms),
         "speedup": round(single_ms / m["device_ms"], 3) if m["device_ms"] > 0 else None}
+    # the batched network against the heuristic: five 64-source batches each,
+    # interleaved, same tuned knobs
+    from paper_1701_01170_amd import selector
+    if selector.load_policy(ctx):
+        ol = autotune.tuned_opts(g, "bfs_multi", policy=gr.POLICY_LEARNED)
+        hm, lm, te = [], [], []
+        for b in range(5):
+            sb = gg.sources(hg, 64, seed=2300 + b).astype(np.int32)
+            pair = [("h", om), ("l", ol)] if b % 2 == 0 else [("l", ol), ("h", om)]
+            for label, o in pair:
+                st = gr.bfs_multi(g, sb, opts=o, out=(depth, parent))[2]
+                (hm if label == "h" else lm).append(st["device_ms"])
+            te.append(st["teps_edges"])
+        ctx.set_policy(None)
+        out["bfs_64_sources_rmat20"]["learned_vs_heuristic"] = {
+            "batches": 5, "heuristic_median_ms": round(statistics.median(hm), 4),
+            "learned_median_ms": round(statistics.median(lm), 4),
+            "heuristic_gteps": _gteps(sum(te), sum(hm)), "learned_gteps": _gteps(sum(te), sum(lm)),
+            "learned_speedup": round(sum(hm) / sum(lm), 4) if sum(lm) > 0 else None}
     del depth, parent
     g.free()
     del hg
@@ -451,14 +470,11 @@ def large(args, gr, gg, torch):
     g = gr.Graph.from_host(ctx, hg, symmetric=True)
     srcs = gg.sources(hg, 16, seed=1000).astype(np.int32)
     V = hg.n_vertices
-    policy = "heuristic"
-    if os.path.exists(selector.WEIGHTS):
-        ctx.set_policy(np.load(selector.WEIGHTS))
-        policy = "learned"
+    policy = "learned" if selector.load_policy(ctx) else "heuristic"
     kw = {"policy": gr.POLICY_LEARNED} if policy == "learned" else {}
     depth = torch.empty((16, V), dtype=torch.int32, device="cuda")
     parent = torch.empty((16, V), dtype=torch.int32, device="cuda")
-    om = autotune.tuned_opts(g, "bfs_multi")
+    om = autotune.tuned_opts(g, "bfs_multi", **kw)
     gr.bfs_multi(g, srcs[:2], opts=om, out=(depth[:2], parent[:2]))  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -508,7 +524,7 @@ def large(args, gr, gg, torch):
         "config": {"workload": "rmat_s25_e16, int32 CSR, uint32 weights 1..64; gr_bfs_multi with 16 "
                                "sources + gr_sssp_multi with the same 16 sources",
                    "policy": {"sssp_single_source_comparison": policy,
-                              "bfs_multi": "push / pull by its active-edge rule",
+                              "bfs_multi": policy + " (batched network when trained)",
                               "sssp_multi": "load-balanced push every iteration"},
                    "n_vertices": V, "n_edges": g.n_edges},
         "roofline": roof,

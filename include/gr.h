@@ -224,8 +224,11 @@ void gr_opts_default(gr_opts* opts);
 gr_status gr_ctx_create(int32_t device, gr_ctx** out);
 gr_status gr_ctx_destroy(gr_ctx* ctx);
 
-/* Load selector MLP parameters (host float array of GR_MLP_N_PARAMS values,
- * layout given at gr_mlp_forward).  params = NULL unloads (heuristic again). */
+/* Load selector MLP parameters (host float array, layout given at
+ * gr_mlp_forward): n_params = GR_MLP_N_PARAMS loads one network for every
+ * traversal; n_params = 2 * GR_MLP_N_PARAMS loads two, the first for gr_bfs /
+ * gr_sssp and the second for gr_bfs_multi.  params = NULL unloads (heuristic
+ * again). */
 #define GR_MLP_N_PARAMS 1476
 gr_status gr_ctx_set_policy(gr_ctx* ctx, const float* params, int32_t n_params);
 
@@ -299,9 +302,15 @@ gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, in
  * processed 64 per pass, one bit per source in per-vertex 64-bit masks.
  * depth: device int32[k][V] (required), parent: device int32[k][V] or NULL,
  * row s holding the single-source result for sources[s].  Needs GR_SYMMETRIC
- * (parents are found by pulling over in-edges).  A level pulls over every
- * vertex when the vertices active in it carry more than E * opts.do_a edges,
- * else it pushes from them with the opts' LB / TWC knobs. */
+ * (parents are found by pulling over in-edges).  Per level, the heuristic
+ * pulls over every vertex when the vertices active in it carry more than
+ * E * opts.do_a edges, else it pushes from them with the opts' LB / TWC knobs;
+ * GR_POLICY_FIXED / RANDOM pick the action as for gr_bfs (both pull actions
+ * use the one pull kernel), and GR_POLICY_LEARNED runs the selector network
+ * (the batched one when two are loaded) in the kernel that publishes each
+ * level's statistics, on the features of gr_mlp_forward with n_u / m_u the
+ * unvisited vertex and edge counts averaged over the pass's sources, guarded
+ * by learned_margin as for gr_bfs.  opts.trace records every level. */
 gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);

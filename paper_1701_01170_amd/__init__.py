@@ -188,7 +188,9 @@ class Context:
         self.device = int(device)
 
     def set_policy(self, params) -> None:
-        """Load selector MLP parameters (1476 float32) or None to unload."""
+        """Load selector MLP parameters (1476 float32: one network for every
+        traversal; 2 x 1476: the single-source network, then the batched-BFS
+        one) or None to unload."""
         if params is None:
             check(lib().gr_ctx_set_policy(self.handle, None, 0))
             return

@@ -1508,6 +1508,10 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
   gr_run_stats rs{};
   int64_t inspected = 0;
   int max_levels = 0;
+  const bool learned = opts.policy == GR_POLICY_LEARNED && ctx->policy_loaded;
+  const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr) + ctx->mlp_multi_offset;
+  const bool tracing = opts_in && opts_in->trace;
+  uint64_t rng = opts.policy_seed ^ 0x9e3779b97f4a7c15ull;
   for (int32_t p0 = 0; p0 < k; p0 += 64) {
     const int32_t kk = std::min<int32_t>(64, k - p0);
     const u64 full = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
@@ -1528,43 +1532,88 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
     GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * uniq.size(), hipMemcpyHostToDevice, st));
     GR_HIP(launch_fill_u32(&ctrl->q_count[0], 1, (uint32_t)uniq.size(), st));
     GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
-    GR_HIP(launch_ms_seed(src_dev, src_dev + kk, kk, visit, front[0], dpass, V, st));
+    GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->ms_pairs), 4, 0u, st));
+    GR_HIP(launch_ms_seed(src_dev, src_dev + kk, kk, visit, front[0], dpass, V, g->R, ctrl, st));
     int cur = 0, fc = 0, sp = 0, level = 0;
+    bool prev_pull = false;
+    // the network's inputs for the frontier measured at slot `slot`
+    auto select_at = [&](int slot) {
+      MlpSelect m{mlp, slot, V, E, 0, 0, prev_pull ? 1 : 0, 0xF};
+      m.ms_k = kk;
+      return m;
+    };
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                  &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-    GR_TRY(read_ctrl(ctx, ctrl, st));  // also keeps the host source vectors alive for the copies
+    MlpSelect msel = select_at(sp);
+    // (the read-back also keeps the host source vectors alive for the copies)
+    GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
     int64_t n_a = hc->n_f[sp], m_a = hc->m_f[sp];
     while (n_a > 0 && (opts.max_iterations <= 0 || level < opts.max_iterations)) {
-      // pull (every vertex with unreached source bits ORs its neighbours'
-      // frontier masks) once the active vertices carry more than E * do_a edges
-      const bool pull = (double)m_a > (double)E * (double)opts.do_a;
+      // heuristic: pull (every vertex with unreached source bits ORs its
+      // neighbours' frontier masks) once the active vertices carry more than
+      // E * do_a edges; fixed / random / learned policies as for gr_bfs (both
+      // pull actions map to the one pull kernel)
+      const int h = (double)m_a > (double)E * (double)opts.do_a ? GR_PULL_TWC
+                                                                : (use_lb ? GR_PUSH_LB : GR_PUSH_TWC);
+      int action = h;
+      if (opts.policy == GR_POLICY_FIXED) {
+        action = opts.fixed_action;
+      } else if (opts.policy == GR_POLICY_RANDOM) {
+        action = (int)(Selector::next(rng) % 4);
+      } else if (learned) {
+        const int c = hc->action;
+        if (c >= 0 && c < 4 && c != h && hc->pred[c] + opts.learned_margin < hc->pred[h]) action = c;
+      }
+      LevelFeatures lf{};
+      lf.level = level;
+      lf.V = V;
+      lf.E = E;
+      lf.n_f = n_a;
+      lf.m_f = m_a;
+      lf.n_u = V - hc->ms_pairs / kk;
+      lf.m_u = E - hc->ms_pair_edges / kk;
+      lf.max_deg_f = hc->max_deg[sp];
+      lf.prev_pull = prev_pull ? 1 : 0;
+      const bool pull = action >= GR_PULL_TWC;
+      int kernel = 4;
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       if (pull) {
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_ms_pull(V, g->R, g->C, front[fc], visit, full, next, q[(cur + 1) % 3],
                               &ctrl->q_count[(cur + 1) % 3], ppass, g->perm, st));
-        rs.action_count[GR_PULL_TWC]++;
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       } else {
-        const int mode = !use_lb ? 0 : (n_a < opts.lb_light_threshold ? 1 : 2);
+        const int mode = action == GR_PUSH_TWC ? 0 : (n_a < opts.lb_light_threshold ? 1 : 2);
+        kernel = mode;
         if (mode == 2)
           GR_HIP(launch_frontier_offsets(q[cur], n_a, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                          chunks, chunk, st));
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_ms_push(mode, q[cur], offsets, rstart, chunks, n_a, m_a, g->R, g->C,
                               front[fc], visit, next, q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], adv,
                               st));
-        rs.action_count[use_lb ? GR_PUSH_LB : GR_PUSH_TWC]++;
+        if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
       }
+      rs.action_count[action]++;
       inspected += pull ? E : m_a;
       // a pull level has written its parents already
       GR_HIP(launch_ms_finalize(q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], pull ? V : std::min(V, m_a),
                                 g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass,
-                                pull ? nullptr : ppass, g->perm, V, level + 1, st));
+                                pull ? nullptr : ppass, g->perm, V, level + 1, ctrl, st));
       GR_HIP(launch_ms_clear(q[cur], &ctrl->q_count[cur], n_a, front[fc], st));
+      if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+      prev_pull = pull;
       fc ^= 1;
       cur = (cur + 1) % 3;
       sp ^= 1;
       ++level;
       GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
                                    &ctrl->q_count[(cur + 1) % 3], nullptr, st));
-      GR_TRY(read_ctrl(ctx, ctrl, st));
+      msel = select_at(sp);
+      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
+      if (tracing)
+        GR_TRY(record_trace(ctx, opts_in, lf, action, kernel, hc->n_f[sp],
+                            StepWork{pull ? V : n_a, pull ? E : m_a}));
       n_a = hc->n_f[sp];
       m_a = hc->m_f[sp];
     }
@@ -1850,18 +1899,21 @@ extern "C" gr_status gr_ctx_set_policy(gr_ctx* ctx, const float* params, int32_t
   if (!ctx) return fail(GR_EINVAL, "gr_ctx_set_policy: ctx is NULL");
   if (!params) {
     ctx->policy_loaded = false;
+    ctx->mlp_multi_offset = 0;
     return GR_OK;
   }
-  if (n_params != GR_MLP_N_PARAMS)
+  if (n_params != GR_MLP_N_PARAMS && n_params != 2 * GR_MLP_N_PARAMS)
     return fail(GR_EINVAL, "gr_ctx_set_policy: expected " + std::to_string(GR_MLP_N_PARAMS) +
-                               " parameters, got " + std::to_string(n_params));
+                               " or " + std::to_string(2 * GR_MLP_N_PARAMS) + " parameters, got " +
+                               std::to_string(n_params));
   for (int32_t i = 0; i < n_params; ++i)
     if (!std::isfinite(params[i])) return fail(GR_EINVAL, "gr_ctx_set_policy: non-finite parameter");
   DeviceGuard dg(ctx->device);
   float* d = nullptr;
-  GR_TRY(pool_typed(ctx, S_MLP, GR_MLP_N_PARAMS, &d));
-  GR_HIP(hipMemcpy(d, params, sizeof(float) * GR_MLP_N_PARAMS, hipMemcpyHostToDevice));
+  GR_TRY(pool_typed(ctx, S_MLP, 2 * (size_t)GR_MLP_N_PARAMS, &d));
+  GR_HIP(hipMemcpy(d, params, sizeof(float) * n_params, hipMemcpyHostToDevice));
   ctx->policy_loaded = true;
+  ctx->mlp_multi_offset = n_params == 2 * GR_MLP_N_PARAMS ? GR_MLP_N_PARAMS : 0;
   return GR_OK;
 }
 

@@ -110,6 +110,10 @@ struct Ctrl {
   int32_t pq_fc[2];         // far pile in use (of three rotating piles)
   uint32_t far_count[3];    // far pile lengths
   uint32_t pad2;
+  // multi-source BFS: (source, vertex) pairs reached so far and the sum of
+  // their degrees (the selector's unvisited counts, averaged over sources)
+  int64_t ms_pairs;
+  int64_t ms_pair_edges;
 };
 
 }  // namespace gr
@@ -127,6 +131,9 @@ struct gr_ctx {
   uint32_t* publish_flag_dev = nullptr;
   uint32_t publish_seq = 0;
   bool policy_loaded = false;
+  // offset of the batched-traversal network in the selector parameters (0:
+  // the same network serves every traversal)
+  int32_t mlp_multi_offset = 0;
   // Device address of this device's copy of the library's static workspace
   // (gr_bfs_static), looked up once per device when the context is created.
   void* static_ws = nullptr;
@@ -347,7 +354,7 @@ hipError_t launch_bitmap_merge(uint32_t* bm, int p, int64_t n_words, hipStream_t
 // caller's [k][V] arrays in caller ids (perm nullable)
 hipError_t launch_ms_seed(const int32_t* src_dev, const int32_t* src_orig_dev, int32_t k,
                           unsigned long long* visit, unsigned long long* front, int32_t* depth,
-                          int64_t V, hipStream_t st);
+                          int64_t V, const int32_t* R, Ctrl* ctrl, hipStream_t st);
 hipError_t launch_ms_push(int mode, const int32_t* active, const int32_t* offsets,
                           const int32_t* rstart, const int32_t* chunk_start, int64_t n_a,
                           int64_t m_a, const int32_t* R, const int32_t* C,
@@ -365,7 +372,8 @@ hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched,
                               const int32_t* R, const int32_t* C, const unsigned long long* front,
                               unsigned long long* front_next, unsigned long long* visit,
                               unsigned long long* next, int32_t* depth, int32_t* parent,
-                              const int32_t* perm, int64_t V, int32_t next_depth, hipStream_t st);
+                              const int32_t* perm, int64_t V, int32_t next_depth, Ctrl* ctrl,
+                              hipStream_t st);
 hipError_t launch_ms_clear(const int32_t* list, const uint32_t* n, int64_t max_n,
                            unsigned long long* front, hipStream_t st);
 hipError_t launch_ms_teps(const unsigned long long* visit, const int32_t* R, int64_t V, int64_t* out,
@@ -390,6 +398,10 @@ struct MlpSelect {
   int prev_pull;
   int allowed;
   int after_block;  // n_u / m_u before the frontier: V / E minus the block's visited counts
+  // multi-source BFS over ms_k sources: n_u = V - ms_pairs / ms_k and
+  // m_u = E - ms_pair_edges / ms_k (the average over the sources of the
+  // unvisited counts after the current frontier; 0: not multi-source)
+  int ms_k;
 };
 // The network's predicted log2 step times (pred, +inf where not allowed) and
 // its argmin (action) written into the control block, which is then published

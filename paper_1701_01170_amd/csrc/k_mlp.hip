@@ -217,8 +217,12 @@ __global__ __launch_bounds__(128) void k_publish_select(MlpSelect m, Ctrl* __res
       nub = m.V - ctrl->dl_vn[k & 1];
       mub = m.E - ctrl->dl_vm[k & 1];
     }
-    const int64_t n_u = nub > 0 ? nub - n_f : 0;
-    const int64_t m_u = mub > 0 ? mub - m_f : 0;
+    int64_t n_u = nub > 0 ? nub - n_f : 0;
+    int64_t m_u = mub > 0 ? mub - m_f : 0;
+    if (m.ms_k > 0) {
+      n_u = m.V - ctrl->ms_pairs / m.ms_k;
+      m_u = m.E - ctrl->ms_pair_edges / m.ms_k;
+    }
     s_x[threadIdx.x] = mlp_feature(threadIdx.x, n_f, m_f, n_u, m_u, ctrl->max_deg[m.sp], m.V, m.E,
                                    m.prev_pull);
   }

@@ -140,8 +140,9 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
     const int32_t* __restrict__ R, const int32_t* __restrict__ C, const u64* __restrict__ front,
     u64* __restrict__ front_next, u64* __restrict__ visit, u64* __restrict__ next,
     int32_t* __restrict__ depth, int32_t* __restrict__ parent, const int32_t* __restrict__ perm,
-    int64_t V, int32_t next_depth) {
+    int64_t V, int32_t next_depth, Ctrl* __restrict__ ctrl) {
   constexpr int U = 8;
+  __shared__ int64_t s_pairs[256 / kWave], s_pe[256 / kWave];
   const int64_t n = *n_touched;
   if ((int64_t)blockIdx.x * blockDim.x >= n) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,9 +158,26 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
     visit[v] |= nw;
     front_next[v] = nw;
     for (u64 b = nw; b; b &= b - 1) depth[(int64_t)(__ffsll(b) - 1) * V + vo] = next_depth;
-    if (parent) {
-      rb = R[v];
-      re = R[v + 1];
+    rb = R[v];
+    re = R[v + 1];
+  }
+  // the pairs reached at this level and their degrees (selector features)
+  {
+    const int64_t pc = __popcll(nw);
+    const int64_t wp = wave_sum(pc), we = wave_sum(pc * (int64_t)(re - rb));
+    if (lane() == 0) {
+      s_pairs[threadIdx.x / kWave] = wp;
+      s_pe[threadIdx.x / kWave] = we;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tp = 0, te = 0;
+      for (int k = 0; k < 256 / kWave; ++k) {
+        tp += s_pairs[k];
+        te += s_pe[k];
+      }
+      if (tp) atomicAdd((unsigned long long*)&ctrl->ms_pairs, (unsigned long long)tp);
+      if (te) atomicAdd((unsigned long long*)&ctrl->ms_pair_edges, (unsigned long long)te);
     }
   }
   if (!parent) return;
@@ -217,17 +235,23 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
   }
 }
 
+// Sources: their bits in visit / front, depth 0, and the reached-pair
+// counters start at the k source pairs.
 __global__ __launch_bounds__(256) void k_ms_seed(const int32_t* __restrict__ src,
                                                  const int32_t* __restrict__ src_orig, int32_t k,
                                                  u64* __restrict__ visit, u64* __restrict__ front,
-                                                 int32_t* __restrict__ depth, int64_t V) {
+                                                 int32_t* __restrict__ depth, int64_t V,
+                                                 const int32_t* __restrict__ R,
+                                                 Ctrl* __restrict__ ctrl) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < k) {
     const int32_t v = src[s];
     atomicOr(&visit[v], 1ull << s);
     atomicOr(&front[v], 1ull << s);
     depth[(int64_t)s * V + src_orig[s]] = 0;
+    atomicAdd((unsigned long long*)&ctrl->ms_pair_edges, (unsigned long long)(R[v + 1] - R[v]));
   }
+  if (s == 0) atomicAdd((unsigned long long*)&ctrl->ms_pairs, (unsigned long long)k);
 }
 
 __global__ __launch_bounds__(256) void k_ms_clear(const int32_t* __restrict__ list,
@@ -275,8 +299,9 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 hipError_t launch_ms_seed(const int32_t* src_dev, const int32_t* src_orig_dev, int32_t k,
-                          u64* visit, u64* front, int32_t* depth, int64_t V, hipStream_t st) {
-  k_ms_seed<<<1, 256, 0, st>>>(src_dev, src_orig_dev, k, visit, front, depth, V);
+                          u64* visit, u64* front, int32_t* depth, int64_t V, const int32_t* R,
+                          Ctrl* ctrl, hipStream_t st) {
+  k_ms_seed<<<1, 256, 0, st>>>(src_dev, src_orig_dev, k, visit, front, depth, V, R, ctrl);
   return hipGetLastError();
 }
 
@@ -303,11 +328,11 @@ hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched,
                               const int32_t* R, const int32_t* C, const u64* front,
                               u64* front_next, u64* visit, u64* next, int32_t* depth,
                               int32_t* parent, const int32_t* perm, int64_t V, int32_t next_depth,
-                              hipStream_t st) {
+                              Ctrl* ctrl, hipStream_t st) {
   if (max_n <= 0) return hipSuccess;
   k_ms_finalize<<<blocks_for(max_n, 256), 256, 0, st>>>(touched, n_touched, R, C, front,
                                                         front_next, visit, next, depth, parent,
-                                                        perm, V, next_depth);
+                                                        perm, V, next_depth, ctrl);
   return hipGetLastError();
 }
 

@@ -15,7 +15,14 @@ Training runs on the GPU with the library's own kernels (gr_mlp_loss_grad,
 gr_mlp_adam); evaluation compares event-timed traversal time with the
 heuristic and with the network on held-out sources.
 
+A second network serves the batched BFS (gr_bfs_multi, 64 sources per
+pass): its traces come from batched runs with each fixed action and with
+seeded random actions, its features are the same eight with the unvisited
+counts averaged over the pass's sources.  Both networks are loaded together
+(gr_ctx_set_policy with 2 x 1476 parameters, see load_policy).
+
 CLI:  python -m paper_1701_01170_amd.selector [--quick] [--epochs N]
+      python -m paper_1701_01170_amd.selector --multi [--quick] [--epochs N]
 """
 from __future__ import annotations
 
@@ -27,12 +34,27 @@ import time
 import numpy as np
 
 from . import (MLP_N_PARAMS, POLICY_FIXED, POLICY_HEURISTIC, POLICY_LEARNED, POLICY_RANDOM,
-               Context, Graph, LevelTrace, bfs, default_opts, mlp_adam, mlp_loss_grad, sssp)
+               Context, Graph, LevelTrace, bfs, bfs_multi, default_opts, mlp_adam, mlp_loss_grad,
+               sssp)
 from . import graphgen as gg
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "tuning", "selector_gfx950.npy")
 REPORT = os.path.join(HERE, "tuning", "selector_gfx950.json")
+WEIGHTS_MULTI = os.path.join(HERE, "tuning", "selector_multi_gfx950.npy")
+REPORT_MULTI = os.path.join(HERE, "tuning", "selector_multi_gfx950.json")
+
+
+def load_policy(ctx: Context) -> bool:
+    """Load the trained networks into ctx: the single-source one, followed by
+    the batched-BFS one when it exists.  False when no weights are stored."""
+    if not os.path.exists(WEIGHTS):
+        return False
+    p = np.load(WEIGHTS).astype(np.float32)
+    if os.path.exists(WEIGHTS_MULTI):
+        p = np.concatenate([p, np.load(WEIGHTS_MULTI).astype(np.float32)])
+    ctx.set_policy(p)
+    return True
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -101,6 +123,98 @@ def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 4, sssp
     w = len(grp) / (len(counts) * counts[inv])
     M *= w[:, None].astype(np.float32)
     return (np.asarray(X, np.float32), np.asarray(T, np.float32), M)
+
+
+def collect_multi(ctx: Context, graphs, k: int = 64, random_runs: int = 4, log=print):
+    """Samples from batched BFS runs (k sources) with each fixed action and
+    with seeded random actions, one host round trip per level, so every record
+    times one level of the action it names."""
+    from . import autotune
+    cap = 1 << 15
+    buf = (LevelTrace * cap)()
+    X, T, M, grp = [], [], [], []
+    for name, hg in graphs:
+        t0 = time.time()
+        g = Graph.from_host(ctx, hg, symmetric=True)
+        srcs = gg.sources(hg, k, seed=3000).astype(np.int32)
+        pols = [dict(policy=POLICY_FIXED, fixed_action=a) for a in (0, 1, 2)]
+        pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r) for r in range(random_runs)]
+        for kw in pols:
+            o = autotune.tuned_opts(g, "bfs_multi", trace=buf, trace_capacity=cap, **kw)
+            bfs_multi(g, srcs, opts=o)
+            for f, a, us in _records(buf, min(o.trace_count, cap)):
+                X.append(f)
+                t = np.zeros(4, np.float32)
+                m = np.zeros(4, np.float32)
+                t[a] = np.log2(us)
+                m[a] = 1.0
+                T.append(t)
+                M.append(m)
+                grp.append(name)
+        g.free()
+        log(f"traced batched {name}: {len(X)} samples so far ({time.time() - t0:.1f}s)")
+    M = np.asarray(M, np.float32)
+    _, inv, counts = np.unique(np.asarray(grp), return_inverse=True, return_counts=True)
+    w = len(grp) / (len(counts) * counts[inv])
+    M *= w[:, None].astype(np.float32)
+    return (np.asarray(X, np.float32), np.asarray(T, np.float32), M)
+
+
+def evaluate_multi(ctx: Context, graphs, params_multi, k: int = 64, reps: int = 3,
+                   margins=(0.0,), log=print) -> list[dict]:
+    """Batched BFS (k sources) under the heuristic and under the batched
+    network, tuned knobs, best of `reps` device times each."""
+    from . import autotune
+    single = np.load(WEIGHTS).astype(np.float32) if os.path.exists(WEIGHTS) else \
+        np.zeros(MLP_N_PARAMS, np.float32)
+    ctx.set_policy(np.concatenate([single, params_multi.astype(np.float32)]))
+    rows = []
+    try:
+        for name, hg in graphs:
+            g = Graph.from_host(ctx, hg, symmetric=True)
+            srcs = gg.sources(hg, k, seed=9100).astype(np.int32)
+            cfgs = {"heuristic": autotune.tuned_opts(g, "bfs_multi")}
+            for mg in margins:
+                cfgs[f"learned_margin{mg:g}"] = autotune.tuned_opts(
+                    g, "bfs_multi", policy=POLICY_LEARNED, learned_margin=mg)
+            res = {}
+            for label, o in cfgs.items():
+                best, st = float("inf"), None
+                for _ in range(reps):
+                    st = bfs_multi(g, srcs, opts=o)[2]
+                    best = min(best, st["device_ms"])
+                res[label] = dict(ms=round(best, 4),
+                                  gteps=round(st["teps_edges"] / (best * 1e-3) / 1e9, 3),
+                                  actions=st["action_count"])
+            row = dict(graph=name, kind="bfs_multi", k=k, **res)
+            rows.append(row)
+            log(json.dumps(row))
+            g.free()
+    finally:
+        ctx.set_policy(None)
+    return rows
+
+
+def training_graphs_multi(quick: bool):
+    """R-MAT scales 16..20 with a in [0.45, 0.65], Erdos-Renyi average degree
+    4..64, grids 256^2 and 512^2 (batched runs over the larger grids take
+    thousands of levels per source pass)."""
+    gs = []
+    for s in ([16, 18] if quick else [16, 18, 20]):
+        for a in (0.45, 0.55, 0.65):
+            gs.append((f"rmat_s{s}_a{a}", gg.rmat_family(s, 16, a, seed=11 + s)))
+    for d in ((4, 64) if quick else (4, 16, 64)):
+        gs.append((f"er_n262144_d{d}", gg.erdos_renyi(1 << 18, d, seed=5)))
+    for n in (256, 512):
+        gs.append((f"grid_{n}", gg.grid(n, n)))
+    return gs
+
+
+def eval_graphs_multi():
+    return [("rmat_s20_e16", gg.rmat(20, 16, seed=1)),
+            ("rmat_s18_e16_seed3", gg.rmat(18, 16, seed=3)),
+            ("er_n262144_d8", gg.erdos_renyi(1 << 18, 8, seed=77)),
+            ("grid_384", gg.grid(384, 384))]
 
 
 def train(ctx: Context, X, T, M, epochs: int = 400, lr: float = 3e-3, seed: int = 0, log=print):
@@ -199,9 +313,22 @@ def main():
     ap.add_argument("--sources", type=int, default=3)
     ap.add_argument("--eval-only", action="store_true", help="evaluate the stored weights")
     ap.add_argument("--margins", default="0,0.1,0.25,0.5")
+    ap.add_argument("--multi", action="store_true", help="train the batched-BFS network")
     args = ap.parse_args()
     margins = [float(x) for x in args.margins.split(",")]
     ctx = Context(0)
+    if args.multi:
+        log = lambda m: print(m, flush=True)  # noqa: E731
+        t0 = time.time()
+        X, T, M = collect_multi(ctx, training_graphs_multi(args.quick), log=log)
+        print(f"collected {X.shape[0]} batched samples in {time.time() - t0:.1f}s", flush=True)
+        params = train(ctx, X, T, M, epochs=args.epochs, log=log)
+        os.makedirs(os.path.dirname(WEIGHTS_MULTI), exist_ok=True)
+        np.save(WEIGHTS_MULTI, params.astype(np.float32))
+        rows = evaluate_multi(ctx, eval_graphs_multi(), params, margins=margins, log=log)
+        with open(REPORT_MULTI, "w") as f:
+            json.dump(dict(samples=int(X.shape[0]), epochs=args.epochs, eval=rows), f, indent=1)
+        return
     if args.eval_only:
         rows = evaluate(ctx, eval_graphs(), np.load(WEIGHTS), margins=margins,
                         log=lambda s: print(s, flush=True))

@@ -82,3 +82,61 @@ def test_multi_errors(ctx, rmat14):
     with pytest.raises(gr.GrError) as ei:
         gr.bfs_multi(g2, [0, rmat14.n_vertices])
     assert ei.value.code == gr.GR_EINVAL
+
+
+MULTI_POLICIES = [
+    ("fixed_push_twc", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_TWC)),
+    ("fixed_push_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB)),
+    ("fixed_pull", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_TWC)),
+    ("fixed_pull_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_LB)),
+    ("random7", dict(policy=gr.POLICY_RANDOM, policy_seed=7)),
+    ("random8", dict(policy=gr.POLICY_RANDOM, policy_seed=8, lb_light_threshold=0)),
+    ("learned", dict(policy=gr.POLICY_LEARNED)),
+    ("learned_margin", dict(policy=gr.POLICY_LEARNED, learned_margin=0.25)),
+]
+
+
+def test_multi_policies_change_only_time(ctx, rmat14):
+    """Every per-level action choice of the batched BFS gives the oracle's
+    rows: fixed, random and learned policies (the learned one with a random
+    network for the batched traversal, so its choices vary)."""
+    rng = np.random.default_rng(4)
+    single = rng.standard_normal(gr.MLP_N_PARAMS).astype(np.float32)
+    multi = rng.standard_normal(gr.MLP_N_PARAMS).astype(np.float32)
+    for hg in (rmat14, gg.grid(41, 29)):
+        g = gr.Graph.from_host(ctx, hg)
+        srcs = gg.sources(hg, 40, seed=77)
+        for loaded in (None, np.concatenate([single, multi]), single):
+            ctx.set_policy(loaded)
+            for name, kw in MULTI_POLICIES:
+                d, p, st = gr.bfs_multi(g, srcs, opts=gr.default_opts(**kw))
+                check_rows(hg, srcs, d, p)
+        ctx.set_policy(None)
+        g.free()
+
+
+def test_multi_trace_records(ctx, rmat14):
+    """The batched BFS traces every level: its frontier statistics, the action
+    taken, and the unvisited counts averaged over the sources."""
+    g = gr.Graph.from_host(ctx, rmat14)
+    srcs = gg.sources(rmat14, 16, seed=78)
+    cap = 256
+    tr = (gr.LevelTrace * cap)()
+    o = gr.default_opts(trace=tr, trace_capacity=cap, policy=gr.POLICY_RANDOM, policy_seed=3)
+    d, p, st = gr.bfs_multi(g, srcs, opts=o)
+    check_rows(rmat14, srcs, d, p)
+    recs = tr[:o.trace_count]
+    assert len(recs) == st["iterations"] > 0
+    dn = d.cpu().numpy()
+    R = rmat14.row_offsets
+    deg = np.diff(R).astype(np.int64)
+    for r in recs:
+        active = (dn == r.level).any(axis=0)
+        assert r.n_f == int(active.sum())
+        assert r.m_f == int(deg[active].sum())
+        reached = (dn >= 0) & (dn <= r.level)
+        assert r.n_u == rmat14.n_vertices - int(reached.sum()) // len(srcs)
+        assert r.m_u == rmat14.n_edges - int((reached * deg[None, :]).sum()) // len(srcs)
+        assert r.step_us > 0
+    assert [r.action for r in recs].count(gr.PULL_TWC) + [r.action for r in recs].count(gr.PULL_LB) \
+        == st["action_count"][2] + st["action_count"][3]
