@@ -125,10 +125,10 @@ def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 4, sssp
     return (np.asarray(X, np.float32), np.asarray(T, np.float32), M)
 
 
-def collect_multi(ctx: Context, graphs, k: int = 64, random_runs: int = 4, log=print):
-    """Samples from batched BFS runs (k sources) with each fixed action and
-    with seeded random actions, one host round trip per level, so every record
-    times one level of the action it names."""
+def collect_multi(ctx: Context, graphs, ks=(16, 64), random_runs: int = 4, log=print):
+    """Samples from batched BFS runs (k sources for each k in ks) with each
+    fixed action and with seeded random actions, one host round trip per
+    level, so every record times one level of the action it names."""
     from . import autotune
     cap = 1 << 15
     buf = (LevelTrace * cap)()
@@ -136,21 +136,22 @@ def collect_multi(ctx: Context, graphs, k: int = 64, random_runs: int = 4, log=p
     for name, hg in graphs:
         t0 = time.time()
         g = Graph.from_host(ctx, hg, symmetric=True)
-        srcs = gg.sources(hg, k, seed=3000).astype(np.int32)
         pols = [dict(policy=POLICY_FIXED, fixed_action=a) for a in (0, 1, 2)]
         pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r) for r in range(random_runs)]
-        for kw in pols:
-            o = autotune.tuned_opts(g, "bfs_multi", trace=buf, trace_capacity=cap, **kw)
-            bfs_multi(g, srcs, opts=o)
-            for f, a, us in _records(buf, min(o.trace_count, cap)):
-                X.append(f)
-                t = np.zeros(4, np.float32)
-                m = np.zeros(4, np.float32)
-                t[a] = np.log2(us)
-                m[a] = 1.0
-                T.append(t)
-                M.append(m)
-                grp.append(name)
+        for k in ks:
+            srcs = gg.sources(hg, k, seed=3000).astype(np.int32)
+            for kw in pols:
+                o = autotune.tuned_opts(g, "bfs_multi", trace=buf, trace_capacity=cap, **kw)
+                bfs_multi(g, srcs, opts=o)
+                for f, a, us in _records(buf, min(o.trace_count, cap)):
+                    X.append(f)
+                    t = np.zeros(4, np.float32)
+                    m = np.zeros(4, np.float32)
+                    t[a] = np.log2(us)
+                    m[a] = 1.0
+                    T.append(t)
+                    M.append(m)
+                    grp.append(f"{name}/k{k}")
         g.free()
         log(f"traced batched {name}: {len(X)} samples so far ({time.time() - t0:.1f}s)")
     M = np.asarray(M, np.float32)
@@ -160,7 +161,7 @@ def collect_multi(ctx: Context, graphs, k: int = 64, random_runs: int = 4, log=p
     return (np.asarray(X, np.float32), np.asarray(T, np.float32), M)
 
 
-def evaluate_multi(ctx: Context, graphs, params_multi, k: int = 64, reps: int = 3,
+def evaluate_multi(ctx: Context, graphs, params_multi, ks=(16, 64), reps: int = 3,
                    margins=(0.0,), log=print) -> list[dict]:
     """Batched BFS (k sources) under the heuristic and under the batched
     network, tuned knobs, best of `reps` device times each."""
@@ -172,23 +173,24 @@ def evaluate_multi(ctx: Context, graphs, params_multi, k: int = 64, reps: int = 
     try:
         for name, hg in graphs:
             g = Graph.from_host(ctx, hg, symmetric=True)
-            srcs = gg.sources(hg, k, seed=9100).astype(np.int32)
-            cfgs = {"heuristic": autotune.tuned_opts(g, "bfs_multi")}
-            for mg in margins:
-                cfgs[f"learned_margin{mg:g}"] = autotune.tuned_opts(
-                    g, "bfs_multi", policy=POLICY_LEARNED, learned_margin=mg)
-            res = {}
-            for label, o in cfgs.items():
-                best, st = float("inf"), None
-                for _ in range(reps):
-                    st = bfs_multi(g, srcs, opts=o)[2]
-                    best = min(best, st["device_ms"])
-                res[label] = dict(ms=round(best, 4),
-                                  gteps=round(st["teps_edges"] / (best * 1e-3) / 1e9, 3),
-                                  actions=st["action_count"])
-            row = dict(graph=name, kind="bfs_multi", k=k, **res)
-            rows.append(row)
-            log(json.dumps(row))
+            for k in ks:
+                srcs = gg.sources(hg, k, seed=9100).astype(np.int32)
+                cfgs = {"heuristic": autotune.tuned_opts(g, "bfs_multi")}
+                for mg in margins:
+                    cfgs[f"learned_margin{mg:g}"] = autotune.tuned_opts(
+                        g, "bfs_multi", policy=POLICY_LEARNED, learned_margin=mg)
+                res = {}
+                for label, o in cfgs.items():
+                    best, st = float("inf"), None
+                    for _ in range(reps):
+                        st = bfs_multi(g, srcs, opts=o)[2]
+                        best = min(best, st["device_ms"])
+                    res[label] = dict(ms=round(best, 4),
+                                      gteps=round(st["teps_edges"] / (best * 1e-3) / 1e9, 3),
+                                      actions=st["action_count"])
+                row = dict(graph=name, kind="bfs_multi", k=k, **res)
+                rows.append(row)
+                log(json.dumps(row))
             g.free()
     finally:
         ctx.set_policy(None)
@@ -196,11 +198,11 @@ def evaluate_multi(ctx: Context, graphs, params_multi, k: int = 64, reps: int = 
 
 
 def training_graphs_multi(quick: bool):
-    """R-MAT scales 16..20 with a in [0.45, 0.65], Erdos-Renyi average degree
+    """R-MAT scales 16..22 with a in [0.45, 0.65], Erdos-Renyi average degree
     4..64, grids 256^2 and 512^2 (batched runs over the larger grids take
     thousands of levels per source pass)."""
     gs = []
-    for s in ([16, 18] if quick else [16, 18, 20]):
+    for s in ([16, 18] if quick else [16, 18, 20, 22]):
         for a in (0.45, 0.55, 0.65):
             gs.append((f"rmat_s{s}_a{a}", gg.rmat_family(s, 16, a, seed=11 + s)))
     for d in ((4, 64) if quick else (4, 16, 64)):
@@ -211,7 +213,8 @@ def training_graphs_multi(quick: bool):
 
 
 def eval_graphs_multi():
-    return [("rmat_s20_e16", gg.rmat(20, 16, seed=1)),
+    return [("rmat_s22_e16", gg.rmat(22, 16, seed=1)),
+            ("rmat_s20_e16", gg.rmat(20, 16, seed=1)),
             ("rmat_s18_e16_seed3", gg.rmat(18, 16, seed=3)),
             ("er_n262144_d8", gg.erdos_renyi(1 << 18, 8, seed=77)),
             ("grid_384", gg.grid(384, 384))]
