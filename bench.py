@@ -481,6 +481,8 @@ def large(args, gr, gg, torch):
     mb = gr.bfs_multi(g, srcs, opts=om, out=(depth, parent))[2]
     torch.cuda.synchronize()
     bfs_wall = time.perf_counter() - t0
+    # the same batch under the heuristic, for comparison (untimed by the step clock)
+    mbh = gr.bfs_multi(g, srcs, opts=autotune.tuned_opts(g, "bfs_multi"), out=(depth, parent))[2]
     del depth, parent
     # batched SSSP: the 16 sources in one sweep per iteration
     dist16 = torch.empty((16, V), dtype=torch.int32, device="cuda")
@@ -530,6 +532,7 @@ def large(args, gr, gg, torch):
         "roofline": roof,
         "breakdown": {"bfs_multi16_ms": round(mb["device_ms"], 3),
                       "bfs_multi16_gteps_device": _gteps(mb["teps_edges"], mb["device_ms"]),
+                      "bfs_multi16_heuristic_ms": round(mbh["device_ms"], 3),
                       "sssp_multi16_ms": round(ms16["device_ms"], 3),
                       "sssp_multi16_gteps_device": _gteps(ms16["teps_edges"], ms16["device_ms"]),
                       "sssp_multi16_iterations": ms16["iterations"],

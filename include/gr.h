@@ -309,8 +309,11 @@ gr_status gr_sssp(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, in
  * use the one pull kernel), and GR_POLICY_LEARNED runs the selector network
  * (the batched one when two are loaded) in the kernel that publishes each
  * level's statistics, on the features of gr_mlp_forward with n_u / m_u the
- * unvisited vertex and edge counts averaged over the pass's sources, guarded
- * by learned_margin as for gr_bfs.  opts.trace records every level. */
+ * unvisited vertex and edge counts averaged over the pass's sources and the
+ * last feature the pass's number of sources, guarded by learned_margin as for
+ * gr_bfs.  Small push levels run in blocks of device-predicated levels as in
+ * gr_bfs (device_max_edges; not while tracing or under GR_POLICY_RANDOM).
+ * opts.trace records every level. */
 gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t k,
                        int32_t* depth, int32_t* parent, gr_opts* opts, void* stream,
                        gr_run_stats* stats);

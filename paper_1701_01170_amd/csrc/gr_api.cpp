@@ -1512,6 +1512,13 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
   const float* mlp = static_cast<const float*>(ctx->pool[S_MLP].ptr) + ctx->mlp_multi_offset;
   const bool tracing = opts_in && opts_in->trace;
   uint64_t rng = opts.policy_seed ^ 0x9e3779b97f4a7c15ull;
+  // small push levels run in blocks of device-predicated levels (as gr_bfs):
+  // not while tracing (a record per level) or under the random policy
+  const bool dl_on = opts.device_max_edges >= 0 && !tracing && opts.policy != GR_POLICY_RANDOM;
+  const int64_t dl_max_m = opts.device_max_edges > 0 ? opts.device_max_edges : kDlDefaultMaxEdges;
+  const double dl_do_a = opts.policy == GR_POLICY_FIXED ? -1.0 : (double)opts.do_a;
+  const int dl_blocks = ctx->cu_count > 0 ? ctx->cu_count : 256;
+  int dl_len = kDlFirstLen;
   for (int32_t p0 = 0; p0 < k; p0 += 64) {
     const int32_t kk = std::min<int32_t>(64, k - p0);
     const u64 full = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
@@ -1563,6 +1570,10 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
       } else if (learned) {
         const int c = hc->action;
         if (c >= 0 && c < 4 && c != h && hc->pred[c] + opts.learned_margin < hc->pred[h]) action = c;
+        // as in gr_bfs: a push level that fits a device block stays a push
+        // (the network was trained on levels with one round trip each)
+        if (dl_on && n_a <= kDlMaxN && m_a <= dl_max_m && h < GR_PULL_TWC && action >= GR_PULL_TWC)
+          action = h;
       }
       LevelFeatures lf{};
       lf.level = level;
@@ -1574,7 +1585,45 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
       lf.m_u = E - hc->ms_pair_edges / kk;
       lf.max_deg_f = hc->max_deg[sp];
       lf.prev_pull = prev_pull ? 1 : 0;
+      lf.ms_k = kk;
       const bool pull = action >= GR_PULL_TWC;
+      if (dl_on && !pull && n_a <= kDlMaxN && m_a <= dl_max_m) {
+        // a block of device-predicated push levels, one read-back per block;
+        // its first level is the one just decided, the others follow the
+        // heuristic's push test on the device
+        int kmax = dl_len;
+        if (opts.max_iterations > 0) kmax = std::min(kmax, opts.max_iterations - level);
+        GR_HIP(launch_dl_begin(ctrl, cur, 0, 0, 0u, 0, 0, st));
+        for (int i = 0; i < kmax; ++i) {
+          const int qc = (cur + i) % 3;
+          const int fi = fc ^ (i & 1);
+          DlArgs da{g->R, g->C, q[qc], q[(qc + 1) % 3], qc, i, kDlMaxN, dl_max_m, E, dl_do_a, V,
+                    nullptr, ctrl};
+          da.edges_vs_all = 1;
+          const MsLevel ml{g->R, g->C, front[fi], front[fi ^ 1], visit, next, dpass, ppass,
+                           g->perm, V, level + i + 1};
+          GR_HIP(launch_ms_dlevel(da, ml, dl_blocks, std::min<int64_t>(V, dl_max_m), st));
+        }
+        sp ^= 1;
+        GR_HIP(launch_frontier_stats_after_block(Queues3{{qA, qB, qC}}, cur, g->R, bsums, ctrl, sp,
+                                                 st));
+        prev_pull = false;
+        msel = select_at(sp);
+        GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
+        const int kd = hc->dl_levels;
+        if (kd == kmax) dl_len = std::min(2 * dl_len, kDlMaxLevels);
+        else if (2 * kd < kmax) dl_len = std::max(dl_len / 2, kDlFirstLen);
+        rs.action_count[action] += kd;
+        inspected += hc->dl_vm[kd & 1];
+        cur = (cur + kd) % 3;
+        fc ^= kd & 1;
+        level += kd;
+        n_a = hc->n_f[sp];
+        m_a = hc->m_f[sp];
+        if (kd > 0) continue;
+        // no level ran: the same frontier continues on the host path
+        lf.max_deg_f = hc->max_deg[sp];
+      }
       int kernel = 4;
       if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
       if (pull) {

@@ -376,6 +376,26 @@ hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched,
                               hipStream_t st);
 hipError_t launch_ms_clear(const int32_t* list, const uint32_t* n, int64_t max_n,
                            unsigned long long* front, hipStream_t st);
+struct DlArgs;
+// One device-predicated level of the batched BFS (small push levels): the
+// expansion as a k_dstep, then finalize and clear, both skipping when a level
+// of the block declined (ctrl->dl_stop).  front_cur / front_next alternate by
+// level; depth / parent are the pass's output rows.
+struct MsLevel {
+  const int32_t* R;
+  const int32_t* C;
+  const unsigned long long* front_cur;
+  unsigned long long* front_next;
+  unsigned long long* visit;
+  unsigned long long* next;
+  int32_t* depth;
+  int32_t* parent;
+  const int32_t* perm;
+  int64_t V;
+  int32_t next_depth;
+};
+hipError_t launch_ms_dlevel(const DlArgs& a, const MsLevel& m, int n_blocks, int64_t max_touched,
+                            hipStream_t st);
 hipError_t launch_ms_teps(const unsigned long long* visit, const int32_t* R, int64_t V, int64_t* out,
                           hipStream_t st);
 
@@ -432,6 +452,7 @@ struct DlArgs {
   int64_t V;
   int64_t* log;               // [kDlMaxLevels][3]
   Ctrl* ctrl;
+  int32_t edges_vs_all = 0;   // 1: push -> pull when m_f > E * do_a (batched BFS's rule)
 };
 hipError_t launch_dl_begin(Ctrl* ctrl, int cur, int64_t vm, int64_t vn, uint32_t pq_T,
                            int32_t pq_epoch, int32_t pq_fc, hipStream_t st);

@@ -23,12 +23,14 @@ struct LevelFeatures {
   int64_t V = 0, E = 0;
   int64_t n_f = 0, m_f = 0, n_u = 0, m_u = 0, max_deg_f = 0;
   int32_t prev_pull = 0;  // the previous step pulled (the unvisited frontier exists)
+  int32_t ms_k = 0;       // batched traversal: its number of sources (0: single source)
 };
 
 // The eight selector inputs, each log2(1 + x) / 32:
 //   n_f, m_f, n_u, m_u, max frontier degree, V, E, and the size of the
 //   unvisited-frontier generation a pull step would need now (V after a push
-//   step, 0 after a pull step).
+//   step, 0 after a pull step) -- for a batched traversal instead its number
+//   of sources.
 inline void selector_features(const LevelFeatures& lf, float out[8]) {
   auto f = [](double x) { return (float)(std::log2(1.0 + (x > 0 ? x : 0.0)) / 32.0); };
   out[0] = f((double)lf.n_f);
@@ -38,7 +40,7 @@ inline void selector_features(const LevelFeatures& lf, float out[8]) {
   out[4] = f((double)lf.max_deg_f);
   out[5] = f((double)lf.V);
   out[6] = f((double)lf.E);
-  out[7] = f(lf.prev_pull ? 0.0 : (double)lf.V);
+  out[7] = lf.ms_k > 0 ? f((double)lf.ms_k) : f(lf.prev_pull ? 0.0 : (double)lf.V);
 }
 
 struct Selector {

@@ -112,7 +112,8 @@ __global__ __launch_bounds__(kAdvBlock) void k_dstep(DlArgs a, F f) {
   // heuristic, while its push test holds (Sec. 5.1 push -> pull); every
   // workgroup computes the same total, so all take the same decision
   bool run = total <= a.max_m;
-  if (run && a.do_a >= 0.0 && (double)total > (double)(a.E - vm - total) * a.do_a) run = false;
+  const double pull_bound = a.edges_vs_all ? (double)a.E : (double)(a.E - vm - total);
+  if (run && a.do_a >= 0.0 && (double)total > pull_bound * a.do_a) run = false;
   if (!run) {
     if (lead) ctrl->dl_stop = 1;
     return;

@@ -223,8 +223,12 @@ __global__ __launch_bounds__(128) void k_publish_select(MlpSelect m, Ctrl* __res
       n_u = m.V - ctrl->ms_pairs / m.ms_k;
       m_u = m.E - ctrl->ms_pair_edges / m.ms_k;
     }
-    s_x[threadIdx.x] = mlp_feature(threadIdx.x, n_f, m_f, n_u, m_u, ctrl->max_deg[m.sp], m.V, m.E,
-                                   m.prev_pull);
+    // a batched traversal's last feature is its number of sources (its pull
+    // builds no unvisited list, so the single-source meaning does not apply)
+    s_x[threadIdx.x] = m.ms_k > 0 && threadIdx.x == kIn - 1
+                           ? mlp_feat((double)m.ms_k)
+                           : mlp_feature(threadIdx.x, n_f, m_f, n_u, m_u, ctrl->max_deg[m.sp], m.V,
+                                         m.E, m.prev_pull);
   }
   const int best = mlp_argmin(s_p, s_x, s_h1, s_h2, s_y, m.allowed);
   if (threadIdx.x < kOut) {

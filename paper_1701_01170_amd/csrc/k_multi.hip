@@ -12,6 +12,7 @@
 //            neighbour u (ascending) with bit s in front[u] = the smallest-id
 //            parent of the single-source definition.
 #include "k_advance.h"
+#include "k_dloop.h"
 
 namespace gr {
 
@@ -36,6 +37,10 @@ struct MsPush {
     const u64 m = fm & ~visit[v];
     return atomicOr(&next[v], m) == 0ull;  // first setter lists v once
   }
+  // hooks of a device-predicated level (k_dstep): nothing to prepare or carry
+  __device__ __forceinline__ void frontier_vertex(int32_t) const {}
+  __device__ __forceinline__ MsPush prepare(const Ctrl*, int) const { return *this; }
+  __device__ __forceinline__ void advance(Ctrl*, int, bool) const {}
 };
 
 __device__ __forceinline__ u64 wave_or(u64 x) {
@@ -140,9 +145,10 @@ __global__ __launch_bounds__(256) void k_ms_finalize(
     const int32_t* __restrict__ R, const int32_t* __restrict__ C, const u64* __restrict__ front,
     u64* __restrict__ front_next, u64* __restrict__ visit, u64* __restrict__ next,
     int32_t* __restrict__ depth, int32_t* __restrict__ parent, const int32_t* __restrict__ perm,
-    int64_t V, int32_t next_depth, Ctrl* __restrict__ ctrl) {
+    int64_t V, int32_t next_depth, Ctrl* __restrict__ ctrl, bool predicated) {
   constexpr int U = 8;
   __shared__ int64_t s_pairs[256 / kWave], s_pe[256 / kWave];
+  if (predicated && ctrl->dl_stop) return;  // a level of the block declined
   const int64_t n = *n_touched;
   if ((int64_t)blockIdx.x * blockDim.x >= n) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,7 +262,9 @@ __global__ __launch_bounds__(256) void k_ms_seed(const int32_t* __restrict__ src
 
 __global__ __launch_bounds__(256) void k_ms_clear(const int32_t* __restrict__ list,
                                                   const uint32_t* __restrict__ n,
-                                                  u64* __restrict__ front) {
+                                                  u64* __restrict__ front,
+                                                  const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->dl_stop) return;  // predicated: a level of the block declined
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < (int64_t)*n) front[list[i]] = 0ull;
 }
@@ -332,14 +340,30 @@ hipError_t launch_ms_finalize(const int32_t* touched, const uint32_t* n_touched,
   if (max_n <= 0) return hipSuccess;
   k_ms_finalize<<<blocks_for(max_n, 256), 256, 0, st>>>(touched, n_touched, R, C, front,
                                                         front_next, visit, next, depth, parent,
-                                                        perm, V, next_depth, ctrl);
+                                                        perm, V, next_depth, ctrl, false);
+  return hipGetLastError();
+}
+
+hipError_t launch_ms_dlevel(const DlArgs& a, const MsLevel& m, int n_blocks, int64_t max_touched,
+                            hipStream_t st) {
+  const MsPush f{m.visit, m.next, m.front_cur};
+  k_dstep<MsPush><<<n_blocks, kAdvBlock, 0, st>>>(a, f);
+  const int next = (a.cur + 1) % 3;
+  uint32_t* n_next = &a.ctrl->q_count[next];
+  uint32_t* n_cur = &a.ctrl->q_count[a.cur];
+  if (max_touched > 0)
+    k_ms_finalize<<<blocks_for(max_touched, 256), 256, 0, st>>>(
+        a.q_next, n_next, m.R, m.C, m.front_cur, m.front_next, m.visit, m.next, m.depth, m.parent,
+        m.perm, m.V, m.next_depth, a.ctrl, true);
+  k_ms_clear<<<blocks_for(a.max_n, 256), 256, 0, st>>>(a.q_cur, n_cur,
+                                                      const_cast<u64*>(m.front_cur), a.ctrl);
   return hipGetLastError();
 }
 
 hipError_t launch_ms_clear(const int32_t* list, const uint32_t* n, int64_t max_n, u64* front,
                            hipStream_t st) {
   if (max_n <= 0) return hipSuccess;
-  k_ms_clear<<<blocks_for(max_n, 256), 256, 0, st>>>(list, n, front);
+  k_ms_clear<<<blocks_for(max_n, 256), 256, 0, st>>>(list, n, front, nullptr);
   return hipGetLastError();
 }
 

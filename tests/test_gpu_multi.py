@@ -140,3 +140,38 @@ def test_multi_trace_records(ctx, rmat14):
         assert r.step_us > 0
     assert [r.action for r in recs].count(gr.PULL_TWC) + [r.action for r in recs].count(gr.PULL_LB) \
         == st["action_count"][2] + st["action_count"][3]
+
+
+@pytest.mark.parametrize("kw", [dict(device_max_edges=-1), dict(device_max_edges=64),
+                                dict(device_max_edges=1 << 24),
+                                dict(policy=gr.POLICY_FIXED, fixed_action=gr.PUSH_LB,
+                                     device_max_edges=1 << 24)])
+def test_multi_device_blocks(ctx, kw):
+    """Small push levels of the batched BFS run in device-predicated blocks
+    (finalize and clear predicated on the block's stop flag): off, stopped by a
+    tiny edge bound, covering every push level, and under a fixed push policy."""
+    for hg in (gg.grid(61, 47), gg.rmat(13, 8, seed=5)):
+        g = gr.Graph.from_host(ctx, hg)
+        srcs = gg.sources(hg, 37, seed=91)
+        d, p, st = gr.bfs_multi(g, srcs, opts=gr.default_opts(**kw))
+        check_rows(hg, srcs, d, p)
+        g.free()
+
+
+@pytest.mark.parametrize("cap", [1, 2, 5, 9, 40])
+def test_multi_max_iterations(ctx, cap):
+    """A level cap (also one that falls inside a device block) keeps exactly
+    the levels it allows: depths up to the cap, their parents."""
+    hg = gg.grid(33, 29)
+    g = gr.Graph.from_host(ctx, hg)
+    srcs = np.array([0, 500, 956], np.int32)
+    d, p, st = gr.bfs_multi(g, srcs, opts=gr.default_opts(max_iterations=cap))
+    dn, pn = d.cpu().numpy(), p.cpu().numpy()
+    for i, s in enumerate(srcs):
+        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
+        keep = (ed >= 0) & (ed <= cap)
+        np.testing.assert_array_equal(dn[i], np.where(keep, ed, -1), err_msg=f"row {i}")
+        np.testing.assert_array_equal(pn[i], np.where(keep, ep, -1), err_msg=f"row {i}")
+    assert st["iterations"] == min(cap, max(int(oracle.bfs(hg.row_offsets, hg.col_indices, int(s))[0].max())
+                                             for s in srcs) + 1)
+    g.free()
