@@ -198,13 +198,16 @@ def evaluate_multi(ctx: Context, graphs, params_multi, ks=(16, 64), reps: int = 
 
 
 def training_graphs_multi(quick: bool):
-    """R-MAT scales 16..22 with a in [0.45, 0.65], Erdos-Renyi average degree
-    4..64, grids 256^2 and 512^2 (batched runs over the larger grids take
-    thousands of levels per source pass)."""
+    """R-MAT scales 16..22 with a in [0.45, 0.65] and scale 24 with the
+    paper's a, Erdos-Renyi average degree 4..64, grids 256^2 and 512^2
+    (batched runs over the larger grids take thousands of levels per source
+    pass)."""
     gs = []
     for s in ([16, 18] if quick else [16, 18, 20, 22]):
         for a in (0.45, 0.55, 0.65):
             gs.append((f"rmat_s{s}_a{a}", gg.rmat_family(s, 16, a, seed=11 + s)))
+    if not quick:
+        gs.append(("rmat_s24_a0.57", gg.rmat(24, 16, seed=35)))
     for d in ((4, 64) if quick else (4, 16, 64)):
         gs.append((f"er_n262144_d{d}", gg.erdos_renyi(1 << 18, d, seed=5)))
     for n in (256, 512):
