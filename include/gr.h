@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 2
+#define GR_ABI_VERSION 3
 
 typedef enum gr_status {
   GR_OK = 0,
@@ -166,7 +166,19 @@ typedef struct gr_opts {
                                 graph (the instantiated graph of a block of the same length is
                                 kept in the context and updated); 0 = the block's kernels are
                                 enqueued one by one.  Ignored while tracing and by gr_bfs_static. */
+  int32_t sssp_opt_off;      /* SSSP refinements of the iterations with the byte-mark filter
+                                switched off, a bit set of GR_SSSP_OPT_* (0: all on); none
+                                changes the results */
 } gr_opts;
+
+/* gr_opts.sssp_opt_off bits */
+#define GR_SSSP_OPT_CULL 1  /* drop from the next frontier a vertex whose edges this iteration
+                               already relaxed with its final distance (a further
+                               Remove_Redundant, Alg. 1) */
+#define GR_SSSP_OPT_BINS 2  /* list the next frontier in bins of distance, smallest first, so
+                               that small distances are relaxed first (the ordering aim of the
+                               Sec. 5.1 priority queue, without its extra iterations); not used
+                               with sssp_delta > 0 */
 
 /* gr_opts.bfs_filter (Sec. 5.2: idempotent vs. non-idempotent operations).
  * Results are identical for all three; only the time differs. */

@@ -35,6 +35,7 @@ ACTION_NAMES = ["PUSH_TWC", "PUSH_LB", "PULL_TWC", "PULL_LB"]
 SYMMETRIC, DEVICE_INPUT, RENUMBER = 0x1, 0x2, 0x4
 BFS_FILTER_AUTO, BFS_FILTER_ATOMIC, BFS_FILTER_IDEMPOTENT = 0, 1, 2
 IDEM_CULL_WAVE, IDEM_CULL_HISTORY, IDEM_CULL_LABEL = 0x1, 0x2, 0x4
+SSSP_OPT_CULL, SSSP_OPT_BINS = 0x1, 0x2
 MLP_N_PARAMS = 1476
 
 
@@ -65,7 +66,8 @@ class Opts(ctypes.Structure):
                 ("learned_margin", ctypes.c_float), ("bfs_filter", ctypes.c_int32),
                 ("idem_culls_off", ctypes.c_int32), ("idem_table_log2", ctypes.c_int32),
                 ("adv_block", ctypes.c_int32), ("twc_wave_min", ctypes.c_int32),
-                ("twc_block_min", ctypes.c_int32), ("graph_blocks", ctypes.c_int32)]
+                ("twc_block_min", ctypes.c_int32), ("graph_blocks", ctypes.c_int32),
+                ("sssp_opt_off", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):

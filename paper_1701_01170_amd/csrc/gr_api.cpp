@@ -584,6 +584,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->twc_block_min must be >= twc_wave_min");
   if (opts->graph_blocks != 0 && opts->graph_blocks != 1)
     return fail(GR_EINVAL, "opts->graph_blocks must be 0 or 1");
+  if (opts->sssp_opt_off & ~(GR_SSSP_OPT_CULL | GR_SSSP_OPT_BINS))
+    return fail(GR_EINVAL, "opts->sssp_opt_off: unknown bits");
   if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
     return fail(GR_EINVAL, "opts->bfs_filter out of range");
   if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
@@ -1223,6 +1225,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
   uint16_t* mirror;
   GR_TRY(pool_typed(ctx, S_MIRROR, V, &mirror));
+  uint32_t* relaxed = nullptr;
+  if (!(opts.sssp_opt_off & GR_SSSP_OPT_CULL)) GR_TRY(pool_typed(ctx, S_RELAXED, V, &relaxed));
   // src_dev: the sources in traversal ids, then in caller ids
   GR_TRY(pool_typed(ctx, S_TMP0, 2 * (size_t)n_src, &src_dev));
   std::vector<int32_t> src_both(2 * (size_t)n_src);
@@ -1242,6 +1246,15 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     GR_TRY(pool_typed(ctx, S_FAR, 3 * V, &pq.far_base));
     GR_TRY(pool_typed(ctx, S_FAR_TAGS, V, &pq.far_tag));
   }
+  // distance bins of the marks compaction: width 2^shift, the bins spanning
+  // about two to four times the largest weight
+  SsspBins bins{nullptr, 0u};
+  if (!use_pq && !(opts.sssp_opt_off & GR_SSSP_OPT_BINS)) {
+    GR_TRY(pool_typed(ctx, S_SSSP_BINS, kSsspBinWords, &bins.state));
+    uint32_t span = 1;  // smallest power of two above max_weight
+    while (span <= g->max_weight && span < (1u << 31)) span <<= 1;
+    while ((uint64_t)kSsspBins << bins.shift < 2ull * span) ++bins.shift;
+  }
   Ctrl* hc = ctx->host_ctrl;
   int32_t* q[3] = {qA, qB, qC};
 
@@ -1250,7 +1263,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_HIP(hipMemcpyAsync(qA, src_both.data(), sizeof(int32_t) * n_src, hipMemcpyHostToDevice, st));
   GR_HIP(hipStreamSynchronize(st));  // the host vector must outlive the copies
   GR_HIP(hipEventRecord(ctx->ev_start, st));
-  GR_HIP(launch_sssp_init(keys, tags, use_pq ? pq.far_tag : nullptr, mirror, V, ctrl, st));
+  GR_HIP(launch_sssp_init(keys, tags, use_pq ? pq.far_tag : nullptr, mirror, relaxed, bins.state,
+                          V, ctrl, st));
   GR_HIP(launch_sssp_seed(src_dev, n_src, keys, tags, ctrl, st));
   int cur = 0, sp = 0;
   GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
@@ -1401,13 +1415,17 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         kernel += kTraceMarksOffset;
         const bool screen = expanded + n_f + far_n >= V / kSsspMirrorDivisor;
         GR_HIP(launch_sssp_relax_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                       g->W, keys, perm, marks, mirror, screen, adv, st));
+                                       g->W, keys, perm, marks, mirror, relaxed, screen, adv,
+                                       st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
         if (use_pq)
-          GR_HIP(launch_sssp_pq_mark_compact(marks, V, keys, mirror, pq, ctrl, q[(cur + 1) % 3],
-                                             &ctrl->q_count[(cur + 1) % 3], st));
+          GR_HIP(launch_sssp_pq_mark_compact(marks, V, keys, mirror, relaxed, pq, ctrl,
+                                             q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], st));
+        else if (bins.state)
+          GR_HIP(launch_sssp_bin_compact(marks, V, keys, mirror, relaxed, bins, q[(cur + 1) % 3],
+                                         &ctrl->q_count[(cur + 1) % 3], st));
         else
-          GR_HIP(launch_sssp_mark_compact(marks, V, keys, mirror, q[(cur + 1) % 3],
+          GR_HIP(launch_sssp_mark_compact(marks, V, keys, mirror, relaxed, q[(cur + 1) % 3],
                                           &ctrl->q_count[(cur + 1) % 3], st));
       } else if (use_pq) {
         GR_HIP(launch_sssp_pq_relax(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,

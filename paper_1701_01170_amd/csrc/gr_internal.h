@@ -66,6 +66,8 @@ enum Slot : int {
   S_MARKS,         // one byte per vertex, all zero between uses
   S_MLP_WS,        // selector gradient partial sums
   S_MIRROR,        // shortest-path 16-bit distance mirror [V]
+  S_RELAXED,       // shortest-path: 1 + distance a frontier vertex's edges were relaxed with [V]
+  S_SSSP_BINS,     // shortest-path distance bins: histograms, cursors, base
   S_UL_A,          // BFS pull: unvisited vertices with neighbours (two lists, ping-pong)
   S_UL_B,
   S_CAND,          // BFS idempotent advance: candidate list [V]
@@ -488,8 +490,12 @@ hipError_t launch_sssp_pq_dstep(const DlArgs& a, const uint32_t* W, unsigned lon
                                 hipStream_t st);
 
 // SSSP
+// relaxed (nullable): the cull of vertices already relaxed with their final
+// distance (cleared here; raised by the marks relaxation, read by the
+// compactions); bin_state (nullable): the distance bins' state, cleared
 hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag,
-                            uint16_t* mirror, int64_t V, Ctrl* ctrl, hipStream_t st);
+                            uint16_t* mirror, uint32_t* relaxed, uint32_t* bin_state, int64_t V,
+                            Ctrl* ctrl, hipStream_t st);
 hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long long* keys,
                             int32_t* tags, Ctrl* ctrl, hipStream_t st);
 // keys hold (dist << 32 | predecessor in caller ids); perm nullable
@@ -508,15 +514,32 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
                                    const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
-                                   bool filter, const AdvCfg& cfg, hipStream_t st);
+                                   uint32_t* relaxed, bool filter, const AdvCfg& cfg,
+                                   hipStream_t st);
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                    uint16_t* mirror, int32_t* out_q, uint32_t* out_count,
-                                    hipStream_t st);
+                                    uint16_t* mirror, uint32_t* relaxed, int32_t* out_q,
+                                    uint32_t* out_count, hipStream_t st);
+// Distance-ordered compaction: the marked vertices (minus the culled ones)
+// listed in bins of distance, smallest first; *out_count is set, not added to.
+constexpr int kSsspBins = 128;
+constexpr int kBinCopies = 8;
+constexpr int kSsspBinHist = 0;                                 // [kBinCopies][kSsspBins]
+constexpr int kSsspBinCursor = kBinCopies * kSsspBins;          // [kBinCopies][kSsspBins]
+constexpr int kSsspBinBase = 2 * kBinCopies * kSsspBins;        // lower bound of the distances
+constexpr int kSsspBinWords = 2 * kBinCopies * kSsspBins + 1;
+struct SsspBins {
+  uint32_t* state;  // kSsspBinWords words
+  uint32_t shift;   // bin width 2^shift
+};
+hipError_t launch_sssp_bin_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
+                                   uint16_t* mirror, uint32_t* relaxed, const SsspBins& bins,
+                                   int32_t* out_q, uint32_t* out_count, hipStream_t st);
 // Priority-queue form: marked vertices below pq.T go to out_q, the others to
 // far pile pq.fc (once per far-pile generation).
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                       uint16_t* mirror, const PqState& pq, Ctrl* ctrl,
-                                       int32_t* out_q, uint32_t* out_count, hipStream_t st);
+                                       uint16_t* mirror, uint32_t* relaxed, const PqState& pq,
+                                       Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
+                                       hipStream_t st);
 // dist / pred written at caller ids; src_orig_dev: the sources in caller ids
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
                                 uint32_t* dist, int32_t* pred, const int32_t* perm,

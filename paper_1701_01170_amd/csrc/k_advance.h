@@ -10,6 +10,8 @@
 //   kFar                                     true for functors whose commit
 //                                            returns 0 / 1 / 2: 2 appends v to
 //                                            a second queue (f.far_q, f.far_count)
+//   seg_note(u, payload)                     optional: told each frontier vertex's
+//                                            payload as its edges are staged
 //   kBatchCommit                             true for functors that provide
 //                                            commit_batch<B>(u, pay, v, ev, ok, code):
 //                                            the commits of a lane's B edges in
@@ -57,6 +59,20 @@ template <class F, class = void>
 struct has_out_cap : std::false_type {};
 template <class F>
 struct has_out_cap<F, std::void_t<decltype(&F::out_cap)>> : std::true_type {};
+
+template <class F, class = void>
+struct has_seg_note : std::false_type {};
+template <class F>
+struct has_seg_note<F, std::void_t<decltype(std::declval<const F&>().seg_note(
+                           0, std::declval<typename F::pay_t>()))>> : std::true_type {};
+
+// seg_note(u, payload): told the payload a frontier vertex's edges are about
+// to be processed with (once per vertex and chunk of its row).
+template <class F>
+__device__ __forceinline__ void functor_seg_note(const F& f, int32_t u,
+                                                 const typename F::pay_t& pay) {
+  if constexpr (has_seg_note<F>::value) f.seg_note(u, pay);
+}
 
 template <class F>
 __device__ __forceinline__ void functor_block_init(const F& f) {
@@ -187,7 +203,9 @@ __global__ __launch_bounds__(BLOCK) void k_push_lb(
       s_off[i] = offsets[s];
       s_u[i] = u;
       s_rb[i] = rstart[s];
-      s_pay[i] = f.seg_payload(u);
+      const typename F::pay_t pu = f.seg_payload(u);
+      s_pay[i] = pu;
+      functor_seg_note(f, u, pu);
     }
     if (threadIdx.x == 0) s_off[cnt] = offsets[pb + cnt];
     for (int j = threadIdx.x; j < N; j += BLOCK) s_seg[j] = 0;
@@ -270,6 +288,7 @@ __global__ __launch_bounds__(BLOCK) void k_push_light(
     rb = R[u0];
     d = R[u0 + 1] - rb;
     pay0 = f.seg_payload(u0);
+    functor_seg_note(f, u0, pay0);
   }
   int64_t total;
   const int64_t ex = block_excl_scan<BLOCK>((int64_t)d, s_tot, &total);
@@ -323,6 +342,7 @@ __global__ __launch_bounds__(BLOCK) void k_push_twc(
     rb = R[u0];
     d = R[u0 + 1] - rb;
     pay0 = f.seg_payload(u0);
+    functor_seg_note(f, u0, pay0);
   }
   // workgroup tier
   bool big = d > block_min;

@@ -101,6 +101,17 @@ struct SsspVisit {
 // neither shorten the distance nor tie it, and skips the 8-byte key gather.
 // The mirror is a quarter of the keys' size, so its gathers hit the caches
 // more often; the filter pays off once most vertices have been reached.
+//
+// With `relaxed` (nullable), every chunk that stages a frontier vertex u
+// raises relaxed[u] to 1 + the distance it relaxes u's edges with; the
+// compaction resets relaxed[] to 0 for the vertices it lets into the next
+// frontier.  Distances only decrease, so after an iteration relaxed[v] equals
+// dist(v) + 1 exactly when v was in the frontier and every chunk of its row
+// already read its final distance: its edges went out with that distance, and
+// the compaction drops v from the next frontier (Remove_Redundant applied to
+// work already done).  A value left from an earlier iteration is larger than
+// 1 + any distance v can have after dropping in this one, and 0 never
+// matches, so nothing else is dropped.
 constexpr uint32_t kMirrorNone = 0xffffu;
 
 template <bool FILTER>
@@ -110,12 +121,17 @@ struct SsspMark {
   uint8_t* __restrict__ marks;
   const int32_t* __restrict__ perm;
   const uint16_t* __restrict__ mirror;
+  uint32_t* __restrict__ relaxed;  // nullable
 
   using pay_t = int32_t;
   static constexpr bool kFar = false;
   static constexpr bool kBatchCommit = true;
   __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
     return (int32_t)(uint32_t)(keys[u] >> 32);
+  }
+  // a frontier vertex's distance is below UINT32_MAX, so du + 1 does not wrap
+  __device__ __forceinline__ void seg_note(int32_t u, int32_t du) const {
+    if (relaxed) atomicMax(&relaxed[u], (uint32_t)du + 1u);
   }
   __device__ __forceinline__ uint32_t edge_value(int64_t e) const { return W[e]; }
   // the key test happens in commit_batch, whose loads are batched anyway
@@ -174,41 +190,257 @@ __device__ __forceinline__ void word_keys(const unsigned long long* __restrict__
   }
 }
 
+// relaxed[] of the 32 consecutive vertices v0 .. v0 + 31 (v0 a multiple of
+// 32, all below V), four per 16-byte load.
+__device__ __forceinline__ void word_relaxed(const uint32_t* __restrict__ relaxed, int64_t v0,
+                                             uint32_t (&r)[32]) {
+  const uint4* __restrict__ r4 = reinterpret_cast<const uint4*>(relaxed + v0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint4 x = r4[j];
+    r[4 * j] = x.x;
+    r[4 * j + 1] = x.y;
+    r[4 * j + 2] = x.z;
+    r[4 * j + 3] = x.w;
+  }
+}
+
+// Whether marked vertex v (key k, relaxed value r) stays out of the next
+// frontier; otherwise its relaxed[] entry is reset for the iteration it joins.
+__device__ __forceinline__ bool drop_relaxed(uint32_t* __restrict__ relaxed, int64_t v,
+                                             unsigned long long k, uint32_t r) {
+  if (r == (uint32_t)(k >> 32) + 1u) return true;
+  if (r != 0u) relaxed[v] = 0u;
+  return false;
+}
+
 // One thread per 32 vertices: gather and clear the marks, list the marked
-// vertices (ascending within each workgroup).
+// vertices (ascending within each workgroup), except those whose edges this
+// iteration already relaxed with their final distance (relaxed, nullable).
 // The distance mirror of every marked vertex is refreshed on the way.
 __global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__ marks, int64_t V,
                                                            const unsigned long long* __restrict__ keys,
                                                            uint16_t* __restrict__ mirror,
+                                                           uint32_t* __restrict__ relaxed,
                                                            int32_t* __restrict__ out_q,
                                                            uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t mask = take_marks(marks, w, V);
+  uint32_t mask = take_marks(marks, w, V);
   const int64_t v0 = w * 32;
   if (mask && v0 + 32 <= V) {
     unsigned long long k[32];
     word_keys(keys, v0, k);
+    if (relaxed) {
+      uint32_t r[32];
+      word_relaxed(relaxed, v0, r);
 #pragma unroll
-    for (int b = 0; b < 32; ++b)
-      if ((mask >> b) & 1u) mirror[v0 + b] = mirror_of(k[b]);
+      for (int b = 0; b < 32; ++b) {
+        if (!((mask >> b) & 1u)) continue;
+        mirror[v0 + b] = mirror_of(k[b]);
+        if (drop_relaxed(relaxed, v0 + b, k[b], r[b])) mask &= ~(1u << b);
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 32; ++b)
+        if ((mask >> b) & 1u) mirror[v0 + b] = mirror_of(k[b]);
+    }
   } else {
     for (uint32_t m = mask; m; m &= m - 1) {
-      const int64_t v = v0 + __ffs(m) - 1;
-      mirror[v] = mirror_of(keys[v]);
+      const int b = __ffs(m) - 1;
+      const int64_t v = v0 + b;
+      const unsigned long long key = keys[v];
+      mirror[v] = mirror_of(key);
+      if (relaxed && drop_relaxed(relaxed, v, key, relaxed[v])) mask &= ~(1u << b);
     }
   }
   append_mask<256>(mask, w, out_q, out_count);
+}
+
+// Distance-ordered compaction (without the priority queue).  Vertices are
+// relaxed roughly in frontier order (workgroups start in chunk order), so a
+// frontier that lists small distances first lets their improvements reach the
+// larger-distance vertices before those are staged: fewer edges go out with
+// a distance that later drops (Sec. 5.1: the priority queue's aim, without its
+// extra iterations).  The marked vertices are binned by
+// (dist - base) >> shift into kSsspBins bins (the last takes everything
+// beyond), where base is a lower bound of every distance the iteration can
+// have produced: the lower edge of the previous binned frontier's first
+// non-empty bin (distances assigned in an iteration are at least the
+// smallest distance of its frontier).  Pass 1 culls, refreshes the mirror,
+// writes bin + 1 into the mark byte and counts bins per workgroup into one of
+// kBinCopies histograms; the scan lays the bins out (copies of a bin in
+// order) and moves base; pass 2, on the same grid, scatters each vertex into
+// its bin's range (order inside a bin: by workgroup, then arbitrary).
+__device__ __forceinline__ uint32_t peek_marks(const uint8_t* __restrict__ marks, int64_t w,
+                                               int64_t V, uint8_t (&m)[32]) {
+  const int64_t v0 = w * 32;
+  uint32_t mask = 0;
+  if (v0 + 32 <= V) {
+    const uint4* m4 = reinterpret_cast<const uint4*>(marks + v0);
+    const uint4 a = m4[0], b = m4[1];
+    const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        m[4 * i + k] = (uint8_t)(q[i] >> (8 * k));
+        if (m[4 * i + k]) mask |= 1u << (4 * i + k);
+      }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+      m[b] = v0 + b < V ? marks[v0 + b] : (uint8_t)0;
+      if (m[b]) mask |= 1u << b;
+    }
+  }
+  return mask;
+}
+
+__device__ __forceinline__ void put_marks(uint8_t* __restrict__ marks, int64_t w, int64_t V,
+                                          const uint8_t (&m)[32]) {
+  const int64_t v0 = w * 32;
+  if (v0 + 32 <= V) {
+    uint32_t q[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      q[i] = (uint32_t)m[4 * i] | ((uint32_t)m[4 * i + 1] << 8) | ((uint32_t)m[4 * i + 2] << 16) |
+             ((uint32_t)m[4 * i + 3] << 24);
+    uint4* z = reinterpret_cast<uint4*>(marks + v0);
+    z[0] = make_uint4(q[0], q[1], q[2], q[3]);
+    z[1] = make_uint4(q[4], q[5], q[6], q[7]);
+  } else {
+    for (int b = 0; b < 32 && v0 + b < V; ++b) marks[v0 + b] = m[b];
+  }
+}
+
+__device__ __forceinline__ uint32_t dist_bin(uint32_t d, uint32_t base, uint32_t shift) {
+  const uint32_t x = d > base ? (d - base) >> shift : 0u;
+  return x < (uint32_t)kSsspBins ? x : (uint32_t)kSsspBins - 1u;
+}
+
+__global__ __launch_bounds__(256) void k_sssp_bin_count(uint8_t* __restrict__ marks, int64_t V,
+                                                        const unsigned long long* __restrict__ keys,
+                                                        uint16_t* __restrict__ mirror,
+                                                        uint32_t* __restrict__ relaxed,
+                                                        SsspBins bins) {
+  __shared__ uint32_t s_h[kSsspBins];
+  for (int i = threadIdx.x; i < kSsspBins; i += 256) s_h[i] = 0;
+  __syncthreads();
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t base = bins.state[kSsspBinBase];
+  uint8_t m[32];
+  const uint32_t mask = w < (V + 31) / 32 ? peek_marks(marks, w, V, m) : 0u;
+  if (mask) {
+    const int64_t v0 = w * 32;
+    unsigned long long k[32];
+    uint32_t r[32];
+    if (v0 + 32 <= V) {
+      word_keys(keys, v0, k);
+      if (relaxed) word_relaxed(relaxed, v0, r);
+    } else {
+#pragma unroll
+      for (int b = 0; b < 32; ++b) {
+        const bool in = (mask >> b) & 1u;
+        k[b] = in ? keys[v0 + b] : 0ull;
+        r[b] = in && relaxed ? relaxed[v0 + b] : 0u;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+      if (!((mask >> b) & 1u)) continue;
+      mirror[v0 + b] = mirror_of(k[b]);
+      if (relaxed && drop_relaxed(relaxed, v0 + b, k[b], r[b])) {
+        m[b] = 0;
+        continue;
+      }
+      const uint32_t bin = dist_bin((uint32_t)(k[b] >> 32), base, bins.shift);
+      m[b] = (uint8_t)(bin + 1u);
+      atomicAdd(&s_h[bin], 1u);
+    }
+    put_marks(marks, w, V, m);
+  }
+  __syncthreads();
+  uint32_t* h = bins.state + kSsspBinHist + (blockIdx.x % kBinCopies) * kSsspBins;
+  for (int i = threadIdx.x; i < kSsspBins; i += 256)
+    if (s_h[i]) atomicAdd(&h[i], s_h[i]);
+}
+
+// One workgroup of kSsspBins threads: bin ranges (cursor of copy c of bin b =
+// start of bin b + the counts of copies before c), the histograms cleared,
+// the next base, and the frontier size.
+__global__ __launch_bounds__(kSsspBins) void k_sssp_bin_scan(SsspBins bins,
+                                                             uint32_t* __restrict__ out_count) {
+  __shared__ uint32_t s_tmp[kSsspBins / kWave];
+  __shared__ uint32_t s_first;
+  const int b = threadIdx.x;
+  uint32_t* h = bins.state + kSsspBinHist;
+  uint32_t* cur = bins.state + kSsspBinCursor;
+  uint32_t c[kBinCopies];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBinCopies; ++i) {
+    c[i] = h[i * kSsspBins + b];
+    tot += c[i];
+  }
+  if (b == 0) s_first = kSsspBins;
+  const uint32_t inc = wave_incl_scan(tot);
+  if (lane() == kWave - 1) s_tmp[b / kWave] = inc;
+  __syncthreads();
+  if (tot) atomicMin(&s_first, (uint32_t)b);
+  uint32_t start = inc - tot;
+  for (int i = 0; i < b / kWave; ++i) start += s_tmp[i];
+#pragma unroll
+  for (int i = 0; i < kBinCopies; ++i) {
+    cur[i * kSsspBins + b] = start;
+    start += c[i];
+    h[i * kSsspBins + b] = 0u;
+  }
+  __syncthreads();
+  if (b == kSsspBins - 1) {
+    *out_count = start;
+    const uint32_t f = s_first;
+    if (f < (uint32_t)kSsspBins) bins.state[kSsspBinBase] += f << bins.shift;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sssp_bin_scatter(uint8_t* __restrict__ marks, int64_t V,
+                                                          SsspBins bins,
+                                                          int32_t* __restrict__ out_q) {
+  __shared__ uint32_t s_n[kSsspBins];
+  for (int i = threadIdx.x; i < kSsspBins; i += 256) s_n[i] = 0;
+  __syncthreads();
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  uint8_t m[32];
+  const uint32_t mask = w < (V + 31) / 32 ? peek_marks(marks, w, V, m) : 0u;
+  uint32_t rank[32];
+#pragma unroll
+  for (int b = 0; b < 32; ++b) rank[b] = (mask >> b) & 1u ? atomicAdd(&s_n[m[b] - 1], 1u) : 0u;
+  if (mask) {
+    uint8_t z[32];
+#pragma unroll
+    for (int b = 0; b < 32; ++b) z[b] = 0;
+    put_marks(marks, w, V, z);
+  }
+  __syncthreads();
+  uint32_t* cur = bins.state + kSsspBinCursor + (blockIdx.x % kBinCopies) * kSsspBins;
+  for (int i = threadIdx.x; i < kSsspBins; i += 256)
+    if (s_n[i]) s_n[i] = atomicAdd(&cur[i], s_n[i]);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 32; ++b)
+    if ((mask >> b) & 1u) out_q[s_n[m[b] - 1] + rank[b]] = (int32_t)(w * 32 + b);
 }
 
 // The same with the near / far split of the priority queue: a marked vertex
 // whose distance is below the threshold T joins the next frontier, any other
 // joins far pile fc unless it is already there in this generation (far_tag).
 // Only the thread owning a vertex reads or writes its far tag here; the
-// distance mirror is refreshed as in k_sssp_mark_compact.
+// distance mirror is refreshed and vertices already relaxed with their final
+// distance are dropped as in k_sssp_mark_compact.
 __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
     uint8_t* __restrict__ marks, int64_t V, const unsigned long long* __restrict__ keys,
-    uint16_t* __restrict__ mirror, uint32_t T, int32_t epoch, int32_t* __restrict__ far_tag,
-    int32_t* __restrict__ far_q,
+    uint16_t* __restrict__ mirror, uint32_t* __restrict__ relaxed, uint32_t T, int32_t epoch,
+    int32_t* __restrict__ far_tag, int32_t* __restrict__ far_q,
     uint32_t* __restrict__ far_count, int32_t* __restrict__ out_q,
     uint32_t* __restrict__ out_count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,6 +449,8 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
   if (mask && v0 + 32 <= V) {
     unsigned long long k[32];
     word_keys(keys, v0, k);
+    uint32_t rl[32];
+    if (relaxed) word_relaxed(relaxed, v0, rl);
     int32_t ft[32];
     const int4* __restrict__ f4 = reinterpret_cast<const int4*>(far_tag + v0);
 #pragma unroll
@@ -231,6 +465,7 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
     for (int b = 0; b < 32; ++b) {
       if (!((mask >> b) & 1u)) continue;
       mirror[v0 + b] = mirror_of(k[b]);
+      if (relaxed && drop_relaxed(relaxed, v0 + b, k[b], rl[b])) continue;
       if ((uint32_t)(k[b] >> 32) < T) {
         near |= 1u << b;
       } else if (ft[b] != epoch) {
@@ -244,6 +479,7 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
       const int64_t v = v0 + b;
       const unsigned long long key = keys[v];
       mirror[v] = mirror_of(key);
+      if (relaxed && drop_relaxed(relaxed, v, key, relaxed[v])) continue;
       if ((uint32_t)(key >> 32) < T) {
         near |= 1u << b;
       } else if (far_tag[v] != epoch) {
@@ -417,14 +653,19 @@ __global__ __launch_bounds__(kAdvBlock) void k_sssp_pq_refill(const unsigned lon
 __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restrict__ keys,
                                                    int32_t* __restrict__ tags,
                                                    int32_t* __restrict__ far_tag,
-                                                   uint16_t* __restrict__ mirror, int64_t V,
+                                                   uint16_t* __restrict__ mirror,
+                                                   uint32_t* __restrict__ relaxed,
+                                                   uint32_t* __restrict__ bin_state, int64_t V,
                                                    Ctrl* __restrict__ ctrl) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (bin_state && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kSsspBinWords; i += blockDim.x) bin_state[i] = 0u;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
     keys[v] = ~0ull;
     tags[v] = -1;
     if (far_tag) far_tag[v] = -1;
     mirror[v] = (uint16_t)kMirrorNone;
+    if (relaxed) relaxed[v] = 0u;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->far_count[0] = ctrl->far_count[1] = ctrl->far_count[2] = 0;
@@ -505,10 +746,11 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag,
-                            uint16_t* mirror, int64_t V, Ctrl* ctrl, hipStream_t st) {
+                            uint16_t* mirror, uint32_t* relaxed, uint32_t* bin_state, int64_t V,
+                            Ctrl* ctrl, hipStream_t st) {
   unsigned g = blocks_for(V, 256);
   if (g > 4096) g = 4096;
-  k_sssp_init<<<g, 256, 0, st>>>(keys, tags, far_tag, mirror, V, ctrl);
+  k_sssp_init<<<g, 256, 0, st>>>(keys, tags, far_tag, mirror, relaxed, bin_state, V, ctrl);
   return hipGetLastError();
 }
 
@@ -593,35 +835,49 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
                                    const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
-                                   bool filter, const AdvCfg& cfg, hipStream_t st) {
+                                   uint32_t* relaxed, bool filter, const AdvCfg& cfg,
+                                   hipStream_t st) {
   if (filter) {
-    const SsspMark<true> f{W, keys, marks, perm, mirror};
+    const SsspMark<true> f{W, keys, marks, perm, mirror, relaxed};
     return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
                          nullptr, cfg, st);
   }
-  const SsspMark<false> f{W, keys, marks, perm, mirror};
+  const SsspMark<false> f{W, keys, marks, perm, mirror, relaxed};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
                        nullptr, cfg, st);
 }
 
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                       uint16_t* mirror, const PqState& pq, Ctrl* ctrl,
-                                       int32_t* out_q, uint32_t* out_count, hipStream_t st) {
+                                       uint16_t* mirror, uint32_t* relaxed, const PqState& pq,
+                                       Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
+                                       hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   if (n_words <= 0) return hipSuccess;
   k_sssp_pq_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(
-      marks, V, keys, mirror, pq.T, pq.epoch, pq.far_tag, pq.far_base + (int64_t)pq.fc * pq.V,
+      marks, V, keys, mirror, relaxed, pq.T, pq.epoch, pq.far_tag, pq.far_base + (int64_t)pq.fc * pq.V,
       &ctrl->far_count[pq.fc], out_q, out_count);
   return hipGetLastError();
 }
 
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                    uint16_t* mirror, int32_t* out_q, uint32_t* out_count,
-                                    hipStream_t st) {
+                                    uint16_t* mirror, uint32_t* relaxed, int32_t* out_q,
+                                    uint32_t* out_count, hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   if (n_words <= 0) return hipSuccess;
-  k_sssp_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, keys, mirror, out_q,
-                                                                out_count);
+  k_sssp_mark_compact<<<blocks_for(n_words, 256), 256, 0, st>>>(marks, V, keys, mirror, relaxed,
+                                                                out_q, out_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sssp_bin_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
+                                   uint16_t* mirror, uint32_t* relaxed, const SsspBins& bins,
+                                   int32_t* out_q, uint32_t* out_count, hipStream_t st) {
+  const int64_t n_words = (V + 31) / 32;
+  if (n_words <= 0) return hipSuccess;
+  const unsigned g = blocks_for(n_words, 256);
+  k_sssp_bin_count<<<g, 256, 0, st>>>(marks, V, keys, mirror, relaxed, bins);
+  k_sssp_bin_scan<<<1, kSsspBins, 0, st>>>(bins, out_count);
+  k_sssp_bin_scatter<<<g, 256, 0, st>>>(marks, V, bins, out_q);
   return hipGetLastError();
 }
 

@@ -69,6 +69,12 @@ SSSP_POLICIES = POLICIES + [
     ("pq7_light", dict(sssp_delta=7, lb_light_threshold=1 << 30)),
     ("pq_huge", dict(sssp_delta=1 << 30)),
     ("pq16_graph", dict(sssp_delta=16, graph_blocks=1)),
+    # every improved vertex kept in the next frontier (the cull of vertices
+    # already relaxed with their final distance switched off)
+    ("cull_off", dict(sssp_opt_off=gr.SSSP_OPT_CULL)),
+    ("bins_off", dict(sssp_opt_off=gr.SSSP_OPT_BINS)),
+    ("opts_off", dict(sssp_opt_off=gr.SSSP_OPT_CULL | gr.SSSP_OPT_BINS)),
+    ("pq16_cull_off", dict(sssp_delta=16, sssp_opt_off=gr.SSSP_OPT_CULL)),
 ]
 
 
@@ -167,6 +173,39 @@ def test_sssp_distance_mirror(ctx, lo, hi):
     # push distances across the mirror's saturation value 0xffff
     hg = gg.add_weights(gg.erdos_renyi(30001, 8, seed=11), seed=12, lo=lo, hi=hi)
     run_sssp_all(ctx, hg, [[int(s)] for s in gg.sources(hg, 2, seed=13)])
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 3), (1, 64)])
+def test_sssp_cull_of_relaxed_vertices(ctx, lo, hi):
+    # Large R-MAT levels relax through the byte-mark filter, whose compaction
+    # drops vertices whose edges already went out with their final distance
+    # and lists the rest in bins of distance: results identical with either
+    # refinement on or off (also with zero weights, where distance 0 and ties
+    # are common, and with the priority queue), and fewer edges relaxed with
+    # them on.  A vertex can only be dropped when its distance fell before a
+    # chunk of its row was staged, i.e. in levels with more chunks than
+    # resident workgroups: hence 1024-edge chunks at scale 18.
+    hg = gg.add_weights(gg.rmat(18, 16, seed=7), seed=17, lo=lo, hi=hi)
+    lb = dict(lb_chunk=1024, lb_light_threshold=0)
+    offs = (0, gr.SSSP_OPT_CULL, gr.SSSP_OPT_BINS, gr.SSSP_OPT_CULL | gr.SSSP_OPT_BINS)
+    for keep in ORDERS:
+        g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=keep)
+        inspected = {off: 0 for off in offs}
+        for s in gg.sources(hg, 3, seed=5):
+            ed, ep = oracle.sssp(hg.row_offsets, hg.col_indices, hg.weights, [int(s)])
+            for off in offs:
+                for extra in (lb, dict(), dict(sssp_delta=8, **lb), dict(adv_block=512),
+                              dict(lb_light_threshold=1 << 30), dict(device_max_edges=-1, **lb)):
+                    d, p, st = gr.sssp(g, [int(s)], opts=gr.default_opts(sssp_opt_off=off, **extra))
+                    msg = f"src={s} sssp_opt_off={off} {extra} renumber={keep}"
+                    np.testing.assert_array_equal(np_of(d).view(np.uint32), ed, err_msg="dist " + msg)
+                    np.testing.assert_array_equal(np_of(p), ep, err_msg="pred " + msg)
+                    if extra is lb:
+                        inspected[off] += st["inspected_edges"]
+        both = gr.SSSP_OPT_CULL | gr.SSSP_OPT_BINS
+        assert inspected[0] < inspected[both], inspected
+        assert inspected[gr.SSSP_OPT_BINS] < inspected[both], inspected
+        g.free()
 
 
 def test_unsorted_input_is_sorted_on_ingest(ctx, rmat14):
