@@ -1733,10 +1733,13 @@ extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t
 
   unsigned long long* keys;
   uint32_t *amask, *nmask, *fmask = nullptr;
-  int32_t *qA, *qB, *offsets, *rstart, *chunks, *src_dev, *piles = nullptr;
+  int32_t *qA, *qB, *qC, *offsets, *rstart, *chunks, *src_dev, *piles = nullptr;
   int64_t* bsums;
   Ctrl* ctrl;
   GR_TRY(pool_typed(ctx, S_MS_KEYS, (size_t)V * KSmax, &keys));
+  uint32_t* relaxed = nullptr;
+  if (!(opts.sssp_opt_off & GR_SSSP_OPT_CULL))
+    GR_TRY(pool_typed(ctx, S_MS_RELAXED, (size_t)V * KSmax, &relaxed));
   GR_TRY(pool_typed(ctx, S_MS_AMASK, V, &amask));
   GR_TRY(pool_typed(ctx, S_MS_NMASK, V, &nmask));
   // near / far split (sssp_delta > 0): far-pair masks and two far piles
@@ -1745,6 +1748,7 @@ extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t
   if (use_pq) GR_TRY(pool_typed(ctx, S_FAR, 2 * (size_t)V, &piles));
   GR_TRY(pool_typed(ctx, S_Q_A, V, &qA));
   GR_TRY(pool_typed(ctx, S_Q_B, V, &qB));
+  GR_TRY(pool_typed(ctx, S_Q_C, V, &qC));
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
   GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
@@ -1752,7 +1756,10 @@ extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_TMP0, 2 * kPass, &src_dev));
   Ctrl* hc = ctx->host_ctrl;
-  int32_t* q[2] = {qA, qB};
+  // q[cur]: the frontier; relax appends the improved vertices to q[cur + 1],
+  // rotate lists those with an active source left in q[cur + 2], the next
+  // frontier (queue indices mod 3)
+  int32_t* q[3] = {qA, qB, qC};
 
   GR_HIP(hipEventRecord(ctx->ev_start, st));
   GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->reached_edges), 2, 0u, st));
@@ -1775,12 +1782,12 @@ extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t
     GR_HIP(hipMemcpyAsync(qA, uniq.data(), sizeof(int32_t) * uniq.size(), hipMemcpyHostToDevice, st));
     GR_HIP(launch_fill_u32(&ctrl->q_count[0], 1, (uint32_t)uniq.size(), st));
     GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
-    GR_HIP(launch_msssp_init(keys, KS, amask, nmask, fmask, V, src_dev, kk, st));
+    GR_HIP(launch_msssp_init(keys, KS, amask, nmask, fmask, relaxed, V, src_dev, kk, st));
     GR_HIP(launch_fill_u32(&ctrl->far_count[0], 2, 0u, st));
     int cur = 0, sp = 0, it = 0, pile = 0;
     uint32_t T = (uint32_t)opts.sssp_delta;
     GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                 &ctrl->q_count[cur ^ 1], nullptr, st));
+                                 &ctrl->q_count[(cur + 1) % 3], &ctrl->q_count[(cur + 2) % 3], st));
     GR_TRY(read_ctrl(ctx, ctrl, st));  // also keeps the host source vectors alive for the copies
     int64_t n_f = hc->n_f[sp], m_f = hc->m_f[sp], far_n = 0;
     while ((n_f > 0 || far_n > 0) && (opts.max_iterations <= 0 || it < opts.max_iterations)) {
@@ -1800,20 +1807,22 @@ extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t
                                        chunks, chunk, st));
         const MsFar far{fmask, use_pq ? piles + (int64_t)pile * V : nullptr, &ctrl->far_count[pile],
                         T};
+        const int q1 = (cur + 1) % 3, q2 = (cur + 2) % 3;
         GR_HIP(launch_msssp_relax(KS, chunk, q[cur], offsets, rstart, chunks, n_f, m_f, g->C, g->W,
-                                  keys, amask, nmask, use_pq ? &far : nullptr, g->perm, q[cur ^ 1],
-                                  &ctrl->q_count[cur ^ 1], st));
-        GR_HIP(launch_msssp_rotate(q[cur], &ctrl->q_count[cur], n_f, q[cur ^ 1],
-                                   &ctrl->q_count[cur ^ 1], std::min<int64_t>(V, m_f), amask, nmask,
-                                   st));
+                                  keys, amask, nmask, use_pq ? &far : nullptr, g->perm, relaxed,
+                                  q[q1], &ctrl->q_count[q1], st));
+        GR_HIP(launch_msssp_rotate(q[cur], &ctrl->q_count[cur], n_f, q[q1], &ctrl->q_count[q1],
+                                   std::min<int64_t>(V, m_f), amask, nmask, keys, KS, relaxed,
+                                   q[q2], &ctrl->q_count[q2], st));
         rs.inspected_edges += m_f;
         rs.action_count[GR_PUSH_LB]++;
-        cur ^= 1;
+        cur = q2;
         sp ^= 1;
       }
       ++it;
       GR_HIP(launch_frontier_stats(q[cur], &ctrl->q_count[cur], g->R, bsums, ctrl, sp,
-                                   &ctrl->q_count[cur ^ 1], nullptr, st));
+                                   &ctrl->q_count[(cur + 1) % 3], &ctrl->q_count[(cur + 2) % 3],
+                                   st));
       GR_TRY(read_ctrl(ctx, ctrl, st));
       n_f = hc->n_f[sp];
       m_f = hc->m_f[sp];

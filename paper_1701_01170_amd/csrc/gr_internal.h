@@ -68,6 +68,7 @@ enum Slot : int {
   S_MIRROR,        // shortest-path 16-bit distance mirror [V]
   S_RELAXED,       // shortest-path: 1 + distance a frontier vertex's edges were relaxed with [V]
   S_SSSP_BINS,     // shortest-path distance bins: histograms, cursors, base
+  S_MS_RELAXED,    // batched shortest paths: per (vertex, source) cull values [V * row]
   S_UL_A,          // BFS pull: unvisited vertices with neighbours (two lists, ping-pong)
   S_UL_B,
   S_CAND,          // BFS idempotent advance: candidate list [V]
@@ -328,23 +329,31 @@ struct MsFar {
   uint32_t* pile_count;
   uint32_t T;
 };
+// relaxed (nullable, V * KS words): the per-source cull of pairs already
+// relaxed with their final distance (cleared by init, raised by relax, read
+// and reset by rotate)
 hipError_t launch_msssp_init(unsigned long long* keys, int KS, uint32_t* amask, uint32_t* nmask,
-                             uint32_t* fmask, int64_t V, const int32_t* src_dev, int32_t k,
-                             hipStream_t st);
+                             uint32_t* fmask, uint32_t* relaxed, int64_t V, const int32_t* src_dev,
+                             int32_t k, hipStream_t st);
 hipError_t launch_msssp_relax(int KS, int chunk, const int32_t* frontier, const int32_t* offsets,
                               const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                               int64_t m_f, const int32_t* C, const uint32_t* W,
                               unsigned long long* keys, const uint32_t* amask, uint32_t* nmask,
-                              const MsFar* far, const int32_t* perm, int32_t* out_q,
-                              uint32_t* out_count, hipStream_t st);
+                              const MsFar* far, const int32_t* perm, uint32_t* relaxed,
+                              int32_t* out_q, uint32_t* out_count, hipStream_t st);
 hipError_t launch_msssp_refill(const int32_t* pile, const uint32_t* n_pile, int64_t max_pile,
                                int32_t* pile_next, uint32_t* n_pile_next,
                                const unsigned long long* keys, int KS, uint32_t* fmask,
                                uint32_t* amask, uint32_t T0, uint32_t T1, int32_t* out_q,
                                uint32_t* out_count, hipStream_t st);
+// amask of the current frontier cleared; the next frontier's vertices get
+// amask = nmask (minus culled pairs), nmask = 0, and those with an active
+// source left are appended to out_q (out_count zero before)
 hipError_t launch_msssp_rotate(const int32_t* cur_q, const uint32_t* cur_n, int64_t max_cur,
                                const int32_t* next_q, const uint32_t* next_n, int64_t max_next,
-                               uint32_t* amask, uint32_t* nmask, hipStream_t st);
+                               uint32_t* amask, uint32_t* nmask, const unsigned long long* keys,
+                               int KS, uint32_t* relaxed, int32_t* out_q, uint32_t* out_count,
+                               hipStream_t st);
 hipError_t launch_msssp_finalize(const unsigned long long* keys, int KS, int32_t k,
                                  const int32_t* R, int64_t V, uint32_t* dist, int32_t* pred,
                                  const int32_t* perm, const int32_t* src_orig_dev,

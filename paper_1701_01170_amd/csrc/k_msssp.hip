@@ -16,7 +16,17 @@
 //          into nmask[v]; the first setter appends v to the next frontier
 //          (Remove_Redundant for the union);
 //   clear  amask of the current frontier = 0;
-//   move   for the next frontier: amask = nmask, nmask = 0.
+//   move   for the next frontier: amask = nmask, nmask = 0, listing the
+//          vertices with an active source left.
+// With `relaxed` (nullable, KS words per vertex like the keys), each chunk
+// raises relaxed[u][s] to 1 + the distance of (u, s) as it stages u, for every
+// active source s of u (its items read the key after that, so they see that
+// distance or a smaller one), and move resets it when the pair joins the next
+// frontier.  A pair whose relaxed value equals 1 + its distance at move time
+// was active and had every edge relaxed with that final distance, so move
+// drops it (the single-source cull of vertices already relaxed with their
+// final distance, per source); a value from an earlier iteration is larger
+// than 1 + a distance that has dropped since, and 0 never matches.
 // Keys only decrease, so a source's bit is set exactly when the vertex's
 // distance for that source dropped in the iteration; every vertex then
 // relaxes its edges with its final distance for every source at least once,
@@ -63,8 +73,8 @@ __global__ __launch_bounds__(256) void k_msssp_relax(
     int32_t m_f, const int32_t* __restrict__ C, const uint32_t* __restrict__ W, int KS,
     u64* __restrict__ keys, const uint32_t* __restrict__ amask, uint32_t* __restrict__ nmask,
     uint32_t* __restrict__ fmask, int32_t* __restrict__ far_q, uint32_t* __restrict__ far_count,
-    uint32_t T, const int32_t* __restrict__ perm, int32_t* __restrict__ out_q,
-    uint32_t* __restrict__ out_count) {
+    uint32_t T, const int32_t* __restrict__ perm, uint32_t* __restrict__ relaxed,
+    int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count) {
   constexpr int BLOCK = 256;
   constexpr int CAP = lb_cap(N);
   constexpr int SPT = (CAP + BLOCK - 1) / BLOCK;  // segments per thread in the item scan
@@ -89,7 +99,14 @@ __global__ __launch_bounds__(256) void k_msssp_relax(
       s_off[i] = offsets[s];
       s_u[i] = u;
       s_rb[i] = rstart[s];
-      s_am[i] = amask[u];
+      const uint32_t am = amask[u];
+      s_am[i] = am;
+      if (relaxed) {
+        for (uint32_t b = am; b; b &= b - 1) {
+          const int64_t x = (int64_t)u * KS + (__ffs(b) - 1);
+          atomicMax(&relaxed[x], (uint32_t)(keys[x] >> 32) + 1u);
+        }
+      }
     }
     if (threadIdx.x == 0) s_off[cnt] = offsets[pb + cnt];
     __syncthreads();
@@ -237,11 +254,13 @@ __global__ __launch_bounds__(256) void k_msssp_refill(
 __global__ __launch_bounds__(256) void k_msssp_init(u64* __restrict__ keys, int KS,
                                                     uint32_t* __restrict__ amask,
                                                     uint32_t* __restrict__ nmask,
-                                                    uint32_t* __restrict__ fmask, int64_t V) {
+                                                    uint32_t* __restrict__ fmask,
+                                                    uint32_t* __restrict__ relaxed, int64_t V) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t n = V * KS;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     keys[i] = ~0ull;
+    if (relaxed) relaxed[i] = 0u;
     if (i < V) {
       amask[i] = 0u;
       nmask[i] = 0u;
@@ -268,16 +287,35 @@ __global__ __launch_bounds__(256) void k_msssp_clear(const int32_t* __restrict__
   if (i < (int64_t)*n) amask[q[i]] = 0u;
 }
 
+// Every workgroup thread calls block_append once, so no early return.
 __global__ __launch_bounds__(256) void k_msssp_move(const int32_t* __restrict__ q,
                                                     const uint32_t* __restrict__ n,
                                                     uint32_t* __restrict__ amask,
-                                                    uint32_t* __restrict__ nmask) {
+                                                    uint32_t* __restrict__ nmask,
+                                                    const u64* __restrict__ keys, int KS,
+                                                    uint32_t* __restrict__ relaxed,
+                                                    int32_t* __restrict__ out_q,
+                                                    uint32_t* __restrict__ out_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t v = 0;
+  uint32_t nm = 0;
   if (i < (int64_t)*n) {
-    const int32_t v = q[i];
-    amask[v] = nmask[v];
+    v = q[i];
+    nm = nmask[v];
     nmask[v] = 0u;
+    if (relaxed) {
+      for (uint32_t b = nm; b; b &= b - 1) {
+        const int sI = __ffs(b) - 1;
+        const int64_t x = (int64_t)v * KS + sI;
+        const uint32_t r = relaxed[x];
+        if (r == (uint32_t)(keys[x] >> 32) + 1u) nm &= ~(1u << sI);
+        else if (r) relaxed[x] = 0u;
+      }
+    }
+    amask[v] = nm;
   }
+  const uint32_t a = block_append<256>(nm ? 1u : 0u, out_count);
+  if (nm) out_q[a] = v;
 }
 
 // dist[s][v] / pred[s][v] at caller ids for the k sources of the pass, and the
@@ -328,12 +366,12 @@ hipError_t relax_n(int chunk, unsigned g, const int32_t* frontier, const int32_t
                    const int32_t* rstart, const int32_t* chunk_start, int32_t n_f, int32_t m_f,
                    const int32_t* C, const uint32_t* W, int KS, u64* keys, const uint32_t* amask,
                    uint32_t* nmask, uint32_t* fmask, int32_t* far_q, uint32_t* far_count,
-                   uint32_t T, const int32_t* perm, int32_t* out_q, uint32_t* out_count,
-                   hipStream_t st) {
+                   uint32_t T, const int32_t* perm, uint32_t* relaxed, int32_t* out_q,
+                   uint32_t* out_count, hipStream_t st) {
 #define GR_MS_RELAX(CH)                                                                        \
   k_msssp_relax<CH, PQ><<<g, 256, 0, st>>>(frontier, offsets, rstart, chunk_start, n_f, m_f, C, \
                                            W, KS, keys, amask, nmask, fmask, far_q, far_count,   \
-                                           T, perm, out_q, out_count)
+                                           T, perm, relaxed, out_q, out_count)
   if (chunk == 512) GR_MS_RELAX(512);
   else if (chunk == 2048) GR_MS_RELAX(2048);
   else GR_MS_RELAX(1024);
@@ -348,10 +386,11 @@ int msssp_row(int k) { return k <= 4 ? 4 : (k <= 8 ? 8 : 16); }
 int msssp_chunk(int chunk) { return chunk == 512 || chunk == 2048 ? chunk : 1024; }
 
 hipError_t launch_msssp_init(u64* keys, int KS, uint32_t* amask, uint32_t* nmask, uint32_t* fmask,
-                             int64_t V, const int32_t* src_dev, int32_t k, hipStream_t st) {
+                             uint32_t* relaxed, int64_t V, const int32_t* src_dev, int32_t k,
+                             hipStream_t st) {
   int64_t g = blocks_for(V * KS, 256);
   if (g > 8192) g = 8192;
-  k_msssp_init<<<(unsigned)g, 256, 0, st>>>(keys, KS, amask, nmask, fmask, V);
+  k_msssp_init<<<(unsigned)g, 256, 0, st>>>(keys, KS, amask, nmask, fmask, relaxed, V);
   k_msssp_seed<<<1, 64, 0, st>>>(src_dev, k, KS, keys, amask);
   return hipGetLastError();
 }
@@ -360,18 +399,18 @@ hipError_t launch_msssp_relax(int KS, int chunk, const int32_t* frontier, const 
                               const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                               int64_t m_f, const int32_t* C, const uint32_t* W, u64* keys,
                               const uint32_t* amask, uint32_t* nmask, const MsFar* far,
-                              const int32_t* perm, int32_t* out_q, uint32_t* out_count,
-                              hipStream_t st) {
+                              const int32_t* perm, uint32_t* relaxed, int32_t* out_q,
+                              uint32_t* out_count, hipStream_t st) {
   if (n_f <= 0 || m_f <= 0) return hipSuccess;
   const int ch = msssp_chunk(chunk);
   const unsigned g = blocks_for(m_f, ch);
   if (far)
     return relax_n<true>(ch, g, frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f,
                          C, W, KS, keys, amask, nmask, far->fmask, far->pile, far->pile_count,
-                         far->T, perm, out_q, out_count, st);
+                         far->T, perm, relaxed, out_q, out_count, st);
   return relax_n<false>(ch, g, frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f,
-                        C, W, KS, keys, amask, nmask, nullptr, nullptr, nullptr, 0u, perm, out_q,
-                        out_count, st);
+                        C, W, KS, keys, amask, nmask, nullptr, nullptr, nullptr, 0u, perm, relaxed,
+                        out_q, out_count, st);
 }
 
 hipError_t launch_msssp_refill(const int32_t* pile, const uint32_t* n_pile, int64_t max_pile,
@@ -388,10 +427,13 @@ hipError_t launch_msssp_refill(const int32_t* pile, const uint32_t* n_pile, int6
 
 hipError_t launch_msssp_rotate(const int32_t* cur_q, const uint32_t* cur_n, int64_t max_cur,
                                const int32_t* next_q, const uint32_t* next_n, int64_t max_next,
-                               uint32_t* amask, uint32_t* nmask, hipStream_t st) {
+                               uint32_t* amask, uint32_t* nmask, const u64* keys, int KS,
+                               uint32_t* relaxed, int32_t* out_q, uint32_t* out_count,
+                               hipStream_t st) {
   if (max_cur > 0) k_msssp_clear<<<blocks_for(max_cur, 256), 256, 0, st>>>(cur_q, cur_n, amask);
   if (max_next > 0)
-    k_msssp_move<<<blocks_for(max_next, 256), 256, 0, st>>>(next_q, next_n, amask, nmask);
+    k_msssp_move<<<blocks_for(max_next, 256), 256, 0, st>>>(next_q, next_n, amask, nmask, keys, KS,
+                                                            relaxed, out_q, out_count);
   return hipGetLastError();
 }
 

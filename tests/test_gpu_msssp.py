@@ -51,7 +51,8 @@ def test_duplicate_sources_and_chunks(ctx, rmat14):
     s = [int(x) for x in gg.sources(rmat14, 4, seed=3100)]
     srcs = [s[0], s[1], s[0], s[2], s[3], s[1]]
     check(ctx, rmat14, srcs, renumber=(False,),
-          opts_list=({}, {"lb_chunk": 512}, {"lb_chunk": 2048}, {"lb_chunk": 16384}) + PQ_OPTS)
+          opts_list=({}, {"lb_chunk": 512}, {"lb_chunk": 2048}, {"lb_chunk": 16384},
+                     {"sssp_opt_off": gr.SSSP_OPT_CULL}) + PQ_OPTS)
 
 
 @pytest.mark.parametrize("k", [4, 16])
@@ -74,7 +75,7 @@ def test_directed_zero_weights_and_unreached(ctx):
     w = rng.integers(0, 4, size=30000)  # zero weights included
     hg = gg.sort_adjacency(gg.from_edges(V, e, w))
     check(ctx, hg, [0, 1, 2, 5999, 17, 17, 4000, 3], symmetric=False,
-          opts_list=({}, {"sssp_delta": 2}))
+          opts_list=({}, {"sssp_delta": 2}, {"sssp_opt_off": gr.SSSP_OPT_CULL}))
 
 
 def test_union_of_small_graphs(ctx):
@@ -95,4 +96,8 @@ def test_rmat20_16_sources_all_rows(ctx):
     hg = gg.add_weights(gg.rmat(20, 16, seed=1), seed=101)
     srcs = gg.sources(hg, 16, seed=3300)
     print(f"sssp_multi rmat20 V={hg.n_vertices} E={hg.n_edges} k=16", flush=True)
-    check(ctx, hg, srcs, renumber=(False,), opts_list=({}, {"sssp_delta": 8}))
+    # with and without the per-source cull of pairs already relaxed with
+    # their final distance (levels of many more chunks than resident
+    # workgroups, where pairs do get culled)
+    check(ctx, hg, srcs, renumber=(False,),
+          opts_list=({}, {"sssp_delta": 8}, {"sssp_opt_off": gr.SSSP_OPT_CULL}))
