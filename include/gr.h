@@ -174,11 +174,12 @@ typedef struct gr_opts {
 /* gr_opts.sssp_opt_off bits */
 #define GR_SSSP_OPT_CULL 1  /* drop from the next frontier a vertex whose edges this iteration
                                already relaxed with its final distance (a further
-                               Remove_Redundant, Alg. 1) */
-#define GR_SSSP_OPT_BINS 2  /* list the next frontier in bins of distance, smallest first, so
-                               that small distances are relaxed first (the ordering aim of the
-                               Sec. 5.1 priority queue, without its extra iterations); not used
-                               with sssp_delta > 0 */
+                               Remove_Redundant, Alg. 1); in gr_sssp_multi per (vertex, source)
+                               pair, in every iteration */
+#define GR_SSSP_OPT_BINS 2  /* gr_sssp: list the next frontier in bins of distance, smallest
+                               first, so that small distances are relaxed first (the ordering aim
+                               of the Sec. 5.1 priority queue, without its extra iterations); not
+                               used with sssp_delta > 0 nor by gr_sssp_multi */
 
 /* gr_opts.bfs_filter (Sec. 5.2: idempotent vs. non-idempotent operations).
  * Results are identical for all three; only the time differs. */

@@ -1249,14 +1249,11 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     GR_TRY(pool_typed(ctx, S_FAR, 3 * V, &pq.far_base));
     GR_TRY(pool_typed(ctx, S_FAR_TAGS, V, &pq.far_tag));
   }
-  // distance bins of the marks compaction: width 2^shift, the bins spanning
-  // about two to four times the largest weight
+  // distance bins of the marks compaction
   SsspBins bins{nullptr, 0u};
   if (!use_pq && !(opts.sssp_opt_off & GR_SSSP_OPT_BINS)) {
     GR_TRY(pool_typed(ctx, S_SSSP_BINS, kSsspBinWords, &bins.state));
-    uint32_t span = 1;  // smallest power of two above max_weight
-    while (span <= g->max_weight && span < (1u << 31)) span <<= 1;
-    while ((uint64_t)kSsspBins << bins.shift < 2ull * span) ++bins.shift;
+    bins.shift = bin_shift_for(g->max_weight);
   }
   Ctrl* hc = ctx->host_ctrl;
   int32_t* q[3] = {qA, qB, qC};

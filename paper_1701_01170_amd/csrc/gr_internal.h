@@ -543,6 +543,14 @@ struct SsspBins {
 hipError_t launch_sssp_bin_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
                                    uint16_t* mirror, uint32_t* relaxed, const SsspBins& bins,
                                    int32_t* out_q, uint32_t* out_count, hipStream_t st);
+// bin width 2^shift for a graph whose largest weight is max_weight: the bins
+// span about two to four times it
+inline uint32_t bin_shift_for(uint32_t max_weight) {
+  uint32_t span = 1, shift = 0;  // smallest power of two above max_weight
+  while (span <= max_weight && span < (1u << 31)) span <<= 1;
+  while ((uint64_t)kSsspBins << shift < 2ull * span) ++shift;
+  return shift;
+}
 // Priority-queue form: marked vertices below pq.T go to out_q, the others to
 // far pile pq.fc (once per far-pile generation).
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
