@@ -290,12 +290,15 @@ def evaluate(ctx: Context, graphs, params, n_sources: int = 5, margins=(0.0,),
 
 def training_graphs(quick: bool):
     """Synthetic training set: R-MAT scales 16..22 with a in [0.45, 0.65]
-    (b:c:d kept), Erdos-Renyi average degree 4..64, grids 256^2..2048^2."""
+    (b:c:d kept) and scale 24 with the paper's a, Erdos-Renyi average degree
+    4..64, grids 256^2..2048^2."""
     gs = []
     scales = [16, 18] if quick else [16, 18, 20, 22]
     for s in scales:
         for a in (0.45, 0.55, 0.65):
             gs.append((f"rmat_s{s}_a{a}", gg.add_weights(gg.rmat_family(s, 16, a, seed=11 + s), seed=7)))
+    if not quick:
+        gs.append(("rmat_s24_a0.57", gg.add_weights(gg.rmat(24, 16, seed=35), seed=7)))
     for d in ((4, 64) if quick else (4, 16, 64)):
         gs.append((f"er_n262144_d{d}", gg.add_weights(gg.erdos_renyi(1 << 18, d, seed=5), seed=7)))
     for n in ((256, 512) if quick else (256, 512, 1024, 2048)):
