@@ -1031,7 +1031,17 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
       if (mode == 2)
         GR_HIP(launch_frontier_offsets(q[cur], n_f, g->R, bsums, &ctrl->m_f[sp], offsets, rstart,
                                        chunks, chunk, st));
-      const bool atomic_parent = !idem && parent && (!pull_ok || m_f <= kAtomicParentMaxEdges);
+      // canonical parents by an atomic minimum in the push (about one atomic
+      // per frontier edge) or by the fix-up scan of the new vertices, which
+      // reads each sorted list up to its first frontier neighbour: about E / m_f
+      // entries when the frontier holds m_f of the E edge ends, for at most
+      // min(m_f, unvisited) new vertices.  A small frontier of hubs makes the
+      // scans long (R-MAT 22 BFS: 0.53-0.56 ms with this rule against
+      // 0.58-0.60 ms with a fixed 4 M-edge bound and 0.61-0.63 ms with 1 M).
+      const double new_max = (double)std::min<int64_t>(m_f, V - visited_n);
+      const bool atomic_cheaper = (double)m_f * (double)m_f <= 2.0 * new_max * (double)E;
+      const bool atomic_parent =
+          !idem && parent && (!pull_ok || m_f <= kAtomicParentMaxEdges || atomic_cheaper);
       if (idem) {
         // idempotent advance into the candidate list, then the exact filter
         kernel = kTraceKernelIdem + mode;
