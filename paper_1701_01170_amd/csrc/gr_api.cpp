@@ -1053,14 +1053,16 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
         GR_HIP(launch_bfs_idem_filter(a.cand, &ctrl->cand_count, V, V, bm, p, depth, next_depth,
                                       q[(cur + 1) % 3], &ctrl->q_count[(cur + 1) % 3], st));
-      } else if (opts.bfs_filter != GR_BFS_FILTER_ATOMIC && !atomic_parent &&
-                 m_f >= V / kMarksFilterDivisor) {
+      } else if (opts.bfs_filter != GR_BFS_FILTER_ATOMIC && m_f >= V / kMarksFilterDivisor) {
+        // byte marks; parents by the fix-up scan, or by atomic minima in the
+        // push (no returning atomic either way)
         uint8_t* marks;
         GR_TRY(marks_buffer(ctx, ar, V, &marks, st));
         kernel = mode == 2 ? 3 : mode;
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_bfs_push_marks(mode, q[cur], offsets, rstart, chunks, n_f, m_f, g->R, g->C,
-                                     bm, p, marks, adv, st));
+                                     bm, p, marks, atomic_parent ? parent : nullptr, perm, adv,
+                                     st));
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k1, st));
         GR_HIP(launch_bfs_mark_compact(marks, V, bm, p, depth, next_depth, q[(cur + 1) % 3],
                                        &ctrl->q_count[(cur + 1) % 3], st));

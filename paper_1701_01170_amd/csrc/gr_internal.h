@@ -259,7 +259,8 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                  const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                  int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
-                                 int p, uint8_t* marks, const AdvCfg& cfg, hipStream_t st);
+                                 int p, uint8_t* marks, int32_t* parent, const int32_t* perm,
+                                 const AdvCfg& cfg, hipStream_t st);
 hipError_t launch_bfs_mark_compact(uint8_t* marks, int64_t V, uint32_t* bm, int p, int32_t* depth,
                                    int32_t next_depth, int32_t* out_q, uint32_t* out_count,
                                    hipStream_t st);

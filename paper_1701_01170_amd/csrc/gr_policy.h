@@ -83,8 +83,11 @@ struct Selector {
     // The paper has a single pull advance; its early exit makes per-vertex
     // dynamic grouping the natural mapping, so the heuristic pulls with TWC.
     if (pull) return GR_PULL_TWC;
-    const bool lb = avg_degree >= (double)o.lb_min_avg_degree;
-    return lb ? GR_PUSH_LB : GR_PUSH_TWC;
+    return push_action();
+  }
+
+  int push_action() const {
+    return avg_degree >= (double)o.lb_min_avg_degree ? GR_PUSH_LB : GR_PUSH_TWC;
   }
 
   // device_choice: the network's argmin over the allowed actions, pred: its
@@ -92,22 +95,27 @@ struct Selector {
   // The learned policy is guarded: it keeps the heuristic's action unless the
   // network predicts its own choice faster by more than o.learned_margin.
   // keep_push: the level fits a block of device-predicated push levels, which
-  // makes pushing it far cheaper than the one-round-trip levels the network
-  // was trained on; the network may then turn the heuristic's pull into a
-  // push, but not a push into a pull.
+  // makes pushing it far cheaper than a level with its own host round trip
+  // (the tail levels of a direction-optimised BFS stay in pull mode, since
+  // m_f < m_u * do_b rarely holds once few vertices are left, and each would
+  // cost a round trip for a few microseconds of work): such a level is
+  // pushed; the network may turn the heuristic's pull into a push, but not a
+  // push into a pull.  last_heuristic keeps the threshold rule's own answer,
+  // so that a block started against it keeps pushing.
   int decide(const LevelFeatures& lf, int device_choice = -1, const float* pred = nullptr,
              bool keep_push = false) {
     int a;
+    const int raw = (o.policy == GR_POLICY_FIXED || o.policy == GR_POLICY_RANDOM) ? -1 : heuristic(lf);
+    const int h = keep_push && raw >= GR_PULL_TWC ? push_action() : raw;
     if (o.policy == GR_POLICY_FIXED) a = o.fixed_action;
     else if (o.policy == GR_POLICY_RANDOM) a = (int)(next(rng) % 4);
     else if (o.policy == GR_POLICY_LEARNED && learned && device_choice >= 0 && pred) {
-      const int h = heuristic(lf);
       a = (device_choice != h && pred[device_choice] + o.learned_margin < pred[h]) ? device_choice : h;
       if (keep_push && h < GR_PULL_TWC && a >= GR_PULL_TWC) a = h;
-      last_heuristic = h;
+      last_heuristic = raw;
     } else {
-      a = heuristic(lf);
-      last_heuristic = a;
+      a = h;
+      last_heuristic = raw;
     }
     if (!pull_ok && a >= GR_PULL_TWC) a -= 2;  // same balancing, push direction
     mode_pull = a >= GR_PULL_TWC;

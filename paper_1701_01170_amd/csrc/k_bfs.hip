@@ -111,25 +111,39 @@ struct BfsVisit {
   __device__ __forceinline__ void advance(Ctrl*, int, bool) const {}
 };
 
-// Push without atomics (for levels that discover many vertices): every edge
-// into a vertex outside old and live stores a one-byte mark; all writers store
-// the same value, so the race is benign.  k_bfs_mark_compact then turns the
-// marks into depths, live bits and an ordered next frontier.
+// Push without returning atomics (for levels that discover many vertices):
+// every edge into a vertex outside old and live stores a one-byte mark; all
+// writers store the same value, so the race is benign.  k_bfs_mark_compact
+// then turns the marks into depths, live bits and an ordered next frontier.
+// With parent (nullable) every such edge also takes the atomic minimum of the
+// parent, whose result nobody waits for (canonical parents without the
+// fix-up scan; live holds no vertex of this level, so the probe passes every
+// edge into a vertex not in old).
 struct BfsMark {
   const uint32_t* __restrict__ bm;
   uint8_t* __restrict__ marks;
   int32_t p;
+  int32_t* __restrict__ parent;
+  const int32_t* __restrict__ perm;
 
-  using pay_t = int32_t;
+  using pay_t = int32_t;  // the frontier vertex's caller id when parents are taken
   static constexpr bool kFar = false;
   static constexpr bool kBatchCommit = false;
-  __device__ __forceinline__ int32_t seg_payload(int32_t) const { return 0; }
+  __device__ __forceinline__ int32_t seg_payload(int32_t u) const {
+    return parent ? caller_id(perm, u) : 0;
+  }
   __device__ __forceinline__ uint32_t edge_value(int64_t) const { return 0u; }
   __device__ __forceinline__ bool probe(int32_t, int32_t, int32_t v, uint32_t) const {
     const uint2 x = bm_pair(bm, v >> 5);
     return !(((x.x | x.y) >> (v & 31)) & 1u);
   }
-  __device__ __forceinline__ bool commit(int32_t, int32_t, int32_t v, uint32_t) const {
+  __device__ __forceinline__ bool commit(int32_t, int32_t pu, int32_t v, uint32_t) const {
+    if (parent) {
+      // frontier rows are handled roughly in ascending order, so most edges
+      // find a smaller parent already and skip the atomic
+      uint32_t* pv = reinterpret_cast<uint32_t*>(&parent[v]);
+      if ((uint32_t)pu < *pv) atomicMin(pv, (uint32_t)pu);
+    }
     marks[v] = 1;
     return false;
   }
@@ -674,8 +688,9 @@ hipError_t launch_bfs_push(int mode, bool atomic_parent, const int32_t* frontier
 hipError_t launch_bfs_push_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                  const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                  int64_t m_f, const int32_t* R, const int32_t* C, uint32_t* bm,
-                                 int p, uint8_t* marks, const AdvCfg& cfg, hipStream_t st) {
-  BfsMark f{bm, marks, p};
+                                 int p, uint8_t* marks, int32_t* parent, const int32_t* perm,
+                                 const AdvCfg& cfg, hipStream_t st) {
+  BfsMark f{bm, marks, p, parent, perm};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
                        nullptr, cfg, st);
 }
