@@ -407,7 +407,10 @@ __device__ __forceinline__ int32_t first_frontier_nbr(bool valid, int32_t rb, in
 // Pull over the visited bitmap (Alg. 2, with the unvisited set read from the
 // bitmap instead of a generated list): each wavefront owns kPullRuns runs of
 // 64 consecutive vertices, i.e. their bitmap words, which no other wavefront
-// writes during the step.  A vertex outside old scans its ascending
+// writes during the step.  The runs of a wavefront are spread over the whole
+// id range (run k of wavefront w of workgroup b is run (k G + b) NW + w), so
+// that every workgroup gets a similar share of unvisited vertices even when
+// the ids are degree ordered (hubs, reached first, at the low ids).  A vertex outside old scans its ascending
 // adjacency for its first frontier neighbour (the smallest-id parent); the
 // wavefront ORs its hits into live with one plain store per word and the
 // workgroup appends them to the next frontier with a single atomic.
@@ -436,8 +439,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ int64_t s_insp[NW];
   __shared__ uint32_t s_base;
   const int w = threadIdx.x / kWave;
-  const int64_t base = ((int64_t)blockIdx.x * NW + w) * kWave * kPullRuns;
-  uint32_t hits = 0;  // bit k: vertex base + 64 k + lane was found
+  // first vertex of run k of this wavefront
+  auto run_v0 = [&](int k) -> int64_t {
+    return (((int64_t)k * gridDim.x + blockIdx.x) * NW + w) * kWave;
+  };
+  uint32_t hits = 0;  // bit k: vertex run_v0(k) + lane was found
   uint32_t rems = 0;  // bit k: that vertex has neighbours and stays unvisited
   int64_t scanned = 0;
   // GW == 1: the smallest-id neighbour of every candidate of kPullBatch runs
@@ -449,14 +455,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   bool pc[kPullBatch], ph[kPullBatch];
 #pragma unroll
   for (int k = 0; k < kPullRuns; ++k) {
-    const int64_t v0 = base + (int64_t)k * kWave;
-    if (v0 >= V) break;  // uniform across the wavefront
+    const int64_t v0 = run_v0(k);
+    if (v0 >= V) break;  // uniform across the wavefront; run_v0 grows with k
     const int kb = k % kPullBatch;
     if constexpr (GW == 1) {
       if (kb == 0) {
 #pragma unroll
         for (int j = 0; j < kPullBatch; ++j) {
-          const int64_t v = v0 + (int64_t)j * kWave + lane();
+          const int64_t v = run_v0(k + j) + lane();
           pc[j] = false;
           prb[j] = pre[j] = 0;
           if (v < V) {
@@ -582,12 +588,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __syncthreads();
   uint32_t slot = s_base + s_cnt[w] + inc - n;
   for (int k = 0; k < kPullRuns; ++k)
-    if ((hits >> k) & 1u) out_q[slot++] = (int32_t)(base + (int64_t)k * kWave + lane());
+    if ((hits >> k) & 1u) out_q[slot++] = (int32_t)(run_v0(k) + lane());
   // the vertices still unvisited (and not isolated): the next pull level's list
   if (rem_q) {
     uint32_t rs = block_append<256>(__popc(rems), rem_count);
     for (int k = 0; k < kPullRuns; ++k)
-      if ((rems >> k) & 1u) rem_q[rs++] = (int32_t)(base + (int64_t)k * kWave + lane());
+      if ((rems >> k) & 1u) rem_q[rs++] = (int32_t)(run_v0(k) + lane());
   }
 }
 
