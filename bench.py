@@ -467,7 +467,7 @@ def large(args, gr, gg, torch):
     print(f"# generated {hg.name}: V={hg.n_vertices} E={hg.n_edges} in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
     ctx = gr.Context(0)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
     srcs = gg.sources(hg, 16, seed=1000).astype(np.int32)
     V = hg.n_vertices
     policy = "learned" if selector.load_policy(ctx) else "heuristic"
@@ -494,6 +494,11 @@ def large(args, gr, gg, torch):
     ms16 = gr.sssp_multi(g, srcs, opts=omsssp, out=(dist16, pred16))[2]
     torch.cuda.synchronize()
     msssp_wall = time.perf_counter() - t0
+    # the other batching mode, for comparison (untimed by the step clock)
+    oshared = autotune.tuned_opts(g, "sssp_multi", sssp_multi_sweep=1 - omsssp.sssp_multi_sweep)
+    if oshared.sssp_multi_sweep == 0:
+        oshared.lb_chunk, oshared.sssp_delta = 0, 0
+    ms16_other = gr.sssp_multi(g, srcs, opts=oshared, out=(dist16, pred16))[2]
     del dist16, pred16
     dist = torch.empty(V, dtype=torch.int32, device="cuda")
     pred = torch.empty(V, dtype=torch.int32, device="cuda")
@@ -523,11 +528,13 @@ def large(args, gr, gg, torch):
         "value": round(teps / wall / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
         "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "rmat_s25_e16, int32 CSR, uint32 weights 1..64; gr_bfs_multi with 16 "
-                               "sources + gr_sssp_multi with the same 16 sources",
+        "config": {"workload": "rmat_s25_e16, int32 CSR degree-renumbered on ingest (results in the "
+                               "caller's ids), uint32 weights 1..64; gr_bfs_multi with 16 sources + "
+                               "gr_sssp_multi with the same 16 sources",
                    "policy": {"sssp_single_source_comparison": policy,
                               "bfs_multi": policy + " (batched network when trained)",
-                              "sssp_multi": "load-balanced push every iteration"},
+                              "sssp_multi": ("one source per sweep (tuned)" if omsssp.sssp_multi_sweep
+                                             else "sources share each sweep (tuned)")},
                    "n_vertices": V, "n_edges": g.n_edges},
         "roofline": roof,
         "breakdown": {"bfs_multi16_ms": round(mb["device_ms"], 3),
@@ -537,7 +544,9 @@ def large(args, gr, gg, torch):
                       "sssp_multi16_gteps_device": _gteps(ms16["teps_edges"], ms16["device_ms"]),
                       "sssp_multi16_iterations": ms16["iterations"],
                       "sssp_multi16_knobs": {"lb_chunk": omsssp.lb_chunk,
-                                             "sssp_delta": omsssp.sssp_delta},
+                                             "sssp_delta": omsssp.sssp_delta,
+                                             "sssp_multi_sweep": omsssp.sssp_multi_sweep},
+                      "sssp_multi16_other_sweep_mode_ms": round(ms16_other["device_ms"], 3),
                       "sssp_multi16_union_edges": ms16["inspected_edges"],
                       "sssp_batched_speedup_over_16_single": round(sssp_ms / ms16["device_ms"], 3)
                       if ms16["device_ms"] > 0 else None,
@@ -585,7 +594,7 @@ def main():
           file=sys.stderr, flush=True)
 
     ctx = gr.Context(0)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
     dev = torch.device("cuda", 0)
     V = hg.n_vertices
     depth = torch.empty(V, dtype=torch.int32, device=dev)
@@ -670,7 +679,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rmat_s{args.scale}_e{args.edge_factor} BFS+SSSP from one seeded source "
                                f"per step, fixed-threshold heuristic policy with autotuned thresholds, "
-                               f"int32 CSR, uint32 weights 1..64",
+                               f"int32 CSR degree-renumbered on ingest (results in the caller's ids), "
+                               f"uint32 weights 1..64",
                    "n_vertices": V, "n_edges": hg.n_edges,
                    "knobs": {k: {t: round(float(x), 6) for t, x in v.items()} for k, v in knobs.items()}},
         "roofline": roof,

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 3
+#define GR_ABI_VERSION 4
 
 typedef enum gr_status {
   GR_OK = 0,
@@ -169,6 +169,10 @@ typedef struct gr_opts {
   int32_t sssp_opt_off;      /* SSSP refinements of the iterations with the byte-mark filter
                                 switched off, a bit set of GR_SSSP_OPT_* (0: all on); none
                                 changes the results */
+  int32_t sssp_multi_sweep;  /* gr_sssp_multi: 0 = up to 16 sources share each sweep over the
+                                graph (one key row per vertex); 1 = one source per sweep, each
+                                run as gr_sssp runs it (with its distance-ordered frontier, which
+                                a shared sweep cannot give every source).  Same results. */
 } gr_opts;
 
 /* gr_opts.sssp_opt_off bits */

@@ -586,6 +586,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->graph_blocks must be 0 or 1");
   if (opts->sssp_opt_off & ~(GR_SSSP_OPT_CULL | GR_SSSP_OPT_BINS))
     return fail(GR_EINVAL, "opts->sssp_opt_off: unknown bits");
+  if (opts->sssp_multi_sweep != 0 && opts->sssp_multi_sweep != 1)
+    return fail(GR_EINVAL, "opts->sssp_multi_sweep must be 0 or 1");
   if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
     return fail(GR_EINVAL, "opts->bfs_filter out of range");
   if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
@@ -1736,6 +1738,24 @@ extern "C" gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* g, const int32_t
   DeviceGuard dg(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t V = g->V, E = g->E;
+  if (opts.sssp_multi_sweep == 1) {
+    // one source per sweep: row s is gr_sssp from sources[s]
+    gr_opts o1 = opts;
+    o1.trace = nullptr;
+    o1.trace_capacity = 0;
+    gr_run_stats agg{}, s1{};
+    for (int32_t i = 0; i < k; ++i) {
+      GR_TRY(gr_sssp(ctx, g, sources + i, 1, dist + (int64_t)i * V,
+                     pred ? pred + (int64_t)i * V : nullptr, &o1, stream, &s1));
+      agg.iterations = std::max(agg.iterations, s1.iterations);
+      for (int a = 0; a < 4; ++a) agg.action_count[a] += s1.action_count[a];
+      agg.teps_edges += s1.teps_edges;
+      agg.inspected_edges += s1.inspected_edges;
+      agg.device_ms += s1.device_ms;
+    }
+    if (stats) *stats = agg;
+    return GR_OK;
+  }
   const int chunk = msssp_chunk(opts.lb_chunk > 0 ? opts.lb_chunk : 1024);
   constexpr int kPass = 16;
   const int KSmax = msssp_row(std::min<int32_t>(k, kPass));

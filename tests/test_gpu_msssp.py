@@ -52,7 +52,8 @@ def test_duplicate_sources_and_chunks(ctx, rmat14):
     srcs = [s[0], s[1], s[0], s[2], s[3], s[1]]
     check(ctx, rmat14, srcs, renumber=(False,),
           opts_list=({}, {"lb_chunk": 512}, {"lb_chunk": 2048}, {"lb_chunk": 16384},
-                     {"sssp_opt_off": gr.SSSP_OPT_CULL}) + PQ_OPTS)
+                     {"sssp_opt_off": gr.SSSP_OPT_CULL}, {"sssp_multi_sweep": 1},
+                     {"sssp_multi_sweep": 1, "sssp_delta": 8}) + PQ_OPTS)
 
 
 @pytest.mark.parametrize("k", [4, 16])
@@ -75,7 +76,8 @@ def test_directed_zero_weights_and_unreached(ctx):
     w = rng.integers(0, 4, size=30000)  # zero weights included
     hg = gg.sort_adjacency(gg.from_edges(V, e, w))
     check(ctx, hg, [0, 1, 2, 5999, 17, 17, 4000, 3], symmetric=False,
-          opts_list=({}, {"sssp_delta": 2}, {"sssp_opt_off": gr.SSSP_OPT_CULL}))
+          opts_list=({}, {"sssp_delta": 2}, {"sssp_opt_off": gr.SSSP_OPT_CULL},
+                     {"sssp_multi_sweep": 1}))
 
 
 def test_union_of_small_graphs(ctx):
@@ -99,5 +101,6 @@ def test_rmat20_16_sources_all_rows(ctx):
     # with and without the per-source cull of pairs already relaxed with
     # their final distance (levels of many more chunks than resident
     # workgroups, where pairs do get culled)
-    check(ctx, hg, srcs, renumber=(False,),
-          opts_list=({}, {"sssp_delta": 8}, {"sssp_opt_off": gr.SSSP_OPT_CULL}))
+    check(ctx, hg, srcs, renumber=(False, True),
+          opts_list=({}, {"sssp_delta": 8}, {"sssp_opt_off": gr.SSSP_OPT_CULL},
+                     {"sssp_multi_sweep": 1}))
