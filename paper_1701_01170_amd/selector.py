@@ -21,6 +21,9 @@ seeded random actions, its features are the same eight with the unvisited
 counts averaged over the pass's sources.  Both networks are loaded together
 (gr_ctx_set_policy with 2 x 1476 parameters, see load_policy).
 
+Graphs are ingested degree-renumbered (GR_RENUMBER), the layout the benchmark
+and the tuner use, unless --no-renumber is given.
+
 CLI:  python -m paper_1701_01170_amd.selector [--quick] [--epochs N]
       python -m paper_1701_01170_amd.selector --multi [--quick] [--epochs N]
 """
@@ -37,6 +40,8 @@ from . import (MLP_N_PARAMS, POLICY_FIXED, POLICY_HEURISTIC, POLICY_LEARNED, POL
                Context, Graph, LevelTrace, bfs, bfs_multi, default_opts, mlp_adam, mlp_loss_grad,
                sssp)
 from . import graphgen as gg
+
+RENUMBER = True  # ingest the traces' graphs degree-renumbered
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "tuning", "selector_gfx950.npy")
@@ -97,7 +102,7 @@ def collect(ctx: Context, graphs, n_sources: int = 3, random_runs: int = 4, sssp
     from . import autotune
     for name, hg in graphs:
         t0 = time.time()
-        g = Graph.from_host(ctx, hg, symmetric=True)
+        g = Graph.from_host(ctx, hg, symmetric=True, renumber=RENUMBER)
         # R-MAT graphs (the workload the selector serves first) get more sources
         srcs = gg.sources(hg, 2 * n_sources if name.startswith("rmat") else n_sources, seed=3000)
         # the tuned chunk sizes and thresholds of this graph's class, and one
@@ -135,7 +140,7 @@ def collect_multi(ctx: Context, graphs, ks=(16, 64), random_runs: int = 4, log=p
     X, T, M, grp = [], [], [], []
     for name, hg in graphs:
         t0 = time.time()
-        g = Graph.from_host(ctx, hg, symmetric=True)
+        g = Graph.from_host(ctx, hg, symmetric=True, renumber=RENUMBER)
         pols = [dict(policy=POLICY_FIXED, fixed_action=a) for a in (0, 1, 2)]
         pols += [dict(policy=POLICY_RANDOM, policy_seed=100 + r) for r in range(random_runs)]
         for k in ks:
@@ -172,7 +177,7 @@ def evaluate_multi(ctx: Context, graphs, params_multi, ks=(16, 64), reps: int = 
     rows = []
     try:
         for name, hg in graphs:
-            g = Graph.from_host(ctx, hg, symmetric=True)
+            g = Graph.from_host(ctx, hg, symmetric=True, renumber=RENUMBER)
             for k in ks:
                 srcs = gg.sources(hg, k, seed=9100).astype(np.int32)
                 cfgs = {"heuristic": autotune.tuned_opts(g, "bfs_multi")}
@@ -251,7 +256,7 @@ def evaluate(ctx: Context, graphs, params, n_sources: int = 5, margins=(0.0,),
     rows = []
     try:
         for name, hg in graphs:
-            g = Graph.from_host(ctx, hg, symmetric=True)
+            g = Graph.from_host(ctx, hg, symmetric=True, renumber=RENUMBER)
             srcs = gg.sources(hg, n_sources, seed=9000)
             for kind in ("bfs", "sssp"):
                 if kind == "sssp" and hg.weights is None:
@@ -323,7 +328,11 @@ def main():
     ap.add_argument("--eval-only", action="store_true", help="evaluate the stored weights")
     ap.add_argument("--margins", default="0,0.1,0.25,0.5")
     ap.add_argument("--multi", action="store_true", help="train the batched-BFS network")
+    ap.add_argument("--no-renumber", action="store_true",
+                    help="ingest the graphs in generation order instead of degree-renumbered")
     args = ap.parse_args()
+    global RENUMBER
+    RENUMBER = not args.no_renumber
     margins = [float(x) for x in args.margins.split(",")]
     ctx = Context(0)
     if args.multi:
