@@ -1133,7 +1133,7 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
     visited_m += m_f;
   }
   if (perm && !internal_ids)
-    GR_HIP(launch_permute_out(perm, V, depth, parent, out_depth, out_parent, st));
+    GR_HIP(launch_permute_out(g->inv, V, depth, parent, out_depth, out_parent, st));
   GR_HIP(hipEventRecord(ctx->ev_stop, st));
   GR_HIP(hipEventSynchronize(ctx->ev_stop));
   if (stats) {
@@ -1469,7 +1469,8 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
     max_deg = hc->max_deg[sp];
   }
   int64_t* reached = &ctrl->reached_edges;
-  GR_HIP(launch_sssp_finalize(keys, g->R, V, dist, pred, perm, src_dev + n_src, n_src, reached, st));
+  GR_HIP(launch_sssp_finalize(keys, perm ? g->R_orig : g->R, V, dist, pred, perm ? g->inv : nullptr,
+                              src_dev + n_src, n_src, reached, st));
   GR_HIP(hipEventRecord(ctx->ev_stop, st));
   GR_TRY(read_ctrl(ctx, ctrl, st));
   if (stats) {

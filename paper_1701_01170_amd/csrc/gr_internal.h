@@ -236,8 +236,9 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s
 // copy *src into host-visible memory, then store seq to *flag (system scope)
 hipError_t launch_publish(const Ctrl* src, Ctrl* host_dst, uint32_t* host_flag, uint32_t seq,
                           hipStream_t st);
-// out[perm[i]] = in[i] for the depth and (nullable) parent arrays
-hipError_t launch_permute_out(const int32_t* perm, int64_t V, const int32_t* depth_in,
+// out[c] = in[inv[c]] for the depth and (nullable) parent arrays (inv: caller
+// id -> traversal id)
+hipError_t launch_permute_out(const int32_t* inv, int64_t V, const int32_t* depth_in,
                               const int32_t* parent_in, int32_t* depth_out, int32_t* parent_out,
                               hipStream_t st);
 
@@ -558,9 +559,11 @@ hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned
                                        uint16_t* mirror, uint32_t* relaxed, const PqState& pq,
                                        Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
                                        hipStream_t st);
-// dist / pred written at caller ids; src_orig_dev: the sources in caller ids
+// dist / pred written at caller ids; src_orig_dev: the sources in caller ids.
+// inv (nullable): caller id -> traversal id of a renumbered graph, and then R
+// is the caller's row offsets
 hipError_t launch_sssp_finalize(const unsigned long long* keys, const int32_t* R, int64_t V,
-                                uint32_t* dist, int32_t* pred, const int32_t* perm,
+                                uint32_t* dist, int32_t* pred, const int32_t* inv,
                                 const int32_t* src_orig_dev, int32_t n_src, int64_t* reached_edges,
                                 hipStream_t st);
 
