@@ -60,13 +60,14 @@ def _check_bfs_invariants(R, C, s, depth, parent, n_sample=20_000, chunk=1 << 26
 
 
 def test_rmat22_bfs_sssp_bit_exact(ctx):
-    """The headline step exactly as bench.py times it (its opts constructor,
-    tuned knobs, per-iteration tracing on, bench's first timed sources and
-    preallocated outputs), whole outputs against the oracle; the traced
-    per-level BFS statistics against the oracle's level profile too."""
+    """The headline step exactly as bench.py times it (degree-renumbered
+    ingest, its opts constructor, tuned knobs, per-iteration tracing on,
+    bench's first timed sources and preallocated outputs), whole outputs
+    against the oracle; the traced per-level BFS statistics against the
+    oracle's level profile too."""
     import bench
     hg = gg.add_weights(gg.rmat(22, 16, seed=1), seed=101)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
     ob, os_, tb, ts = bench.headline_opts(gr, g)
     V = hg.n_vertices
     out_b = (torch.empty(V, dtype=torch.int32, device="cuda"),
@@ -174,11 +175,13 @@ def _check_sssp_invariants(R, C, W, s, dist, pred, n_sample=20_000, chunk=1 << 2
 
 def test_rmat25_batched_sampled(ctx):
     """The largest workload (R-MAT scale 25, ~1.05e9 directed edges) with the
-    scale-25 run's configuration: rows 0, 3, 7, 9 and 15 of the 16-source batch
-    compared whole against single-source oracle runs;
-    one SSSP checked by the distance and predecessor invariants."""
+    scale-25 run's configuration (degree-renumbered ingest, tuned knobs):
+    rows 0, 3, 7, 9 and 15 of the 16-source batched BFS compared whole against
+    single-source oracle runs; the 16-source batched SSSP, one of its rows
+    checked by the distance and predecessor invariants and another equal to
+    the single-source SSSP from its source."""
     hg = gg.add_weights(gg.rmat(25, 16, seed=1), seed=101)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
     srcs = gg.sources(hg, 16, seed=1000).astype(np.int32)
     depth, parent, _ = gr.bfs_multi(g, srcs, opts=autotune.tuned_opts(g, "bfs_multi"))
     for i in (0, 3, 7, 9, 15):
@@ -186,7 +189,15 @@ def test_rmat25_batched_sampled(ctx):
         np.testing.assert_array_equal(depth[i].cpu().numpy(), ed, err_msg=f"source {i}")
         np.testing.assert_array_equal(parent[i].cpu().numpy(), ep, err_msg=f"source {i}")
     del ed, ep, depth, parent
-    dist, pred, _ = gr.sssp(g, [int(srcs[5])], opts=autotune.tuned_opts(g, "sssp"))
-    _check_sssp_invariants(hg.row_offsets, hg.col_indices, hg.weights, int(srcs[5]),
-                           dist.cpu().numpy().view(np.uint32), pred.cpu().numpy())
+    dist16, pred16, _ = gr.sssp_multi(g, srcs, opts=autotune.tuned_opts(g, "sssp_multi"))
+    d5 = dist16[5].cpu().numpy().view(np.uint32)
+    p5 = pred16[5].cpu().numpy()
+    d11 = dist16[11].cpu().numpy()
+    p11 = pred16[11].cpu().numpy()
+    del dist16, pred16
+    _check_sssp_invariants(hg.row_offsets, hg.col_indices, hg.weights, int(srcs[5]), d5, p5)
+    # row 11 of the batch equals the single-source SSSP from its source
+    dist, pred, _ = gr.sssp(g, [int(srcs[11])], opts=autotune.tuned_opts(g, "sssp"))
+    np.testing.assert_array_equal(dist.cpu().numpy(), d11)
+    np.testing.assert_array_equal(pred.cpu().numpy(), p11)
     g.free()
