@@ -33,6 +33,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import statistics
@@ -619,6 +620,14 @@ def main():
     teps = bfs_teps = sssp_teps = 0
     bfs_ms = sssp_ms = 0.0
     bfs_bytes = 0.0
+    def snapshot(buf, n):
+        """A copy of the first n trace records (the per-kernel byte and time
+        sums are made after the timed region)."""
+        c = (gr.LevelTrace * max(n, 1))()
+        ctypes.memmove(c, buf, ctypes.sizeof(gr.LevelTrace) * n)
+        return c, n
+
+    traces = []
     t0 = time.perf_counter()
     for i in range(args.steps):
         sb, ss = step(srcs[args.warmup + i])
@@ -627,12 +636,14 @@ def main():
         sssp_teps += ss["teps_edges"]
         bfs_ms += sb["device_ms"]
         sssp_ms += ss["device_ms"]
-        bfs_bytes += accumulate(per_kernel, "bfs", tb, min(ob.trace_count, cap), V)
-        accumulate(per_kernel, "sssp", ts, min(os_.trace_count, cap), V)
+        traces.append((snapshot(tb, min(ob.trace_count, cap)), snapshot(ts, min(os_.trace_count, cap))))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     value = teps / wall / 1e9
+    for (cb, nb), (cs, ns) in traces:
+        bfs_bytes += accumulate(per_kernel, "bfs", cb, nb, V)
+        accumulate(per_kernel, "sssp", cs, ns, V)
 
     # the same steps with the paper's default knobs, for comparison (untimed by the step clock)
     paper_ms = {"bfs": 0.0, "sssp": 0.0}
