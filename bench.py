@@ -133,13 +133,14 @@ def headline_opts(gr, g, cap: int = 4096):
     """The timed configuration of the headline step: the heuristic policy with
     the knobs the autotuner stored for this graph's class and size (paper
     defaults when none are stored), and per-iteration tracing into host
-    buffers of `cap` records.  Returns (bfs opts, sssp opts, bfs trace,
-    sssp trace); the trace buffers must outlive the opts."""
+    buffers of `cap` records (advance kernels only: trace_steps_off).
+    Returns (bfs opts, sssp opts, bfs trace, sssp trace); the trace buffers
+    must outlive the opts."""
     from paper_1701_01170_amd import autotune
     tb = (gr.LevelTrace * cap)()
     ts = (gr.LevelTrace * cap)()
-    ob = autotune.tuned_opts(g, "bfs", trace=tb, trace_capacity=cap)
-    os_ = autotune.tuned_opts(g, "sssp", trace=ts, trace_capacity=cap)
+    ob = autotune.tuned_opts(g, "bfs", trace=tb, trace_capacity=cap, trace_steps_off=1)
+    os_ = autotune.tuned_opts(g, "sssp", trace=ts, trace_capacity=cap, trace_steps_off=1)
     return ob, os_, tb, ts
 
 

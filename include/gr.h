@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 4
+#define GR_ABI_VERSION 5
 
 typedef enum gr_status {
   GR_OK = 0,
@@ -173,6 +173,9 @@ typedef struct gr_opts {
                                 graph (one key row per vertex); 1 = one source per sweep, each
                                 run as gr_sssp runs it (with its distance-ordered frontier, which
                                 a shared sweep cannot give every source).  Same results. */
+  int32_t trace_steps_off;   /* with trace: 1 = time only each iteration's advance kernel
+                                (kernel_us; step_us left 0), which saves two event records per
+                                iteration; 0 = time both (the selector's training data) */
 } gr_opts;
 
 /* gr_opts.sssp_opt_off bits */

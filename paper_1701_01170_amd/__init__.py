@@ -67,7 +67,8 @@ class Opts(ctypes.Structure):
                 ("idem_culls_off", ctypes.c_int32), ("idem_table_log2", ctypes.c_int32),
                 ("adv_block", ctypes.c_int32), ("twc_wave_min", ctypes.c_int32),
                 ("twc_block_min", ctypes.c_int32), ("graph_blocks", ctypes.c_int32),
-                ("sssp_opt_off", ctypes.c_int32), ("sssp_multi_sweep", ctypes.c_int32)]
+                ("sssp_opt_off", ctypes.c_int32), ("sssp_multi_sweep", ctypes.c_int32),
+                ("trace_steps_off", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):

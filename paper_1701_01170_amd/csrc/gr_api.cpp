@@ -168,12 +168,13 @@ struct OffsetsJob {
 };
 
 gr_status read_ctrl(gr_ctx* ctx, Ctrl* dev, hipStream_t st, const MlpSelect* sel = nullptr,
-                    const OffsetsJob* pre = nullptr) {
+                    const OffsetsJob* pre = nullptr, const PublishExtra* extra = nullptr) {
   const uint32_t seq = ++ctx->publish_seq;
+  const PublishExtra x = extra ? *extra : PublishExtra{};
   if (sel)
-    GR_HIP(launch_publish_select(*sel, dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
+    GR_HIP(launch_publish_select(*sel, dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st, x));
   else
-    GR_HIP(launch_publish(dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st));
+    GR_HIP(launch_publish(dev, ctx->host_ctrl_dev, ctx->publish_flag_dev, seq, st, x));
   if (pre)
     GR_HIP(launch_frontier_offsets(pre->frontier, 0, pre->R, pre->block_sums, pre->total,
                                    pre->offsets, pre->rstart, pre->chunk_start, pre->chunk, st,
@@ -275,9 +276,12 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
     const long long ms = std::atoll(w);
     if (ms > 0) c->wait_limit = std::chrono::milliseconds(ms);
   }
-  // control block mirror + publish flag: coherent, device-mapped pinned memory
+  // control block mirror, block log and publish flag: coherent, device-mapped
+  // pinned memory
   void* hc = nullptr;
-  const size_t mirror_bytes = (sizeof(Ctrl) + 255) / 256 * 256 + 256;
+  const size_t ctrl_bytes = (sizeof(Ctrl) + 255) / 256 * 256;
+  const size_t dlog_bytes = (sizeof(int64_t) * 3 * kDlMaxLevels + 255) / 256 * 256;
+  const size_t mirror_bytes = ctrl_bytes + dlog_bytes + 256;
   if (hipHostMalloc(&hc, mirror_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     delete c;
     return fail(GR_ENOMEM, "pinned host allocation failed");
@@ -296,6 +300,8 @@ extern "C" gr_status gr_ctx_create(int32_t device, gr_ctx** out) {
   }
   c->host_ctrl = static_cast<Ctrl*>(hc);
   c->host_ctrl_dev = static_cast<Ctrl*>(hd);
+  c->host_dlog = reinterpret_cast<int64_t*>(static_cast<char*>(hc) + ctrl_bytes);
+  c->host_dlog_dev = reinterpret_cast<int64_t*>(static_cast<char*>(hd) + ctrl_bytes);
   const size_t flag_off = mirror_bytes - 256;
   c->publish_flag = reinterpret_cast<volatile uint32_t*>(static_cast<char*>(hc) + flag_off);
   c->publish_flag_dev = reinterpret_cast<uint32_t*>(static_cast<char*>(hd) + flag_off);
@@ -588,6 +594,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->sssp_opt_off: unknown bits");
   if (opts->sssp_multi_sweep != 0 && opts->sssp_multi_sweep != 1)
     return fail(GR_EINVAL, "opts->sssp_multi_sweep must be 0 or 1");
+  if (opts->trace_steps_off != 0 && opts->trace_steps_off != 1)
+    return fail(GR_EINVAL, "opts->trace_steps_off must be 0 or 1");
   if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
     return fail(GR_EINVAL, "opts->bfs_filter out of range");
   if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
@@ -642,8 +650,8 @@ gr_status record_trace_times(gr_opts* opts, const LevelFeatures& lf, int action,
   return GR_OK;
 }
 
-// Event-timed record of one iteration: ev_a..ev_b brackets the whole step,
-// ev_k0..ev_k1 the advance kernel alone.
+// Event-timed record of one iteration: ev_a..ev_b brackets the whole step
+// (not recorded with trace_steps_off), ev_k0..ev_k1 the advance kernel alone.
 gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int action,
                        int kernel, int64_t n_next, StepWork w) {
   if (!opts || !opts->trace || opts->trace_count >= opts->trace_capacity) {
@@ -651,7 +659,7 @@ gr_status record_trace(gr_ctx* ctx, gr_opts* opts, const LevelFeatures& lf, int 
     return GR_OK;
   }
   float step_ms = 0.f, kernel_ms = 0.f;
-  GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &step_ms));
+  if (!opts->trace_steps_off) GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &step_ms));
   GR_TRY(elapsed_ms(ctx->ev_k0, ctx->ev_k1, &kernel_ms));
   return record_trace_times(opts, lf, action, kernel, n_next, step_ms, kernel_ms, w);
 }
@@ -980,15 +988,15 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
                                                st));
       msel = select_at(sp, 0, 0, 0);
       msel.after_block = 1;
-      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
+      // while tracing, the publication also copies the block's level log
+      const PublishExtra lgx{reinterpret_cast<const uint32_t*>(dl.log),
+                             reinterpret_cast<uint32_t*>(ctx->host_dlog_dev), 6 * kmax};
+      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr, nullptr, tracing ? &lgx : nullptr));
       const int k = hc->dl_levels;
       if (k > 0) {
-        int64_t lg[3 * kDlMaxLevels];  // the block's level log (host copy)
+        const int64_t* lg = ctx->host_dlog;  // the block's level log (host copy)
         float block_ms = 0.f;
-        if (tracing) {
-          GR_HIP(hipMemcpy(lg, dl.log, sizeof(int64_t) * 3 * (size_t)k, hipMemcpyDeviceToHost));
-          GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
-        }
+        if (tracing) GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         // full blocks double the next one; blocks that stop early halve it
         if (k == kmax) dl.len = std::min(2 * dl.len, kDlMaxLevels);
         else if (2 * k < kmax) dl.len = std::max(dl.len / 2, kDlFirstLen);
@@ -1025,7 +1033,7 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
         continue;
       }
     }
-    if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+    if (tracing && !opts.trace_steps_off) GR_HIP(hipEventRecord(ctx->ev_a, st));
     const int next_depth = level + 1;
     int kernel = 0;
     if (action == GR_PUSH_LB || action == GR_PUSH_TWC) {
@@ -1105,7 +1113,7 @@ gr_status bfs_run(gr_ctx* ctx, const gr_graph* g, int32_t source, int32_t* depth
       list_ok = true;
     }
     GR_HIP(launch_bitmap_merge(bm, p, NW, st));
-    if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+    if (tracing && !opts.trace_steps_off) GR_HIP(hipEventRecord(ctx->ev_b, st));
     rs.action_count[action]++;
     p ^= 1;
     cur = (cur + 1) % 3;
@@ -1358,7 +1366,10 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       GR_HIP(launch_frontier_stats_after_block(Queues3{{qA, qB, qC}}, cur, g->R, bsums, ctrl, sp,
                                                st));
       msel.sp = sp;
-      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr));
+      // while tracing, the publication also copies the block's level log
+      const PublishExtra lgx{reinterpret_cast<const uint32_t*>(dl.log),
+                             reinterpret_cast<uint32_t*>(ctx->host_dlog_dev), 6 * kmax};
+      GR_TRY(read_ctrl(ctx, ctrl, st, learned ? &msel : nullptr, nullptr, tracing ? &lgx : nullptr));
       const int k = hc->dl_levels;
       if (use_pq) {
         pq.T = hc->pq_T[k & 1];
@@ -1367,12 +1378,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         far_n = hc->far_count[pq.fc];
       }
       if (k > 0) {
-        int64_t lg[3 * kDlMaxLevels];  // the block's level log (host copy)
+        const int64_t* lg = ctx->host_dlog;  // the block's level log (host copy)
         float block_ms = 0.f;
-        if (tracing) {
-          GR_HIP(hipMemcpy(lg, dl.log, sizeof(int64_t) * 3 * (size_t)k, hipMemcpyDeviceToHost));
-          GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
-        }
+        if (tracing) GR_TRY(elapsed_ms(ctx->ev_a, ctx->ev_b, &block_ms));
         // full blocks double the next one; blocks that stop early halve it
         if (k == kmax) dl.len = std::min(2 * dl.len, kDlMaxLevels);
         else if (2 * k < kmax) dl.len = std::max(dl.len / 2, kDlFirstLen);
@@ -1399,7 +1407,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
         continue;
       }
     }
-    if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+    if (tracing && !opts.trace_steps_off) GR_HIP(hipEventRecord(ctx->ev_a, st));
     int kernel = kTraceKernelRefill;
     const int64_t refill_in = far_n;
     if (n_f == 0) {
@@ -1456,7 +1464,7 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
       expanded += n_f;
       rs.action_count[action]++;
     }
-    if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+    if (tracing && !opts.trace_steps_off) GR_HIP(hipEventRecord(ctx->ev_b, st));
     cur = (cur + 1) % 3;
     sp ^= 1;
     ++it;
@@ -1658,7 +1666,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
         lf.max_deg_f = hc->max_deg[sp];
       }
       int kernel = 4;
-      if (tracing) GR_HIP(hipEventRecord(ctx->ev_a, st));
+      if (tracing && !opts.trace_steps_off) GR_HIP(hipEventRecord(ctx->ev_a, st));
       if (pull) {
         if (tracing) GR_HIP(hipEventRecord(ctx->ev_k0, st));
         GR_HIP(launch_ms_pull(V, g->R, g->C, front[fc], visit, full, next, q[(cur + 1) % 3],
@@ -1683,7 +1691,7 @@ extern "C" gr_status gr_bfs_multi(gr_ctx* ctx, const gr_graph* g, const int32_t*
                                 g->R, g->C, front[fc], front[fc ^ 1], visit, next, dpass,
                                 pull ? nullptr : ppass, g->perm, V, level + 1, ctrl, st));
       GR_HIP(launch_ms_clear(q[cur], &ctrl->q_count[cur], n_a, front[fc], st));
-      if (tracing) GR_HIP(hipEventRecord(ctx->ev_b, st));
+      if (tracing && !opts.trace_steps_off) GR_HIP(hipEventRecord(ctx->ev_b, st));
       prev_pull = pull;
       fc ^= 1;
       cur = (cur + 1) % 3;

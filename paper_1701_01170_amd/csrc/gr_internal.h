@@ -132,6 +132,10 @@ struct gr_ctx {
   gr::Ctrl* host_ctrl_dev = nullptr;        // the same memory, device address
   volatile uint32_t* publish_flag = nullptr;
   uint32_t* publish_flag_dev = nullptr;
+  // a device-predicated block's level log (3 x kDlMaxLevels int64), copied
+  // here by the publication that ends the block while tracing
+  int64_t* host_dlog = nullptr;
+  int64_t* host_dlog_dev = nullptr;
   uint32_t publish_seq = 0;
   bool policy_loaded = false;
   // offset of the batched-traversal network in the selector parameters (0:
@@ -234,8 +238,15 @@ hipError_t launch_frontier_offsets(const int32_t* frontier, int64_t n_f, const i
                                    const uint32_t* n_f_dev = nullptr);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t st);
 // copy *src into host-visible memory, then store seq to *flag (system scope)
+// Extra words a publication copies to host memory before its fence (a block
+// log, while tracing); n_words = 0: none.
+struct PublishExtra {
+  const uint32_t* src = nullptr;
+  uint32_t* dst = nullptr;
+  int n_words = 0;
+};
 hipError_t launch_publish(const Ctrl* src, Ctrl* host_dst, uint32_t* host_flag, uint32_t seq,
-                          hipStream_t st);
+                          hipStream_t st, const PublishExtra& extra = PublishExtra{});
 // out[c] = in[inv[c]] for the depth and (nullable) parent arrays (inv: caller
 // id -> traversal id)
 hipError_t launch_permute_out(const int32_t* inv, int64_t V, const int32_t* depth_in,
@@ -440,7 +451,8 @@ struct MlpSelect {
 // its argmin (action) written into the control block, which is then published
 // to host memory as launch_publish does; one kernel for both.
 hipError_t launch_publish_select(const MlpSelect& m, Ctrl* ctrl, Ctrl* host_dst,
-                                 uint32_t* host_flag, uint32_t seq, hipStream_t st);
+                                 uint32_t* host_flag, uint32_t seq, hipStream_t st,
+                                 const PublishExtra& extra = PublishExtra{});
 
 // Device-predicated level blocks (iteration control): up to kDlMaxLevels
 // push levels are enqueued back to back; each level kernel first decides on

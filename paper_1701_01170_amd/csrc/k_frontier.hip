@@ -232,8 +232,9 @@ __global__ __launch_bounds__(256) void k_permute_out(const int32_t* __restrict__
 // sequence number the host waits for.
 __global__ __launch_bounds__(128) void k_publish(const uint32_t* __restrict__ src,
                                                  uint32_t* __restrict__ dst, int n_words,
-                                                 uint32_t* flag, uint32_t seq) {
+                                                 uint32_t* flag, uint32_t seq, PublishExtra x) {
   for (int i = threadIdx.x; i < n_words; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < x.n_words; i += blockDim.x) x.dst[i] = x.src[i];
   __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -326,11 +327,11 @@ hipError_t launch_permute_out(const int32_t* inv, int64_t V, const int32_t* dept
 }
 
 hipError_t launch_publish(const Ctrl* src, Ctrl* host_dst, uint32_t* host_flag, uint32_t seq,
-                          hipStream_t st) {
+                          hipStream_t st, const PublishExtra& extra) {
   static_assert(sizeof(Ctrl) % 4 == 0, "control block is copied as 32-bit words");
   k_publish<<<1, 128, 0, st>>>(reinterpret_cast<const uint32_t*>(src),
                                reinterpret_cast<uint32_t*>(host_dst), (int)(sizeof(Ctrl) / 4),
-                               host_flag, seq);
+                               host_flag, seq, extra);
   return hipGetLastError();
 }
 

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 // ordered at system scope, and one thread releases the sequence number.
 __global__ __launch_bounds__(128) void k_publish_select(MlpSelect m, Ctrl* __restrict__ ctrl,
                                                         uint32_t* __restrict__ dst, uint32_t* flag,
-                                                        uint32_t seq) {
+                                                        uint32_t seq, PublishExtra x) {
   __shared__ float s_p[kNP];
   __shared__ float s_x[kIn], s_h1[kH], s_h2[kH], s_y[kOut];
   __shared__ uint32_t s_dec[kOut + 1];
@@ -252,6 +252,7 @@ __global__ __launch_bounds__(128) void k_publish_select(MlpSelect m, Ctrl* __res
     else w = src[i];
     dst[i] = w;
   }
+  for (int i = threadIdx.x; i < x.n_words; i += blockDim.x) x.dst[i] = x.src[i];
   __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -286,10 +287,11 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, floa
 }
 
 hipError_t launch_publish_select(const MlpSelect& m, Ctrl* ctrl, Ctrl* host_dst,
-                                 uint32_t* host_flag, uint32_t seq, hipStream_t st) {
+                                 uint32_t* host_flag, uint32_t seq, hipStream_t st,
+                                 const PublishExtra& extra) {
   static_assert(sizeof(Ctrl) % 4 == 0, "control block is copied as 32-bit words");
   k_publish_select<<<1, 128, 0, st>>>(m, ctrl, reinterpret_cast<uint32_t*>(host_dst), host_flag,
-                                      seq);
+                                      seq, extra);
   return hipGetLastError();
 }
 

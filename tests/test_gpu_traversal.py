@@ -356,23 +356,32 @@ def test_trace_records(ctx, rmat14, dme):
     assert (6 in kernels) == (dme != -1), kernels
 
 
+@pytest.mark.parametrize("steps_off", [0, 1])
 @pytest.mark.parametrize("delta", [0, 16])
 @pytest.mark.parametrize("dme", [0, -1])
-def test_traced_sssp_outputs(ctx, rmat14, dme, delta):
+def test_traced_sssp_outputs(ctx, rmat14, dme, delta, steps_off):
     """Tracing takes its own paths (event records around every advance
-    kernel, the block logs of device-predicated levels copied back); the
-    traced SSSP must still match the oracle element by element."""
+    kernel, the block logs of device-predicated levels published with the
+    control block); the traced SSSP must still match the oracle element by
+    element.  With trace_steps_off only the advance kernels are timed: step
+    times stay 0 outside device-predicated blocks."""
     g = gr.Graph.from_host(ctx, rmat14)
     cap = 256
     buf = (gr.LevelTrace * cap)()
     for s in gg.sources(rmat14, 2, seed=1000):
-        o = gr.default_opts(trace=buf, trace_capacity=cap, device_max_edges=dme, sssp_delta=delta)
+        o = gr.default_opts(trace=buf, trace_capacity=cap, device_max_edges=dme, sssp_delta=delta,
+                            trace_steps_off=steps_off)
         d, p, st = gr.sssp(g, [int(s)], opts=o)
         ed, ep = oracle.sssp(rmat14.row_offsets, rmat14.col_indices, rmat14.weights, [int(s)])
         np.testing.assert_array_equal(np_of(d).view(np.uint32), ed)
         np.testing.assert_array_equal(np_of(p), ep)
         assert 0 < o.trace_count <= cap
-        assert all(t.step_us > 0 for t in buf[:o.trace_count])
+        recs = buf[:o.trace_count]
+        assert all(t.kernel_us > 0 for t in recs)
+        if steps_off:
+            assert all(t.step_us == 0 for t in recs if t.kernel != 6)
+        else:
+            assert all(t.step_us > 0 for t in recs)
     g.free()
 
 
