@@ -428,6 +428,24 @@ def extras(gr, gg, ctx, torch, log):
     return out
 
 
+def bc_rmat22(gr, g, sources) -> dict:
+    """Betweenness centrality (gr_bc, Brandes's two passes on the advance
+    operator) from each source alone and from all of them in one call: device
+    time and the rate over the reached vertices' edges per source (teps_edges
+    of the stats), which the forward and the backward pass each push over."""
+    gr.bc(g, [int(sources[0])])  # warm-up
+    ms, te = [], 0
+    for s in sources:
+        st = gr.bc(g, [int(s)])[2]
+        ms.append(st["device_ms"])
+        te += st["teps_edges"]
+    allst = gr.bc(g, [int(s) for s in sources])[2]
+    return {"sources": len(sources), "median_ms_per_source": round(statistics.median(ms), 4),
+            "gteps": _gteps(te, sum(ms)),
+            "all_sources_one_call_ms": round(allst["device_ms"], 4),
+            "all_sources_one_call_gteps": _gteps(allst["teps_edges"], allst["device_ms"])}
+
+
 def cpu_baseline(hg, srcs, budget_s: float = 10.0, max_pairs: int = 4) -> dict:
     """The CPU oracle (single thread) on BFS + SSSP pairs of the same graph,
     until about budget_s seconds of CPU work."""
@@ -720,6 +738,8 @@ def main():
             gr, g, ctx, gg.sources(hg, 12, seed=1100),
             outs={"bfs": (depth, parent), "sssp": (dist, pred)})
         log("# learned vs heuristic done")
+        out["breakdown"]["bc_rmat22"] = bc_rmat22(gr, g, gg.sources(hg, 4, seed=1300))
+        log("# betweenness centrality done")
         out["breakdown"]["bfs_filter_ablation_rmat22"] = filter_ablation(
             gr, g, gg.sources(hg, 8, seed=1200), (depth, parent))
         log("# filter ablation done")
