@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 5
+#define GR_ABI_VERSION 6
 
 typedef enum gr_status {
   GR_OK = 0,
@@ -176,7 +176,16 @@ typedef struct gr_opts {
   int32_t trace_steps_off;   /* with trace: 1 = time only each iteration's advance kernel
                                 (kernel_us; step_us left 0), which saves two event records per
                                 iteration; 0 = time both (the selector's training data) */
+  int32_t bc_push;           /* gr_bc: passes run in push form (each edge adds into the sum of
+                                its other end with an fp64 atomic), a bit set of GR_BC_PUSH_*;
+                                the other passes gather each vertex's sum over its own row.
+                                Same results up to the order of the additions. */
 } gr_opts;
+
+/* gr_opts.bc_push bits */
+#define GR_BC_PUSH_SIGMA 1  /* forward pass: each level adds sigma into its successors */
+#define GR_BC_PUSH_DEP 2    /* backward pass: each level adds its payload into its
+                               predecessors' dependency sums */
 
 /* gr_opts.sssp_opt_off bits */
 #define GR_SSSP_OPT_CULL 1  /* drop from the next frontier a vertex whose edges this iteration

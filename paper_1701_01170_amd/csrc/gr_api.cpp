@@ -596,6 +596,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->sssp_multi_sweep must be 0 or 1");
   if (opts->trace_steps_off != 0 && opts->trace_steps_off != 1)
     return fail(GR_EINVAL, "opts->trace_steps_off must be 0 or 1");
+  if (opts->bc_push & ~(GR_BC_PUSH_SIGMA | GR_BC_PUSH_DEP))
+    return fail(GR_EINVAL, "opts->bc_push: unknown bits");
   if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
     return fail(GR_EINVAL, "opts->bfs_filter out of range");
   if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
@@ -1900,7 +1902,7 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
       return fail(GR_EINVAL, "gr_bc: source " + std::to_string(sources[i]) + " out of range");
   if (sigma && n_sources != 1) return fail(GR_EINVAL, "gr_bc: sigma needs exactly one source");
   if (!(g->flags & GR_SYMMETRIC))
-    return fail(GR_EUNSUPPORTED, "gr_bc needs a symmetric graph (the backward pass pushes over in-edges)");
+    return fail(GR_EUNSUPPORTED, "gr_bc needs a symmetric graph (each pass follows edges against their direction)");
   gr_opts opts;
   GR_TRY(check_opts(opts_in, &opts));
   if (opts_in) opts_in->trace_count = 0;
@@ -1913,6 +1915,8 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   const AdvCfg adv = adv_cfg(opts);
   const int chunk = adv.chunk;
   const bool lb = (double)E / (double)V >= (double)opts.lb_min_avg_degree;
+  const bool push_sigma = (opts.bc_push & GR_BC_PUSH_SIGMA) != 0;
+  const bool push_dep = (opts.bc_push & GR_BC_PUSH_DEP) != 0;
 
   int32_t *depth, *levels, *offsets, *rstart, *chunks;
   double *sig, *acc;
@@ -1940,12 +1944,13 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   std::vector<uint32_t> hn;
   std::vector<unsigned long long> hm;
   std::vector<uint32_t> off;
-  // a level's workload mapping (as the heuristic picks it for a push level),
-  // with the degree scan queued first when it balances edges
+  // a level's workload mapping (as the heuristic picks it for a push level,
+  // always LB for a pull), with the degree scan queued first when it balances
+  // edges
   int sp = 0;
-  auto prepare_level = [&](int64_t n, const int32_t* front, const uint32_t* n_dev,
+  auto prepare_level = [&](int64_t n, const int32_t* front, const uint32_t* n_dev, bool pull,
                            int* mode) -> gr_status {
-    *mode = !lb ? 0 : (n < opts.lb_light_threshold ? 1 : 2);
+    *mode = pull ? 2 : !lb ? 0 : (n < opts.lb_light_threshold ? 1 : 2);
     if (*mode == 2) {
       GR_HIP(launch_frontier_stats(front, n_dev, g->R, bsums, ctrl, sp, nullptr, nullptr, st));
       GR_HIP(launch_frontier_offsets(front, n, g->R, bsums, &ctrl->m_f[sp], offsets, rstart, chunks,
@@ -1975,23 +1980,35 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
     GR_HIP(launch_bc_scatter(depth, V, L, lvl_n + L, levels, st));
     GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
     sp = 0;
-    // forward: sigma of level d + 1 from level d
+    // forward: sigma of level d + 1 from level d, pushed by level d or
+    // gathered by level d + 1
     for (int32_t d = 0; d + 1 < L; ++d) {
-      if (hm[d] == 0) continue;
-      const int32_t* front = levels + off[d];
+      const int32_t x = push_sigma ? d : d + 1;  // the level whose rows are swept
+      if (hm[x] == 0) continue;
+      const int32_t* front = levels + off[x];
       int mode = 0;
-      GR_TRY(prepare_level(hn[d], front, lvl_n + d, &mode));
-      GR_HIP(launch_bc_sigma(mode, front, offsets, rstart, chunks, hn[d], (int64_t)hm[d], g->R, g->C,
-                             depth, sig, d + 1, adv, st));
+      GR_TRY(prepare_level(hn[x], front, lvl_n + x, !push_sigma, &mode));
+      if (push_sigma)
+        GR_HIP(launch_bc_sigma(mode, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], g->R,
+                               g->C, depth, sig, d + 1, adv, st));
+      else
+        GR_HIP(launch_bc_pull(false, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], chunk,
+                              g->C, depth, d, sig, acc, st));
     }
-    // backward: dependency sums of level d - 1 from level d
-    for (int32_t d = L - 1; d >= 1; --d) {
-      if (hm[d] == 0) continue;
-      const int32_t* front = levels + off[d];
+    // backward: dependency sums of level d - 1 from level d, pushed by level d
+    // or gathered by level d - 1 (the source's own sum is not needed)
+    for (int32_t d = L - 1; d >= (push_dep ? 1 : 2); --d) {
+      const int32_t x = push_dep ? d : d - 1;
+      if (hm[x] == 0) continue;
+      const int32_t* front = levels + off[x];
       int mode = 0;
-      GR_TRY(prepare_level(hn[d], front, lvl_n + d, &mode));
-      GR_HIP(launch_bc_dependency(mode, front, offsets, rstart, chunks, hn[d], (int64_t)hm[d], g->R,
-                                  g->C, depth, sig, acc, d - 1, adv, st));
+      GR_TRY(prepare_level(hn[x], front, lvl_n + x, !push_dep, &mode));
+      if (push_dep)
+        GR_HIP(launch_bc_dependency(mode, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x],
+                                    g->R, g->C, depth, sig, acc, d - 1, adv, st));
+      else
+        GR_HIP(launch_bc_pull(true, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], chunk,
+                              g->C, depth, d, sig, acc, st));
     }
     GR_HIP(launch_bc_finalize(depth, sig, acc, V, src, g->perm, bc, sigma, st));
     // the host vectors are reused by the next source: finish their copies

@@ -310,8 +310,9 @@ hipError_t launch_bfs_idem_filter(const int32_t* cand, const uint32_t* cand_coun
                                   int64_t V, uint32_t* bm, int p, const int32_t* depth,
                                   int32_t next_depth, int32_t* out_q, uint32_t* out_count,
                                   hipStream_t st);
-// betweenness centrality (levels by counting sort of the depths, then push
-// advances per level with fp64 atomic sums; see k_bc.hip)
+// betweenness centrality (levels by counting sort of the depths, then per
+// level a push advance with fp64 atomic sums or a pull of the sums; see
+// k_bc.hip)
 hipError_t launch_bc_levels(const int32_t* depth, const int32_t* R, int64_t V, int32_t source,
                             int32_t n_levels, uint32_t* lvl_n, unsigned long long* lvl_m,
                             double* sigma, double* acc, hipStream_t st);
@@ -326,6 +327,13 @@ hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t
                                 int64_t m_f, const int32_t* R, const int32_t* C,
                                 const int32_t* depth, const double* sigma, double* acc,
                                 int32_t prev_depth, const AdvCfg& cfg, hipStream_t st);
+// pull form of either pass over one level with the LB mapping of `chunk` edges
+// (dependency: acc of the level from its successors at depth `want`;
+// otherwise sigma of the level from its predecessors at depth `want`)
+hipError_t launch_bc_pull(bool dependency, const int32_t* frontier, const int32_t* offsets,
+                          const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                          int64_t m_f, int chunk, const int32_t* C, const int32_t* depth,
+                          int32_t want, double* sigma, double* acc, hipStream_t st);
 hipError_t launch_bc_finalize(const int32_t* depth, const double* sigma, const double* acc,
                               int64_t V, int32_t source, const int32_t* perm, double* bc,
                               double* sigma_out, hipStream_t st);

@@ -167,6 +167,37 @@ __device__ __forceinline__ void edge_batch(const F& f, const int32_t* __restrict
   }
 }
 
+// Inclusive max-scan over s_seg[0, SPT * BLOCK) in place, SPT consecutive
+// slots per thread: turns the scattered segment starts into each edge slot's
+// segment index.  s_tmp holds BLOCK / kWave + 1 entries.  Every thread of the
+// workgroup calls it (one barrier inside); the caller adds the barrier after.
+template <int SPT, int BLOCK>
+__device__ __forceinline__ void lb_seg_maxscan(uint16_t* s_seg, int32_t* s_tmp) {
+  int32_t run = 0;
+  for (int r = 0; r < SPT; ++r) {
+    const int32_t x = s_seg[threadIdx.x * SPT + r];
+    run = x > run ? x : run;
+  }
+  int32_t inc = run;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o);
+    if (lane() >= o) inc = y > inc ? y : inc;
+  }
+  if (lane() == kWave - 1) s_tmp[threadIdx.x / kWave] = inc;
+  __syncthreads();
+  int32_t ex = 0;
+  for (int i = 0; i < (int)threadIdx.x / kWave; ++i) ex = s_tmp[i] > ex ? s_tmp[i] : ex;
+  int32_t wx = __shfl_up(inc, 1);
+  if (lane() == 0) wx = 0;
+  run = wx > ex ? wx : ex;
+  for (int r = 0; r < SPT; ++r) {
+    const int32_t x = s_seg[threadIdx.x * SPT + r];
+    run = x > run ? x : run;
+    s_seg[threadIdx.x * SPT + r] = (uint16_t)run;
+  }
+}
+
 // One workgroup per chunk of NB * EPT * 256 edges of the output frontier.  The
 // frontier segments overlapping the chunk are staged in LDS (lb_cap per pass);
 // a 16-bit segment index per edge slot comes from scattering segment starts and
@@ -219,32 +250,7 @@ __global__ __launch_bounds__(BLOCK) void k_push_lb(
       if (pos < hi - lo && s_off[k + 1] > s_off[k]) s_seg[pos] = (uint16_t)k;
     }
     __syncthreads();
-    // inclusive max-scan over s_seg[0, N): SPT consecutive slots per thread
-    {
-      int32_t run = 0;
-      for (int r = 0; r < SPT; ++r) {
-        const int32_t x = s_seg[threadIdx.x * SPT + r];
-        run = x > run ? x : run;
-      }
-      int32_t inc = run;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int32_t y = __shfl_up(inc, o);
-        if (lane() >= o) inc = y > inc ? y : inc;
-      }
-      if (lane() == kWave - 1) s_tmp[threadIdx.x / kWave] = inc;
-      __syncthreads();
-      int32_t ex = 0;
-      for (int i = 0; i < (int)threadIdx.x / kWave; ++i) ex = s_tmp[i] > ex ? s_tmp[i] : ex;
-      int32_t wx = __shfl_up(inc, 1);
-      if (lane() == 0) wx = 0;
-      run = wx > ex ? wx : ex;
-      for (int r = 0; r < SPT; ++r) {
-        const int32_t x = s_seg[threadIdx.x * SPT + r];
-        run = x > run ? x : run;
-        s_seg[threadIdx.x * SPT + r] = (uint16_t)run;
-      }
-    }
+    lb_seg_maxscan<SPT, BLOCK>(s_seg, s_tmp);
     __syncthreads();
     for (int b = 0; b < NB; ++b) {
       if (lo + (int64_t)b * BATCH >= hi) break;

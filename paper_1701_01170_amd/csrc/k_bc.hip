@@ -146,6 +146,130 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_level_scatter(
   }
 }
 
+// Per-edge values summed by the pull passes: sigma(u) of a predecessor in the
+// forward pass, (1 + delta(w)) / sigma(w) = 1 / sigma(w) + acc(w) of a
+// successor in the backward pass.
+struct BcSigmaVal {
+  const double* __restrict__ sigma;
+  __device__ __forceinline__ double operator()(int32_t u) const { return sigma[u]; }
+};
+struct BcDependencyVal {
+  const double* __restrict__ sigma;
+  const double* __restrict__ acc;
+  __device__ __forceinline__ double operator()(int32_t w) const { return 1.0 / sigma[w] + acc[w]; }
+};
+
+// Sum over the 64 lanes' consecutive edges by segment (key non-decreasing
+// over the lanes): each lane gets the sum of its key's lanes up to itself;
+// *last marks the last lane of each key's run.
+__device__ __forceinline__ double wave_seg_sum(double x, int key, bool* last) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(x, o);
+    const int ky = __shfl_up(key, o);
+    if (lane() >= o && ky == key) x += y;
+  }
+  const int kn = __shfl_down(key, 1);
+  *last = lane() == kWave - 1 || kn != key;
+  return x;
+}
+
+// Pull form of a pass (the vertex that owns a sum gathers it, instead of the
+// sum being scattered onto it by atomics): for every vertex v of a level and
+// every edge (v, w) with depth(w) == want, out(v) += val(w).  On a symmetric
+// graph this is the push form's sum with the edge's ends swapped: the
+// dependency of v gathers over its successors one level deeper, sigma(w) over
+// its predecessors one level up.  Where a few vertices of the level before
+// receive most of a large level's edges (hubs of a power-law graph) the push
+// form queues every edge's fp64 atomic on those few addresses; here no edge
+// makes an atomic.  The rows are balanced as in k_push_lb (equal chunks of the
+// level's edges per workgroup, the chunk -> first-row map from the offsets
+// kernel, each edge's row from a max-scan of row starts); every wavefront
+// reduces its 64 consecutive edges by row with a shuffle scan, the last lane
+// of each run adds the run into its row's LDS slot, and each row the chunk
+// touches is written once: a plain store when the chunk holds the whole row
+// (out starts at 0 and no other workgroup writes it), else one fp64 atomic.
+template <class Val, int EPT, int NB>
+__global__ __launch_bounds__(kBcBlock) void k_bc_pull_lb(
+    const int32_t* __restrict__ frontier, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ rstart, const int32_t* __restrict__ chunk_start, int32_t n_f,
+    int32_t m_f, const int32_t* __restrict__ C, const int32_t* __restrict__ depth, int32_t want,
+    Val val, double* __restrict__ out) {
+  constexpr int BATCH = kBcBlock * EPT;
+  constexpr int N = BATCH * NB;
+  constexpr int SPT = N / kBcBlock;
+  constexpr int CAP = lb_cap(N);
+  constexpr int kNoRow = 0xFFFF;  // lanes past the chunk's last edge (above every row index)
+  __shared__ uint16_t s_seg[N];
+  __shared__ int32_t s_off[CAP + 1];
+  __shared__ int32_t s_u[CAP];
+  __shared__ int32_t s_rb[CAP];
+  __shared__ double s_sum[CAP];
+  __shared__ int32_t s_tmp[kBcBlock / kWave + 1];
+  const int c = blockIdx.x;
+  const int64_t e0 = (int64_t)c * N;
+  const int64_t e1 = e0 + N < m_f ? e0 + N : m_f;
+  const int nchunks = (int)(((int64_t)m_f + N - 1) / N);
+  const int sb = chunk_start[c];
+  const int se = c + 1 < nchunks ? chunk_start[c + 1] : n_f - 1;
+  for (int pb = sb; pb <= se; pb += CAP) {
+    const int cnt = (se - pb + 1) < CAP ? (se - pb + 1) : CAP;
+    for (int i = threadIdx.x; i < cnt; i += kBcBlock) {
+      const int s = pb + i;
+      s_off[i] = offsets[s];
+      s_u[i] = frontier[s];
+      s_rb[i] = rstart[s];
+      s_sum[i] = 0.0;
+    }
+    if (threadIdx.x == 0) s_off[cnt] = offsets[pb + cnt];
+    for (int j = threadIdx.x; j < N; j += kBcBlock) s_seg[j] = 0;
+    __syncthreads();
+    const int64_t lo = e0 > (int64_t)s_off[0] ? e0 : (int64_t)s_off[0];
+    const int64_t hi = e1 < (int64_t)s_off[cnt] ? e1 : (int64_t)s_off[cnt];
+    for (int k = 1 + threadIdx.x; k < cnt; k += kBcBlock) {
+      const int64_t pos = (int64_t)s_off[k] - lo;
+      if (pos < hi - lo && s_off[k + 1] > s_off[k]) s_seg[pos] = (uint16_t)k;
+    }
+    __syncthreads();
+    lb_seg_maxscan<SPT, kBcBlock>(s_seg, s_tmp);
+    __syncthreads();
+    for (int b = 0; b < NB; ++b) {
+      if (lo + (int64_t)b * BATCH >= hi) break;
+      int key[EPT];
+      int32_t w[EPT];
+      double x[EPT];
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) {
+        const int j = b * BATCH + r * kBcBlock + threadIdx.x;
+        const int64_t e = lo + j;
+        key[r] = e < hi ? (int)s_seg[j] : kNoRow;
+        w[r] = key[r] != kNoRow ? C[s_rb[key[r]] + (int32_t)(e - s_off[key[r]])] : 0;
+      }
+#pragma unroll
+      for (int r = 0; r < EPT; ++r)
+        if (key[r] != kNoRow && depth[w[r]] != want) w[r] = -1;
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) x[r] = key[r] != kNoRow && w[r] >= 0 ? val(w[r]) : 0.0;
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) {
+        bool last;
+        const double sum = wave_seg_sum(x[r], key[r], &last);
+        if (last && key[r] != kNoRow && sum != 0.0) atomicAdd(&s_sum[key[r]], sum);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += kBcBlock) {
+      const int64_t a = s_off[i], z = s_off[i + 1];
+      if (z <= lo || a >= hi || z <= a) continue;  // no edge of this row in the chunk
+      if (a >= e0 && z <= e1)
+        out[s_u[i]] = s_sum[i];
+      else if (s_sum[i] != 0.0)
+        unsafeAtomicAdd(&out[s_u[i]], s_sum[i]);
+    }
+    __syncthreads();
+  }
+}
+
 // bc(v) += delta(v) = sigma(v) * acc(v) for reached v != source; sigma out
 // (nullable) for the caller.  Outputs at caller ids (perm nullable).
 __global__ __launch_bounds__(kBcBlock) void k_bc_finalize(
@@ -198,6 +322,39 @@ hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t
   const BcDependency f{depth, sigma, acc, prev_depth};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
                        nullptr, cfg, st);
+}
+
+hipError_t launch_bc_pull(bool dependency, const int32_t* frontier, const int32_t* offsets,
+                          const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
+                          int64_t m_f, int chunk, const int32_t* C, const int32_t* depth,
+                          int32_t want, double* sigma, double* acc, hipStream_t st) {
+  if (n_f <= 0 || m_f <= 0) return hipSuccess;
+  const unsigned g = blocks_of(m_f, chunk);
+#define GR_BC_PULL(CH)                                                                          \
+  case CH: {                                                                                    \
+    constexpr int ept = (CH / kBcBlock) < 16 ? (CH / kBcBlock) : 16;                            \
+    constexpr int nb = CH / (kBcBlock * ept);                                                   \
+    if (dependency)                                                                             \
+      k_bc_pull_lb<BcDependencyVal, ept, nb><<<g, kBcBlock, 0, st>>>(                           \
+          frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f, C, depth, want,   \
+          BcDependencyVal{sigma, acc}, acc);                                                    \
+    else                                                                                        \
+      k_bc_pull_lb<BcSigmaVal, ept, nb><<<g, kBcBlock, 0, st>>>(                                \
+          frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f, C, depth, want,   \
+          BcSigmaVal{sigma}, sigma);                                                            \
+    break;                                                                                      \
+  }
+  switch (chunk) {
+    GR_BC_PULL(512)
+    GR_BC_PULL(1024)
+    GR_BC_PULL(2048)
+    GR_BC_PULL(4096)
+    GR_BC_PULL(16384)
+    default:
+      GR_BC_PULL(8192)
+  }
+#undef GR_BC_PULL
+  return hipGetLastError();
 }
 
 hipError_t launch_bc_finalize(const int32_t* depth, const double* sigma, const double* acc,

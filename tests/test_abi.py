@@ -21,7 +21,7 @@ def header_functions():
 
 def test_library_loads_and_version():
     L = gr.lib()
-    assert L.gr_abi_version() == 5
+    assert L.gr_abi_version() == 6
 
 
 def test_every_declared_symbol_is_exported_and_bound():

@@ -4,7 +4,7 @@ passes) against the float64 CPU oracle, element by element.
 Tolerance: both sides compute in IEEE double.  Path counts are integers and
 exact while below 2^53, so sigma is compared exactly on these graphs.  The
 dependencies are sums of positive terms taken in a different order (the GPU
-adds them with atomics, the oracle in adjacency order); each term carries a
+adds them with atomics or per-row reductions, the oracle in adjacency order); each term carries a
 few roundings and the sums chain over the levels, so the relative error stays
 below (levels + largest degree) * 4 * 2^-53 < 1e-9 here; the test allows
 rtol 1e-9 against max(1, |expected|)."""
@@ -28,7 +28,16 @@ POLICIES = [
     ("light_only", dict(lb_light_threshold=1 << 30)),
     ("twc_levels", dict(lb_min_avg_degree=math.inf)),
     ("pull_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_LB)),
+    # both passes in push form (fp64 atomics onto the other end of each edge)
+    ("push_passes", dict(bc_push=gr.BC_PUSH_SIGMA | gr.BC_PUSH_DEP)),
+    ("push_sigma_light", dict(bc_push=gr.BC_PUSH_SIGMA, lb_light_threshold=1 << 30)),
+    ("push_dep_twc", dict(bc_push=gr.BC_PUSH_DEP, policy=gr.POLICY_FIXED,
+                          fixed_action=gr.PUSH_TWC)),
+    # pull chunks: 16384 edges take four batches per workgroup and, on rows of a
+    # few edges, more rows than one LDS stage holds
+    ("pull_chunk16384", dict(lb_chunk=16384)),
 ]
+PUSH_PULL = [POLICIES[0], POLICIES[2], POLICIES[7], POLICIES[10]]
 
 
 @pytest.fixture(scope="module")
@@ -77,7 +86,7 @@ def test_grid_sigma_closed_form(ctx):
 
 def test_er_and_union(ctx):
     er = gg.erdos_renyi(20001, 6, seed=3)
-    check_graph(ctx, er, [[int(x) for x in gg.sources(er, 3, seed=4)]], policies=POLICIES[:3])
+    check_graph(ctx, er, [[int(x) for x in gg.sources(er, 3, seed=4)]], policies=PUSH_PULL)
     parts = [gg.rmat(s, 8, seed=10 + s) for s in (7, 9, 10)]
     u, voff = gg.disjoint_union(parts)
     check_graph(ctx, u, [[int(voff[0]) + 1, int(voff[1]) + 2, int(voff[2]) + 3]],
@@ -136,4 +145,4 @@ def test_rmat20_two_sources(ctx):
     hg = gg.rmat(20, 16, seed=1)
     srcs = [int(x) for x in gg.sources(hg, 2, seed=3000)]
     print(f"bc rmat20 V={hg.n_vertices} E={hg.n_edges} sources={srcs}", flush=True)
-    check_graph(ctx, hg, [srcs], policies=POLICIES[:1], renumber=(False,))
+    check_graph(ctx, hg, [srcs], policies=[POLICIES[0], POLICIES[7]], renumber=(False,))
