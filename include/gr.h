@@ -176,16 +176,21 @@ typedef struct gr_opts {
   int32_t trace_steps_off;   /* with trace: 1 = time only each iteration's advance kernel
                                 (kernel_us; step_us left 0), which saves two event records per
                                 iteration; 0 = time both (the selector's training data) */
-  int32_t bc_push;           /* gr_bc: passes run in push form (each edge adds into the sum of
-                                its other end with an fp64 atomic), a bit set of GR_BC_PUSH_*;
-                                the other passes gather each vertex's sum over its own row.
+  int32_t bc_dir;            /* gr_bc: how each pass crosses a pair of adjacent levels, a
+                                GR_BC_DIR_* for the forward pass | another << 2 for the backward
+                                pass.  Push: the level the sums come from sweeps its rows and
+                                adds into the other end of each edge with an fp64 atomic; pull:
+                                the level the sums belong to sweeps its own rows and gathers
+                                them (no atomic per edge).  Auto: per pair, push where the
+                                level the sums come from has under a quarter of the other
+                                level's edges and under 64 edges per vertex of it, else pull.
                                 Same results up to the order of the additions. */
 } gr_opts;
 
-/* gr_opts.bc_push bits */
-#define GR_BC_PUSH_SIGMA 1  /* forward pass: each level adds sigma into its successors */
-#define GR_BC_PUSH_DEP 2    /* backward pass: each level adds its payload into its
-                               predecessors' dependency sums */
+/* gr_opts.bc_dir values, per pass */
+#define GR_BC_DIR_AUTO 0
+#define GR_BC_DIR_PUSH 1
+#define GR_BC_DIR_PULL 2
 
 /* gr_opts.sssp_opt_off bits */
 #define GR_SSSP_OPT_CULL 1  /* drop from the next frontier a vertex whose edges this iteration
@@ -377,10 +382,12 @@ gr_status gr_sssp_multi(gr_ctx* ctx, const gr_graph* graph, const int32_t* sourc
  * normalisation).  sigma: device double[V] or NULL; with exactly one source it
  * receives sigma_sv (the number of shortest paths from the source to v; 0 if
  * unreached, 1 at the source).  Arithmetic in double precision; sums are
- * accumulated with atomic adds, so the last bits may vary from run to run.
- * Each source runs one gr_bfs with `opts` (its policy and knobs; tracing and
- * max_iterations are ignored), then one push advance per level in each
- * direction.  Needs GR_SYMMETRIC (GR_EUNSUPPORTED otherwise).  stats:
+ * accumulated with atomic adds in an order that varies, so the last bits may
+ * vary from run to run.  Each source runs one gr_bfs with `opts` (its policy
+ * and knobs; tracing and max_iterations are ignored), then one advance per
+ * pair of adjacent levels in each pass, pushed or pulled as opts->bc_dir says,
+ * over LB chunks of lb_chunk edges (TWC for a pushed level where the average
+ * degree is below lb_min_avg_degree).  Needs GR_SYMMETRIC (GR_EUNSUPPORTED otherwise).  stats:
  * iterations and teps_edges summed over the sources' BFS runs; device_ms for
  * the whole call. */
 gr_status gr_bc(gr_ctx* ctx, const gr_graph* graph, const int32_t* sources, int32_t n_sources,

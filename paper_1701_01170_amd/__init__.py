@@ -36,7 +36,7 @@ SYMMETRIC, DEVICE_INPUT, RENUMBER = 0x1, 0x2, 0x4
 BFS_FILTER_AUTO, BFS_FILTER_ATOMIC, BFS_FILTER_IDEMPOTENT = 0, 1, 2
 IDEM_CULL_WAVE, IDEM_CULL_HISTORY, IDEM_CULL_LABEL = 0x1, 0x2, 0x4
 SSSP_OPT_CULL, SSSP_OPT_BINS = 0x1, 0x2
-BC_PUSH_SIGMA, BC_PUSH_DEP = 0x1, 0x2
+BC_DIR_AUTO, BC_DIR_PUSH, BC_DIR_PULL = 0, 1, 2
 MLP_N_PARAMS = 1476
 
 
@@ -69,7 +69,7 @@ class Opts(ctypes.Structure):
                 ("adv_block", ctypes.c_int32), ("twc_wave_min", ctypes.c_int32),
                 ("twc_block_min", ctypes.c_int32), ("graph_blocks", ctypes.c_int32),
                 ("sssp_opt_off", ctypes.c_int32), ("sssp_multi_sweep", ctypes.c_int32),
-                ("trace_steps_off", ctypes.c_int32), ("bc_push", ctypes.c_int32)]
+                ("trace_steps_off", ctypes.c_int32), ("bc_dir", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):

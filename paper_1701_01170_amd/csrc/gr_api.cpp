@@ -596,8 +596,8 @@ gr_status check_opts(gr_opts* opts, gr_opts* local) {
     return fail(GR_EINVAL, "opts->sssp_multi_sweep must be 0 or 1");
   if (opts->trace_steps_off != 0 && opts->trace_steps_off != 1)
     return fail(GR_EINVAL, "opts->trace_steps_off must be 0 or 1");
-  if (opts->bc_push & ~(GR_BC_PUSH_SIGMA | GR_BC_PUSH_DEP))
-    return fail(GR_EINVAL, "opts->bc_push: unknown bits");
+  if (opts->bc_dir < 0 || opts->bc_dir > 15 || (opts->bc_dir & 3) == 3 || (opts->bc_dir >> 2) == 3)
+    return fail(GR_EINVAL, "opts->bc_dir: each pass takes GR_BC_DIR_AUTO, _PUSH or _PULL");
   if (opts->bfs_filter < GR_BFS_FILTER_AUTO || opts->bfs_filter > GR_BFS_FILTER_IDEMPOTENT)
     return fail(GR_EINVAL, "opts->bfs_filter out of range");
   if (opts->idem_culls_off & ~(int32_t)(GR_IDEM_CULL_WAVE | GR_IDEM_CULL_HISTORY | GR_IDEM_CULL_LABEL))
@@ -1915,10 +1915,20 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   const AdvCfg adv = adv_cfg(opts);
   const int chunk = adv.chunk;
   const bool lb = (double)E / (double)V >= (double)opts.lb_min_avg_degree;
-  const bool push_sigma = (opts.bc_push & GR_BC_PUSH_SIGMA) != 0;
-  const bool push_dep = (opts.bc_push & GR_BC_PUSH_DEP) != 0;
+  const int dir_sigma = opts.bc_dir & 3, dir_dep = opts.bc_dir >> 2;
+  // push when forced, or (auto) when the level the sums come from has under
+  // 1 / kBcPushBias of the edges of the level they belong to and under
+  // kBcPushFanIn edges per vertex of that level: a pushed edge costs about
+  // what a pulled one does until many of them add into the same few
+  // vertices, whose fp64 atomics then queue one behind another
+  constexpr unsigned long long kBcPushBias = 4, kBcPushFanIn = 64;
+  auto use_push = [](int dir, unsigned long long m_from, unsigned long long m_to,
+                     unsigned long long n_to) {
+    if (dir != GR_BC_DIR_AUTO) return dir == GR_BC_DIR_PUSH;
+    return m_from * kBcPushBias < m_to && m_from < n_to * kBcPushFanIn;
+  };
 
-  int32_t *depth, *levels, *offsets, *rstart, *chunks;
+  int32_t *depth, *levels, *offsets, *rstart, *chunks, *all_offs, *all_rstart;
   double *sig, *acc;
   uint32_t* lvl_n;
   unsigned long long* lvl_m;
@@ -1933,6 +1943,8 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
   GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
   GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
+  GR_TRY(pool_typed(ctx, S_BC_OFFS, V + 1, &all_offs));
+  GR_TRY(pool_typed(ctx, S_BC_RSTART, V, &all_rstart));
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, stats_grid() + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
 
@@ -1944,13 +1956,14 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   std::vector<uint32_t> hn;
   std::vector<unsigned long long> hm;
   std::vector<uint32_t> off;
-  // a level's workload mapping (as the heuristic picks it for a push level,
-  // always LB for a pull), with the degree scan queued first when it balances
-  // edges
+  std::vector<int64_t> tab;
+  // a pushed level's workload mapping: LB chunks (TWC where the average
+  // degree is below lb_min_avg_degree), with the degree scan queued first for
+  // LB
   int sp = 0;
-  auto prepare_level = [&](int64_t n, const int32_t* front, const uint32_t* n_dev, bool pull,
+  auto prepare_level = [&](const int32_t* front, const uint32_t* n_dev, int64_t n,
                            int* mode) -> gr_status {
-    *mode = pull ? 2 : !lb ? 0 : (n < opts.lb_light_threshold ? 1 : 2);
+    *mode = lb ? 2 : 0;
     if (*mode == 2) {
       GR_HIP(launch_frontier_stats(front, n_dev, g->R, bsums, ctrl, sp, nullptr, nullptr, st));
       GR_HIP(launch_frontier_offsets(front, n, g->R, bsums, &ctrl->m_f[sp], offsets, rstart, chunks,
@@ -1975,40 +1988,75 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
     GR_HIP(hipMemcpyAsync(hm.data(), lvl_m, sizeof(unsigned long long) * L, hipMemcpyDeviceToHost,
                           st));
     GR_HIP(hipStreamSynchronize(st));
-    for (int32_t d = 0; d < L; ++d) off[d + 1] = off[d] + hn[d];
+    // per level: first vertex index, first edge position and first chunk of
+    // the pull passes' maps (levels stored one after another)
+    tab.assign(3 * (size_t)L, 0);
+    for (int32_t d = 0; d < L; ++d) {
+      off[d + 1] = off[d] + hn[d];
+      tab[d] = off[d];
+      if (d + 1 < L) {
+        tab[L + d + 1] = tab[L + d] + (int64_t)hm[d];
+        tab[2 * L + d + 1] = tab[2 * L + d] + ((int64_t)hm[d] + chunk - 1) / chunk;
+      }
+    }
+    const int64_t n_r = off[L];
+    const int64_t n_chunks = tab[2 * L + L - 1] + ((int64_t)hm[L - 1] + chunk - 1) / chunk;
+    int64_t* tab_dev;
+    int32_t* bc_chunks;
+    GR_TRY(pool_typed(ctx, S_BC_TAB, tab.size(), &tab_dev));
+    GR_TRY(pool_typed(ctx, S_BC_CHUNKS, (size_t)n_chunks + 1, &bc_chunks));
     GR_HIP(hipMemcpyAsync(lvl_n + L, off.data(), sizeof(uint32_t) * L, hipMemcpyHostToDevice, st));
+    GR_HIP(hipMemcpyAsync(tab_dev, tab.data(), sizeof(int64_t) * tab.size(), hipMemcpyHostToDevice,
+                          st));
     GR_HIP(launch_bc_scatter(depth, V, L, lvl_n + L, levels, st));
     GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
     sp = 0;
+    // the pull passes' LB maps for all levels at once: one degree scan over
+    // the reached vertices in level order (its chunk output is not used: the
+    // chunk size given puts every edge in chunk 0 or 1), then every level's
+    // chunk map (the last level's cursor ends at n_r)
+    GR_HIP(launch_frontier_stats(levels, lvl_n + L + L - 1, g->R, bsums, ctrl, sp, nullptr, nullptr,
+                                 st));
+    GR_HIP(launch_frontier_offsets(levels, n_r, g->R, bsums, &ctrl->m_f[sp], all_offs, all_rstart,
+                                   chunks, 1 << 30, st));
+    sp ^= 1;
+    GR_HIP(launch_bc_chunk_map(levels, depth, n_r, all_offs, tab_dev, L, chunk, bc_chunks, st));
+    auto pull_level = [&](bool dependency, int32_t x, int32_t want) -> hipError_t {
+      return launch_bc_pull(dependency, levels + off[x], all_offs + off[x], all_rstart + off[x],
+                            bc_chunks + tab[2 * L + x], hn[x], (int64_t)hm[x], tab[L + x], chunk,
+                            g->C, depth, want, sig, acc, st);
+    };
     // forward: sigma of level d + 1 from level d, pushed by level d or
     // gathered by level d + 1
     for (int32_t d = 0; d + 1 < L; ++d) {
-      const int32_t x = push_sigma ? d : d + 1;  // the level whose rows are swept
+      const bool push = use_push(dir_sigma, hm[d], hm[d + 1], hn[d + 1]);
+      const int32_t x = push ? d : d + 1;  // the level whose rows are swept
       if (hm[x] == 0) continue;
-      const int32_t* front = levels + off[x];
-      int mode = 0;
-      GR_TRY(prepare_level(hn[x], front, lvl_n + x, !push_sigma, &mode));
-      if (push_sigma)
+      if (push) {
+        const int32_t* front = levels + off[x];
+        int mode = 0;
+        GR_TRY(prepare_level(front, lvl_n + x, hn[x], &mode));
         GR_HIP(launch_bc_sigma(mode, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], g->R,
                                g->C, depth, sig, d + 1, adv, st));
-      else
-        GR_HIP(launch_bc_pull(false, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], chunk,
-                              g->C, depth, d, sig, acc, st));
+      } else {
+        GR_HIP(pull_level(false, x, d));
+      }
     }
     // backward: dependency sums of level d - 1 from level d, pushed by level d
     // or gathered by level d - 1 (the source's own sum is not needed)
-    for (int32_t d = L - 1; d >= (push_dep ? 1 : 2); --d) {
-      const int32_t x = push_dep ? d : d - 1;
+    for (int32_t d = L - 1; d >= 2; --d) {
+      const bool push = use_push(dir_dep, hm[d], hm[d - 1], hn[d - 1]);
+      const int32_t x = push ? d : d - 1;
       if (hm[x] == 0) continue;
-      const int32_t* front = levels + off[x];
-      int mode = 0;
-      GR_TRY(prepare_level(hn[x], front, lvl_n + x, !push_dep, &mode));
-      if (push_dep)
+      if (push) {
+        const int32_t* front = levels + off[x];
+        int mode = 0;
+        GR_TRY(prepare_level(front, lvl_n + x, hn[x], &mode));
         GR_HIP(launch_bc_dependency(mode, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x],
                                     g->R, g->C, depth, sig, acc, d - 1, adv, st));
-      else
-        GR_HIP(launch_bc_pull(true, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], chunk,
-                              g->C, depth, d, sig, acc, st));
+      } else {
+        GR_HIP(pull_level(true, x, d));
+      }
     }
     GR_HIP(launch_bc_finalize(depth, sig, acc, V, src, g->perm, bc, sigma, st));
     // the host vectors are reused by the next source: finish their copies

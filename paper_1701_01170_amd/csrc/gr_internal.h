@@ -78,6 +78,10 @@ enum Slot : int {
   S_BC_LEVELS,     // vertices grouped by level [V]
   S_BC_LVL_N,      // vertices per level, then level cursors [L + 1]
   S_BC_LVL_M,      // degree sum per level [L + 1]
+  S_BC_OFFS,       // exclusive scan of the degrees of all levels' vertices [V + 1]
+  S_BC_RSTART,     // row start of every vertex in level order [V]
+  S_BC_CHUNKS,     // per-level LB chunk -> first-row maps, level after level
+  S_BC_TAB,        // per level: first vertex index, first edge position, first chunk [3 L]
   S_MS_KEYS,       // batched SSSP: packed keys, KS per vertex [V * KS]
   S_MS_AMASK,      // batched SSSP: sources a frontier vertex is active for [V]
   S_MS_NMASK,      // batched SSSP: sources whose distance dropped this iteration [V]
@@ -327,13 +331,21 @@ hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t
                                 int64_t m_f, const int32_t* R, const int32_t* C,
                                 const int32_t* depth, const double* sigma, double* acc,
                                 int32_t prev_depth, const AdvCfg& cfg, hipStream_t st);
+// per-level chunk maps of the pull passes for every level at once (offsets:
+// the degree scan over all n_r vertices in level order; tab: per level its
+// first vertex index, first edge position and first chunk, 3 * n_levels)
+hipError_t launch_bc_chunk_map(const int32_t* levels, const int32_t* depth, int64_t n_r,
+                               const int32_t* offsets, const int64_t* tab, int32_t n_levels,
+                               int32_t chunk, int32_t* chunk_map, hipStream_t st);
 // pull form of either pass over one level with the LB mapping of `chunk` edges
 // (dependency: acc of the level from its successors at depth `want`;
-// otherwise sigma of the level from its predecessors at depth `want`)
+// otherwise sigma of the level from its predecessors at depth `want`); the
+// level's edges sit at positions e_base .. e_base + m_f - 1 of `offsets`
 hipError_t launch_bc_pull(bool dependency, const int32_t* frontier, const int32_t* offsets,
                           const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
-                          int64_t m_f, int chunk, const int32_t* C, const int32_t* depth,
-                          int32_t want, double* sigma, double* acc, hipStream_t st);
+                          int64_t m_f, int64_t e_base, int chunk, const int32_t* C,
+                          const int32_t* depth, int32_t want, double* sigma, double* acc,
+                          hipStream_t st);
 hipError_t launch_bc_finalize(const int32_t* depth, const double* sigma, const double* acc,
                               int64_t V, int32_t source, const int32_t* perm, double* bc,
                               double* sigma_out, hipStream_t st);

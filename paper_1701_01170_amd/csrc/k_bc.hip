@@ -193,8 +193,8 @@ template <class Val, int EPT, int NB>
 __global__ __launch_bounds__(kBcBlock) void k_bc_pull_lb(
     const int32_t* __restrict__ frontier, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ rstart, const int32_t* __restrict__ chunk_start, int32_t n_f,
-    int32_t m_f, const int32_t* __restrict__ C, const int32_t* __restrict__ depth, int32_t want,
-    Val val, double* __restrict__ out) {
+    int32_t m_f, int64_t e_base, const int32_t* __restrict__ C, const int32_t* __restrict__ depth,
+    int32_t want, Val val, double* __restrict__ out) {
   constexpr int BATCH = kBcBlock * EPT;
   constexpr int N = BATCH * NB;
   constexpr int SPT = N / kBcBlock;
@@ -207,8 +207,8 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_pull_lb(
   __shared__ double s_sum[CAP];
   __shared__ int32_t s_tmp[kBcBlock / kWave + 1];
   const int c = blockIdx.x;
-  const int64_t e0 = (int64_t)c * N;
-  const int64_t e1 = e0 + N < m_f ? e0 + N : m_f;
+  const int64_t e0 = e_base + (int64_t)c * N;
+  const int64_t e1 = e0 + N < e_base + m_f ? e0 + N : e_base + m_f;
   const int nchunks = (int)(((int64_t)m_f + N - 1) / N);
   const int sb = chunk_start[c];
   const int se = c + 1 < nchunks ? chunk_start[c + 1] : n_f - 1;
@@ -270,6 +270,27 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_pull_lb(
   }
 }
 
+// The chunk -> first-row maps of the pull passes for every level in one
+// launch.  The n_r reached vertices are stored level after level (`levels`)
+// and `offsets` is one exclusive scan of their degrees over all of them, so
+// level x's rows are vertex indexes tab[x] .. and its edges positions
+// tab[L + x] ..; its chunks of `chunk` edges, counted from its first edge, are
+// entries tab[2L + x] .. of chunk_map, each set to the level-local index of
+// the row holding the chunk's first edge (the sorted search of 0, N, 2N, ...
+// done by scattering from the rows).
+__global__ __launch_bounds__(kBcBlock) void k_bc_chunk_map(
+    const int32_t* __restrict__ levels, const int32_t* __restrict__ depth, int64_t n_r,
+    const int32_t* __restrict__ offsets, const int64_t* __restrict__ tab, int32_t L,
+    int32_t chunk, int32_t* __restrict__ chunk_map) {
+  const int64_t i = (int64_t)blockIdx.x * kBcBlock + threadIdx.x;
+  if (i >= n_r) return;
+  const int32_t x = depth[levels[i]];
+  const int64_t o = (int64_t)offsets[i] - tab[L + x];
+  const int64_t d = (int64_t)offsets[i + 1] - offsets[i];
+  int32_t* map = chunk_map + tab[2 * L + x];
+  for (int64_t c = (o + chunk - 1) / chunk; c * chunk < o + d; ++c) map[c] = (int32_t)(i - tab[x]);
+}
+
 // bc(v) += delta(v) = sigma(v) * acc(v) for reached v != source; sigma out
 // (nullable) for the caller.  Outputs at caller ids (perm nullable).
 __global__ __launch_bounds__(kBcBlock) void k_bc_finalize(
@@ -324,10 +345,20 @@ hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t
                        nullptr, cfg, st);
 }
 
+hipError_t launch_bc_chunk_map(const int32_t* levels, const int32_t* depth, int64_t n_r,
+                               const int32_t* offsets, const int64_t* tab, int32_t n_levels,
+                               int32_t chunk, int32_t* chunk_map, hipStream_t st) {
+  if (n_r <= 0) return hipSuccess;
+  k_bc_chunk_map<<<blocks_of(n_r, kBcBlock), kBcBlock, 0, st>>>(levels, depth, n_r, offsets, tab,
+                                                                n_levels, chunk, chunk_map);
+  return hipGetLastError();
+}
+
 hipError_t launch_bc_pull(bool dependency, const int32_t* frontier, const int32_t* offsets,
                           const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
-                          int64_t m_f, int chunk, const int32_t* C, const int32_t* depth,
-                          int32_t want, double* sigma, double* acc, hipStream_t st) {
+                          int64_t m_f, int64_t e_base, int chunk, const int32_t* C,
+                          const int32_t* depth, int32_t want, double* sigma, double* acc,
+                          hipStream_t st) {
   if (n_f <= 0 || m_f <= 0) return hipSuccess;
   const unsigned g = blocks_of(m_f, chunk);
 #define GR_BC_PULL(CH)                                                                          \
@@ -336,12 +367,12 @@ hipError_t launch_bc_pull(bool dependency, const int32_t* frontier, const int32_
     constexpr int nb = CH / (kBcBlock * ept);                                                   \
     if (dependency)                                                                             \
       k_bc_pull_lb<BcDependencyVal, ept, nb><<<g, kBcBlock, 0, st>>>(                           \
-          frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f, C, depth, want,   \
-          BcDependencyVal{sigma, acc}, acc);                                                    \
+          frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f, e_base, C, depth, \
+          want, BcDependencyVal{sigma, acc}, acc);                                              \
     else                                                                                        \
       k_bc_pull_lb<BcSigmaVal, ept, nb><<<g, kBcBlock, 0, st>>>(                                \
-          frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f, C, depth, want,   \
-          BcSigmaVal{sigma}, sigma);                                                            \
+          frontier, offsets, rstart, chunk_start, (int32_t)n_f, (int32_t)m_f, e_base, C, depth, \
+          want, BcSigmaVal{sigma}, sigma);                                                      \
     break;                                                                                      \
   }
   switch (chunk) {

@@ -28,16 +28,18 @@ POLICIES = [
     ("light_only", dict(lb_light_threshold=1 << 30)),
     ("twc_levels", dict(lb_min_avg_degree=math.inf)),
     ("pull_lb", dict(policy=gr.POLICY_FIXED, fixed_action=gr.PULL_LB)),
-    # both passes in push form (fp64 atomics onto the other end of each edge)
-    ("push_passes", dict(bc_push=gr.BC_PUSH_SIGMA | gr.BC_PUSH_DEP)),
-    ("push_sigma_light", dict(bc_push=gr.BC_PUSH_SIGMA, lb_light_threshold=1 << 30)),
-    ("push_dep_twc", dict(bc_push=gr.BC_PUSH_DEP, policy=gr.POLICY_FIXED,
-                          fixed_action=gr.PUSH_TWC)),
-    # pull chunks: 16384 edges take four batches per workgroup and, on rows of a
-    # few edges, more rows than one LDS stage holds
-    ("pull_chunk16384", dict(lb_chunk=16384)),
+    # per-pass directions (forward | backward << 2): both pushed (fp64 atomics
+    # onto the other end of each edge), both pulled, and mixed
+    ("push_both", dict(bc_dir=gr.BC_DIR_PUSH | gr.BC_DIR_PUSH << 2)),
+    ("pull_both", dict(bc_dir=gr.BC_DIR_PULL | gr.BC_DIR_PULL << 2)),
+    ("push_fwd_twc", dict(bc_dir=gr.BC_DIR_PUSH | gr.BC_DIR_PULL << 2,
+                          lb_min_avg_degree=math.inf)),
+    # pull chunks of 16384 edges take four batches per workgroup and, on rows
+    # of a few edges, more rows than one LDS stage holds
+    ("pull_chunk16384", dict(bc_dir=gr.BC_DIR_PULL | gr.BC_DIR_PULL << 2, lb_chunk=16384)),
+    ("push_bwd_chunk512", dict(bc_dir=gr.BC_DIR_AUTO | gr.BC_DIR_PUSH << 2, lb_chunk=512)),
 ]
-PUSH_PULL = [POLICIES[0], POLICIES[2], POLICIES[7], POLICIES[10]]
+PUSH_PULL = [POLICIES[0], POLICIES[7], POLICIES[8], POLICIES[10]]
 
 
 @pytest.fixture(scope="module")
@@ -145,4 +147,4 @@ def test_rmat20_two_sources(ctx):
     hg = gg.rmat(20, 16, seed=1)
     srcs = [int(x) for x in gg.sources(hg, 2, seed=3000)]
     print(f"bc rmat20 V={hg.n_vertices} E={hg.n_edges} sources={srcs}", flush=True)
-    check_graph(ctx, hg, [srcs], policies=[POLICIES[0], POLICIES[7]], renumber=(False,))
+    check_graph(ctx, hg, [srcs], policies=[POLICIES[0], POLICIES[7], POLICIES[8]], renumber=(False,))
