@@ -432,15 +432,19 @@ def bc_rmat22(gr, g, sources) -> dict:
     """Betweenness centrality (gr_bc, Brandes's two passes on the advance
     operator) from each source alone and from all of them in one call: device
     time and the rate over the reached vertices' edges per source (teps_edges
-    of the stats), which the forward and the backward pass each push over."""
-    gr.bc(g, [int(sources[0])])  # warm-up
+    of the stats; each pass then sweeps, per pair of adjacent levels, the rows
+    of one of the two), with the autotuner's knobs for BC."""
+    from paper_1701_01170_amd import autotune
+    o = autotune.tuned_opts(g, "bc")
+    gr.bc(g, [int(sources[0])], opts=o)  # warm-up
     ms, te = [], 0
     for s in sources:
-        st = gr.bc(g, [int(s)])[2]
+        st = gr.bc(g, [int(s)], opts=o)[2]
         ms.append(st["device_ms"])
         te += st["teps_edges"]
-    allst = gr.bc(g, [int(s) for s in sources])[2]
-    return {"sources": len(sources), "median_ms_per_source": round(statistics.median(ms), 4),
+    allst = gr.bc(g, [int(s) for s in sources], opts=o)[2]
+    return {"sources": len(sources), "knobs": {"lb_chunk": o.lb_chunk, "adv_block": o.adv_block},
+            "median_ms_per_source": round(statistics.median(ms), 4),
             "gteps": _gteps(te, sum(ms)),
             "all_sources_one_call_ms": round(allst["device_ms"], 4),
             "all_sources_one_call_gteps": _gteps(allst["teps_edges"], allst["device_ms"])}

@@ -24,7 +24,10 @@ Batched BFS ("bfs_multi", 64 sources per call) searches 1, 2, 3 and its
 push -> pull switch do_a in {1/4 .. 1/64}; batched SSSP ("sssp_multi", 16
 sources per call) its chunk {512, 1024, 2048} and sssp_delta {0, 2, ..., 64}
 with the sources sharing each sweep, then one sweep per source
-(sssp_multi_sweep = 1) with the stored single-source knobs.
+(sssp_multi_sweep = 1) with the stored single-source knobs.  Betweenness
+centrality ("bc", one source per call) starts from the stored BFS knobs,
+searches 2 and 3 for its passes over the levels, then 8 (without bfs_filter)
+and 7 for its BFS, which keeps no parents.
 The graphs are degree-renumbered on ingest (GR_RENUMBER) unless --no-renumber
 is given: the stored knobs serve the layout the benchmark uses.
 
@@ -43,7 +46,7 @@ import time
 
 import numpy as np
 
-from . import Graph, default_opts, bfs, bfs_multi, sssp, sssp_multi  # noqa: F401
+from . import Graph, default_opts, bc, bfs, bfs_multi, sssp, sssp_multi  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
@@ -122,6 +125,8 @@ def _time(g: Graph, kind: str, sources, knobs: dict, reps: int = 1) -> float:
         for _ in range(reps + 1):
             if kind == "bfs":
                 _, _, st = bfs(g, int(s), opts=o)
+            elif kind == "bc":
+                _, _, st = bc(g, [int(s)], opts=o)
             else:
                 _, _, st = sssp(g, [int(s)], opts=o)
             best = min(best, st["device_ms"])
@@ -166,6 +171,29 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
             log(f"[{kind}] one source per sweep with the single-source knobs: {ms:.3f} ms")
             if ms < best_ms * 0.99:
                 best, best_ms = cand, ms
+        return best, best_ms, base_ms
+    if kind == "bc":
+        # the BFS of each source runs with the stored BFS knobs; the passes
+        # over the levels search their LB chunk and workgroup size
+        single = lookup(g, "bfs")
+        if single:
+            cand = dict(best, **{k: v for k, v in single.items() if k in KNOBS})
+            ms = _time(g, kind, sources, cand)
+            log(f"[{kind}] the BFS knobs: {ms:.3f} ms")
+            if ms < best_ms * 0.99:
+                best, best_ms = cand, ms
+        try_set("lb_chunk", [512, 1024, 2048, 4096, 8192, 16384])
+        try_set("adv_block", ADV_BLOCK)
+        # its BFS keeps depths only (no parents), so its direction switch
+        # and level blocks are searched again
+        for a in DO_A:
+            for b in DO_B:
+                cand = dict(best, do_a=a, do_b=b)
+                ms = _time(g, kind, sources, cand)
+                log(f"[{kind}] do_a=1/{1 / a:.0f} do_b=1/{1 / b:.0f}: {ms:.3f} ms")
+                if ms < best_ms * 0.99:
+                    best, best_ms = cand, ms
+        try_set("device_max_edges", DEVICE_MAX_EDGES)
         return best, best_ms, base_ms
     try_set("lb_light_threshold", [0, 1024, 4096])
     try_set("lb_chunk", [512, 1024, 2048, 4096, 8192, 16384])

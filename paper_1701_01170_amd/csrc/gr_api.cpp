@@ -1928,7 +1928,7 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
     return m_from * kBcPushBias < m_to && m_from < n_to * kBcPushFanIn;
   };
 
-  int32_t *depth, *levels, *offsets, *rstart, *chunks, *all_offs, *all_rstart;
+  int32_t *depth, *levels, *chunks, *all_offs, *all_rstart;
   double *sig, *acc;
   uint32_t* lvl_n;
   unsigned long long* lvl_m;
@@ -1940,11 +1940,10 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   GR_TRY(pool_typed(ctx, S_BC_LEVELS, V, &levels));
   GR_TRY(pool_typed(ctx, S_BC_LVL_N, 2 * (size_t)(V + 1), &lvl_n));  // counts, then cursors
   GR_TRY(pool_typed(ctx, S_BC_LVL_M, V + 1, &lvl_m));
-  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &offsets));
-  GR_TRY(pool_typed(ctx, S_RSTART, V, &rstart));
+  // degree scan and row starts of all levels' vertices (level order)
+  GR_TRY(pool_typed(ctx, S_OFFSETS, V + 1, &all_offs));
+  GR_TRY(pool_typed(ctx, S_RSTART, V, &all_rstart));
   GR_TRY(pool_typed(ctx, S_CHUNKS, E / 512 + 2, &chunks));
-  GR_TRY(pool_typed(ctx, S_BC_OFFS, V + 1, &all_offs));
-  GR_TRY(pool_typed(ctx, S_BC_RSTART, V, &all_rstart));
   GR_TRY(pool_typed(ctx, S_BLOCK_SUMS, stats_grid() + 1, &bsums));
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
 
@@ -1957,21 +1956,7 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
   std::vector<unsigned long long> hm;
   std::vector<uint32_t> off;
   std::vector<int64_t> tab;
-  // a pushed level's workload mapping: LB chunks (TWC where the average
-  // degree is below lb_min_avg_degree), with the degree scan queued first for
-  // LB
   int sp = 0;
-  auto prepare_level = [&](const int32_t* front, const uint32_t* n_dev, int64_t n,
-                           int* mode) -> gr_status {
-    *mode = lb ? 2 : 0;
-    if (*mode == 2) {
-      GR_HIP(launch_frontier_stats(front, n_dev, g->R, bsums, ctrl, sp, nullptr, nullptr, st));
-      GR_HIP(launch_frontier_offsets(front, n, g->R, bsums, &ctrl->m_f[sp], offsets, rstart, chunks,
-                                     chunk, st));
-      sp ^= 1;
-    }
-    return GR_OK;
-  };
   for (int32_t i = 0; i < n_sources; ++i) {
     gr_run_stats bs{};
     GR_TRY(bfs_run(ctx, g, sources[i], depth, nullptr, nullptr, opts, st, &bs, ar,
@@ -2011,20 +1996,33 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
     GR_HIP(launch_bc_scatter(depth, V, L, lvl_n + L, levels, st));
     GR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(&ctrl->m_f[0]), 8, 0u, st));  // m_f, max_deg
     sp = 0;
-    // the pull passes' LB maps for all levels at once: one degree scan over
-    // the reached vertices in level order (its chunk output is not used: the
-    // chunk size given puts every edge in chunk 0 or 1), then every level's
-    // chunk map (the last level's cursor ends at n_r)
+    // the LB maps of all levels at once: one degree scan over the reached
+    // vertices in level order (its chunk output is not used: the chunk size
+    // given puts every edge in chunk 0 or 1), then every level's chunk map
+    // (the last level's cursor ends at n_r)
     GR_HIP(launch_frontier_stats(levels, lvl_n + L + L - 1, g->R, bsums, ctrl, sp, nullptr, nullptr,
                                  st));
     GR_HIP(launch_frontier_offsets(levels, n_r, g->R, bsums, &ctrl->m_f[sp], all_offs, all_rstart,
                                    chunks, 1 << 30, st));
     sp ^= 1;
     GR_HIP(launch_bc_chunk_map(levels, depth, n_r, all_offs, tab_dev, L, chunk, bc_chunks, st));
-    auto pull_level = [&](bool dependency, int32_t x, int32_t want) -> hipError_t {
-      return launch_bc_pull(dependency, levels + off[x], all_offs + off[x], all_rstart + off[x],
-                            bc_chunks + tab[2 * L + x], hn[x], (int64_t)hm[x], tab[L + x], chunk,
-                            g->C, depth, want, sig, acc, st);
+    // one pass over level x's rows (edges into depth `want`): pulled, or
+    // pushed over LB chunks (TWC where the average degree is below
+    // lb_min_avg_degree)
+    auto sweep_level = [&](bool dependency, bool push, int32_t x, int32_t want) -> hipError_t {
+      const int32_t* f = levels + off[x];
+      const int32_t* o = all_offs + off[x];
+      const int32_t* r = all_rstart + off[x];
+      const int32_t* cm = bc_chunks + tab[2 * L + x];
+      if (!push)
+        return launch_bc_pull(dependency, f, o, r, cm, hn[x], (int64_t)hm[x], tab[L + x], chunk,
+                              g->C, depth, want, sig, acc, st);
+      const int mode = lb ? 2 : 0;
+      if (dependency)
+        return launch_bc_dependency(mode, f, o, r, cm, hn[x], (int64_t)hm[x], tab[L + x], g->R,
+                                    g->C, depth, sig, acc, want, adv, st);
+      return launch_bc_sigma(mode, f, o, r, cm, hn[x], (int64_t)hm[x], tab[L + x], g->R, g->C,
+                             depth, sig, want, adv, st);
     };
     // forward: sigma of level d + 1 from level d, pushed by level d or
     // gathered by level d + 1
@@ -2032,15 +2030,7 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
       const bool push = use_push(dir_sigma, hm[d], hm[d + 1], hn[d + 1]);
       const int32_t x = push ? d : d + 1;  // the level whose rows are swept
       if (hm[x] == 0) continue;
-      if (push) {
-        const int32_t* front = levels + off[x];
-        int mode = 0;
-        GR_TRY(prepare_level(front, lvl_n + x, hn[x], &mode));
-        GR_HIP(launch_bc_sigma(mode, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x], g->R,
-                               g->C, depth, sig, d + 1, adv, st));
-      } else {
-        GR_HIP(pull_level(false, x, d));
-      }
+      GR_HIP(sweep_level(false, push, x, push ? d + 1 : d));
     }
     // backward: dependency sums of level d - 1 from level d, pushed by level d
     // or gathered by level d - 1 (the source's own sum is not needed)
@@ -2048,15 +2038,7 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
       const bool push = use_push(dir_dep, hm[d], hm[d - 1], hn[d - 1]);
       const int32_t x = push ? d : d - 1;
       if (hm[x] == 0) continue;
-      if (push) {
-        const int32_t* front = levels + off[x];
-        int mode = 0;
-        GR_TRY(prepare_level(front, lvl_n + x, hn[x], &mode));
-        GR_HIP(launch_bc_dependency(mode, front, offsets, rstart, chunks, hn[x], (int64_t)hm[x],
-                                    g->R, g->C, depth, sig, acc, d - 1, adv, st));
-      } else {
-        GR_HIP(pull_level(true, x, d));
-      }
+      GR_HIP(sweep_level(true, push, x, push ? d - 1 : d));
     }
     GR_HIP(launch_bc_finalize(depth, sig, acc, V, src, g->perm, bc, sigma, st));
     // the host vectors are reused by the next source: finish their copies

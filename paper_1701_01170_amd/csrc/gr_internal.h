@@ -78,9 +78,8 @@ enum Slot : int {
   S_BC_LEVELS,     // vertices grouped by level [V]
   S_BC_LVL_N,      // vertices per level, then level cursors [L + 1]
   S_BC_LVL_M,      // degree sum per level [L + 1]
-  S_BC_OFFS,       // exclusive scan of the degrees of all levels' vertices [V + 1]
-  S_BC_RSTART,     // row start of every vertex in level order [V]
-  S_BC_CHUNKS,     // per-level LB chunk -> first-row maps, level after level
+  S_BC_CHUNKS,     // per-level LB chunk -> first-row maps, level after level (the
+                   // levels' degree scan and row starts use S_OFFSETS / S_RSTART)
   S_BC_TAB,        // per level: first vertex index, first edge position, first chunk [3 L]
   S_MS_KEYS,       // batched SSSP: packed keys, KS per vertex [V * KS]
   S_MS_AMASK,      // batched SSSP: sources a frontier vertex is active for [V]
@@ -322,16 +321,19 @@ hipError_t launch_bc_levels(const int32_t* depth, const int32_t* R, int64_t V, i
                             double* sigma, double* acc, hipStream_t st);
 hipError_t launch_bc_scatter(const int32_t* depth, int64_t V, int32_t n_levels, uint32_t* cursor,
                              int32_t* levels, hipStream_t st);
+// push form of either pass over one level (mode 0 = TWC, 2 = LB; the level's
+// edges at positions e_base .. of `offsets`)
 hipError_t launch_bc_sigma(int mode, const int32_t* frontier, const int32_t* offsets,
                            const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
-                           int64_t m_f, const int32_t* R, const int32_t* C, const int32_t* depth,
-                           double* sigma, int32_t next_depth, const AdvCfg& cfg, hipStream_t st);
+                           int64_t m_f, int64_t e_base, const int32_t* R, const int32_t* C,
+                           const int32_t* depth, double* sigma, int32_t next_depth,
+                           const AdvCfg& cfg, hipStream_t st);
 hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t* offsets,
                                 const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
-                                int64_t m_f, const int32_t* R, const int32_t* C,
+                                int64_t m_f, int64_t e_base, const int32_t* R, const int32_t* C,
                                 const int32_t* depth, const double* sigma, double* acc,
                                 int32_t prev_depth, const AdvCfg& cfg, hipStream_t st);
-// per-level chunk maps of the pull passes for every level at once (offsets:
+// per-level chunk maps of both passes for every level at once (offsets:
 // the degree scan over all n_r vertices in level order; tab: per level its
 // first vertex index, first edge position and first chunk, 3 * n_levels)
 hipError_t launch_bc_chunk_map(const int32_t* levels, const int32_t* depth, int64_t n_r,

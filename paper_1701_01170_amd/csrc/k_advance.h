@@ -198,7 +198,9 @@ __device__ __forceinline__ void lb_seg_maxscan(uint16_t* s_seg, int32_t* s_tmp) 
   }
 }
 
-// One workgroup per chunk of NB * EPT * 256 edges of the output frontier.  The
+// One workgroup per chunk of NB * EPT * 256 edges of the output frontier
+// (its edges are positions e_base .. e_base + m_f - 1 of `offsets`, normally
+// from 0; a frontier inside a longer scanned list starts further on).  The
 // frontier segments overlapping the chunk are staged in LDS (lb_cap per pass);
 // a 16-bit segment index per edge slot comes from scattering segment starts and
 // a max-scan; the edges are then processed in NB batches of EPT per thread
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(BLOCK) void k_push_lb(
     const int32_t* __restrict__ frontier, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ rstart, const int32_t* __restrict__ chunk_start, int32_t n_f,
     int32_t m_f, const int32_t* __restrict__ C, F f,
-    int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count) {
+    int32_t* __restrict__ out_q, uint32_t* __restrict__ out_count, int64_t e_base) {
   constexpr int BATCH = BLOCK * EPT;
   constexpr int N = BATCH * NB;
   constexpr int SPT = N / BLOCK;  // segment-map slots per thread
@@ -221,8 +223,8 @@ __global__ __launch_bounds__(BLOCK) void k_push_lb(
   __shared__ int32_t s_tmp[BLOCK / kWave + 1];
   functor_block_init(f);
   const int c = blockIdx.x;
-  const int64_t e0 = (int64_t)c * N;
-  const int64_t e1 = e0 + N < m_f ? e0 + N : m_f;
+  const int64_t e0 = e_base + (int64_t)c * N;
+  const int64_t e1 = e0 + N < e_base + m_f ? e0 + N : e_base + m_f;
   const int nchunks = (int)(((int64_t)m_f + N - 1) / N);
   const int sb = chunk_start[c];
   const int se = c + 1 < nchunks ? chunk_start[c + 1] : n_f - 1;
@@ -446,14 +448,14 @@ template <class F, int BLOCK>
 inline void launch_lb(int chunk, unsigned g, const int32_t* frontier, const int32_t* offsets,
                       const int32_t* rstart, const int32_t* chunk_start, int32_t n_f, int32_t m_f,
                       const int32_t* C, const F& f, int32_t* out_q, uint32_t* out_count,
-                      hipStream_t st) {
+                      hipStream_t st, int64_t e_base = 0) {
 #define GR_LB(CH)                                                                              \
   case CH: {                                                                                   \
     constexpr int cap = BLOCK >= 512 ? 16 : 32;                                                \
     constexpr int ept = (CH / BLOCK) < cap ? (CH / BLOCK) : cap;                               \
     constexpr int nb = CH / (BLOCK * ept);                                                     \
     k_push_lb<F, ept, nb, BLOCK><<<g, BLOCK, 0, st>>>(frontier, offsets, rstart, chunk_start,   \
-                                                     n_f, m_f, C, f, out_q, out_count);          \
+                                                     n_f, m_f, C, f, out_q, out_count, e_base);  \
     break;                                                                                     \
   }
   switch (chunk) {
@@ -473,7 +475,8 @@ inline hipError_t push_dispatch_block(int mode, const int32_t* frontier, const i
                                       const int32_t* rstart, const int32_t* chunk_start,
                                       int64_t n_f, int64_t m_f, const int32_t* R,
                                       const int32_t* C, const F& f, int32_t* out_q,
-                                      uint32_t* out_count, const AdvCfg& cfg, hipStream_t st) {
+                                      uint32_t* out_count, const AdvCfg& cfg, hipStream_t st,
+                                      int64_t e_base) {
   if (mode == 0) {
     int32_t wmin = cfg.twc_wave_min >= 0 ? cfg.twc_wave_min : kWave;
     int32_t bmin = cfg.twc_block_min >= 0 ? cfg.twc_block_min : BLOCK;
@@ -486,31 +489,32 @@ inline hipError_t push_dispatch_block(int mode, const int32_t* frontier, const i
   } else {
     if (m_f <= 0) return hipSuccess;
     launch_lb<F, BLOCK>(cfg.chunk, adv_blocks(m_f, cfg.chunk), frontier, offsets, rstart,
-                        chunk_start, (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count, st);
+                        chunk_start, (int32_t)n_f, (int32_t)m_f, C, f, out_q, out_count, st,
+                        e_base);
   }
   return hipGetLastError();
 }
 
 // mode: 0 = TWC, 1 = LB_LIGHT, 2 = LB with cfg.chunk edges per workgroup
-// (512, 1024, 2048, 4096, 8192 or 16384); workgroups of cfg.block threads
-// (128, 256 or 512).
+// (512, 1024, 2048, 4096, 8192 or 16384; the frontier's edges at positions
+// e_base .. of `offsets`); workgroups of cfg.block threads (128, 256 or 512).
 template <class F>
 inline hipError_t push_dispatch(int mode, const int32_t* frontier, const int32_t* offsets,
                                 const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                 int64_t m_f, const int32_t* R, const int32_t* C, const F& f,
                                 int32_t* out_q, uint32_t* out_count, const AdvCfg& cfg,
-                                hipStream_t st) {
+                                hipStream_t st, int64_t e_base = 0) {
   if (n_f <= 0) return hipSuccess;
   switch (cfg.block) {
     case 128:
       return push_dispatch_block<F, 128>(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R,
-                                         C, f, out_q, out_count, cfg, st);
+                                         C, f, out_q, out_count, cfg, st, e_base);
     case 512:
       return push_dispatch_block<F, 512>(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R,
-                                         C, f, out_q, out_count, cfg, st);
+                                         C, f, out_q, out_count, cfg, st, e_base);
     default:
       return push_dispatch_block<F, 256>(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R,
-                                         C, f, out_q, out_count, cfg, st);
+                                         C, f, out_q, out_count, cfg, st, e_base);
   }
 }
 

@@ -328,21 +328,22 @@ hipError_t launch_bc_scatter(const int32_t* depth, int64_t V, int32_t n_levels, 
 
 hipError_t launch_bc_sigma(int mode, const int32_t* frontier, const int32_t* offsets,
                            const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
-                           int64_t m_f, const int32_t* R, const int32_t* C, const int32_t* depth,
-                           double* sigma, int32_t next_depth, const AdvCfg& cfg, hipStream_t st) {
+                           int64_t m_f, int64_t e_base, const int32_t* R, const int32_t* C,
+                           const int32_t* depth, double* sigma, int32_t next_depth,
+                           const AdvCfg& cfg, hipStream_t st) {
   const BcSigma f{depth, sigma, next_depth};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
-                       nullptr, cfg, st);
+                       nullptr, cfg, st, e_base);
 }
 
 hipError_t launch_bc_dependency(int mode, const int32_t* frontier, const int32_t* offsets,
                                 const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
-                                int64_t m_f, const int32_t* R, const int32_t* C,
+                                int64_t m_f, int64_t e_base, const int32_t* R, const int32_t* C,
                                 const int32_t* depth, const double* sigma, double* acc,
                                 int32_t prev_depth, const AdvCfg& cfg, hipStream_t st) {
   const BcDependency f{depth, sigma, acc, prev_depth};
   return push_dispatch(mode, frontier, offsets, rstart, chunk_start, n_f, m_f, R, C, f, nullptr,
-                       nullptr, cfg, st);
+                       nullptr, cfg, st, e_base);
 }
 
 hipError_t launch_bc_chunk_map(const int32_t* levels, const int32_t* depth, int64_t n_r,
