@@ -1,16 +1,18 @@
 // Betweenness centrality (Sec. 6, betweenness centrality; Brandes's two
 // passes) on the advance operator.  The forward pass is the BFS (depths) and
-// then, level by level, a push advance over each level's vertices that adds
-// sigma(u) into sigma(w) for every edge (u, w) into the next level; the
-// backward pass walks the levels in reverse, each a push advance over the
-// level's vertices w that adds 1 / sigma(w) + acc(w) into acc(v) for every edge
-// (w, v) into the level before, where acc(v) = sum over v's successors w of
-// (1 + delta(w)) / sigma(w), so delta(v) = sigma(v) * acc(v) and the payload
-// (1 + delta(w)) / sigma(w) equals 1 / sigma(w) + acc(w).  The edges of a
-// level are balanced by the same TWC / LB kernels as the traversals; the
-// per-vertex sums use hardware fp64 atomic adds on the targets (device memory
-// from hipMalloc, coarse grained).  Levels come from a counting sort of the
-// depths, so every level's vertices are contiguous.
+// then, level by level, sigma(w) = sum of sigma(u) over the edges (u, w) from
+// the level before; the backward pass walks the levels in reverse with
+// acc(v) = sum over v's successors w (edges into the level after) of
+// (1 + delta(w)) / sigma(w) = 1 / sigma(w) + acc(w), so that
+// delta(v) = sigma(v) * acc(v).  Each sum over the edges between two adjacent
+// levels is either pushed (the level the terms come from sweeps its rows and
+// adds each term into the other end with a hardware fp64 atomic; device
+// memory from hipMalloc, coarse grained) or pulled (the level the sums belong
+// to sweeps its own rows and reduces them without per-edge atomics; the graph
+// is symmetric, so a vertex's row holds its predecessors and successors).
+// Both forms use the traversals' LB mapping; levels come from a counting sort
+// of the depths, so every level's vertices are contiguous and one degree scan
+// over them serves every level.
 #include "k_advance.h"
 
 namespace gr {
