@@ -677,7 +677,7 @@ constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filt
 // SSSP iterations whose frontier has at least V / kSsspMarksDivisor edges use
 // the byte-mark filter.
 constexpr int64_t kSsspMarksDivisor = 4;
-// ... and screen their edges with the 16-bit distance mirror once the
+// ... and screen their edges with the one-byte distance mirror once the
 // frontiers so far, this one included, and the far pile of the priority queue
 // sum to at least V / kSsspMirrorDivisor vertices (an estimate of the vertices
 // reached): before that most edges reach unvisited vertices, pass the screen
@@ -1250,8 +1250,9 @@ extern "C" gr_status gr_sssp(gr_ctx* ctx, const gr_graph* g, const int32_t* sour
   GR_TRY(pool_typed(ctx, S_CTRL, 1, &ctrl));
   GR_TRY(pool_typed(ctx, S_KEYS, V, &keys));
   GR_TRY(pool_typed(ctx, S_TAGS, V, &tags));
-  uint16_t* mirror;
-  GR_TRY(pool_typed(ctx, S_MIRROR, V, &mirror));
+  uint8_t* mirror_p;
+  GR_TRY(pool_typed(ctx, S_MIRROR, V, &mirror_p));
+  const DistMirror mirror{mirror_p, mirror_shift_for(g->max_weight)};
   uint32_t* relaxed = nullptr;
   if (!(opts.sssp_opt_off & GR_SSSP_OPT_CULL)) GR_TRY(pool_typed(ctx, S_RELAXED, V, &relaxed));
   // src_dev: the sources in traversal ids, then in caller ids

@@ -65,7 +65,7 @@ enum Slot : int {
   S_CHUNKS,        // LB chunk -> first frontier segment map
   S_MARKS,         // one byte per vertex, all zero between uses
   S_MLP_WS,        // selector gradient partial sums
-  S_MIRROR,        // shortest-path 16-bit distance mirror [V]
+  S_MIRROR,        // shortest-path one-byte distance mirror [V]
   S_RELAXED,       // shortest-path: 1 + distance a frontier vertex's edges were relaxed with [V]
   S_SSSP_BINS,     // shortest-path distance bins: histograms, cursors, base
   S_MS_RELAXED,    // batched shortest paths: per (vertex, source) cull values [V * row]
@@ -534,12 +534,26 @@ hipError_t launch_sssp_pq_dstep(const DlArgs& a, const uint32_t* W, unsigned lon
                                 int32_t* tags, int32_t next_tag, const PqState& pq, int n_blocks,
                                 hipStream_t st);
 
+// The SSSP distance mirror: one byte per vertex, ceil(dist / 2^shift) of an
+// earlier moment (255: unknown or too large), an upper bound of the distance
+// that screens relaxations before their key gathers.
+struct DistMirror {
+  uint8_t* p;
+  uint32_t shift;
+};
+// quantum 2^shift for a graph whose largest weight is max_weight: 254 steps
+// cover at least four times it
+inline uint32_t mirror_shift_for(uint32_t max_weight) {
+  uint32_t s = 0;
+  while ((254ull << s) < 4ull * max_weight && s < 31) ++s;
+  return s;
+}
 // SSSP
 // relaxed (nullable): the cull of vertices already relaxed with their final
 // distance (cleared here; raised by the marks relaxation, read by the
 // compactions); bin_state (nullable): the distance bins' state, cleared
 hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag,
-                            uint16_t* mirror, uint32_t* relaxed, uint32_t* bin_state, int64_t V,
+                            DistMirror mirror, uint32_t* relaxed, uint32_t* bin_state, int64_t V,
                             Ctrl* ctrl, hipStream_t st);
 hipError_t launch_sssp_seed(const int32_t* src_dev, int32_t n, unsigned long long* keys,
                             int32_t* tags, Ctrl* ctrl, hipStream_t st);
@@ -552,17 +566,17 @@ hipError_t launch_sssp_relax(int mode, const int32_t* frontier, const int32_t* o
                              hipStream_t st);
 // Relaxation with the non-atomic filter (byte marks, all zero before and after
 // the pair of calls), then the ordered list of the marked vertices.  With
-// filter, the 16-bit distance mirror screens the edges before the key gather;
+// filter, the one-byte distance mirror screens the edges before the key gather;
 // the compaction refreshes the mirror of every marked vertex.
 hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int32_t* offsets,
                                    const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
-                                   const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
+                                   const int32_t* perm, uint8_t* marks, DistMirror mirror,
                                    uint32_t* relaxed, bool filter, const AdvCfg& cfg,
                                    hipStream_t st);
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                    uint16_t* mirror, uint32_t* relaxed, int32_t* out_q,
+                                    DistMirror mirror, uint32_t* relaxed, int32_t* out_q,
                                     uint32_t* out_count, hipStream_t st);
 // Distance-ordered compaction: the marked vertices (minus the culled ones)
 // listed in bins of distance, smallest first; *out_count is set, not added to.
@@ -577,7 +591,7 @@ struct SsspBins {
   uint32_t shift;   // bin width 2^shift
 };
 hipError_t launch_sssp_bin_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                   uint16_t* mirror, uint32_t* relaxed, const SsspBins& bins,
+                                   DistMirror mirror, uint32_t* relaxed, const SsspBins& bins,
                                    int32_t* out_q, uint32_t* out_count, hipStream_t st);
 // bin width 2^shift for a graph whose largest weight is max_weight: the bins
 // span about two to four times it
@@ -590,7 +604,7 @@ inline uint32_t bin_shift_for(uint32_t max_weight) {
 // Priority-queue form: marked vertices below pq.T go to out_q, the others to
 // far pile pq.fc (once per far-pile generation).
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                       uint16_t* mirror, uint32_t* relaxed, const PqState& pq,
+                                       DistMirror mirror, uint32_t* relaxed, const PqState& pq,
                                        Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
                                        hipStream_t st);
 // dist / pred written at caller ids; src_orig_dev: the sources in caller ids.

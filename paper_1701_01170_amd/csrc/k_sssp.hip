@@ -94,13 +94,15 @@ struct SsspVisit {
 // this iteration, by this edge or by a concurrent one: the marks are the
 // next frontier, which k_sssp_mark_compact lists in ascending order.
 //
-// With FILTER, a 16-bit distance mirror (min(dist, 0xffff) of an earlier
-// moment, refreshed by the compaction for every marked vertex) screens the
-// edges first.  Distances only decrease, so a mirror value below 0xffff is an
-// upper bound of the current distance: an edge whose candidate exceeds it can
-// neither shorten the distance nor tie it, and skips the 8-byte key gather.
-// The mirror is a quarter of the keys' size, so its gathers hit the caches
-// more often; the filter pays off once most vertices have been reached.
+// With FILTER, a one-byte distance mirror (ceil(dist / 2^shift) of an
+// earlier moment, 255 when unknown or too large; refreshed by the compaction
+// for every marked vertex) screens the edges first.  Distances only decrease,
+// so a mirror value m below 255 bounds the current distance by m * 2^shift: an
+// edge whose candidate exceeds that can neither shorten the distance nor tie
+// it, and skips the 8-byte key gather.  The mirror is an eighth of the keys'
+// size, so its gathers hit the caches more often; the filter pays off once
+// most vertices have been reached.  The quantum 2^shift is chosen per graph
+// so that 254 steps cover about four times its largest weight.
 //
 // With `relaxed` (nullable), every chunk that stages a frontier vertex u
 // raises relaxed[u] to 1 + the distance it relaxes u's edges with; the
@@ -112,7 +114,7 @@ struct SsspVisit {
 // work already done).  A value left from an earlier iteration is larger than
 // 1 + any distance v can have after dropping in this one, and 0 never
 // matches, so nothing else is dropped.
-constexpr uint32_t kMirrorNone = 0xffffu;
+constexpr uint32_t kMirrorNone = 0xffu;
 
 template <bool FILTER>
 struct SsspMark {
@@ -120,7 +122,7 @@ struct SsspMark {
   unsigned long long* __restrict__ keys;
   uint8_t* __restrict__ marks;
   const int32_t* __restrict__ perm;
-  const uint16_t* __restrict__ mirror;
+  DistMirror mirror;
   uint32_t* __restrict__ relaxed;  // nullable
 
   using pay_t = int32_t;
@@ -146,10 +148,11 @@ struct SsspMark {
     if constexpr (FILTER) {
       uint32_t m[B];
 #pragma unroll
-      for (int r = 0; r < B; ++r) m[r] = ok[r] ? (uint32_t)mirror[v[r]] : 0u;
+      for (int r = 0; r < B; ++r) m[r] = ok[r] ? (uint32_t)mirror.p[v[r]] : 0u;
 #pragma unroll
       for (int r = 0; r < B; ++r)
-        pass[r] = ok[r] && (m[r] == kMirrorNone || (uint64_t)(uint32_t)du[r] + w[r] <= m[r]);
+        pass[r] = ok[r] && (m[r] == kMirrorNone ||
+                            (uint64_t)(uint32_t)du[r] + w[r] <= ((uint64_t)m[r] << mirror.shift));
     } else {
 #pragma unroll
       for (int r = 0; r < B; ++r) pass[r] = ok[r];
@@ -170,9 +173,11 @@ struct SsspMark {
   __device__ __forceinline__ bool commit(int32_t, int32_t, int32_t, uint32_t) const { return false; }
 };
 
-__device__ __forceinline__ uint16_t mirror_of(unsigned long long key) {
-  const uint32_t d = (uint32_t)(key >> 32);
-  return (uint16_t)(d < kMirrorNone ? d : kMirrorNone);
+// mirror entry of a vertex with this key: ceil(dist / 2^shift), or 255
+__device__ __forceinline__ uint8_t mirror_of(unsigned long long key, uint32_t shift) {
+  const uint64_t d = key >> 32;
+  const uint64_t q = (d + ((1ull << shift) - 1ull)) >> shift;
+  return (uint8_t)(q < kMirrorNone ? q : kMirrorNone);
 }
 
 // Keys of the 32 consecutive vertices v0 .. v0 + 31 (v0 a multiple of 32, all
@@ -220,7 +225,7 @@ __device__ __forceinline__ bool drop_relaxed(uint32_t* __restrict__ relaxed, int
 // The distance mirror of every marked vertex is refreshed on the way.
 __global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__ marks, int64_t V,
                                                            const unsigned long long* __restrict__ keys,
-                                                           uint16_t* __restrict__ mirror,
+                                                           DistMirror mirror,
                                                            uint32_t* __restrict__ relaxed,
                                                            int32_t* __restrict__ out_q,
                                                            uint32_t* __restrict__ out_count) {
@@ -236,20 +241,20 @@ __global__ __launch_bounds__(256) void k_sssp_mark_compact(uint8_t* __restrict__
 #pragma unroll
       for (int b = 0; b < 32; ++b) {
         if (!((mask >> b) & 1u)) continue;
-        mirror[v0 + b] = mirror_of(k[b]);
+        mirror.p[v0 + b] = mirror_of(k[b], mirror.shift);
         if (drop_relaxed(relaxed, v0 + b, k[b], r[b])) mask &= ~(1u << b);
       }
     } else {
 #pragma unroll
       for (int b = 0; b < 32; ++b)
-        if ((mask >> b) & 1u) mirror[v0 + b] = mirror_of(k[b]);
+        if ((mask >> b) & 1u) mirror.p[v0 + b] = mirror_of(k[b], mirror.shift);
     }
   } else {
     for (uint32_t m = mask; m; m &= m - 1) {
       const int b = __ffs(m) - 1;
       const int64_t v = v0 + b;
       const unsigned long long key = keys[v];
-      mirror[v] = mirror_of(key);
+      mirror.p[v] = mirror_of(key, mirror.shift);
       if (relaxed && drop_relaxed(relaxed, v, key, relaxed[v])) mask &= ~(1u << b);
     }
   }
@@ -320,7 +325,7 @@ __device__ __forceinline__ uint32_t dist_bin(uint32_t d, uint32_t base, uint32_t
 
 __global__ __launch_bounds__(256) void k_sssp_bin_count(uint8_t* __restrict__ marks, int64_t V,
                                                         const unsigned long long* __restrict__ keys,
-                                                        uint16_t* __restrict__ mirror,
+                                                        DistMirror mirror,
                                                         uint32_t* __restrict__ relaxed,
                                                         SsspBins bins) {
   __shared__ uint32_t s_h[kSsspBins];
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(256) void k_sssp_bin_count(uint8_t* __restrict__ ma
 #pragma unroll
     for (int b = 0; b < 32; ++b) {
       if (!((mask >> b) & 1u)) continue;
-      mirror[v0 + b] = mirror_of(k[b]);
+      mirror.p[v0 + b] = mirror_of(k[b], mirror.shift);
       if (relaxed && drop_relaxed(relaxed, v0 + b, k[b], r[b])) {
         m[b] = 0;
         continue;
@@ -439,7 +444,7 @@ __global__ __launch_bounds__(256) void k_sssp_bin_scatter(uint8_t* __restrict__ 
 // distance are dropped as in k_sssp_mark_compact.
 __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
     uint8_t* __restrict__ marks, int64_t V, const unsigned long long* __restrict__ keys,
-    uint16_t* __restrict__ mirror, uint32_t* __restrict__ relaxed, uint32_t T, int32_t epoch,
+    DistMirror mirror, uint32_t* __restrict__ relaxed, uint32_t T, int32_t epoch,
     int32_t* __restrict__ far_tag, int32_t* __restrict__ far_q,
     uint32_t* __restrict__ far_count, int32_t* __restrict__ out_q,
     uint32_t* __restrict__ out_count) {
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
 #pragma unroll
     for (int b = 0; b < 32; ++b) {
       if (!((mask >> b) & 1u)) continue;
-      mirror[v0 + b] = mirror_of(k[b]);
+      mirror.p[v0 + b] = mirror_of(k[b], mirror.shift);
       if (relaxed && drop_relaxed(relaxed, v0 + b, k[b], rl[b])) continue;
       if ((uint32_t)(k[b] >> 32) < T) {
         near |= 1u << b;
@@ -478,7 +483,7 @@ __global__ __launch_bounds__(256) void k_sssp_pq_mark_compact(
       const int b = __ffs(m) - 1;
       const int64_t v = v0 + b;
       const unsigned long long key = keys[v];
-      mirror[v] = mirror_of(key);
+      mirror.p[v] = mirror_of(key, mirror.shift);
       if (relaxed && drop_relaxed(relaxed, v, key, relaxed[v])) continue;
       if ((uint32_t)(key >> 32) < T) {
         near |= 1u << b;
@@ -653,7 +658,7 @@ __global__ __launch_bounds__(kAdvBlock) void k_sssp_pq_refill(const unsigned lon
 __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restrict__ keys,
                                                    int32_t* __restrict__ tags,
                                                    int32_t* __restrict__ far_tag,
-                                                   uint16_t* __restrict__ mirror,
+                                                   DistMirror mirror,
                                                    uint32_t* __restrict__ relaxed,
                                                    uint32_t* __restrict__ bin_state, int64_t V,
                                                    Ctrl* __restrict__ ctrl) {
@@ -664,7 +669,7 @@ __global__ __launch_bounds__(256) void k_sssp_init(unsigned long long* __restric
     keys[v] = ~0ull;
     tags[v] = -1;
     if (far_tag) far_tag[v] = -1;
-    mirror[v] = (uint16_t)kMirrorNone;
+    mirror.p[v] = (uint8_t)kMirrorNone;
     if (relaxed) relaxed[v] = 0u;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -753,7 +758,7 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 hipError_t launch_sssp_init(unsigned long long* keys, int32_t* tags, int32_t* far_tag,
-                            uint16_t* mirror, uint32_t* relaxed, uint32_t* bin_state, int64_t V,
+                            DistMirror mirror, uint32_t* relaxed, uint32_t* bin_state, int64_t V,
                             Ctrl* ctrl, hipStream_t st) {
   unsigned g = blocks_for(V, 256);
   if (g > 4096) g = 4096;
@@ -841,7 +846,7 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
                                    const int32_t* rstart, const int32_t* chunk_start, int64_t n_f,
                                    int64_t m_f, const int32_t* R, const int32_t* C,
                                    const uint32_t* W, unsigned long long* keys,
-                                   const int32_t* perm, uint8_t* marks, const uint16_t* mirror,
+                                   const int32_t* perm, uint8_t* marks, const DistMirror mirror,
                                    uint32_t* relaxed, bool filter, const AdvCfg& cfg,
                                    hipStream_t st) {
   if (filter) {
@@ -855,7 +860,7 @@ hipError_t launch_sssp_relax_marks(int mode, const int32_t* frontier, const int3
 }
 
 hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                       uint16_t* mirror, uint32_t* relaxed, const PqState& pq,
+                                       DistMirror mirror, uint32_t* relaxed, const PqState& pq,
                                        Ctrl* ctrl, int32_t* out_q, uint32_t* out_count,
                                        hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
@@ -867,7 +872,7 @@ hipError_t launch_sssp_pq_mark_compact(uint8_t* marks, int64_t V, const unsigned
 }
 
 hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                    uint16_t* mirror, uint32_t* relaxed, int32_t* out_q,
+                                    DistMirror mirror, uint32_t* relaxed, int32_t* out_q,
                                     uint32_t* out_count, hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   if (n_words <= 0) return hipSuccess;
@@ -877,7 +882,7 @@ hipError_t launch_sssp_mark_compact(uint8_t* marks, int64_t V, const unsigned lo
 }
 
 hipError_t launch_sssp_bin_compact(uint8_t* marks, int64_t V, const unsigned long long* keys,
-                                   uint16_t* mirror, uint32_t* relaxed, const SsspBins& bins,
+                                   DistMirror mirror, uint32_t* relaxed, const SsspBins& bins,
                                    int32_t* out_q, uint32_t* out_count, hipStream_t st) {
   const int64_t n_words = (V + 31) / 32;
   if (n_words <= 0) return hipSuccess;

@@ -38,8 +38,11 @@ POLICIES = [
     # of a few edges, more rows than one LDS stage holds
     ("pull_chunk16384", dict(bc_dir=gr.BC_DIR_PULL | gr.BC_DIR_PULL << 2, lb_chunk=16384)),
     ("push_bwd_chunk512", dict(bc_dir=gr.BC_DIR_AUTO | gr.BC_DIR_PUSH << 2, lb_chunk=512)),
+    # the knobs the autotuner stores for BC on R-MAT 22 (the benchmark's setting)
+    ("tuned_like", dict(lb_light_threshold=0, lb_chunk=1024, do_a=1 / 64, do_b=1 / 64,
+                        device_max_edges=1 << 20)),
 ]
-PUSH_PULL = [POLICIES[0], POLICIES[7], POLICIES[8], POLICIES[10]]
+PUSH_PULL = [POLICIES[0], POLICIES[7], POLICIES[8], POLICIES[10], POLICIES[12]]
 
 
 @pytest.fixture(scope="module")
@@ -147,4 +150,5 @@ def test_rmat20_two_sources(ctx):
     hg = gg.rmat(20, 16, seed=1)
     srcs = [int(x) for x in gg.sources(hg, 2, seed=3000)]
     print(f"bc rmat20 V={hg.n_vertices} E={hg.n_edges} sources={srcs}", flush=True)
-    check_graph(ctx, hg, [srcs], policies=[POLICIES[0], POLICIES[7], POLICIES[8]], renumber=(False,))
+    check_graph(ctx, hg, [srcs], policies=[POLICIES[0], POLICIES[7], POLICIES[8], POLICIES[12]],
+                renumber=(False, True))

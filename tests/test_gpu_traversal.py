@@ -165,12 +165,14 @@ def test_er_bfs_sssp(ctx):
     run_sssp_all(ctx, hg, [[int(s)] for s in gg.sources(hg, 2, seed=4)])
 
 
-@pytest.mark.parametrize("lo,hi", [(1, 2), (30000, 140000)])
+@pytest.mark.parametrize("lo,hi", [(1, 2), (30000, 140000), (100, 127)])
 def test_sssp_distance_mirror(ctx, lo, hi):
     # large frontiers relax through the byte-mark filter, screened by the
-    # 16-bit distance mirror once most vertices are reached: weights 1..2
-    # make tight in-edges (predecessor ties) common, weights 30000..140000
-    # push distances across the mirror's saturation value 0xffff
+    # one-byte distance mirror (ceil(dist / 2^shift), 255 = unknown) once most
+    # vertices are reached: weights 1..2 make tight in-edges (predecessor
+    # ties) common at quantum 1; weights 30000..140000 quantise by 2^12;
+    # weights 100..127 (quantum 2) leave 83-87% of the distances above the
+    # 254 quanta the mirror holds, so most of its entries saturate
     hg = gg.add_weights(gg.erdos_renyi(30001, 8, seed=11), seed=12, lo=lo, hi=hi)
     run_sssp_all(ctx, hg, [[int(s)] for s in gg.sources(hg, 2, seed=13)])
 
