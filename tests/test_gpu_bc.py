@@ -138,6 +138,10 @@ def test_isolated_source_and_errors(ctx):
     with pytest.raises(gr.GrError) as ei:
         gr.bc(g, [1, 2], want_sigma=True)
     assert ei.value.code == gr.GR_EINVAL
+    for bad in (3, 3 << 2, -1, 16):  # each pass takes AUTO, PUSH or PULL
+        with pytest.raises(gr.GrError) as ei:
+            gr.bc(g, [1], opts=gr.default_opts(bc_dir=bad))
+        assert ei.value.code == gr.GR_EINVAL
     g.free()
     d = gr.Graph.from_host(ctx, hg, symmetric=False)
     with pytest.raises(gr.GrError) as ei:
