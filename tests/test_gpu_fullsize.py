@@ -1,6 +1,6 @@
 """Parity at the benchmark's full sizes, with the knobs and launch
 configuration bench.py times: R-MAT scale 22 BFS + SSSP (whole outputs
-against the oracle), the 2048 x 2048 grid, 64-source batched BFS on R-MAT
+against the oracle) and BC from one source, the 2048 x 2048 grid, 64-source batched BFS on R-MAT
 scale 20 (every row's whole output against a single-source oracle run), and the 256-graph disjoint-union SSSP (every
 part against a single-source oracle run on that part)."""
 import numpy as np
@@ -95,6 +95,27 @@ def test_rmat22_bfs_sssp_bit_exact(ctx):
         np.testing.assert_array_equal(pred.cpu().numpy(), epred, err_msg=f"pred src={s}")
         assert ss["teps_edges"] == oracle.teps_edges(hg.row_offsets, edist != 0xFFFFFFFF)
         assert 0 < os_.trace_count <= os_.trace_capacity
+    g.free()
+
+
+def test_rmat22_bc_tuned(ctx):
+    """Betweenness centrality as bench.py times it (R-MAT 22, degree-renumbered
+    ingest, the tuner's BC knobs, bench's first BC source): sigma exactly (path
+    counts are integers below 2^53 here) and BC within the tolerance of the BC
+    parity tests, against the float64 Brandes oracle over the whole graph."""
+    hg = gg.rmat(22, 16, seed=1)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
+    o = autotune.tuned_opts(g, "bc")
+    s = int(gg.sources(hg, 4, seed=1300)[0])
+    print(f"bc rmat22 source {s} lb_chunk={o.lb_chunk}", flush=True)
+    b, sig, st = gr.bc(g, [s], want_sigma=True, opts=o)
+    eb, es = oracle.bc(hg.row_offsets, hg.col_indices, [s], want_sigma=True)
+    assert es.max() < 2.0 ** 53
+    np.testing.assert_array_equal(sig.cpu().numpy(), es)
+    got = b.cpu().numpy()
+    err = np.abs(got - eb) / np.maximum(1.0, np.abs(eb))
+    assert err.max() <= 1e-9, (int(np.argmax(err)), float(err.max()))
+    assert st["teps_edges"] == oracle.teps_edges(hg.row_offsets, es > 0)
     g.free()
 
 
