@@ -295,7 +295,9 @@ def rmat14(gr, gg, ctx) -> dict:
     against the heuristic on the same graph (BFS and SSSP)."""
     from paper_1701_01170_amd import autotune
     hg = gg.add_weights(gg.rmat(14, 16, seed=1), seed=101)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    # degree-renumbered ingest, the layout the tuner and the selector's
+    # training traces use (results in the caller's ids)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
     srcs = gg.sources(hg, 20, seed=1000)
     ob = autotune.tuned_opts(g, "bfs")
     gr.bfs(g, int(srcs[0]), opts=ob)
@@ -304,7 +306,7 @@ def rmat14(gr, gg, ctx) -> dict:
         st = gr.bfs(g, int(s), opts=ob)[2]
         ms.append(st["device_ms"])
         te.append(st["teps_edges"])
-    out = {"graph": f"rmat_s14_e16 (V={hg.n_vertices}, E={hg.n_edges})",
+    out = {"graph": f"rmat_s14_e16 (V={hg.n_vertices}, E={hg.n_edges}), degree-renumbered ingest",
            "bfs_median_us": round(1e3 * statistics.median(ms), 2),
            "bfs_min_us": round(1e3 * min(ms), 2), "bfs_max_us": round(1e3 * max(ms), 2),
            "bfs_gteps": _gteps(sum(te), sum(ms)), "sources": len(srcs)}
@@ -325,6 +327,18 @@ def rmat14(gr, gg, ctx) -> dict:
     out["iteration_control"] = levels
     out["learned_vs_heuristic"] = learned_vs_heuristic(gr, g, ctx, gg.sources(hg, 20, seed=1100))
     g.free()
+    # the same BFS on the graph in generation order (no renumbering), which
+    # is faster at this size
+    g0 = gr.Graph.from_host(ctx, hg, symmetric=True)
+    gr.bfs(g0, int(srcs[0]), opts=ob)
+    ms0, te0 = [], []
+    for s in srcs:
+        st = gr.bfs(g0, int(s), opts=ob)[2]
+        ms0.append(st["device_ms"])
+        te0.append(st["teps_edges"])
+    out["generation_order"] = {"bfs_median_us": round(1e3 * statistics.median(ms0), 2),
+                               "bfs_gteps": _gteps(sum(te0), sum(ms0))}
+    g0.free()
     return out
 
 
@@ -359,7 +373,7 @@ def extras(gr, gg, ctx, torch, log):
     log("# grid done")
     # 64-source batched BFS, R-MAT scale 20
     hg = gg.rmat(20, 16, seed=1)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
+    g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
     srcs = gg.sources(hg, 64, seed=2000).astype(np.int32)
     ob = autotune.tuned_opts(g, "bfs")
     om = autotune.tuned_opts(g, "bfs_multi")
@@ -376,6 +390,7 @@ def extras(gr, gg, ctx, torch, log):
         single_ms += st["device_ms"]
         single_teps += st["teps_edges"]
     out["bfs_64_sources_rmat20"] = {
+        "graph": "rmat_s20_e16, degree-renumbered ingest",
         "batched_ms": round(m["device_ms"], 3), "batched_gteps": _gteps(m["teps_edges"], m["device_ms"]),
         "batched_iterations": m["iterations"],
         "single_source_ms": round(single_ms, 3), "single_source_gteps": _gteps(single_teps, single_ms),
@@ -399,8 +414,19 @@ def extras(gr, gg, ctx, torch, log):
             "learned_median_ms": round(statistics.median(lm), 4),
             "heuristic_gteps": _gteps(sum(te), sum(hm)), "learned_gteps": _gteps(sum(te), sum(lm)),
             "learned_speedup": round(sum(hm) / sum(lm), 4) if sum(lm) > 0 else None}
-    del depth, parent
     g.free()
+    # the batched and the single-source runs on the graph in generation order
+    g0 = gr.Graph.from_host(ctx, hg, symmetric=True)
+    gr.bfs_multi(g0, srcs, opts=om, out=(depth, parent))
+    m0 = gr.bfs_multi(g0, srcs, opts=om, out=(depth, parent))[2]
+    single0 = 0.0
+    for s in srcs:
+        single0 += gr.bfs(g0, int(s), opts=ob, out=(d1, p1))[2]["device_ms"]
+    out["bfs_64_sources_rmat20"]["generation_order"] = {
+        "batched_ms": round(m0["device_ms"], 3), "single_source_ms": round(single0, 3),
+        "speedup": round(single0 / m0["device_ms"], 3) if m0["device_ms"] > 0 else None}
+    g0.free()
+    del depth, parent
     del hg
     log("# batched bfs done")
     # 256 small graphs, one union SSSP

@@ -175,3 +175,45 @@ def test_multi_max_iterations(ctx, cap):
     assert st["iterations"] == min(cap, max(int(oracle.bfs(hg.row_offsets, hg.col_indices, int(s))[0].max())
                                              for s in srcs) + 1)
     g.free()
+
+
+def test_batched_network_gain_on_grid(ctx):
+    """What the trained batched-BFS network gains over the method without it:
+    64 sources on a 384 x 384 grid (a held-out graph of the network's
+    evaluation), where the heuristic's push -> pull switch pulls about half of
+    the levels and the network keeps pushing, which is faster on this
+    small-frontier, high-diameter graph.  Both policies give the same rows; the
+    learned run is faster (best of three each, interleaved)."""
+    from paper_1701_01170_amd import autotune, selector
+    if not selector.load_policy(ctx):
+        pytest.skip("no trained network stored")
+    try:
+        hg = gg.grid(384, 384)
+        g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=True)
+        srcs = gg.sources(hg, 64, seed=9100).astype(np.int32)
+        cfgs = {"heuristic": autotune.tuned_opts(g, "bfs_multi"),
+                "learned": autotune.tuned_opts(g, "bfs_multi", policy=gr.POLICY_LEARNED)}
+        best = {k: float("inf") for k in cfgs}
+        rows, actions = {}, {}
+        for _ in range(3):
+            for label, o in cfgs.items():
+                d, p, st = gr.bfs_multi(g, srcs, opts=o)
+                best[label] = min(best[label], st["device_ms"])
+                rows[label] = (d.cpu().numpy(), p.cpu().numpy())
+                actions[label] = st["action_count"]
+        np.testing.assert_array_equal(rows["learned"][0], rows["heuristic"][0])
+        np.testing.assert_array_equal(rows["learned"][1], rows["heuristic"][1])
+        check_rows(hg, srcs[:2], *(torch_rows(rows["learned"], 2)))
+        print(f"grid 384 x 384, 64 sources: heuristic {best['heuristic']:.3f} ms "
+              f"(actions {actions['heuristic']}), learned {best['learned']:.3f} ms "
+              f"(actions {actions['learned']})", flush=True)
+        assert best["learned"] < best["heuristic"], (best, actions)
+        g.free()
+    finally:
+        ctx.set_policy(None)
+
+
+def torch_rows(rows, n):
+    """The first n rows of (depth, parent) host arrays, as check_rows takes them."""
+    import torch
+    return torch.from_numpy(rows[0][:n]), torch.from_numpy(rows[1][:n])
