@@ -139,21 +139,37 @@ def test_grid2048_bfs_sssp_bit_exact(ctx):
 
 
 def test_rmat20_64_source_batch(ctx):
-    """All 64 rows of the batch compared whole with single-source oracle runs."""
+    """All 64 rows of the batch compared whole with single-source oracle runs:
+    generation order with the default knobs, and the bench's configuration
+    (degree-renumbered ingest, tuned knobs) under the heuristic and, when a
+    trained network is stored, under the learned policy."""
+    from paper_1701_01170_amd import selector
     hg = gg.rmat(20, 16, seed=1)
-    g = gr.Graph.from_host(ctx, hg, symmetric=True)
     srcs = gg.sources(hg, 64, seed=2000).astype(np.int32)
-    depth, parent, st = gr.bfs_multi(g, srcs)
-    depth = depth.cpu().numpy()
-    parent = parent.cpu().numpy()
-    teps = 0
-    for i, s in enumerate(srcs):
-        ed, ep = oracle.bfs(hg.row_offsets, hg.col_indices, int(s))
-        np.testing.assert_array_equal(depth[i], ed, err_msg=f"source {i}")
-        np.testing.assert_array_equal(parent[i], ep, err_msg=f"source {i}")
-        teps += oracle.teps_edges(hg.row_offsets, ed >= 0)
-    assert st["teps_edges"] == teps
-    g.free()
+    expect = [oracle.bfs(hg.row_offsets, hg.col_indices, int(s)) for s in srcs]
+    teps = sum(oracle.teps_edges(hg.row_offsets, ed >= 0) for ed, _ in expect)
+    learned = selector.load_policy(ctx)
+    try:
+        for keep in (False, True):
+            g = gr.Graph.from_host(ctx, hg, symmetric=True, renumber=keep)
+            cfgs = [("default", gr.default_opts())]
+            if keep:
+                cfgs.append(("tuned", autotune.tuned_opts(g, "bfs_multi")))
+                if learned:
+                    cfgs.append(("learned", autotune.tuned_opts(g, "bfs_multi",
+                                                                policy=gr.POLICY_LEARNED)))
+            for name, o in cfgs:
+                depth, parent, st = gr.bfs_multi(g, srcs, opts=o)
+                depth = depth.cpu().numpy()
+                parent = parent.cpu().numpy()
+                for i, (ed, ep) in enumerate(expect):
+                    msg = f"source {i} renumber={keep} opts={name}"
+                    np.testing.assert_array_equal(depth[i], ed, err_msg=msg)
+                    np.testing.assert_array_equal(parent[i], ep, err_msg=msg)
+                assert st["teps_edges"] == teps
+            g.free()
+    finally:
+        ctx.set_policy(None)
 
 
 def test_union256_sssp_bit_exact(ctx):
