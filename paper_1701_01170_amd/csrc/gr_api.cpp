@@ -1974,8 +1974,8 @@ extern "C" gr_status gr_bc(gr_ctx* ctx, const gr_graph* g, const int32_t* source
     GR_HIP(hipMemcpyAsync(hm.data(), lvl_m, sizeof(unsigned long long) * L, hipMemcpyDeviceToHost,
                           st));
     GR_HIP(hipStreamSynchronize(st));
-    // per level: first vertex index, first edge position and first entry of
-    // its LB chunk map (levels stored one after another)
+    // per level: first vertex index, first edge position and first chunk of
+    // the pull passes' maps (levels stored one after another)
     tab.assign(3 * (size_t)L, 0);
     for (int32_t d = 0; d < L; ++d) {
       off[d + 1] = off[d] + hn[d];
