@@ -25,8 +25,11 @@ work).
 
 Side by side (breakdown): the learned selector against the heuristic, both
 untraced, interleaved per source; the R-MAT scale 14 BFS (single source, and
-learned against heuristic); the 2048 x 2048 grid; batched BFS and the
-256-graph union SSSP against single runs.
+learned against heuristic; degree-renumbered, with the generation-order time
+beside it); the 2048 x 2048 grid; batched BFS (R-MAT 20, renumbered and in
+generation order) and the 256-graph union SSSP against single runs;
+betweenness centrality on the headline graph; the BFS filter x direction
+optimisation ablation.
 
 Prints ONE JSON line.
 """
