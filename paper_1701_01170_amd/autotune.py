@@ -7,7 +7,8 @@ the same knobs on the device it runs on, timing the library's own traversals
 (event-timed device time, several seeded sources), and stores the best setting
 per (gfx arch, graph class, size bucket, traversal) in `tuning/<arch>.json`.
 
-Search (coordinate descent from the paper's defaults):
+Search (coordinate descent from the paper's defaults, or from the setting
+already stored for the graph's class when that is faster):
   1. lb_light_threshold in {0, 1024, 4096}
   2. lb_chunk in {512, 1024, 2048, 4096, 8192, 16384}
   3. adv_block (workgroup size of the push kernels) in {128, 256, 512}
@@ -142,6 +143,15 @@ def tune(g: Graph, kind: str, sources, log=print) -> tuple[dict, float, float]:
     base_ms = _time(g, kind, sources, best)
     best_ms = base_ms
     log(f"[{kind}] paper defaults: {base_ms:.3f} ms")
+    # warm start: the setting already stored for this class (nearest size),
+    # since one knob at a time from the defaults can miss a combination
+    stored = lookup(g, kind)
+    if stored:
+        cand = dict(best, **{k: v for k, v in stored.items() if k in KNOBS})
+        ms = _time(g, kind, sources, cand)
+        log(f"[{kind}] stored setting: {ms:.3f} ms")
+        if ms < best_ms * 0.99:
+            best, best_ms = cand, ms
 
     def try_set(key, values, valid=lambda c: True):
         nonlocal best, best_ms

@@ -52,3 +52,19 @@ def test_tuner_sweeps_every_launch_knob(monkeypatch):
     assert {kn.get("adv_block") for kn in seen} >= {128, 256, 512}
     assert best["twc_wave_min"] == 32 and best_ms == 0.5
     assert set(best) == set(at.KNOBS)
+
+
+def test_tuner_starts_from_the_stored_setting(monkeypatch):
+    """A combination that no single knob change from the defaults reaches (here
+    two knobs that only pay together) is kept when it is the stored setting."""
+    def fake_time(g, kind, sources, knobs, reps=1):
+        both = knobs.get("lb_chunk") == 4096 and knobs.get("adv_block") == 256
+        return 0.4 if both else 1.0
+
+    stored = {"lb_chunk": 4096, "adv_block": 256}
+    monkeypatch.setattr(at, "_time", fake_time)
+    monkeypatch.setattr(at, "lookup", lambda g, kind, arch=at.ARCH: dict(stored))
+    g = fake(1 << 20, 16 << 20, 4)
+    best, best_ms, base = at.tune(g, "bfs_multi", [0], log=lambda m: None)
+    assert best_ms == 0.4 and base == 1.0
+    assert best["lb_chunk"] == 4096 and best["adv_block"] == 256
