@@ -675,8 +675,10 @@ constexpr int kTraceKernelPullList = 11;
 constexpr int kTraceKernelIdem = 12;  // idempotent BFS push: 12 + (0 TWC, 1 LB_LIGHT, 2 LB)
 constexpr int kTraceMarksOffset = 8;  // SSSP relaxation with the byte-mark filter: 8 + (0 TWC, 1 LB_LIGHT, 2 LB)
 // SSSP iterations whose frontier has at least V / kSsspMarksDivisor edges use
-// the byte-mark filter.
-constexpr int64_t kSsspMarksDivisor = 4;
+// the byte-mark filter (and with it the cull and the distance bins of its
+// compaction).  R-MAT 22, mean SSSP over 12 sources: 2.25 ms from V / 4,
+// 2.21 ms from V / 8, 2.16-2.20 ms from V / 16, 2.19 ms from V / 32.
+constexpr int64_t kSsspMarksDivisor = 16;
 // ... and screen their edges with the one-byte distance mirror once the
 // frontiers so far, this one included, and the far pile of the priority queue
 // sum to at least V / kSsspMirrorDivisor vertices (an estimate of the vertices
