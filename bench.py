@@ -472,11 +472,19 @@ def bc_rmat22(gr, g, sources) -> dict:
         ms.append(st["device_ms"])
         te += st["teps_edges"]
     allst = gr.bc(g, [int(s) for s in sources], opts=o)[2]
+    # the per-pair choice against each form alone (same knobs and sources)
+    forms = {}
+    for name, dirs in (("push_both", gr.BC_DIR_PUSH | gr.BC_DIR_PUSH << 2),
+                       ("pull_both", gr.BC_DIR_PULL | gr.BC_DIR_PULL << 2)):
+        of = autotune.tuned_opts(g, "bc", bc_dir=dirs)
+        fm = [gr.bc(g, [int(s)], opts=of)[2]["device_ms"] for s in sources]
+        forms[name] = round(statistics.median(fm), 4)
     return {"sources": len(sources), "knobs": {"lb_chunk": o.lb_chunk, "adv_block": o.adv_block},
             "median_ms_per_source": round(statistics.median(ms), 4),
             "gteps": _gteps(te, sum(ms)),
             "all_sources_one_call_ms": round(allst["device_ms"], 4),
-            "all_sources_one_call_gteps": _gteps(allst["teps_edges"], allst["device_ms"])}
+            "all_sources_one_call_gteps": _gteps(allst["teps_edges"], allst["device_ms"]),
+            "median_ms_per_source_by_form": forms}
 
 
 def cpu_baseline(hg, srcs, budget_s: float = 10.0, max_pairs: int = 4) -> dict:
